@@ -1,0 +1,253 @@
+"""CPU oracle for Generative Monte Carlo cell transmission -- TEST INFRASTRUCTURE ONLY.
+
+Only the tests, `__graft_entry__.smoke()` and the CPU-baseline leg of `bench.py` may import
+this package.  It shares no code with the GPU path (`paper_2512_13965_amd`); the only
+module both sides use is the seeded input generator `paper_2512_13965_amd.inputs`, which
+holds none of the method's arithmetic.
+
+Contents
+  * `gmc_oracle.c` (built to `liboracle.so`): Philox4x32-10, Box-Muller noise, the analog
+    walk through one cell in FP64 (modes C and A), and FP64 cell-to-cell transport.
+  * this module: ctypes bindings for the above, and the FP64 velocity-MLP / Euler sampler
+    with optional BF16 / FP8-e4m3 quantisation emulation, plus the exit decoder.
+
+Paper references are to arXiv 2512.13965 (sections and equation numbers in order of
+appearance).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+SRC_PATH = os.path.join(_HERE, "gmc_oracle.c")
+
+FACE_ABSORBED = -1
+FACE_CAPPED = -2
+
+
+def build(force: bool = True) -> str:
+    """Compile the C oracle with gcc (plain -O2, IEEE semantics, no fast-math)."""
+    if force or not os.path.exists(LIB_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp,
+                               SRC_PATH, "-lm", "-lpthread"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_u01.argtypes = [ctypes.c_uint32]
+        L.orc_u01.restype = ctypes.c_double
+        L.orc_noise_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P]
+        L.orc_mc_transmit.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
+                                      ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_int]
+        L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P, P,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                    ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+# ----------------------------------------------------------------------------------------
+# random numbers
+# ----------------------------------------------------------------------------------------
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(ctr, np.uint32)
+    k = np.ascontiguousarray(key, np.uint32)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_p(c), _p(k), _p(out))
+    return out
+
+
+def u01(u: int) -> float:
+    return float(lib().orc_u01(ctypes.c_uint32(int(u) & 0xFFFFFFFF)))
+
+
+def noise(seed: int, id_base: int, n: int) -> np.ndarray:
+    """z ~ N(0, I_5) per sample from Philox + Box-Muller, FP64, layout [5][n]."""
+    z = np.zeros((5, n), np.float64)
+    lib().orc_noise_batch(seed, id_base, n, _p(z))
+    return z
+
+
+# ----------------------------------------------------------------------------------------
+# analog walk (paper section "Monte Carlo Method", eq. 4; modes C = implicit capture, A)
+# ----------------------------------------------------------------------------------------
+
+def mc_transmit(cond, mode: int, seed: int, id_base: int = 0, nthreads: int = 1) -> dict:
+    """FP64 analog transmissions of a canonical batch.  mode 0 = C (continuous absorption,
+    flights from sigma_s = c*tau), 1 = A (analog absorption).  Returns numpy arrays:
+    face (int32; -1 absorbed), pos, u, v, len (float64, units of L), ncoll (uint32)."""
+    n = len(cond)
+    lt = np.ascontiguousarray(cond.log_tau, np.float32)
+    cc = np.ascontiguousarray(cond.c, np.float32)
+    yy = np.ascontiguousarray(cond.y_in, np.float32)
+    ss = np.ascontiguousarray(cond.sin_th, np.float32)
+    out = dict(face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n), v=np.zeros(n),
+               len=np.zeros(n), ncoll=np.zeros(n, np.uint32))
+    lib().orc_mc_transmit(_p(lt), _p(cc), _p(yy), _p(ss), n, mode, seed, id_base,
+                          _p(out["face"]), _p(out["pos"]), _p(out["u"]), _p(out["v"]),
+                          _p(out["len"]), _p(out["ncoll"]), nthreads)
+    return out
+
+
+def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -> dict:
+    """FP64 cell-to-cell transport (analog mode-C walk in every cell, track-length tally).
+    Returns sums over the histories: flux[n_cells], absorbed[n_cells], leak, cutoff, events."""
+    tau = np.ascontiguousarray(problem.tau, np.float64)
+    c = np.ascontiguousarray(problem.c, np.float64)
+    flux = np.zeros(problem.n_cells)
+    absorbed = np.zeros(problem.n_cells)
+    sc = np.zeros(3)
+    lib().orc_transport(problem.nx, problem.ny, problem.L, _p(tau), _p(c), problem.src_x0,
+                        problem.src_y0, problem.src_nx, problem.src_ny, int(problem.reflect),
+                        problem.w_min, seed, h_begin, h_end, _p(flux), _p(absorbed), _p(sc),
+                        nthreads)
+    return dict(flux=flux, absorbed=absorbed, leak=sc[0], cutoff=sc[1], events=sc[2])
+
+
+# ----------------------------------------------------------------------------------------
+# quantisation emulation (BF16 and OCP FP8 e4m3, round-to-nearest-even)
+# ----------------------------------------------------------------------------------------
+
+def round_bf16(a) -> np.ndarray:
+    """Round each value to the nearest bfloat16 (8 significant bits, ties to even), FP64 out.
+    Values are first taken to float32 (the kernel holds them in float32)."""
+    f = np.asarray(a, np.float64).astype(np.float32)
+    bits = f.view(np.uint32).astype(np.uint64)
+    nan = np.isnan(f)
+    lsb = (bits >> 16) & 1
+    rounded = ((bits + 0x7FFF + lsb) >> 16) << 16
+    out = rounded.astype(np.uint32).view(np.float32).astype(np.float64)
+    out[nan] = np.nan
+    return out
+
+
+def round_e4m3(a) -> np.ndarray:
+    """Round to the nearest OCP FP8 e4m3 value (bias 7, 3 mantissa bits, subnormals down to
+    2^-9, largest finite 448), ties to even, saturating at +-448.  FP64 in and out."""
+    x = np.asarray(a, np.float64)
+    s = np.sign(x)
+    m = np.abs(x)
+    m = np.minimum(m, 448.0)
+    # exponent e of the binade [2^e, 2^(e+1)) holding m, clamped below at -6 so that the
+    # subnormal range keeps the spacing 2^-9
+    _, ex = np.frexp(np.where(m > 0, m, 1.0))
+    e = np.maximum(ex.astype(np.float64) - 1.0, -6.0)
+    q = 2.0 ** (e - 3.0)                    # spacing of representable values in this binade
+    r = np.round(m / q) * q                 # numpy rounds halves to even
+    r = np.minimum(r, 448.0)
+    return s * r
+
+
+# ----------------------------------------------------------------------------------------
+# velocity MLP + Euler sampler (paper "Conditional Flow Matching", eq. 8)
+# ----------------------------------------------------------------------------------------
+
+PREC_FP64 = "fp64"    # exact arithmetic of the network, no rounding
+PREC_BF16 = "bf16"    # inputs of every layer and all weights rounded to bfloat16
+PREC_FP8 = "fp8"      # hidden H x H layers in e4m3 with per-layer scales, first/last in bf16
+
+
+def silu(a):
+    return a / (1.0 + np.exp(-a))
+
+
+def condition_features(cond) -> np.ndarray:
+    """Condition part of the network input: (ln tau, c, 2*y_in - 1, sin theta_in), [n, 4]."""
+    return np.stack([np.asarray(cond.log_tau, np.float64), np.asarray(cond.c, np.float64),
+                     2.0 * np.asarray(cond.y_in, np.float64) - 1.0,
+                     np.asarray(cond.sin_th, np.float64)], axis=1)
+
+
+def velocity(weights, x, t, condf, precision=PREC_FP64):
+    """v_theta(x, t | c) for a batch: x [n,5], t scalar, condf [n,4] -> [n,5].
+    Layers: Linear(10,H) SiLU, 3 x (Linear(H,H) SiLU), Linear(H,5)."""
+    n = x.shape[0]
+    h = np.concatenate([x, np.full((n, 1), float(t)), condf], axis=1)
+    L = len(weights.W)
+    for l in range(L):
+        W = weights.W[l].astype(np.float64)
+        b = weights.b[l].astype(np.float64)
+        hidden_hh = 0 < l < L - 1
+        if precision == PREC_BF16 or (precision == PREC_FP8 and not hidden_hh):
+            h = round_bf16(h) @ round_bf16(W).T + b
+        elif precision == PREC_FP8:
+            sa = float(weights.act_scale[l])
+            sw = float(weights.w_scale[l])
+            h = (round_e4m3(h / sa) @ round_e4m3(W / sw).T) * (sa * sw) + b
+        else:
+            h = h @ W.T + b
+        if l < L - 1:
+            h = silu(h)
+    return h
+
+
+def sample_raw(weights, cond, K: int, z: np.ndarray, precision=PREC_FP64) -> np.ndarray:
+    """Integrate dx/dt = v(x, t) from x(0) = z with K explicit Euler steps, t_k = k / K.
+    z: [5][n].  Returns x_K as [n, 5] FP64."""
+    z = np.asarray(z, np.float64)
+    if z.ndim != 2 or z.shape[0] != 5:
+        raise ValueError("noise must have layout [5][n]")
+    x = z.T.copy()
+    condf = condition_features(cond)
+    dt = 1.0 / K
+    for k in range(K):
+        x = x + dt * velocity(weights, x, k * dt, condf, precision)
+    return x
+
+
+OUTWARD = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])
+
+
+def decode(raw) -> dict:
+    """Exit record from the network output (paper eq. 11; the target layout is
+    a0 = 2r - 1, (a1, a2) = exit direction, a3 = ln(path / L), a4 = face - 1.5).
+
+    face = number of the thresholds -1, 0, 1 that a4 reaches (clamped to 0..3);
+    pos = clamp((a0 + 1) / 2, 0, 1); direction = (a1, a2) normalised (outward normal of the
+    face if the norm is below 1e-6), its normal component reflected if it points into the
+    cell; path = exp(a3).  Also returns per-sample flags: bit0 pos clamped, bit1 direction
+    reflected, bit2 zero-norm direction."""
+    raw = np.asarray(raw, np.float64)
+    a0, a1, a2, a3, a4 = (raw[:, i] for i in range(5))
+    face = (a4 >= -1.0).astype(np.int32) + (a4 >= 0.0) + (a4 >= 1.0)
+    p = (a0 + 1.0) / 2.0
+    flags = np.zeros(raw.shape[0], np.int32)
+    flags |= ((p < 0.0) | (p > 1.0)).astype(np.int32)
+    pos = np.clip(p, 0.0, 1.0)
+    nrm = np.hypot(a1, a2)
+    small = nrm < 1e-6
+    nout = OUTWARD[face]
+    safe = np.where(small, 1.0, nrm)
+    u = np.where(small, nout[:, 0], a1 / safe)
+    v = np.where(small, nout[:, 1], a2 / safe)
+    dn = u * nout[:, 0] + v * nout[:, 1]
+    inward = dn < 0.0
+    u = np.where(inward, u - 2.0 * dn * nout[:, 0], u)
+    v = np.where(inward, v - 2.0 * dn * nout[:, 1], v)
+    flags |= inward.astype(np.int32) << 1
+    flags |= small.astype(np.int32) << 2
+    return dict(face=face, pos=pos, u=u, v=v, len=np.exp(a3), flags=flags)

@@ -1,0 +1,264 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/benchmarks and the CPU oracle.
+
+This module holds no arithmetic of the method itself: it only draws the inputs a
+caller would hand to a cell-transmission sampler (entry conditions, network
+weights, Gaussian noise, transport problem descriptions) and packs the weights
+into the on-disk blob that the C library parses.  Every generator takes an
+explicit integer seed and uses numpy's PCG64, so any input can be re-created
+from its seed alone.
+
+Workload recipes (sizes and laws follow the paper's workloads):
+
+* entry conditions of a cell transmission in the canonical left-entry frame
+  (paper, "Network Architecture and Inputs", eq. 10, and "Transport
+  Algorithm", first stage): optical side tau = sigma_t * L with
+  ln tau ~ U[ln 0.1, ln 100], scattering ratio c ~ U[0, 1], entry height
+  y_in ~ U(0, 1) on the left face, and a cosine-law entry direction.  For a
+  flatland cosine law the pdf of theta is cos(theta)/2 on (-pi/2, pi/2), which
+  makes sin(theta_in) uniform on (-1, 1); we draw sin(theta_in) directly.
+* velocity-network weights: fully connected 10 -> H -> H -> H -> H -> 5,
+  every weight and bias U(-1/sqrt(fan_in), +1/sqrt(fan_in)) (the usual
+  default initialisation of a linear layer), float32.
+* noise z ~ N(0, I_5) when a caller wants to hand the sampler its noise
+  explicitly (paper, "Conditional Flow Matching", eq. 8).
+"""
+from __future__ import annotations
+
+import math
+import struct
+from dataclasses import dataclass, field
+
+import numpy as np
+
+N_IN = 10   # x (5), t (1), condition (4)
+N_OUT = 5   # exit state: position, cos, sin, log path, face
+N_LAYERS = 5
+
+BLOB_MAGIC = b"GMCW0001"
+BLOB_VERSION = 1
+# header: magic[8], version, n_in, hidden, n_out, n_layers, flags, seed, reserved (8 x u32),
+# act_scale[5] f32, w_scale[5] f32
+_HDR = struct.Struct("<8s8I5f5f")
+
+LOG_TAU_MIN = math.log(0.1)
+LOG_TAU_MAX = math.log(100.0)
+
+
+def rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(int(seed)))
+
+
+def _open01(g: np.random.Generator, n: int) -> np.ndarray:
+    """Uniform on the open interval (0, 1) in float32."""
+    u = g.random(n, dtype=np.float64)
+    u = np.clip(u, 2.0 ** -25, 1.0 - 2.0 ** -24)
+    return u.astype(np.float32)
+
+
+@dataclass
+class Conditions:
+    """Structure-of-arrays batch of canonical entry conditions (all float32, length n)."""
+    log_tau: np.ndarray
+    c: np.ndarray
+    y_in: np.ndarray
+    sin_th: np.ndarray
+
+    def __len__(self) -> int:
+        return int(self.log_tau.shape[0])
+
+    def subset(self, idx) -> "Conditions":
+        return Conditions(self.log_tau[idx].copy(), self.c[idx].copy(),
+                          self.y_in[idx].copy(), self.sin_th[idx].copy())
+
+
+def transmission_conditions(n: int, seed: int, log_tau_range=(LOG_TAU_MIN, LOG_TAU_MAX),
+                            c_range=(0.0, 1.0)) -> Conditions:
+    """Mixed-cell batch: ln tau ~ U[range], c ~ U[range], y_in ~ U(0,1), cosine-law entry."""
+    g = rng(seed)
+    lo, hi = log_tau_range
+    log_tau = (lo + (hi - lo) * g.random(n)).astype(np.float32)
+    c = (c_range[0] + (c_range[1] - c_range[0]) * g.random(n)).astype(np.float32)
+    y_in = _open01(g, n)
+    sin_th = (2.0 * _open01(g, n).astype(np.float64) - 1.0).astype(np.float32)
+    return Conditions(log_tau, c, y_in, sin_th)
+
+
+def fixed_cell_conditions(n: int, tau: float, c: float, seed: int) -> Conditions:
+    """One material (tau, c) for every particle; y_in ~ U(0,1), cosine-law entry."""
+    g = rng(seed)
+    y_in = _open01(g, n)
+    sin_th = (2.0 * _open01(g, n).astype(np.float64) - 1.0).astype(np.float32)
+    return Conditions(np.full(n, np.float32(math.log(tau)), np.float32),
+                      np.full(n, np.float32(c), np.float32), y_in, sin_th)
+
+
+def normal_incidence_conditions(n: int, tau: float, c: float, seed: int) -> Conditions:
+    """A beam along +x (sin theta = 0) at uniform entry height."""
+    g = rng(seed)
+    return Conditions(np.full(n, np.float32(math.log(tau)), np.float32),
+                      np.full(n, np.float32(c), np.float32), _open01(g, n),
+                      np.zeros(n, np.float32))
+
+
+def noise(n: int, seed: int) -> np.ndarray:
+    """Explicit N(0, I_5) noise, float32, layout [5][n]."""
+    return rng(seed).standard_normal((N_OUT, n)).astype(np.float32)
+
+
+# --------------------------------------------------------------------------------------
+# velocity-network weights
+# --------------------------------------------------------------------------------------
+
+def layer_dims(hidden: int):
+    return [(hidden, N_IN), (hidden, hidden), (hidden, hidden), (hidden, hidden), (N_OUT, hidden)]
+
+
+@dataclass
+class Weights:
+    """Float32 weights W[l] of shape [out, in] (row-major) and biases b[l] of shape [out]."""
+    hidden: int
+    W: list
+    b: list
+    act_scale: np.ndarray = field(default_factory=lambda: np.ones(N_LAYERS, np.float32))
+    w_scale: np.ndarray = field(default_factory=lambda: np.ones(N_LAYERS, np.float32))
+    seed: int = 0
+
+    def n_params(self) -> int:
+        return int(sum(w.size + bb.size for w, bb in zip(self.W, self.b)))
+
+
+def pow2_ceil_scale(amax: float, fmax: float = 448.0) -> float:
+    """Smallest power of two s with amax / s <= fmax (1.0 for amax == 0)."""
+    if amax <= 0.0:
+        return 1.0
+    return float(2.0 ** math.ceil(math.log2(amax / fmax)))
+
+
+def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5) -> Weights:
+    """Seeded random-init network, U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for W and b.
+
+    The per-layer FP8 scales are stored with the weights: the weight scale is the
+    power of two that brings max|W_l| under the e4m3 maximum 448, and the
+    activation scale of every layer is the constant `act_scale` (a power of two
+    chosen by the model's author; the hidden activations of such a network stay
+    well inside 448 * act_scale).
+    """
+    g = rng(seed)
+    W, b = [], []
+    for (o, i) in layer_dims(hidden):
+        bound = 1.0 / math.sqrt(i)
+        W.append(g.uniform(-bound, bound, size=(o, i)).astype(np.float32))
+        b.append(g.uniform(-bound, bound, size=(o,)).astype(np.float32))
+    w_scale = np.array([pow2_ceil_scale(float(np.abs(w).max())) for w in W], np.float32)
+    a_scale = np.full(N_LAYERS, np.float32(act_scale), np.float32)
+    return Weights(hidden, W, b, a_scale, w_scale, seed)
+
+
+def pack_blob(w: Weights) -> bytes:
+    """Serialise to the versioned little-endian blob read by gmc_model_create()."""
+    hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, N_IN, w.hidden, N_OUT, N_LAYERS, 0,
+                    int(w.seed) & 0xFFFFFFFF, 0,
+                    *[float(x) for x in w.act_scale], *[float(x) for x in w.w_scale])
+    parts = [hdr]
+    for W, b in zip(w.W, w.b):
+        parts.append(np.ascontiguousarray(W, np.float32).tobytes())
+        parts.append(np.ascontiguousarray(b, np.float32).tobytes())
+    return b"".join(parts)
+
+
+def unpack_blob(blob: bytes) -> Weights:
+    fields = _HDR.unpack_from(blob, 0)
+    magic, version, n_in, hidden, n_out, n_layers, _flags, seed, _res = fields[:9]
+    if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in != N_IN or n_out != N_OUT \
+            or n_layers != N_LAYERS:
+        raise ValueError("not a GMC weights blob of a supported version")
+    act = np.array(fields[9:14], np.float32)
+    wsc = np.array(fields[14:19], np.float32)
+    off = _HDR.size
+    W, b = [], []
+    for (o, i) in layer_dims(hidden):
+        W.append(np.frombuffer(blob, np.float32, o * i, off).reshape(o, i).copy())
+        off += 4 * o * i
+        b.append(np.frombuffer(blob, np.float32, o, off).copy())
+        off += 4 * o
+    if off != len(blob):
+        raise ValueError("weights blob has trailing or missing bytes")
+    return Weights(hidden, W, b, act, wsc, seed)
+
+
+def save_blob(w: Weights, path: str) -> None:
+    with open(path, "wb") as f:
+        f.write(pack_blob(w))
+
+
+def load_blob(path: str) -> Weights:
+    with open(path, "rb") as f:
+        return unpack_blob(f.read())
+
+
+# --------------------------------------------------------------------------------------
+# transport problems (2-D grids of square cells)
+# --------------------------------------------------------------------------------------
+
+@dataclass
+class Problem:
+    """A 2-D grid of nx * ny square cells of side L, per-cell (tau, c), a central source block.
+
+    Cell (i, j) has linear index j * nx + i (i along x).  tau = sigma_t * L.
+    The isotropic unit source is uniform over the source block's cells.
+    """
+    nx: int
+    ny: int
+    L: float
+    tau: np.ndarray       # float64 [ny * nx]
+    c: np.ndarray         # float64 [ny * nx]
+    src_x0: int
+    src_y0: int
+    src_nx: int
+    src_ny: int
+    reflect: bool = False
+    w_min: float = 1e-6
+
+    @property
+    def n_cells(self) -> int:
+        return self.nx * self.ny
+
+
+def checkerboard_problem(n: int = 32, tau=(0.5, 50.0), c=(0.5, 0.99), src: int = 4,
+                         L: float = 1.0, reflect: bool = False) -> Problem:
+    """n x n unit cells; (tau[0], c[0]) where i + j is even, (tau[1], c[1]) where odd;
+    isotropic source in the central src x src cells; vacuum boundaries."""
+    i = np.arange(n)[None, :]
+    j = np.arange(n)[:, None]
+    odd = ((i + j) % 2).astype(bool).reshape(-1)
+    t = np.where(odd, tau[1], tau[0]).astype(np.float64)
+    cc = np.where(odd, c[1], c[0]).astype(np.float64)
+    s0 = (n - src) // 2
+    return Problem(n, n, L, t, cc, s0, s0, src, src, reflect)
+
+
+def homogeneous_problem(n: int, tau: float, c: float, reflect: bool, src_all: bool = True,
+                        L: float = 1.0) -> Problem:
+    t = np.full(n * n, tau, np.float64)
+    cc = np.full(n * n, c, np.float64)
+    if src_all:
+        return Problem(n, n, L, t, cc, 0, 0, n, n, reflect)
+    s0 = (n - max(1, n // 8)) // 2
+    return Problem(n, n, L, t, cc, s0, s0, max(1, n // 8), max(1, n // 8), reflect)
+
+
+def random_problem(seed: int, side_range=(16, 128), log_tau_range=(math.log(0.1), math.log(200.0)),
+                   hist_log10_range=(4.0, 7.0)):
+    """A serving request: grid side ~ U{16..128}, per-cell ln tau ~ U[range], c ~ U[0,1],
+    central (side/8)^2 source block, histories log-uniform in [1e4, 1e7].
+    Returns (problem, n_histories)."""
+    g = rng(seed)
+    n = int(g.integers(side_range[0], side_range[1] + 1))
+    lo, hi = log_tau_range
+    tau = np.exp(lo + (hi - lo) * g.random(n * n))
+    c = g.random(n * n)
+    s = max(1, n // 8)
+    s0 = (n - s) // 2
+    nh = int(round(10.0 ** (hist_log10_range[0] + (hist_log10_range[1] - hist_log10_range[0])
+                            * g.random())))
+    return Problem(n, n, 1.0, tau, c, s0, s0, s, s), nh

@@ -1,0 +1,143 @@
+"""Pins for the oracle's cell-to-cell transport (paper section "Transport Algorithm", the
+track-length estimator of eqs. 5-7, and the convergence metric of eq. 12)."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2512_13965_amd import inputs
+
+NT = 8
+
+
+def test_weight_balance_per_run(orc):
+    # P6: every unit of source weight leaks, is absorbed, or is cut off
+    prob = inputs.checkerboard_problem(8, src=2)
+    n = 4000
+    r = orc.transport(prob, seed=1, h_begin=0, h_end=n, nthreads=NT)
+    total = r["leak"] + r["absorbed"].sum() + r["cutoff"]
+    assert abs(total - n) < 1e-9 * n
+    assert r["cutoff"] < 1e-6 * n * 10
+
+
+def test_reflecting_box_flux_equals_source_over_sigma_a(orc):
+    # P7: homogeneous reflecting box, uniform isotropic source of N particles:
+    # all weight is absorbed (up to the cutoff), sum_i sigma_a phi_i V = N, and by symmetry
+    # E[phi_i] = N / (sigma_a V n_cells) in every cell.
+    tau, c, L = 2.0, 0.8, 0.5
+    prob = inputs.homogeneous_problem(6, tau, c, reflect=True, L=L)
+    n = 20_000
+    r = orc.transport(prob, seed=2, h_begin=0, h_end=n, nthreads=NT)
+    sig_a = (1 - c) * tau / L
+    V = L * L
+    assert r["leak"] == 0.0
+    assert abs(r["absorbed"].sum() + r["cutoff"] - n) < 1e-9 * n
+    np.testing.assert_allclose((r["flux"] * sig_a * V).sum(), r["absorbed"].sum(), rtol=1e-12)
+    phi_exp = n / (sig_a * V * prob.n_cells)
+    # per-cell fluctuations: compare with independent repeats
+    reps = [orc.transport(prob, seed=10 + k, h_begin=0, h_end=n, nthreads=NT)["flux"]
+            for k in range(4)]
+    reps = np.array(reps + [r["flux"]])
+    m = reps.mean(0)
+    se = reps.std(0, ddof=1) / math.sqrt(reps.shape[0])
+    z = np.abs(m - phi_exp) / np.maximum(se, 1e-12)
+    assert np.median(z) < 2.0
+    assert abs(m.mean() - phi_exp) / phi_exp < 2e-3
+
+
+def test_vacuum_thin_grid_leaks_everything(orc):
+    prob = inputs.homogeneous_problem(4, 1e-9, 0.0, reflect=False)
+    n = 2000
+    r = orc.transport(prob, seed=3, h_begin=0, h_end=n, nthreads=NT)
+    assert abs(r["leak"] - n) < 1e-6 * n
+    # flux of a pure streamer: track length per unit volume; total track length of
+    # isotropic chords from uniform points in a 4x4 square
+    assert r["flux"].sum() > 0
+
+
+def test_histories_are_independent_of_chunking(orc):
+    prob = inputs.checkerboard_problem(8, src=2)
+    a = orc.transport(prob, seed=4, h_begin=0, h_end=600, nthreads=1)
+    b = orc.transport(prob, seed=4, h_begin=0, h_end=250, nthreads=3)
+    c = orc.transport(prob, seed=4, h_begin=250, h_end=600, nthreads=2)
+    np.testing.assert_allclose(a["flux"], b["flux"] + c["flux"], rtol=1e-12, atol=1e-15)
+    assert a["events"] == b["events"] + c["events"]
+
+
+@pytest.mark.slow
+def test_eq12_statistical_error_decays_as_inverse_sqrt_n(orc):
+    # eq. 12: cell-averaged standard deviation over K = 5 runs, slope -1/2 in log-log
+    prob = inputs.checkerboard_problem(8, src=2)
+    Ns = [1000, 4000, 16000]
+    sig = []
+    for N in Ns:
+        runs = np.array([orc.transport(prob, seed=100 + k, h_begin=0, h_end=N, nthreads=NT)["flux"]
+                         / N for k in range(5)])
+        sig.append(np.mean(runs.std(0, ddof=1)))
+    slope = np.polyfit(np.log(Ns), np.log(sig), 1)[0]
+    assert abs(slope + 0.5) < 0.1
+
+
+def _global_walk_flux(prob, n, seed):
+    """Brute-force reference: one continuous random walk per history in global coordinates
+    over the whole grid (no per-cell canonical frames), flights from the local sigma_s,
+    continuous absorption per segment, track-length tally per segment.  Pure Python."""
+    g = np.random.default_rng(seed)
+    L = prob.L
+    flux = np.zeros(prob.n_cells)
+    for _ in range(n):
+        k = g.integers(prob.src_nx * prob.src_ny)
+        ci = prob.src_x0 + k % prob.src_nx
+        cj = prob.src_y0 + k // prob.src_nx
+        x = (ci + g.random()) * L
+        y = (cj + g.random()) * L
+        ph = 2 * math.pi * g.random()
+        u, v = math.cos(ph), math.sin(ph)
+        w = 1.0
+        d_s = None
+        while True:
+            cell = cj * prob.nx + ci
+            sig_t = prob.tau[cell] / L
+            sig_s = prob.c[cell] * sig_t
+            sig_a = sig_t - sig_s
+            if d_s is None:
+                d_s = -math.log(1.0 - g.random()) / sig_s if sig_s > 0 else math.inf
+            tx = ((ci + 1) * L - x) / u if u > 0 else ((ci * L - x) / u if u < 0 else math.inf)
+            ty = ((cj + 1) * L - y) / v if v > 0 else ((cj * L - y) / v if v < 0 else math.inf)
+            db = min(tx, ty)
+            seg = min(db, d_s)
+            dw = w * (-math.expm1(-sig_a * seg))
+            flux[cell] += (dw / sig_a if sig_a > 0 else w * seg) / (L * L)
+            w -= dw
+            x += seg * u
+            y += seg * v
+            if d_s < db:
+                ph = 2 * math.pi * g.random()
+                u, v = math.cos(ph), math.sin(ph)
+                d_s = None
+                continue
+            d_s = None         # exponential flights are memoryless: redraw in the next cell
+            if tx <= ty:
+                ci += 1 if u > 0 else -1
+            else:
+                cj += 1 if v > 0 else -1
+            if ci < 0 or cj < 0 or ci >= prob.nx or cj >= prob.ny:
+                break
+            if w < prob.w_min:
+                break
+    return flux
+
+
+def test_cell_to_cell_transport_matches_global_walk(orc):
+    # the per-cell canonical rotation (stage 1), face decoding and neighbour move (stage 4)
+    # must reproduce a plain global random walk over the same heterogeneous grid
+    t = np.array([0.3, 2.0, 0.7, 1.5, 0.5, 3.0, 0.9, 0.2, 1.1])
+    c = np.array([0.9, 0.5, 0.99, 0.7, 0.8, 0.95, 0.3, 1.0, 0.6])
+    prob = inputs.Problem(3, 3, 0.7, t, c, 1, 1, 1, 1)
+    n, runs = 3000, 5
+    ref = np.array([_global_walk_flux(prob, n, seed=s) / n for s in range(runs)])
+    got = np.array([orc.transport(prob, seed=40 + s, h_begin=0, h_end=n, nthreads=NT)["flux"] / n
+                    for s in range(runs)])
+    se = np.sqrt(ref.var(0, ddof=1) / runs + got.var(0, ddof=1) / runs)
+    z = np.abs(ref.mean(0) - got.mean(0)) / np.maximum(se, 1e-12)
+    assert z.max() < 5.0, z
