@@ -1,0 +1,204 @@
+#!/usr/bin/env python3
+"""Benchmark of the GMC cell-transmission sampler on one MI355X.
+
+A step is one batch of 65,536 cell transmissions (ln tau ~ U[ln 0.1, ln 100], c ~ U[0, 1],
+uniform entry height, cosine-law entry direction) through the fused velocity-MLP + Euler
+sampler: FP32, 4 hidden layers x 256 SiLU, K = 16 Euler steps, seeded random-init weights,
+Philox noise, decoded exits written to HBM.  `value` is transmissions per second with the
+inputs resident in HBM.
+
+Beside the timed steps the same run measures, with HIP events on the launch stream:
+  * the analog random-walk kernel that the sampler replaces, on 2^20 transmissions per
+    optical thickness tau = 1 .. 100 (c = 1, pure scattering) and the GMC/analog ratio;
+  * the width-512 sampler in BF16 and FP8 (2^20 transmissions, K = 8 / 16 / 32);
+  * the FP64 CPU oracle on a bounded sample of the same workload (cpu_baseline).
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell transmissions/sec GMC vs analog MC at tau=1..100; p50/p99 request latency"
+TAUS = [1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0]
+PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
+
+
+def flops_per_sample(H: int, K: int) -> float:
+    # per velocity evaluation: 2 * (10 H + 3 H^2 + 5 H) multiply-adds counted as 2 flops each
+    return K * 2.0 * (10 * H + 3 * H * H + 5 * H)
+
+
+def time_launches(fn, reps: int, stream):
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for a, b in evs:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    return np.array([a.elapsed_time(b) for a, b in evs])     # ms
+
+
+def cpu_baseline(H, K, budget_s=15.0):
+    """The FP64 oracle sampler, timed on the host on a bounded sample of the workload."""
+    import oracle
+    from threadpoolctl import threadpool_info
+    from paper_2512_13965_amd import inputs
+    w = inputs.random_weights(H, 1)
+    probe = 256
+    cond = inputs.transmission_conditions(probe, 3)
+    z = oracle.noise(2, 0, probe)
+    t0 = time.perf_counter()
+    oracle.sample_raw(w, cond, K, z)
+    dt = time.perf_counter() - t0
+    n = int(min(65536, max(probe, probe * budget_s / max(dt, 1e-6))))
+    cond = inputs.transmission_conditions(n, 3)
+    t0 = time.perf_counter()
+    z = oracle.noise(2, 0, n)
+    raw = oracle.sample_raw(w, cond, K, z)
+    oracle.decode(raw)
+    dt = time.perf_counter() - t0
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": n / dt, "unit": "transmissions/s", "cores": int(threads), "kind": "oracle",
+            "sample": f"{n} transmissions of the same workload (FP64 numpy MLP + Philox/Box-Muller "
+                      f"noise + decode), {dt:.1f} s"}
+
+
+def cpu_baseline_analog(tau=100.0, budget_s=8.0):
+    import oracle
+    from paper_2512_13965_amd import inputs
+    nt = os.cpu_count() or 1
+    n = 4096
+    cond = inputs.fixed_cell_conditions(n, tau, 1.0, 9)
+    t0 = time.perf_counter()
+    oracle.mc_transmit(cond, 0, 2, nthreads=nt)
+    dt = time.perf_counter() - t0
+    n = int(min(1 << 20, max(n, n * budget_s / max(dt, 1e-6))))
+    cond = inputs.fixed_cell_conditions(n, tau, 1.0, 9)
+    t0 = time.perf_counter()
+    oracle.mc_transmit(cond, 0, 2, nthreads=nt)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "transmissions/s", "cores": nt, "kind": "oracle",
+            "sample": f"{n} analog transmissions at tau={tau:g}, c=1, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="only the timed steps (for profiling)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the sampler shards by "
+              f"particle id with no communication, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2512_13965_amd import binding, inputs
+
+    torch.cuda.init()
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    H, K, N = 256, 16, 65536
+    w = inputs.random_weights(H, 1)
+    model = binding.Model(inputs.pack_blob(w), "fp32")
+    cond = binding.DeviceCond.from_host(inputs.transmission_conditions(N, 3), dev)
+    out = binding.DeviceExit.empty(N, dev)
+
+    def step():
+        binding.gmc_transmit(model, cond, K, seed=2, id_base=0, out=out)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        step()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = np.array([a.elapsed_time(b) for a, b in evs])
+    ms_per_step = 1e3 * wall / args.steps
+    value = N / (ms_per_step * 1e-3)
+    fl = flops_per_sample(H, K) * N
+    achieved = fl / (kms.mean() * 1e-3)
+    res = {
+        "metric": METRIC, "value": value, "unit": "transmissions/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "GMC cell-transmission sampler: FP32 velocity MLP 10->256x4->5 SiLU, "
+                               "K=16 Euler steps, batch 65536, ln tau~U[ln 0.1, ln 100], c~U[0,1], "
+                               "seeded random-init weights, Philox noise",
+                   "hidden": H, "K": K, "batch": N, "precision": "fp32"},
+        "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["f32"] / 1e12,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
+                     "kernel": "mlp_ode_kernel<fp32,256>", "avg_launch_ms": float(kms.mean())},
+        "launch_ms_p50": float(np.median(kms)), "launch_ms_p99": float(np.quantile(kms, 0.99)),
+    }
+    if args.quick:
+        print(json.dumps(res))
+        return
+
+    # analog walk vs GMC, tau sweep (pure scattering), 2^20 transmissions per launch
+    NA = 1 << 20
+    sweep = []
+    outA = binding.DeviceExit.empty(NA, dev)
+    for tau in TAUS:
+        c = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(NA, tau, 1.0, 9), dev)
+        fn = lambda: binding.mc_transmit(c, binding.MODE_CONTINUOUS, 2, 0, out=outA)
+        fn()
+        ms = time_launches(fn, 3, stream)
+        sweep.append({"tau": tau, "analog_tps": NA / (np.median(ms) * 1e-3),
+                      "analog_ms": float(np.median(ms)),
+                      "mean_flights_expected": 1 + math.pi * tau / 4})
+    gmc_tps = N / (kms.mean() * 1e-3)
+    for s in sweep:
+        s["gmc_fp32_h256_tps"] = gmc_tps
+        s["gmc_over_analog"] = gmc_tps / s["analog_tps"]
+    res["tau_sweep"] = sweep
+
+    # width-512 sampler in BF16 / FP8 on 2^20 transmissions (cfg2 shape, random-init weights)
+    NB = 1 << 20
+    w5 = inputs.random_weights(512, 1)
+    condB = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
+    outB = binding.DeviceExit.empty(NB, dev)
+    wide = []
+    for prec in ("bf16", "fp8"):
+        m = binding.Model(inputs.pack_blob(w5), prec)
+        for KK in (8, 16, 32):
+            fn = lambda: binding.gmc_transmit(m, condB, KK, 2, 0, out=outB)
+            fn()
+            ms = time_launches(fn, 3, stream)
+            t = float(np.median(ms))
+            fl = flops_per_sample(512, KK) * NB / (t * 1e-3)
+            wide.append({"precision": prec, "hidden": 512, "K": KK, "batch": NB, "ms": t,
+                         "tps": NB / (t * 1e-3), "tflops": fl / 1e12, "frac_peak": fl / PEAK[prec]})
+        m.close()
+    res["wide_sampler"] = wide
+    for s in sweep:
+        s["gmc_bf16_h512_k16_tps"] = next(x["tps"] for x in wide if x["precision"] == "bf16" and x["K"] == 16)
+
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(H, K)
+        res["cpu_baseline_analog_tau100"] = cpu_baseline_analog()
+    print(json.dumps(res))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * gmc.h -- C ABI of the MI355X (gfx950) Generative Monte Carlo cell-transmission library.
+ *
+ * Method: Farmer, Murray, Krotz, McClarren, "Generative Monte Carlo Sampling for
+ * Constant-Cost Particle Transport", arXiv 2512.13965.  A particle entering a square cell is
+ * "teleported" to its exit state by integrating a conditional flow-matching velocity field
+ * from Gaussian noise (section "Conditional Flow Matching", eq. 8) instead of following its
+ * random walk (section "Monte Carlo Method", eq. 4).  Both samplers live behind this ABI.
+ *
+ * Conventions for every entry point
+ *   - Pointers named "device" are HIP device pointers owned by the caller; the library never
+ *     frees them.  Host pointers are read before the call returns.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Every sampling call is
+ *     asynchronous on that stream and returns once its kernels are enqueued.
+ *   - Return value: GMC_OK (0) or a negative gmc_status; no exceptions cross the ABI and the
+ *     library never aborts.  gmc_last_error() gives a thread-local message for the last
+ *     failure on the calling thread.
+ *   - Lengths are in units of the cell side L and directions are in the canonical frame in
+ *     which the particle enters through the left face x = 0 of the unit square (section
+ *     "Transport Algorithm", first stage).  Faces: 0 bottom (y=0), 1 right (x=1), 2 top (y=1),
+ *     3 left (x=0).  The position along an exit face runs counter-clockwise: bottom x,
+ *     right y, top 1-x, left 1-y.
+ *   - Results are a pure function of (weights, condition, seed, particle id, K): they do not
+ *     depend on the batch size or on a particle's position in the batch.
+ */
+#ifndef GMC_H
+#define GMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    GMC_OK = 0,
+    GMC_EINVAL = -1,         /* bad argument (null pointer, size, unsupported K, bad blob) */
+    GMC_ENOMEM = -2,         /* device allocation failed or a capacity would be exceeded */
+    GMC_EDEVICE = -3,        /* a HIP call or kernel launch failed */
+    GMC_EUNSUPPORTED = -4    /* valid request this build does not implement (e.g. width) */
+} gmc_status;
+
+typedef enum {
+    GMC_FP32 = 0,            /* FP32 operands, FP32 MFMA */
+    GMC_BF16 = 1,            /* BF16 operands, FP32 accumulation */
+    GMC_FP8_E4M3 = 2         /* OCP e4m3 hidden layers (per-layer power-of-two scales),
+                                first and last layer BF16, FP32 accumulation */
+} gmc_precision;
+
+typedef enum { GMC_MODE_CONTINUOUS = 0, GMC_MODE_ANALOG = 1 } gmc_walk_mode;
+typedef enum { GMC_SAMPLER_GMC = 0, GMC_SAMPLER_MC = 1 } gmc_sampler;
+
+#define GMC_FACE_ABSORBED (-1)   /* analog-absorption walk ended inside the cell */
+#define GMC_FACE_CAPPED (-2)     /* walk exceeded 2^24 flights (never seen in practice) */
+
+/* Canonical entry conditions of n transmissions, device SoA, float32 [n] each
+ * (paper eq. 10 in the reading ln tau = ln(sigma_t L), c = sigma_s / sigma_t):
+ *   log_tau  natural log of the optical side tau = sigma_t * L
+ *   c        scattering ratio sigma_s / sigma_t in [0, 1]
+ *   y_in     entry height on the left face, in [0, 1]
+ *   sin_th   sine of the entry angle from +x, in (-1, 1) (the direction is
+ *            (sqrt(1 - sin_th^2), sin_th)) */
+typedef struct {
+    const float *log_tau, *c, *y_in, *sin_th;
+} gmc_cond;
+
+/* Exit records of n transmissions, device SoA, [n] each (paper eq. 11):
+ *   face     int32 exit face 0..3 (GMC_FACE_* for walks that did not exit)
+ *   pos      float32 counter-clockwise position along the exit face, [0, 1]
+ *   dir_cos, dir_sin   float32 exit direction (unit vector, pointing out of the face)
+ *   path     float32 total track length in the cell, units of L */
+typedef struct {
+    int32_t *face;
+    float *pos, *dir_cos, *dir_sin, *path;
+} gmc_exit;
+
+typedef struct gmc_model gmc_model;
+
+/* Parses a weights blob and uploads it to the current device in the layout the kernels read.
+ * Blob (little-endian): "GMCW0001", u32 version=1, n_in=10, hidden H, n_out=5, n_layers=5,
+ * flags, seed, reserved; f32 act_scale[5], w_scale[5]; then per layer l = 1..5 the float32
+ * weight matrix W_l[out][in] (row-major) followed by the float32 bias b_l[out].  Layer dims:
+ * 10->H, H->H (x3), H->5.  Network input order: [x0..x4, t, ln tau, c, 2*y_in-1, sin_th];
+ * SiLU after layers 1..4 (paper section "Network Architecture and Inputs", eqs. 10-11).
+ * Supported: H in {128, 256} for GMC_FP32, H in {128, 256, 512} for GMC_BF16 / GMC_FP8_E4M3.
+ * The scales must be positive powers of two.  The blob is host memory owned by the caller.
+ * On success *out owns device memory until gmc_model_destroy(). */
+int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_model **out);
+int gmc_model_destroy(gmc_model *m);
+/* Reports the hidden width and precision of a model (either pointer may be NULL). */
+int gmc_model_info(const gmc_model *m, int *hidden, int *precision);
+
+/* Samples n cell transmissions with the generative sampler (paper "Transport Algorithm",
+ * second stage; eq. 8): x(0) = z ~ N(0, I_5); K explicit Euler steps x += v(x, k/K | c) / K;
+ * the exit record is decoded from x_K (eq. 11: a0 = 2*pos - 1, (a1, a2) = direction,
+ * a3 = ln path, face = number of thresholds -1, 0, 1 reached by a4; position clamped to
+ * [0, 1]; direction normalised and its normal component reflected if it points into the
+ * cell; outward normal if its norm is below 1e-6).
+ *   K          1..1024
+ *   seed, id_base   particle i draws its noise from Philox4x32-10 with key = seed and
+ *              counter (id lo, id hi, j, 1), j = 0, 1, id = id_base + i; Box-Muller pairs
+ *              (w0,w1) (w2,w3) (w4,w5) give z0..z4
+ *   noise_opt  NULL, or device float32 [5][n] (row d holds z_d of every particle): used
+ *              instead of the generator
+ *   raw_opt    NULL, or device float32 [5][n] receiving x_K before decoding
+ *   out        device exit record (all five arrays required)
+ * n = 0 is a no-op.  Errors: GMC_EINVAL (null pointers, K out of range), GMC_EDEVICE. */
+int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t seed,
+                 uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out,
+                 void *stream);
+
+/* Samples n cell transmissions with the analog random walk that the generative sampler
+ * replaces (paper "Monte Carlo Method", eq. 4): flights d = -ln(xi) / sigma with
+ * xi = ((w >> 8) + 1) * 2^-24 in (0, 1], isotropic flatland scattering phi = 2 pi xi'.
+ *   mode GMC_MODE_CONTINUOUS: sigma = c * tau (implicit capture: the caller attenuates the
+ *        weight by exp(-(1 - c) tau path), eqs. 5-6); every walk ends on a face.
+ *   mode GMC_MODE_ANALOG: sigma = tau, a collision absorbs when xi'' > c (face = -1).
+ *   Flight j of particle i uses Philox4x32-10 with key = seed and counter
+ *   (id lo, id hi, j, 2), id = id_base + i: word 0 -> flight length, 1 -> new direction,
+ *   2 -> absorption test.
+ *   ncoll_opt  NULL, or device uint32 [n] receiving the number of collisions in the cell.
+ * Errors: GMC_EINVAL, GMC_EDEVICE. */
+int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
+                gmc_exit out, uint32_t *ncoll_opt, void *stream);
+
+/* Decodes raw network outputs (device float32 [5][n]) into exit records with the rule of
+ * gmc_transmit.  flags_opt: NULL or device int32 [n]: bit0 position clamped, bit1 direction
+ * reflected, bit2 zero-norm direction. */
+int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, void *stream);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *gmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GMC_H */

@@ -1,0 +1,201 @@
+"""Thin Python binding of libgmc.so (the C ABI in include/gmc.h).
+
+Only argument marshalling lives here: torch provides device memory and streams, every step of
+the sampling path runs in the library's HIP kernels.  Loading fails loudly if the library has
+not been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch  # noqa: F401  (must be loaded first: the library then shares torch's HIP runtime)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libgmc.so")
+
+GMC_OK, GMC_EINVAL, GMC_ENOMEM, GMC_EDEVICE, GMC_EUNSUPPORTED = 0, -1, -2, -3, -4
+FP32, BF16, FP8_E4M3 = 0, 1, 2
+MODE_CONTINUOUS, MODE_ANALOG = 0, 1
+SAMPLER_GMC, SAMPLER_MC = 0, 1
+PRECISIONS = {"fp32": FP32, "bf16": BF16, "fp8": FP8_E4M3}
+
+
+class GmcError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class _Cond(ctypes.Structure):
+    _fields_ = [("log_tau", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("y_in", ctypes.c_void_p), ("sin_th", ctypes.c_void_p)]
+
+
+class _Exit(ctypes.Structure):
+    _fields_ = [("face", ctypes.c_void_p), ("pos", ctypes.c_void_p),
+                ("dir_cos", ctypes.c_void_p), ("dir_sin", ctypes.c_void_p),
+                ("path", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -c 'import __graft_entry__ as g; g.build()'`")
+        L = ctypes.CDLL(LIB_PATH)
+        P, I64, U64, I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+        L.gmc_last_error.restype = ctypes.c_char_p
+        L.gmc_model_create.argtypes = [P, ctypes.c_size_t, I, ctypes.POINTER(P)]
+        L.gmc_model_destroy.argtypes = [P]
+        L.gmc_model_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
+        L.gmc_transmit.argtypes = [P, _Cond, I64, I, U64, U64, P, P, _Exit, P]
+        L.mc_transmit.argtypes = [_Cond, I64, I, U64, U64, _Exit, P, P]
+        L.gmc_decode.argtypes = [P, I64, _Exit, P, P]
+        for name in ("gmc_model_create", "gmc_model_destroy", "gmc_model_info", "gmc_transmit",
+                     "mc_transmit", "gmc_decode"):
+            getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != GMC_OK:
+        raise GmcError(rc, lib().gmc_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _need(t, dtype, n, name):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous() and t.numel() >= n):
+        raise ValueError(f"{name}: expected a contiguous {dtype} device tensor of >= {n} elements")
+
+
+@dataclass
+class DeviceCond:
+    """Device SoA of entry conditions (float32 tensors of equal length)."""
+    log_tau: torch.Tensor
+    c: torch.Tensor
+    y_in: torch.Tensor
+    sin_th: torch.Tensor
+
+    @classmethod
+    def from_host(cls, cond, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        return cls(f(cond.log_tau), f(cond.c), f(cond.y_in), f(cond.sin_th))
+
+    def __len__(self):
+        return int(self.log_tau.numel())
+
+    def c_struct(self) -> _Cond:
+        n = len(self)
+        for nm in ("log_tau", "c", "y_in", "sin_th"):
+            _need(getattr(self, nm), torch.float32, n, nm)
+        return _Cond(self.log_tau.data_ptr(), self.c.data_ptr(), self.y_in.data_ptr(),
+                     self.sin_th.data_ptr())
+
+
+@dataclass
+class DeviceExit:
+    face: torch.Tensor
+    pos: torch.Tensor
+    dir_cos: torch.Tensor
+    dir_sin: torch.Tensor
+    path: torch.Tensor
+
+    @classmethod
+    def empty(cls, n: int, device="cuda"):
+        e = lambda dt: torch.empty(n, dtype=dt, device=device)
+        return cls(e(torch.int32), e(torch.float32), e(torch.float32), e(torch.float32),
+                   e(torch.float32))
+
+    def c_struct(self, n: int) -> _Exit:
+        _need(self.face, torch.int32, n, "face")
+        for nm in ("pos", "dir_cos", "dir_sin", "path"):
+            _need(getattr(self, nm), torch.float32, n, nm)
+        return _Exit(self.face.data_ptr(), self.pos.data_ptr(), self.dir_cos.data_ptr(),
+                     self.dir_sin.data_ptr(), self.path.data_ptr())
+
+    def to_host(self) -> dict:
+        return {k: getattr(self, k).cpu().numpy() for k in ("face", "pos", "dir_cos", "dir_sin", "path")}
+
+
+class Model:
+    """Device copy of a velocity network (gmc_model_create / gmc_model_destroy)."""
+
+    def __init__(self, blob: bytes, precision):
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        h = ctypes.c_void_p()
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        _check(lib().gmc_model_create(buf, len(blob), int(precision), ctypes.byref(h)))
+        self._h = h
+        hid, prec = ctypes.c_int(), ctypes.c_int()
+        _check(lib().gmc_model_info(h, ctypes.byref(hid), ctypes.byref(prec)))
+        self.hidden, self.precision = hid.value, prec.value
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _check(lib().gmc_model_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def gmc_transmit(model: Model, cond: DeviceCond, K: int, seed: int, id_base: int = 0,
+                 noise: torch.Tensor | None = None, raw: torch.Tensor | None = None,
+                 out: DeviceExit | None = None, n: int | None = None, stream=None) -> DeviceExit:
+    n = len(cond) if n is None else n
+    if out is None:
+        out = DeviceExit.empty(n, cond.log_tau.device)
+    if noise is not None:
+        _need(noise, torch.float32, 5 * n, "noise")
+    if raw is not None:
+        _need(raw, torch.float32, 5 * n, "raw")
+    _check(lib().gmc_transmit(model.handle, cond.c_struct(), n, int(K), seed, id_base,
+                              _ptr(noise), _ptr(raw), out.c_struct(n), _stream(stream)))
+    return out
+
+
+def mc_transmit(cond: DeviceCond, mode: int, seed: int, id_base: int = 0,
+                ncoll: torch.Tensor | None = None, out: DeviceExit | None = None,
+                n: int | None = None, stream=None) -> DeviceExit:
+    n = len(cond) if n is None else n
+    if out is None:
+        out = DeviceExit.empty(n, cond.log_tau.device)
+    if ncoll is not None:
+        _need(ncoll, torch.int32, n, "ncoll")
+    _check(lib().mc_transmit(cond.c_struct(), n, int(mode), seed, id_base, out.c_struct(n),
+                             _ptr(ncoll), _stream(stream)))
+    return out
+
+
+def gmc_decode(raw: torch.Tensor, n: int, out: DeviceExit | None = None,
+               flags: torch.Tensor | None = None, stream=None) -> DeviceExit:
+    _need(raw, torch.float32, 5 * n, "raw")
+    if out is None:
+        out = DeviceExit.empty(n, raw.device)
+    if flags is not None:
+        _need(flags, torch.int32, n, "flags")
+    _check(lib().gmc_decode(_ptr(raw), n, out.c_struct(n), _ptr(flags), _stream(stream)))
+    return out

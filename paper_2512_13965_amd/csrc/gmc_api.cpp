@@ -1,0 +1,346 @@
+// C ABI of the gfx950 Generative Monte Carlo library: argument checking, error reporting,
+// model upload (weights re-arranged into MFMA fragment order) and kernel dispatch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gmc.h"
+#include "gmc_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GMC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+// ---- host-side rounding used when uploading weights -------------------------------------
+
+uint16_t f32_to_bf16_rne(float f)
+{
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    const uint32_t lsb = (b >> 16) & 1u;
+    return (uint16_t)((b + 0x7FFFu + lsb) >> 16);
+}
+
+// Value of the OCP e4m3 code c (0..0x7E positive finite codes).
+double e4m3_value(int c)
+{
+    const int e = (c >> 3) & 15, m = c & 7;
+    return e == 0 ? std::ldexp((double)m, -9) : std::ldexp(1.0 + m / 8.0, e - 7);
+}
+
+// Nearest e4m3 code, ties to the even code, saturating at 448.
+uint8_t f32_to_e4m3_rne_sat(float f)
+{
+    static std::vector<double> table;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        table.resize(127);
+        for (int c = 0; c < 127; ++c) table[c] = e4m3_value(c);
+    });
+    const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+    const double a = std::fabs((double)f);
+    if (a >= 448.0) return sign | 0x7E;
+    const auto it = std::upper_bound(table.begin(), table.end(), a);
+    const int hi = (int)(it - table.begin());      // first code with value > a
+    if (hi == 0) return sign;
+    const int lo = hi - 1;
+    if (hi >= 127 || table[lo] == a) return sign | (uint8_t)lo;
+    const double dl = a - table[lo], dh = table[hi] - a;
+    int c = dl < dh ? lo : (dh < dl ? hi : ((lo & 1) == 0 ? lo : hi));
+    return sign | (uint8_t)c;
+}
+
+struct BlobHeader {
+    char magic[8];
+    uint32_t version, n_in, hidden, n_out, n_layers, flags, seed, reserved;
+    float act_scale[5], w_scale[5];
+};
+static_assert(sizeof(BlobHeader) == 80, "blob header layout");
+
+bool is_pow2(float s)
+{
+    if (!(s > 0.0f) || !std::isfinite(s)) return false;
+    int e;
+    return std::frexp(s, &e) == 0.5f;
+}
+
+std::mutex g_dev_mu;
+int g_cu[64] = {0};
+unsigned long long *g_queue[64] = {nullptr};
+unsigned g_queue_next[64] = {0};
+constexpr int kQueueRing = 4096;
+
+}  // namespace
+
+namespace gmc {
+
+int device_cu_count()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (g_cu[dev] == 0) {
+        int cu = 0;
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+        g_cu[dev] = cu;
+    }
+    return g_cu[dev];
+}
+
+// A ring of per-call work counters on the current device (allocated once, kept until the
+// process ends).  Each launch takes the next slot and zeroes it on its own stream first.
+unsigned long long *device_queue_counter()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_queue[dev]) {
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(unsigned long long) * kQueueRing) != hipSuccess) return nullptr;
+        g_queue[dev] = (unsigned long long *)p;
+    }
+    unsigned slot = g_queue_next[dev]++ % kQueueRing;
+    return g_queue[dev] + slot;
+}
+
+}  // namespace gmc
+
+struct gmc_model {
+    int precision = 0;
+    int hidden = 0;
+    int device = 0;
+    void *dev_mem = nullptr;
+    gmc::MlpParams tmpl{};   // weight / bias pointers and scales
+};
+
+extern "C" {
+
+const char *gmc_last_error(void) { return g_err.c_str(); }
+
+int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_model **out)
+{
+    using namespace gmc;
+    if (!host_blob || !out) return fail(GMC_EINVAL, "gmc_model_create: null pointer");
+    *out = nullptr;
+    if (precision < GMC_FP32 || precision > GMC_FP8_E4M3)
+        return fail(GMC_EINVAL, "gmc_model_create: unknown precision");
+    if (nbytes < sizeof(BlobHeader)) return fail(GMC_EINVAL, "gmc_model_create: blob too small");
+    BlobHeader hd;
+    std::memcpy(&hd, host_blob, sizeof hd);
+    if (std::memcmp(hd.magic, "GMCW0001", 8) != 0 || hd.version != 1)
+        return fail(GMC_EINVAL, "gmc_model_create: bad magic or version");
+    if (hd.n_in != 10 || hd.n_out != 5 || hd.n_layers != 5)
+        return fail(GMC_EINVAL, "gmc_model_create: network must be 10 -> H x4 -> 5");
+    const int H = (int)hd.hidden;
+    if (!mlp_supported(precision, H))
+        return fail(GMC_EUNSUPPORTED, "gmc_model_create: hidden width " + std::to_string(H) +
+                                          " not built for this precision");
+    const int dims[5][2] = {{H, 10}, {H, H}, {H, H}, {H, H}, {5, H}};
+    size_t need = sizeof(BlobHeader);
+    for (auto &d : dims) need += sizeof(float) * (size_t)(d[0] * d[1] + d[0]);
+    if (nbytes != need) return fail(GMC_EINVAL, "gmc_model_create: blob size does not match header");
+    for (int l = 0; l < 5; ++l)
+        if (!is_pow2(hd.act_scale[l]) || !is_pow2(hd.w_scale[l]))
+            return fail(GMC_EINVAL, "gmc_model_create: scales must be positive powers of two");
+
+    const float *src = (const float *)((const char *)host_blob + sizeof(BlobHeader));
+    std::vector<const float *> W(5), B(5);
+    for (int l = 0; l < 5; ++l) {
+        W[l] = src;
+        src += dims[l][0] * dims[l][1];
+        B[l] = src;
+        src += dims[l][0];
+        for (int i = 0; i < dims[l][0] * (dims[l][1] + 1); ++i)
+            if (!std::isfinite(W[l][i])) return fail(GMC_EINVAL, "gmc_model_create: non-finite weight");
+    }
+
+    // arrange every layer into fragment order, then one device allocation for all of it
+    std::vector<std::vector<uint8_t>> frag(5);
+    std::vector<std::vector<float>> bias(5);
+    gmc_model *m = new gmc_model();
+    m->precision = precision;
+    m->hidden = H;
+    for (int l = 0; l < 5; ++l) {
+        const int P = layer_prec(precision, l);
+        const int KBW = kb_width(P), FB = frag_bytes(P), EB = elem_bytes(P);
+        const int out_dim = dims[l][0], in_dim = dims[l][1];
+        const int kpad = (l == 0) ? 16 : H;
+        const int nkb = kpad / KBW, nt = (out_dim + 31) / 32;
+        const bool f8 = (P == kFP8);
+        const float sw = f8 ? hd.w_scale[l] : 1.0f, sa = f8 ? hd.act_scale[l] : 1.0f;
+        m->tmpl.oscale[l] = sw * sa;
+        m->tmpl.inv_in_scale[l] = 1.0f / sa;
+        frag[l].assign((size_t)nt * nkb * 64 * FB, 0);
+        for (int T = 0; T < nt; ++T)
+            for (int kb = 0; kb < nkb; ++kb)
+                for (int lane = 0; lane < 64; ++lane) {
+                    const int row = 32 * T + (lane & 31), h = lane >> 5;
+                    uint8_t *dst = frag[l].data() + ((size_t)(T * nkb + kb) * 64 + lane) * FB;
+                    for (int e = 0; e < KBW / 2; ++e) {
+                        const int k = kb * KBW + h * (KBW / 2) + e;
+                        const int f = (l == 0) ? (k < in_dim ? k : -1) : phys_to_feature(P, k);
+                        const float w = (row < out_dim && f >= 0 && f < in_dim)
+                                            ? W[l][(size_t)row * in_dim + f] : 0.0f;
+                        if (P == kF32) {
+                            std::memcpy(dst + e * EB, &w, 4);
+                        } else if (P == kBF16) {
+                            const uint16_t q = f32_to_bf16_rne(w);
+                            std::memcpy(dst + e * EB, &q, 2);
+                        } else {
+                            dst[e] = f32_to_e4m3_rne_sat(w / sw);
+                        }
+                    }
+                }
+        bias[l].assign((size_t)nt * 32, 0.0f);
+        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] / (sw * sa);
+    }
+    size_t total = 0;
+    std::vector<size_t> off_f(5), off_b(5);
+    for (int l = 0; l < 5; ++l) {
+        off_f[l] = total;
+        total += (frag[l].size() + 255) & ~(size_t)255;
+        off_b[l] = total;
+        total += (bias[l].size() * sizeof(float) + 255) & ~(size_t)255;
+    }
+    hipError_t e = hipGetDevice(&m->device);
+    if (e != hipSuccess) { delete m; return hip_fail(e, "gmc_model_create: hipGetDevice"); }
+    e = hipMalloc(&m->dev_mem, total);
+    if (e != hipSuccess) { delete m; return fail(GMC_ENOMEM, "gmc_model_create: hipMalloc failed"); }
+    std::vector<uint8_t> staging(total, 0);
+    for (int l = 0; l < 5; ++l) {
+        std::memcpy(staging.data() + off_f[l], frag[l].data(), frag[l].size());
+        std::memcpy(staging.data() + off_b[l], bias[l].data(), bias[l].size() * sizeof(float));
+        m->tmpl.wA[l] = (const char *)m->dev_mem + off_f[l];
+        m->tmpl.bias[l] = (const float *)((const char *)m->dev_mem + off_b[l]);
+    }
+    e = hipMemcpy(m->dev_mem, staging.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(m->dev_mem);
+        delete m;
+        return hip_fail(e, "gmc_model_create: upload");
+    }
+    *out = m;
+    return GMC_OK;
+}
+
+int gmc_model_destroy(gmc_model *m)
+{
+    if (!m) return fail(GMC_EINVAL, "gmc_model_destroy: null model");
+    if (m->dev_mem) {
+        hipError_t e = hipFree(m->dev_mem);
+        if (e != hipSuccess) { delete m; return hip_fail(e, "gmc_model_destroy"); }
+    }
+    delete m;
+    return GMC_OK;
+}
+
+int gmc_model_info(const gmc_model *m, int *hidden, int *precision)
+{
+    if (!m) return fail(GMC_EINVAL, "gmc_model_info: null model");
+    if (hidden) *hidden = m->hidden;
+    if (precision) *precision = m->precision;
+    return GMC_OK;
+}
+
+static bool cond_ok(const gmc_cond &c) { return c.log_tau && c.c && c.y_in && c.sin_th; }
+static bool exit_ok(const gmc_exit &o) { return o.face && o.pos && o.dir_cos && o.dir_sin && o.path; }
+
+int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t seed,
+                 uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out, void *stream)
+{
+    if (!m) return fail(GMC_EINVAL, "gmc_transmit: null model");
+    if (n < 0) return fail(GMC_EINVAL, "gmc_transmit: negative n");
+    if (K < 1 || K > 1024) return fail(GMC_EINVAL, "gmc_transmit: K must be in 1..1024");
+    if (n == 0) return GMC_OK;
+    if (!cond_ok(cond) || !exit_ok(out)) return fail(GMC_EINVAL, "gmc_transmit: null condition or output array");
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev != m->device)
+        return fail(GMC_EINVAL, "gmc_transmit: model lives on another device");
+    gmc::MlpParams p = m->tmpl;
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.y_in = cond.y_in;
+    p.sin_th = cond.sin_th;
+    p.noise = noise_opt;
+    p.raw = raw_opt;
+    p.face = out.face;
+    p.pos = out.pos;
+    p.dcos = out.dir_cos;
+    p.dsin = out.dir_sin;
+    p.path = out.path;
+    p.n = n;
+    p.K = K;
+    p.seed = seed;
+    p.id_base = id_base;
+    const int cu = gmc::device_cu_count();
+    if (cu <= 0) return fail(GMC_EDEVICE, "gmc_transmit: cannot query the device");
+    const int64_t ntiles = (n + gmc::kTileM - 1) / gmc::kTileM;
+    const int grid = (int)std::min<int64_t>(ntiles, cu);
+    hipError_t e = gmc::launch_mlp_ode(m->precision, m->hidden, p, grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gmc_transmit: launch");
+    return GMC_OK;
+}
+
+int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base, gmc_exit out,
+                uint32_t *ncoll_opt, void *stream)
+{
+    if (n < 0) return fail(GMC_EINVAL, "mc_transmit: negative n");
+    if (mode != GMC_MODE_CONTINUOUS && mode != GMC_MODE_ANALOG)
+        return fail(GMC_EINVAL, "mc_transmit: mode must be 0 (continuous) or 1 (analog)");
+    if (n == 0) return GMC_OK;
+    if (!cond_ok(cond) || !exit_ok(out)) return fail(GMC_EINVAL, "mc_transmit: null condition or output array");
+    gmc::WalkParams p{};
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.y_in = cond.y_in;
+    p.sin_th = cond.sin_th;
+    p.face = out.face;
+    p.pos = out.pos;
+    p.dcos = out.dir_cos;
+    p.dsin = out.dir_sin;
+    p.path = out.path;
+    p.ncoll = ncoll_opt;
+    p.n = n;
+    p.mode = mode;
+    p.seed = seed;
+    p.id_base = id_base;
+    p.queue = gmc::device_queue_counter();
+    if (!p.queue) return fail(GMC_ENOMEM, "mc_transmit: cannot allocate the work counter");
+    const int cu = gmc::device_cu_count();
+    if (cu <= 0) return fail(GMC_EDEVICE, "mc_transmit: cannot query the device");
+    const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)cu * 8);
+    hipError_t e = gmc::launch_walk(p, grid, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mc_transmit: launch");
+    return GMC_OK;
+}
+
+int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, void *stream)
+{
+    if (n < 0) return fail(GMC_EINVAL, "gmc_decode: negative n");
+    if (n == 0) return GMC_OK;
+    if (!raw || !exit_ok(out)) return fail(GMC_EINVAL, "gmc_decode: null pointer");
+    if (n > (int64_t)0x7FFFFFFF * 256) return fail(GMC_EINVAL, "gmc_decode: n too large");
+    hipError_t e = gmc::launch_decode(raw, n, out.face, out.pos, out.dir_cos, out.dir_sin, out.path,
+                                      flags_opt, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gmc_decode: launch");
+    return GMC_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,125 @@
+// Device-side helpers shared by the gfx950 kernels: counter-based random numbers, uniform and
+// normal variates, fast transcendentals, and the exit-record decoder.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmc {
+
+constexpr uint32_t kTagNoise = 1u;
+constexpr uint32_t kTagWalk = 2u;
+constexpr uint32_t kTagSource = 3u;
+constexpr uint32_t kMaxFlights = 1u << 24;
+
+struct U4 {
+    uint32_t a, b, c, d;
+};
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32 -> 64 bit
+// multiplies with a Weyl key schedule.
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+__device__ __forceinline__ U4 draw4(uint64_t seed, uint64_t stream, uint32_t index, uint32_t tag)
+{
+    return philox((uint32_t)stream, (uint32_t)(stream >> 32), index, tag, (uint32_t)seed,
+                  (uint32_t)(seed >> 32));
+}
+
+// xi in (0, 1]: the top 24 bits plus one ulp, exact in float32.
+__device__ __forceinline__ float u01(uint32_t w) { return (float)((w >> 8) + 1u) * 0x1p-24f; }
+__device__ __forceinline__ float u01_open(uint32_t w) { return ((float)(w >> 8) + 0.5f) * 0x1p-24f; }
+
+// -ln(xi) from the hardware base-2 logarithm.
+__device__ __forceinline__ float neg_log(float xi) { return -0.69314718055994531f * __builtin_amdgcn_logf(xi); }
+
+// cos / sin of 2 pi x: the hardware sine and cosine take their argument in turns.
+__device__ __forceinline__ float cos_turns(float x) { return __builtin_amdgcn_cosf(x); }
+__device__ __forceinline__ float sin_turns(float x) { return __builtin_amdgcn_sinf(x); }
+
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// SiLU(a) = a / (1 + e^-a) with the hardware exp2 and reciprocal.
+__device__ __forceinline__ float silu(float a)
+{
+    return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * a));
+}
+
+// z ~ N(0, I_5) of one particle: Philox words of counters (id, 0, tag) and (id, 1, tag),
+// Box-Muller on the pairs (w0,w1), (w2,w3), (w4,w5); accurate library log/sincos (this runs
+// once per sample, not in a hot loop).
+__device__ __forceinline__ void normal5(uint64_t seed, uint64_t id, float z[5])
+{
+    const U4 a = draw4(seed, id, 0u, kTagNoise);
+    const U4 b = draw4(seed, id, 1u, kTagNoise);
+    const uint32_t w[6] = {a.a, a.b, a.c, a.d, b.a, b.b};
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const float r = sqrtf(-2.0f * logf(u01(w[2 * p])));
+        float s, c;
+        sincospif(2.0f * u01(w[2 * p + 1]), &s, &c);
+        z[2 * p] = r * c;
+        if (2 * p + 1 < 5) z[2 * p + 1] = r * s;
+    }
+}
+
+// Exit record from x_K (paper eq. 11 in the 5-dim reading): face = number of the thresholds
+// -1, 0, 1 reached by a4; pos = clamp((a0 + 1) / 2); direction (a1, a2) normalised, outward
+// normal if its norm is below 1e-6, normal component reflected if it points inward;
+// path = exp(a3).  Returns flags: bit0 pos clamped, bit1 reflected, bit2 zero norm.
+struct Exit {
+    int32_t face;
+    float pos, u, v, path;
+};
+
+__device__ __forceinline__ int decode_exit(float a0, float a1, float a2, float a3, float a4, Exit &e)
+{
+    int flags = 0;
+    const int face = (a4 >= -1.0f) + (a4 >= 0.0f) + (a4 >= 1.0f);
+    float p = (a0 + 1.0f) * 0.5f;
+    if (p < 0.0f || p > 1.0f) flags |= 1;
+    p = fminf(fmaxf(p, 0.0f), 1.0f);
+    // outward normals: bottom (0,-1), right (1,0), top (0,1), left (-1,0)
+    const float nx = (face == 1) ? 1.0f : ((face == 3) ? -1.0f : 0.0f);
+    const float ny = (face == 2) ? 1.0f : ((face == 0) ? -1.0f : 0.0f);
+    const float nrm = sqrtf(a1 * a1 + a2 * a2);
+    float u, v;
+    if (nrm < 1e-6f) {
+        u = nx;
+        v = ny;
+        flags |= 4;
+    } else {
+        const float inv = 1.0f / nrm;
+        u = a1 * inv;
+        v = a2 * inv;
+    }
+    const float dn = u * nx + v * ny;
+    if (dn < 0.0f) {
+        u -= 2.0f * dn * nx;
+        v -= 2.0f * dn * ny;
+        flags |= 2;
+    }
+    e.face = face;
+    e.pos = p;
+    e.u = u;
+    e.v = v;
+    e.path = expf(a3);
+    return flags;
+}
+
+}  // namespace gmc

@@ -1,0 +1,93 @@
+// Internal interfaces between the C ABI (gmc_api.cpp) and the kernel translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gmc {
+
+enum Prec { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+// Samples per workgroup tile of the fused MLP/ODE kernel and waves per workgroup.
+constexpr int kTileM = 128;
+constexpr int kWaves = 4;
+
+// Operand geometry of one "k-block" for each operand precision: features consumed per
+// k-block, bytes one lane holds per 32-row tile and k-block, MFMA instructions per k-block.
+//   fp32: v_mfma_f32_32x32x2_f32,    k-block 8 features, 16 B per lane, 4 MFMA
+//   bf16: v_mfma_f32_32x32x16_bf16,  k-block 16 features, 16 B per lane, 1 MFMA
+//   fp8:  v_mfma_..._32x32x64_f8f6f4 k-block 64 features, 32 B per lane, 1 MFMA
+__host__ __device__ constexpr int kb_width(int p) { return p == kF32 ? 8 : (p == kBF16 ? 16 : 64); }
+__host__ __device__ constexpr int frag_bytes(int p) { return p == kFP8 ? 32 : 16; }
+__host__ __device__ constexpr int elem_bytes(int p) { return p == kF32 ? 4 : (p == kBF16 ? 2 : 1); }
+
+// Operand precision of each of the five layers for a model precision: FP8 models keep the
+// first (10 -> H) and last (H -> 5) layers in BF16.
+__host__ __device__ constexpr int layer_prec(int model_prec, int layer)
+{
+    return model_prec == kFP8 ? ((layer == 0 || layer == 4) ? kBF16 : kFP8) : model_prec;
+}
+
+// Logical feature stored at physical column p of the LDS activation tile when the producing
+// layer wrote it for a consumer of operand precision `p_in`.  The producer's accumulator of
+// 32-row tile T gives lane half h the rows 8*(i/4) + 4*h + (i%4), i = 0..15; these land in the
+// columns that the consumer's lane half h reads as one contiguous chunk.
+__host__ __device__ inline int phys_to_feature(int p_in, int p)
+{
+    int T, h, i;
+    if (p_in == kF32) {
+        const int kb = p / 8;
+        h = (p % 8) / 4;
+        T = kb / 4;
+        i = 4 * (kb % 4) + p % 4;
+    } else if (p_in == kBF16) {
+        const int kb = p / 16;
+        h = (p % 16) / 8;
+        T = kb / 2;
+        i = 8 * (kb % 2) + p % 8;
+    } else {
+        const int kb = p / 64, w = p % 64;
+        h = w / 32;
+        T = 2 * kb + (w % 32) / 16;
+        i = w % 16;
+    }
+    return 32 * T + 8 * (i / 4) + 4 * h + (i % 4);
+}
+
+struct MlpParams {
+    const void *wA[5];        // arranged operand fragments per layer
+    const float *bias[5];     // per layer, rows padded to a multiple of 32, pre-divided by oscale
+    float oscale[5];          // accumulator multiplier per layer (FP8 hidden layers: sw * sa)
+    float inv_in_scale[5];    // 1 / activation scale of the input of layer l (FP8 hidden layers)
+    const float *log_tau, *c, *y_in, *sin_th;
+    const float *noise;       // optional [5][n]
+    float *raw;               // optional [5][n]
+    int32_t *face;
+    float *pos, *dcos, *dsin, *path;
+    int64_t n;
+    int K;
+    uint64_t seed, id_base;
+};
+
+hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s);
+bool mlp_supported(int prec, int hidden);
+
+struct WalkParams {
+    const float *log_tau, *c, *y_in, *sin_th;
+    int32_t *face;
+    float *pos, *dcos, *dsin, *path;
+    uint32_t *ncoll;          // optional
+    int64_t n;
+    int mode;
+    uint64_t seed, id_base;
+    unsigned long long *queue;  // device work counter, zeroed by the launcher
+};
+
+hipError_t launch_walk(const WalkParams &p, int grid, hipStream_t s);
+hipError_t launch_decode(const float *raw, int64_t n, int32_t *face, float *pos, float *dcos,
+                         float *dsin, float *path, int32_t *flags, hipStream_t s);
+
+int device_cu_count();
+unsigned long long *device_queue_counter();
+
+}  // namespace gmc

@@ -1,0 +1,193 @@
+"""GPU parity of gmc_transmit (fused velocity-MLP + Euler sampler, paper eq. 8, decoded per
+eq. 11) against the FP64 oracle on the same seeded weights and noise.
+
+Tolerances (per sample, infinity norm of x_K - x_K^oracle):
+  * FP32 (MFMA fp32, hardware exp/rcp SiLU) vs exact FP64: 1e-4.  Each layer's dot products
+    carry ~sqrt(H) * 2^-24 relative rounding and the hardware exp / rcp add ~2 ulp, about 1e-6
+    per evaluation; K = 16 evaluations and 5 layers leave the result near 1e-5 in the worst
+    sample.
+  * BF16 / FP8 vs the oracle that rounds the same operands at the same points: both sides
+    round values that differ by the FP32-vs-FP64 error above, so a few roundings per sample
+    land on the other side of a tie (one bf16 ulp = 2^-8 relative, one e4m3 ulp = 2^-3);
+    the p99 bounds below are several times the measured values.
+  * The decoded face is compared exactly where a4 is farther than 1e-3 from a threshold.
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_13965_amd import inputs
+from tests.gpu_util import face_threshold_margin, require_gpu, sample_indices
+
+pytestmark = pytest.mark.gpu
+
+SEED_W, SEED_COND, SEED_NOISE = 1, 3, 2
+
+
+def _run(binding, w, prec, cond_h, K, seed=SEED_NOISE, id_base=0, noise=None):
+    m = binding.Model(inputs.pack_blob(w), prec)
+    dc = binding.DeviceCond.from_host(cond_h)
+    n = len(cond_h)
+    raw = torch.empty(5 * n, dtype=torch.float32, device="cuda")
+    nz = None if noise is None else torch.from_numpy(noise.reshape(-1)).cuda()
+    out = binding.gmc_transmit(m, dc, K, seed, id_base, noise=nz, raw=raw)
+    torch.cuda.synchronize()
+    m.close()
+    return raw.view(5, n).cpu().numpy().astype(np.float64), out.to_host()
+
+
+def _oracle_raw(orc, w, cond_h, idx, K, prec, z_full=None, seed=SEED_NOISE, id_base=0):
+    sub = cond_h.subset(idx)
+    if z_full is None:
+        z = np.stack([orc.noise(seed, id_base + int(i), 1)[:, 0] for i in idx], axis=1)
+    else:
+        z = z_full[:, idx].astype(np.float64)
+    return orc.sample_raw(w, sub, K, z, prec)
+
+
+def _check_decoded(orc, raw_gpu_idx, ref_raw, out, idx, pos_tol=1e-4):
+    d = orc.decode(ref_raw)
+    ok = face_threshold_margin(ref_raw[:, 4]) > 1e-3
+    np.testing.assert_array_equal(out["face"][idx][ok], d["face"][ok])
+    same = ok & (out["face"][idx] == d["face"])
+    np.testing.assert_allclose(out["pos"][idx][same], d["pos"][same], atol=pos_tol)
+    # path = exp(a3): relative tolerance follows the absolute tolerance on a3
+    np.testing.assert_allclose(out["path"][idx][same], d["len"][same], rtol=pos_tol * 2)
+
+
+@pytest.mark.parametrize("use_noise_buffer", [True, False])
+def test_fp32_h256_k16_parity(orc, use_noise_buffer):
+    binding = require_gpu()
+    n = 40_077                                 # 314 tiles: several per workgroup, ragged tail
+    cond = inputs.transmission_conditions(n, SEED_COND)
+    w = inputs.random_weights(256, SEED_W)
+    z = inputs.noise(n, 5) if use_noise_buffer else None
+    raw, out = _run(binding, w, "fp32", cond, 16, noise=z)
+    idx = sample_indices(n, 1200)
+    ref = _oracle_raw(orc, w, cond, idx, 16, orc.PREC_FP64, z_full=z)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    print(f"fp32 noise_buffer={use_noise_buffer}: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
+    assert err.max() < 1e-4
+    _check_decoded(orc, raw[:, idx], ref, out, idx)
+
+
+@pytest.mark.parametrize("n", [1, 5, 127, 128, 129, 300])
+def test_fp32_small_and_ragged_batches(orc, n):
+    binding = require_gpu()
+    cond = inputs.transmission_conditions(n, 11)
+    w = inputs.random_weights(256, 4)
+    raw, _ = _run(binding, w, "fp32", cond, 8, seed=9, id_base=77)
+    idx = np.arange(n)
+    ref = _oracle_raw(orc, w, cond, idx, 8, orc.PREC_FP64, seed=9, id_base=77)
+    assert np.abs(raw.T - ref).max() < 1e-4
+
+
+@pytest.mark.parametrize("K", [1, 2, 32])
+def test_fp32_step_counts(orc, K):
+    binding = require_gpu()
+    n = 700
+    cond = inputs.transmission_conditions(n, 12)
+    w = inputs.random_weights(128, 5)
+    raw, _ = _run(binding, w, "fp32", cond, K)
+    ref = _oracle_raw(orc, w, cond, np.arange(n), K, orc.PREC_FP64)
+    assert np.abs(raw.T - ref).max() < 1e-4
+
+
+def test_fp32_cfg1_full_batch_sampled(orc):
+    # the benchmark's workload: 65,536 transmissions, H = 256, K = 16, Philox noise
+    binding = require_gpu()
+    n = 65_536
+    cond = inputs.transmission_conditions(n, SEED_COND)
+    w = inputs.random_weights(256, SEED_W)
+    raw, out = _run(binding, w, "fp32", cond, 16)
+    idx = sample_indices(n, 400, seed=1)
+    ref = _oracle_raw(orc, w, cond, idx, 16, orc.PREC_FP64)
+    assert np.abs(raw[:, idx].T - ref).max() < 1e-4
+    assert np.all((out["face"] >= 0) & (out["face"] <= 3))
+    assert np.all((out["pos"] >= 0) & (out["pos"] <= 1))
+    np.testing.assert_allclose(out["dir_cos"] ** 2 + out["dir_sin"] ** 2, 1.0, atol=1e-5)
+
+
+def test_results_independent_of_batch_position(orc):
+    binding = require_gpu()
+    n = 1000
+    cond = inputs.transmission_conditions(n, 13)
+    w = inputs.random_weights(256, 6)
+    raw_a, _ = _run(binding, w, "fp32", cond, 16, seed=4, id_base=1000)
+    raw_b, _ = _run(binding, w, "fp32", cond.subset(slice(300, 1000)), 16, seed=4, id_base=1300)
+    np.testing.assert_array_equal(raw_a[:, 300:], raw_b)
+
+
+@pytest.mark.parametrize("prec,H,K", [("bf16", 512, 16), ("bf16", 256, 16), ("bf16", 512, 8),
+                                      ("bf16", 512, 32), ("bf16", 128, 16), ("fp8", 512, 16),
+                                      ("fp8", 256, 16), ("fp8", 128, 16)])
+def test_quantised_parity_vs_emulating_oracle(orc, prec, H, K):
+    binding = require_gpu()
+    n = 9_000 if H < 512 else 20_077
+    cond = inputs.transmission_conditions(n, SEED_COND)
+    w = inputs.random_weights(H, SEED_W)
+    z = inputs.noise(n, 6)
+    raw, out = _run(binding, w, prec, cond, K, noise=z)
+    idx = sample_indices(n, 300, seed=2)
+    oprec = orc.PREC_BF16 if prec == "bf16" else orc.PREC_FP8
+    ref = _oracle_raw(orc, w, cond, idx, K, oprec, z_full=z)
+    exact = _oracle_raw(orc, w, cond, idx, K, orc.PREC_FP64, z_full=z)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    err_exact = np.abs(raw[:, idx].T - exact).max(axis=1)
+    p99 = np.quantile(err, 0.99)
+    print(f"{prec} H={H} K={K}: vs emulation p50 {np.median(err):.2e} p99 {p99:.2e} max "
+          f"{err.max():.2e}; vs fp64 p50 {np.median(err_exact):.2e} p99 "
+          f"{np.quantile(err_exact, 0.99):.2e}")
+    if prec == "bf16":
+        assert p99 < 1e-2 and err.max() < 5e-2
+    else:
+        assert p99 < 5e-2 and err.max() < 2e-1
+    # the emulation must explain the GPU far better than exact arithmetic does
+    assert np.median(err) < 0.5 * np.median(err_exact)
+
+
+def test_cfg2_bf16_full_batch_sampled(orc):
+    # 2^20 transmissions, H = 512, K = 16, BF16, Philox noise
+    binding = require_gpu()
+    n = 1 << 20
+    cond = inputs.transmission_conditions(n, SEED_COND)
+    w = inputs.random_weights(512, SEED_W)
+    raw, out = _run(binding, w, "bf16", cond, 16)
+    idx = sample_indices(n, 120, seed=3)
+    ref = _oracle_raw(orc, w, cond, idx, 16, orc.PREC_BF16)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    assert np.quantile(err, 0.99) < 1e-2
+    assert np.all((out["face"] >= 0) & (out["face"] <= 3))
+
+
+def test_decode_kernel_matches_oracle(orc):
+    binding = require_gpu()
+    n = 50_000
+    g = inputs.rng(21)
+    raw = (g.standard_normal((5, n)) * np.array([[0.8], [1.0], [1.0], [1.5], [1.6]])).astype(np.float32)
+    raw[1:3, :50] = 0.0                          # zero-norm directions
+    raw[4, 50:60] = np.array([-1, 0, 1, -1, 0, 1, -1, 0, 1, -1], np.float32)   # exact thresholds
+    flags = torch.empty(n, dtype=torch.int32, device="cuda")
+    out = binding.gmc_decode(torch.from_numpy(raw.reshape(-1)).cuda(), n, flags=flags).to_host()
+    d = orc.decode(raw.T.astype(np.float64))
+    np.testing.assert_array_equal(out["face"], d["face"])          # same fp32 inputs: exact
+    np.testing.assert_array_equal(flags.cpu().numpy(), d["flags"])
+    np.testing.assert_allclose(out["pos"], d["pos"], atol=1e-7)
+    np.testing.assert_allclose(out["dir_cos"], d["u"], atol=2e-6)
+    np.testing.assert_allclose(out["dir_sin"], d["v"], atol=2e-6)
+    np.testing.assert_allclose(out["path"], d["len"], rtol=2e-6)
+
+
+def test_zero_and_invalid_arguments():
+    binding = require_gpu()
+    w = inputs.random_weights(256, 1)
+    m = binding.Model(inputs.pack_blob(w), "fp32")
+    cond = binding.DeviceCond.from_host(inputs.transmission_conditions(4, 1))
+    binding.gmc_transmit(m, cond, 16, 1, n=0)                          # no-op
+    with pytest.raises(binding.GmcError) as e:
+        binding.gmc_transmit(m, cond, 0, 1)
+    assert e.value.code == binding.GMC_EINVAL
+    with pytest.raises(binding.GmcError) as e:
+        binding.gmc_transmit(m, cond, 2000, 1)
+    assert e.value.code == binding.GMC_EINVAL
+    m.close()
