@@ -35,14 +35,14 @@ struct Mma<kF32> {
     using Frag = u32x4;
     static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b)
     {
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a.x),
-                                                   __builtin_bit_cast(float, b.x), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a.y),
-                                                   __builtin_bit_cast(float, b.y), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a.z),
-                                                   __builtin_bit_cast(float, b.z), acc, 0, 0, 0);
-        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, a.w),
-                                                   __builtin_bit_cast(float, b.w), acc, 0, 0, 0);
+        // reinterpret whole vectors: a bit_cast of a single vector component reads the
+        // vector's first component whatever the index
+        const f32x4 af = __builtin_bit_cast(f32x4, a);
+        const f32x4 bf = __builtin_bit_cast(f32x4, b);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af.x, bf.x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af.y, bf.y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af.z, bf.z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af.w, bf.w, acc, 0, 0, 0);
     }
     static __device__ __forceinline__ Frag load_g(const char *p) { return *(const u32x4 *)p; }
     static __device__ __forceinline__ Frag load_s(const char *p) { return *(const u32x4 *)p; }
