@@ -99,7 +99,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="only the timed steps (for profiling)")
+    ap.add_argument("--copy-ref", action="store_true",
+                    help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_ref:
+        import torch
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_ref_bytes_each_way": src.numel() * 4, "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sampler shards by "
               f"particle id with no communication, see DESIGN.md", file=sys.stderr)

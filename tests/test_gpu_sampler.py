@@ -2,14 +2,16 @@
 eq. 11) against the FP64 oracle on the same seeded weights and noise.
 
 Tolerances (per sample, infinity norm of x_K - x_K^oracle):
-  * FP32 (MFMA fp32, hardware exp/rcp SiLU) vs exact FP64: 1e-4.  Each layer's dot products
-    carry ~sqrt(H) * 2^-24 relative rounding and the hardware exp / rcp add ~2 ulp, about 1e-6
-    per evaluation; K = 16 evaluations and 5 layers leave the result near 1e-5 in the worst
-    sample.
+  * FP32 (MFMA fp32, hardware exp/rcp SiLU) vs exact FP64: 1e-5.  Each layer's dot products
+    carry ~sqrt(H) * 2^-24 relative rounding and the hardware exp / rcp add ~2 ulp; over K = 16
+    evaluations of 5 layers the worst sample measured 8e-7.
   * BF16 / FP8 vs the oracle that rounds the same operands at the same points: both sides
-    round values that differ by the FP32-vs-FP64 error above, so a few roundings per sample
-    land on the other side of a tie (one bf16 ulp = 2^-8 relative, one e4m3 ulp = 2^-3);
-    the p99 bounds below are several times the measured values.
+    round values that differ by the FP32-vs-FP64 error above, so now and then a rounding lands
+    on the other side of a tie (one bf16 ulp = 2^-8 relative, one e4m3 ulp = 2^-3).  Measured:
+    BF16 p99 <= 5e-6, max 6e-6; FP8 p99 <= 3e-5, max 4e-5.  Bounds: BF16 p99 1e-5, max 5e-5;
+    FP8 p99 1e-4, max 3e-4.  The median must also sit 10x below the median distance to exact
+    FP64 arithmetic (measured: BF16 4e-5, FP8 3.5e-4 on these random-init networks), so a
+    dropped rounding step or a wrong scale fails.
   * The decoded face is compared exactly where a4 is farther than 1e-3 from a threshold.
 """
 import numpy as np
@@ -67,7 +69,7 @@ def test_fp32_h256_k16_parity(orc, use_noise_buffer):
     ref = _oracle_raw(orc, w, cond, idx, 16, orc.PREC_FP64, z_full=z)
     err = np.abs(raw[:, idx].T - ref).max(axis=1)
     print(f"fp32 noise_buffer={use_noise_buffer}: max {err.max():.3e} p99 {np.quantile(err, 0.99):.3e}")
-    assert err.max() < 1e-4
+    assert err.max() < 1e-5
     _check_decoded(orc, raw[:, idx], ref, out, idx)
 
 
@@ -79,7 +81,7 @@ def test_fp32_small_and_ragged_batches(orc, n):
     raw, _ = _run(binding, w, "fp32", cond, 8, seed=9, id_base=77)
     idx = np.arange(n)
     ref = _oracle_raw(orc, w, cond, idx, 8, orc.PREC_FP64, seed=9, id_base=77)
-    assert np.abs(raw.T - ref).max() < 1e-4
+    assert np.abs(raw.T - ref).max() < 1e-5
 
 
 @pytest.mark.parametrize("K", [1, 2, 32])
@@ -90,7 +92,7 @@ def test_fp32_step_counts(orc, K):
     w = inputs.random_weights(128, 5)
     raw, _ = _run(binding, w, "fp32", cond, K)
     ref = _oracle_raw(orc, w, cond, np.arange(n), K, orc.PREC_FP64)
-    assert np.abs(raw.T - ref).max() < 1e-4
+    assert np.abs(raw.T - ref).max() < 1e-5
 
 
 def test_fp32_cfg1_full_batch_sampled(orc):
@@ -102,7 +104,7 @@ def test_fp32_cfg1_full_batch_sampled(orc):
     raw, out = _run(binding, w, "fp32", cond, 16)
     idx = sample_indices(n, 400, seed=1)
     ref = _oracle_raw(orc, w, cond, idx, 16, orc.PREC_FP64)
-    assert np.abs(raw[:, idx].T - ref).max() < 1e-4
+    assert np.abs(raw[:, idx].T - ref).max() < 1e-5
     assert np.all((out["face"] >= 0) & (out["face"] <= 3))
     assert np.all((out["pos"] >= 0) & (out["pos"] <= 1))
     np.testing.assert_allclose(out["dir_cos"] ** 2 + out["dir_sin"] ** 2, 1.0, atol=1e-5)
@@ -139,11 +141,11 @@ def test_quantised_parity_vs_emulating_oracle(orc, prec, H, K):
           f"{err.max():.2e}; vs fp64 p50 {np.median(err_exact):.2e} p99 "
           f"{np.quantile(err_exact, 0.99):.2e}")
     if prec == "bf16":
-        assert p99 < 1e-2 and err.max() < 5e-2
+        assert p99 < 1e-5 and err.max() < 5e-5
     else:
-        assert p99 < 5e-2 and err.max() < 2e-1
+        assert p99 < 1e-4 and err.max() < 3e-4
     # the emulation must explain the GPU far better than exact arithmetic does
-    assert np.median(err) < 0.5 * np.median(err_exact)
+    assert np.median(err) < 0.1 * np.median(err_exact)
 
 
 def test_cfg2_bf16_full_batch_sampled(orc):
@@ -156,7 +158,7 @@ def test_cfg2_bf16_full_batch_sampled(orc):
     idx = sample_indices(n, 120, seed=3)
     ref = _oracle_raw(orc, w, cond, idx, 16, orc.PREC_BF16)
     err = np.abs(raw[:, idx].T - ref).max(axis=1)
-    assert np.quantile(err, 0.99) < 1e-2
+    assert np.quantile(err, 0.99) < 1e-5 and err.max() < 5e-5
     assert np.all((out["face"] >= 0) & (out["face"] <= 3))
 
 

@@ -5,8 +5,8 @@ Both sides draw identical 32-bit Philox words, so each particle follows the same
 kernel computes geometry in FP32 with hardware log / sin / cos / reciprocal, so where a
 flight ends within rounding distance of the boundary (d_s ~ d_b) or a corner (t_x ~ t_y) the
 two sides may take different branches and the histories part.  The tests therefore require
-(face, n_coll) to agree for all but a small fraction of particles (the budget below is far
-above the measured rate) and the continuous outputs of agreeing particles to match within
+(face, n_coll) to agree for all but 5e-4 of the particles (none disagreed in 330k walks up to
+tau = 100) and the continuous outputs of agreeing particles to match within
 FP32 accumulation error, and check the exact laws statistically.
 """
 import math
@@ -40,8 +40,8 @@ def _compare(g, o, max_mismatch):
     print(f"mismatch {frac:.2e}  pos max {d_pos.max():.2e} p99 {np.quantile(d_pos, .99):.2e}  "
           f"dir max {d_dir.max():.2e}  len rel max {d_len.max():.2e} p99 {np.quantile(d_len, .99):.2e}")
     assert frac <= max_mismatch
-    assert np.quantile(d_pos, 0.999) < 1e-4 and np.quantile(d_dir, 0.999) < 1e-4
-    assert np.quantile(d_len, 0.999) < 1e-4
+    assert d_pos.max() < 1e-4 and d_dir.max() < 1e-5
+    assert np.quantile(d_len, 0.999) < 1e-5 and d_len.max() < 1e-3
     return same
 
 
@@ -52,7 +52,7 @@ def test_walk_matches_oracle_pure_scattering(orc, tau):
     cond = inputs.fixed_cell_conditions(n, tau, 1.0, seed=31)
     g = _gpu(binding, cond, binding.MODE_CONTINUOUS, seed=2)
     o = orc.mc_transmit(cond, 0, seed=2, nthreads=8)
-    _compare(g, o, max_mismatch=2e-3)
+    _compare(g, o, max_mismatch=5e-4)
 
 
 def test_walk_matches_oracle_mixed_cells(orc):
@@ -61,7 +61,7 @@ def test_walk_matches_oracle_mixed_cells(orc):
     cond = inputs.transmission_conditions(n, 32)
     g = _gpu(binding, cond, binding.MODE_CONTINUOUS, seed=7, id_base=12345)
     o = orc.mc_transmit(cond, 0, seed=7, id_base=12345, nthreads=8)
-    _compare(g, o, max_mismatch=2e-3)
+    _compare(g, o, max_mismatch=5e-4)
 
 
 def test_walk_analog_absorption_matches_oracle(orc):
@@ -71,7 +71,7 @@ def test_walk_analog_absorption_matches_oracle(orc):
     cond = inputs.fixed_cell_conditions(n, 1.0, 0.9, seed=0)
     g = _gpu(binding, cond, binding.MODE_ANALOG, seed=0)
     o = orc.mc_transmit(cond, 1, seed=0)
-    _compare(g, o, max_mismatch=2e-3)
+    _compare(g, o, max_mismatch=5e-4)
     counts = [int(np.sum(g["face"] == f)) for f in (-1, 0, 1, 2, 3)]
     assert sum(counts) == n
 
