@@ -229,6 +229,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         std::memcpy(staging.data() + off_b[l], bias[l].data(), bias[l].size() * sizeof(float));
         m->tmpl.wA[l] = (const char *)m->dev_mem + off_f[l];
         m->tmpl.bias[l] = (const float *)((const char *)m->dev_mem + off_b[l]);
+        m->tmpl.wA_bytes[l] = (uint32_t)frag[l].size();
+        m->tmpl.bias_bytes[l] = (uint32_t)(bias[l].size() * sizeof(float));
     }
     e = hipMemcpy(m->dev_mem, staging.data(), total, hipMemcpyHostToDevice);
     if (e != hipSuccess) {

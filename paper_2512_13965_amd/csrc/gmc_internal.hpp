@@ -57,6 +57,7 @@ __host__ __device__ inline int phys_to_feature(int p_in, int p)
 struct MlpParams {
     const void *wA[5];        // arranged operand fragments per layer
     const float *bias[5];     // per layer, rows padded to a multiple of 32, pre-divided by oscale
+    uint32_t wA_bytes[5], bias_bytes[5];   // sizes of the above (bounds of the buffer loads)
     float oscale[5];          // accumulator multiplier per layer (FP8 hidden layers: sw * sa)
     float inv_in_scale[5];    // 1 / activation scale of the input of layer l (FP8 hidden layers)
     const float *log_tau, *c, *y_in, *sin_th;

@@ -13,6 +13,9 @@
 //     type) writes each accumulator tile back into the LDS activation tile in the column order
 //     the next layer's operand reads expect, so the next layer's B-operand reads are contiguous
 //     16-byte LDS reads; the host permutes the next layer's weight columns to match.
+#include <type_traits>
+#include <utility>
+
 #include "gmc_device.hpp"
 #include "gmc_internal.hpp"
 
@@ -26,6 +29,20 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+using Rsrc = __amdgpu_buffer_rsrc_t;
+
+// Buffer resource over `bytes` bytes at p (raw, 32-bit elements): loads beyond the range return 0.
+__device__ __forceinline__ Rsrc make_rsrc(const void *p, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000);
+}
+
+// 16-byte load at byte offset voff (per lane) + soff (wave-uniform) of a buffer resource.
+__device__ __forceinline__ u32x4 buf_load16(Rsrc r, int voff, int soff)
+{
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, voff, soff, 0));
+}
 
 template <int P>
 struct Mma;
@@ -44,7 +61,7 @@ struct Mma<kF32> {
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af.z, bf.z, acc, 0, 0, 0);
         acc = __builtin_amdgcn_mfma_f32_32x32x2f32(af.w, bf.w, acc, 0, 0, 0);
     }
-    static __device__ __forceinline__ Frag load_g(const char *p) { return *(const u32x4 *)p; }
+    static __device__ __forceinline__ Frag load_g(Rsrc r, int voff, int soff) { return buf_load16(r, voff, soff); }
     static __device__ __forceinline__ Frag load_s(const char *p) { return *(const u32x4 *)p; }
 };
 
@@ -56,7 +73,7 @@ struct Mma<kBF16> {
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                       __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
     }
-    static __device__ __forceinline__ Frag load_g(const char *p) { return *(const u32x4 *)p; }
+    static __device__ __forceinline__ Frag load_g(Rsrc r, int voff, int soff) { return buf_load16(r, voff, soff); }
     static __device__ __forceinline__ Frag load_s(const char *p) { return *(const u32x4 *)p; }
 };
 
@@ -69,65 +86,94 @@ struct Mma<kFP8> {
         // the epilogue with the per-layer power-of-two factors)
         acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
     }
-    static __device__ __forceinline__ Frag load_g(const char *p)
+    static __device__ __forceinline__ Frag cat(u32x4 lo, u32x4 hi)
     {
-        const u32x4 lo = *(const u32x4 *)p, hi = *(const u32x4 *)(p + 16);
         return i32x8{(int)lo.x, (int)lo.y, (int)lo.z, (int)lo.w,
                      (int)hi.x, (int)hi.y, (int)hi.z, (int)hi.w};
     }
-    static __device__ __forceinline__ Frag load_s(const char *p) { return load_g(p); }
+    static __device__ __forceinline__ Frag load_g(Rsrc r, int voff, int soff)
+    {
+        return cat(buf_load16(r, voff, soff), buf_load16(r, voff + 16, soff));
+    }
+    static __device__ __forceinline__ Frag load_s(const char *p)
+    {
+        return cat(*(const u32x4 *)p, *(const u32x4 *)(p + 16));
+    }
 };
 
-// acc[r][c] += W[tile0 + r] (k-blocks 0..NKB-1) x act[col tile c] for one wave.
-// Weight fragment (T, kb) of lane l lives at wA + ((T * NKB + kb) * 64 + l) * frag_bytes.
-// B operand of lane (n, h) for column tile c and k-block kb: LDS row 32c + n, columns
-// kb * W + h * W / 2 ... + W / 2 - 1 (W = k-block width), one contiguous chunk.
-template <int P, int RT, int CT, int NKB>
-__device__ __forceinline__ void mma_layer(f32x16 (&acc)[RT][CT], const char *__restrict__ wA,
-                                          int tile0, const char *act, int stride, int col0,
-                                          int lane)
+template <int... Is, typename F>
+__device__ __forceinline__ void sfor_impl(std::integer_sequence<int, Is...>, F &&f)
+{
+    (f(std::integral_constant<int, Is>{}), ...);
+}
+
+// Calls f(integral_constant<int, i>) for i = 0 .. N-1: every index is a compile-time constant,
+// so register arrays indexed by it stay in registers.
+template <int N, typename F>
+__device__ __forceinline__ void sfor(F &&f)
+{
+    sfor_impl(std::make_integer_sequence<int, N>{}, f);
+}
+
+// acc[r][c] += W[T0 + r] (k-blocks 0..NKB-1) x act[column tile col0 + c] for one wave, k-block
+// loop fully unrolled; hook(kb) runs after the MFMAs of k-block kb are issued (used to
+// overlap the previous pass's epilogue with this pass's matrix work).
+// Weight fragment (T, kb) of lane l lives at wA + ((T * NKB + kb) * 64 + l) * frag_bytes: one
+// contiguous 1 KB (2 KB for FP8) line per wave.  B operand of lane (n, h) for column tile c and
+// k-block kb: LDS row 32 c + n, bytes [kb * KBB + h * KBB / 2, ... + KBB / 2).
+// A fragments are prefetched two k-blocks ahead, B fragments one.
+template <int P, int RP, int CT, int NKB, typename Hook>
+__device__ __forceinline__ void mma_pass(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, const char *act,
+                                         int stride, int col0, int lane, Hook &&hook)
 {
     using M = Mma<P>;
     using Frag = typename M::Frag;
     constexpr int FB = frag_bytes(P);
-    constexpr int KBB = kb_width(P) * elem_bytes(P);   // bytes of one k-block in an LDS row
+    constexpr int KBB = kb_width(P) * elem_bytes(P);
     const int h = lane >> 5, n = lane & 31;
-    const char *ga = wA + ((size_t)tile0 * NKB * 64 + lane) * FB;
+    const int t0 = __builtin_amdgcn_readfirstlane(T0);     // wave-uniform: scalar offsets
+    const int voff = lane * FB;
     const char *sb = act + (col0 * 32 + n) * stride + h * (KBB / 2);
-    Frag a[2][RT], b[2][CT];
+    Frag a[3][RP], b[2][CT];
+    auto loadA = [&](int slot, int kb) {
 #pragma unroll
-    for (int r = 0; r < RT; ++r) a[0][r] = M::load_g(ga + (size_t)r * NKB * 64 * FB);
+        for (int r = 0; r < RP; ++r) a[slot][r] = M::load_g(wA, voff, ((t0 + r) * NKB + kb) * 64 * FB);
+    };
+    auto loadB = [&](int slot, int kb) {
 #pragma unroll
-    for (int c = 0; c < CT; ++c) b[0][c] = M::load_s(sb + c * 32 * stride);
-#pragma unroll 2
-    for (int kb = 0; kb < NKB; ++kb) {
-        const int cur = kb & 1, nxt = cur ^ 1;
-        if (kb + 1 < NKB) {
+        for (int c = 0; c < CT; ++c) b[slot][c] = M::load_s(sb + c * 32 * stride + kb * KBB);
+    };
+    loadA(0, 0);
+    if constexpr (NKB > 1) loadA(1, 1);
+    loadB(0, 0);
+    sfor<NKB>([&](auto KB) {
+        constexpr int kb = decltype(KB)::value;
+        if constexpr (kb + 2 < NKB) loadA((kb + 2) % 3, kb + 2);
+        if constexpr (kb + 1 < NKB) loadB((kb + 1) % 2, kb + 1);
 #pragma unroll
-            for (int r = 0; r < RT; ++r)
-                a[nxt][r] = M::load_g(ga + ((size_t)r * NKB + kb + 1) * 64 * FB);
+        for (int r = 0; r < RP; ++r)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) b[nxt][c] = M::load_s(sb + c * 32 * stride + (kb + 1) * KBB);
-        }
-#pragma unroll
-        for (int r = 0; r < RT; ++r)
-#pragma unroll
-            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[cur][r], b[cur][c]);
-    }
+            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[kb % 3][r], b[kb % 2][c]);
+        hook(KB);
+        // keep each k-block in its own scheduling region: otherwise the scheduler merges the
+        // passes' k-loops (they are independent), which defeats both the prefetch distance and
+        // the epilogue overlap and raises register pressure
+        __builtin_amdgcn_sched_barrier(0);
+    });
 }
 
-// acc[r][c][i] = bias of output row 32 * (tile0 + r) + 8 * (i / 4) + 4 * h + i % 4.
-template <int RT, int CT>
-__device__ __forceinline__ void init_bias(f32x16 (&acc)[RT][CT], const float *__restrict__ bias,
-                                          int tile0, int lane)
+// acc[r][c][i] = bias of output row 32 * (T0 + r) + 8 * (i / 4) + 4 * h + i % 4.
+template <int RP, int CT>
+__device__ __forceinline__ void init_bias(f32x16 (&acc)[RP][CT], Rsrc bias, int T0, int lane)
 {
     const int h = lane >> 5;
+    const int t0 = __builtin_amdgcn_readfirstlane(T0);
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
+    for (int r = 0; r < RP; ++r) {
         f32x16 v;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
-            const f32x4 b4 = *(const f32x4 *)(bias + 32 * (tile0 + r) + 8 * g + 4 * h);
+            const f32x4 b4 = __builtin_bit_cast(f32x4, buf_load16(bias, (8 * g + 4 * h) * 4, 32 * (t0 + r) * 4));
             v[4 * g + 0] = b4.x;
             v[4 * g + 1] = b4.y;
             v[4 * g + 2] = b4.z;
@@ -154,40 +200,112 @@ __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float 
     return (uint32_t)w;
 }
 
-// SiLU(acc * oscale) * inv_next written into the LDS activation tile in the column order of a
-// consumer with operand precision PO (see phys_to_feature()).
-template <int PO, int RT, int CT>
-__device__ __forceinline__ void epilogue(const f32x16 (&acc)[RT][CT], int tile0, char *act,
-                                         int stride, int lane, float oscale, float inv_next)
+// 32-bit words one epilogue unit (4 consecutive accumulator values) packs into.
+__host__ __device__ constexpr int words_per_unit(int po) { return po == kF32 ? 4 : (po == kBF16 ? 2 : 1); }
+
+// One epilogue unit: SiLU(acc * oscale) * inv_next for accumulator values 4g .. 4g+3, packed in
+// the consumer's operand type.
+template <int PO, bool SCALE>
+__device__ __forceinline__ void epi_unit(const f32x16 &acc, int g, float oscale, float inv_next,
+                                         uint32_t *w)
+{
+    float y[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const float a = SCALE ? acc[4 * g + j] * oscale : acc[4 * g + j];
+        y[j] = SCALE ? silu(a) * inv_next : silu(a);
+    }
+    if constexpr (PO == kF32) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) w[j] = __builtin_bit_cast(uint32_t, y[j]);
+    } else if constexpr (PO == kBF16) {
+        w[0] = pack_bf16(y[0], y[1]);
+        w[1] = pack_bf16(y[2], y[3]);
+    } else {
+        w[0] = pack_fp8x4(y[0], y[1], y[2], y[3]);
+    }
+}
+
+// Store the packed epilogue of accumulator tile (row tile T, column tile c) into the LDS
+// activation tile in the column order that a consumer with operand precision PO reads
+// (see phys_to_feature()).
+template <int PO>
+__device__ __forceinline__ void store_tile(const uint32_t *w, int T, int c, char *act, int stride,
+                                           int lane)
 {
     const int h = lane >> 5, n = lane & 31;
+    char *row = act + (c * 32 + n) * stride;
+    if constexpr (PO == kF32) {
 #pragma unroll
-    for (int r = 0; r < RT; ++r) {
-        const int T = tile0 + r;
+        for (int g = 0; g < 4; ++g)
+            *(u32x4 *)(row + ((4 * T + g) * 8 + 4 * h) * 4) =
+                u32x4{w[4 * g], w[4 * g + 1], w[4 * g + 2], w[4 * g + 3]};
+    } else if constexpr (PO == kBF16) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            char *row = act + (c * 32 + n) * stride;
-            float y[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) y[i] = silu(acc[r][c][i] * oscale) * inv_next;
-            if constexpr (PO == kF32) {
-#pragma unroll
-                for (int g = 0; g < 4; ++g)
-                    *(f32x4 *)(row + ((4 * T + g) * 8 + 4 * h) * 4) =
-                        f32x4{y[4 * g], y[4 * g + 1], y[4 * g + 2], y[4 * g + 3]};
-            } else if constexpr (PO == kBF16) {
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-                    *(u32x4 *)(row + ((2 * T + q) * 16 + 8 * h) * 2) =
-                        u32x4{pack_bf16(y[8 * q], y[8 * q + 1]), pack_bf16(y[8 * q + 2], y[8 * q + 3]),
-                              pack_bf16(y[8 * q + 4], y[8 * q + 5]), pack_bf16(y[8 * q + 6], y[8 * q + 7])};
-            } else {
-                *(u32x4 *)(row + (T / 2) * 64 + 32 * h + 16 * (T % 2)) =
-                    u32x4{pack_fp8x4(y[0], y[1], y[2], y[3]), pack_fp8x4(y[4], y[5], y[6], y[7]),
-                          pack_fp8x4(y[8], y[9], y[10], y[11]), pack_fp8x4(y[12], y[13], y[14], y[15])};
-            }
-        }
+        for (int q = 0; q < 2; ++q)
+            *(u32x4 *)(row + ((2 * T + q) * 16 + 8 * h) * 2) =
+                u32x4{w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]};
+    } else {
+        *(u32x4 *)(row + (T / 2) * 64 + 32 * h + 16 * (T % 2)) = u32x4{w[0], w[1], w[2], w[3]};
     }
+}
+
+// One dense layer + SiLU for this wave's RTW row tiles and all 128 samples of the tile.  The
+// rows are done in NP passes of RP row tiles; the epilogue of pass p runs interleaved with the
+// MFMA k-loop of pass p + 1 (it only reads pass p's accumulators), so the SiLU transcendentals
+// overlap the matrix unit.  Those results are held packed in registers until every wave has
+// finished reading the input tile (barrier, when `out` aliases the input); the last pass's
+// epilogue is computed and stored after that barrier.
+template <int PIN, int POUT, int RTW, int NKB, bool SCALE, bool IN_PLACE>
+__device__ __forceinline__ void dense_silu(Rsrc wA, Rsrc bias, int T0, const char *in, int in_stride, char *out,
+                                           int out_stride, int lane, float oscale, float inv_next)
+{
+    constexpr int RP = RTW >= 4 ? RTW / 2 : 1;     // row tiles per pass
+    constexpr int NP = RTW / RP;                   // passes
+    constexpr int UNITS = RP * 4 * 4;              // epilogue units (4 values) per pass
+    constexpr int WPU = words_per_unit(POUT);
+    constexpr int UPK = (UNITS + NKB - 1) / NKB;   // epilogue units per k-block
+    uint32_t pk[NP > 1 ? NP - 1 : 1][UNITS * WPU];
+    f32x16 acc[2][RP][4];
+    auto epi = [&](auto PP, int u) {
+        constexpr int pp = decltype(PP)::value;
+        const int r = u / 16, c = (u / 4) % 4, g = u % 4;
+        epi_unit<POUT, SCALE>(acc[pp % 2][r][c], g, oscale, inv_next, &pk[pp][u * WPU]);
+    };
+    sfor<NP>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        init_bias<RP, 4>(acc[p % 2], bias, T0 + p * RP, lane);
+        mma_pass<PIN, RP, 4, NKB>(acc[p % 2], wA, T0 + p * RP, in, in_stride, 0, lane, [&](auto KB) {
+            constexpr int kb = decltype(KB)::value;
+            if constexpr (p > 0) {
+                sfor<UPK>([&](auto J) {
+                    constexpr int u = kb * UPK + decltype(J)::value;
+                    if constexpr (u < UNITS) epi(std::integral_constant<int, p - 1>{}, u);
+                });
+            }
+        });
+        if constexpr (p > 0 && NKB * UPK < UNITS) {
+            sfor<UNITS - NKB * UPK>([&](auto J) {
+                epi(std::integral_constant<int, p - 1>{}, NKB * UPK + decltype(J)::value);
+            });
+        }
+    });
+    if constexpr (IN_PLACE) __syncthreads();
+    sfor<NP - 1>([&](auto P) {
+        constexpr int p = decltype(P)::value;
+        sfor<RP * 4>([&](auto TC) {
+            constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
+            store_tile<POUT>(&pk[p][(r * 4 + c) * 4 * WPU], T0 + p * RP + r, c, out, out_stride, lane);
+        });
+    });
+    constexpr int pl = NP - 1;
+    sfor<RP * 4>([&](auto TC) {
+        constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
+        uint32_t w[4 * WPU];
+#pragma unroll
+        for (int g = 0; g < 4; ++g) epi_unit<POUT, SCALE>(acc[pl % 2][r][c], g, oscale, inv_next, &w[g * WPU]);
+        store_tile<POUT>(w, T0 + pl * RP + r, c, out, out_stride, lane);
+    });
 }
 
 template <int MP, int H>
@@ -195,10 +313,11 @@ struct Cfg {
     static constexpr int P1 = layer_prec(MP, 0);            // layer 1 operand precision
     static constexpr int PH = layer_prec(MP, 1);            // hidden layers' operand precision
     static constexpr int P5 = layer_prec(MP, 4);            // last layer operand precision
+    static constexpr bool SCALE = (MP == kFP8);             // per-layer FP8 scales
     static constexpr int ACT_ELEM = (MP == kF32) ? 4 : 2;   // widest type stored in the tile
     static constexpr int ACT_STRIDE = H * ACT_ELEM + 16;    // +16 B: conflict-free row reads
     static constexpr int IN_STRIDE = 16 * elem_bytes(P1) + 16;
-    static constexpr int RT = H / (32 * kWaves);            // row tiles per wave
+    static constexpr int RTW = H / (32 * kWaves);           // row tiles per wave
     static constexpr int NKB1 = 16 / kb_width(P1);
     static constexpr int NKBH = H / kb_width(PH);
     static constexpr int NKB5 = H / kb_width(P5);
@@ -222,7 +341,7 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
     const int wave = tid >> 6, lane = tid & 63;
     const int64_t ntiles = (p.n + kTileM - 1) / kTileM;
     const float dt = 1.0f / (float)p.K;
-    const int tile0 = wave * C::RT;
+    const int T0 = wave * C::RTW;
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t base = tile * kTileM;
@@ -253,50 +372,60 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
 
         for (int k = 0; k < p.K; ++k) {
             const float t = (float)k * dt;
-            // layer-1 input row of sample sn: [x0..x4, t, ln tau, c, 2y-1, sin th, 0 x 6]
-            {
-                const int sn = tid & (kTileM - 1), half = tid >> 7;
-                float v[8];
+            // layer-1 input row of sample tid: [x0..x4, t, ln tau, c, 2y-1, sin th, 0 x 6]
+            if (tid < kTileM) {
+                float v[16];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const int q = 8 * half + j;
-                    v[j] = q < 5 ? xs[q * kTileM + sn]
-                                 : (q == 5 ? t : (q < 10 ? cf[(q - 6) * kTileM + sn] : 0.0f));
-                }
-                char *row = in0 + sn * C::IN_STRIDE;
+                for (int d = 0; d < 5; ++d) v[d] = xs[d * kTileM + tid];
+                v[5] = t;
+#pragma unroll
+                for (int d = 0; d < 4; ++d) v[6 + d] = cf[d * kTileM + tid];
+#pragma unroll
+                for (int d = 10; d < 16; ++d) v[d] = 0.0f;
+                char *row = in0 + tid * C::IN_STRIDE;
                 if constexpr (C::P1 == kF32) {
-                    *(f32x4 *)(row + 32 * half) = f32x4{v[0], v[1], v[2], v[3]};
-                    *(f32x4 *)(row + 32 * half + 16) = f32x4{v[4], v[5], v[6], v[7]};
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        *(f32x4 *)(row + 16 * q) = f32x4{v[4 * q], v[4 * q + 1], v[4 * q + 2], v[4 * q + 3]};
                 } else {
-                    *(u32x4 *)(row + 16 * half) = u32x4{pack_bf16(v[0], v[1]), pack_bf16(v[2], v[3]),
-                                                        pack_bf16(v[4], v[5]), pack_bf16(v[6], v[7])};
+#pragma unroll
+                    for (int q = 0; q < 2; ++q)
+                        *(u32x4 *)(row + 16 * q) =
+                            u32x4{pack_bf16(v[8 * q], v[8 * q + 1]), pack_bf16(v[8 * q + 2], v[8 * q + 3]),
+                                  pack_bf16(v[8 * q + 4], v[8 * q + 5]), pack_bf16(v[8 * q + 6], v[8 * q + 7])};
                 }
             }
             __syncthreads();
 
-            f32x16 acc[C::RT][4];
-            // layer 1: 10 -> H
-            init_bias<C::RT, 4>(acc, p.bias[0], tile0, lane);
-            mma_layer<C::P1, C::RT, 4, C::NKB1>(acc, (const char *)p.wA[0], tile0, in0, C::IN_STRIDE, 0, lane);
-            epilogue<C::PH, C::RT, 4>(acc, tile0, act, C::ACT_STRIDE, lane, p.oscale[0], p.inv_in_scale[1]);
+            // layer 1: 10 -> H (reads in0, writes the activation tile: no barrier before writing)
+            dense_silu<C::P1, C::PH, C::RTW, C::NKB1, C::SCALE, false>(
+                make_rsrc(p.wA[0], p.wA_bytes[0]), make_rsrc(p.bias[0], p.bias_bytes[0]), T0, in0, C::IN_STRIDE, act, C::ACT_STRIDE, lane,
+                p.oscale[0], p.inv_in_scale[1]);
             __syncthreads();
-            // hidden layers 2..4: H -> H
+            // hidden layers 2..4: H -> H, in place.  One code instance in a runtime loop (layers
+            // whose output feeds an operand of the same type as their input); an FP8 model's
+            // last hidden layer writes BF16 for the output layer and is a second instance.
+            constexpr int NSAME = (C::PH == C::P5) ? 3 : 2;
 #pragma unroll 1
-            for (int l = 1; l < 4; ++l) {
-                init_bias<C::RT, 4>(acc, p.bias[l], tile0, lane);
-                mma_layer<C::PH, C::RT, 4, C::NKBH>(acc, (const char *)p.wA[l], tile0, act, C::ACT_STRIDE, 0, lane);
+            for (int l = 1; l <= NSAME; ++l) {
+                dense_silu<C::PH, C::PH, C::RTW, C::NKBH, C::SCALE, true>(
+                    make_rsrc(p.wA[l], p.wA_bytes[l]), make_rsrc(p.bias[l], p.bias_bytes[l]), T0,
+                    act, C::ACT_STRIDE, act, C::ACT_STRIDE, lane, p.oscale[l],
+                    l < 3 ? p.inv_in_scale[l + 1] : 1.0f);
                 __syncthreads();
-                if (l < 3)
-                    epilogue<C::PH, C::RT, 4>(acc, tile0, act, C::ACT_STRIDE, lane, p.oscale[l], p.inv_in_scale[l + 1]);
-                else
-                    epilogue<C::P5, C::RT, 4>(acc, tile0, act, C::ACT_STRIDE, lane, p.oscale[l], 1.0f);
+            }
+            if constexpr (NSAME == 2) {
+                dense_silu<C::PH, C::P5, C::RTW, C::NKBH, C::SCALE, true>(
+                    make_rsrc(p.wA[3], p.wA_bytes[3]), make_rsrc(p.bias[3], p.bias_bytes[3]), T0,
+                    act, C::ACT_STRIDE, act, C::ACT_STRIDE, lane, p.oscale[3], 1.0f);
                 __syncthreads();
             }
             // layer 5: H -> 5 (rows padded to 32); wave w handles sample column tile w
             {
                 f32x16 out[1][1];
-                init_bias<1, 1>(out, p.bias[4], 0, lane);
-                mma_layer<C::P5, 1, 1, C::NKB5>(out, (const char *)p.wA[4], 0, act, C::ACT_STRIDE, wave, lane);
+                init_bias<1, 1>(out, make_rsrc(p.bias[4], p.bias_bytes[4]), 0, lane);
+                mma_pass<C::P5, 1, 1, C::NKB5>(out, make_rsrc(p.wA[4], p.wA_bytes[4]), 0, act,
+                                               C::ACT_STRIDE, wave, lane, [](auto) {});
                 const int sn = wave * 32 + (lane & 31);
                 if (lane < 32) {
 #pragma unroll
