@@ -129,6 +129,68 @@ int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_b
  * reflected, bit2 zero-norm direction. */
 int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, void *stream);
 
+/* ---------------------------------------------------------------------------------------- */
+/* Cell-to-cell transport (paper section "Transport Algorithm", stages 1-4; track-length     */
+/* flux estimator of eqs. 5-7).  A world owns one device particle bank shared by up to        */
+/* max_problems problems, so particles of different problems (grids, materials, seeds) are     */
+/* sampled together in one launch.                                                             */
+/* ---------------------------------------------------------------------------------------- */
+typedef struct gmc_world gmc_world;
+
+/* One transport problem: nx * ny square cells of side L (physical length), cell (i, j) at
+ * index j * nx + i (i along x).  tau[cell] = sigma_t * L (>= 0) and c[cell] = sigma_s / sigma_t
+ * (in [0, 1]) are host FP64 arrays read during gmc_problem_add.  An isotropic unit source is
+ * uniform over the cells [src_x0, src_x0 + src_nx) x [src_y0, src_y0 + src_ny).  Boundaries are
+ * vacuum (reflect = 0) or specular (reflect = 1).  A history ends when it leaves the domain or
+ * when its weight drops below w_min after a cell visit (the weight is then tallied as cutoff).
+ * History h draws its birth from Philox key = seed, counter (h, 0, 0, 3); the k-th cell it
+ * visits (k = 0 for the birth cell) uses random stream id h + 2^32 k for its transmission. */
+typedef struct {
+    int32_t nx, ny;
+    double L;
+    const double *tau, *c;
+    int32_t src_x0, src_y0, src_nx, src_ny;
+    int32_t reflect;
+    double w_min;
+    uint64_t seed;
+} gmc_problem_desc;
+
+/* Device bytes gmc_world_create would allocate for these capacities (admission control). */
+int gmc_world_footprint(int64_t bank_capacity, int32_t max_problems, int64_t max_cells, size_t *bytes);
+/* Allocates a world on the current device: a bank of bank_capacity particles (two copies, for
+ * compaction), sampler staging for as many transmissions, max_problems problem slots and
+ * max_cells cells of materials and FP64 tallies shared by the problems.  GMC_ENOMEM if the
+ * device allocation fails. */
+int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_cells, gmc_world **out);
+int gmc_world_destroy(gmc_world *w);
+/* Adds a problem: takes a slot and nx * ny cells, uploads the materials, zeroes its tallies.
+ * Synchronises `stream`.  GMC_ENOMEM when no slot or not enough contiguous free cells. */
+int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid, void *stream);
+/* Frees a problem's slot and cells; GMC_EINVAL while it still has particles in flight. */
+int gmc_problem_remove(gmc_world *w, int32_t pid);
+/* Births of histories [h_begin, h_begin + count) of problem pid (ids below 2^32): source
+ * sampling, the first leg in the birth cell by the analog walk (continuous absorption), its
+ * tally, and the move to the neighbour.  Survivors join the bank.  GMC_ENOMEM if count exceeds
+ * the free bank slots.  Synchronises `stream`; *n_alive_out (optional) = particles in flight. */
+int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count, void *stream,
+                     int64_t *n_alive_out);
+/* One transport step for every particle in flight: canonical conditions (stage 1), one cell
+ * transmission each with the generative sampler (sampler = GMC_SAMPLER_GMC, model m, K Euler
+ * steps) or the analog walk with continuous absorption (GMC_SAMPLER_MC, m unused), FP64
+ * attenuation and tallies (stage 3), move / leak / cutoff and compaction (stage 4).
+ * Synchronises `stream`; *n_alive_out (optional) = particles still in flight. */
+int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
+                       int64_t *n_alive_out);
+/* Particles of problem pid still in flight after the last step or injection. */
+int gmc_problem_alive(const gmc_world *w, int32_t pid, int64_t *n_alive);
+/* Copies problem pid's FP64 tallies, summed over its histories so far, to host arrays of
+ * nx * ny doubles (any pointer may be NULL): track-length flux estimate per cell (eq. 7,
+ * divided by the cell volume L^2), deposited weight per cell (eq. 6), weight that leaked out
+ * of the domain from each boundary cell, weight dropped by the cutoff in each cell.
+ * Synchronises `stream`. */
+int gmc_problem_tally(gmc_world *w, int32_t pid, double *flux, double *absorbed, double *leak,
+                      double *cutoff, void *stream);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *gmc_last_error(void);
 

@@ -199,3 +199,105 @@ def gmc_decode(raw: torch.Tensor, n: int, out: DeviceExit | None = None,
         _need(flags, torch.int32, n, "flags")
     _check(lib().gmc_decode(_ptr(raw), n, out.c_struct(n), _ptr(flags), _stream(stream)))
     return out
+
+
+# ------------------------------------------------------------------------------------------
+# transport world (gmc_world_* / gmc_problem_* / gmc_transport_step)
+# ------------------------------------------------------------------------------------------
+
+class _ProblemDesc(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("L", ctypes.c_double),
+                ("tau", ctypes.c_void_p), ("c", ctypes.c_void_p),
+                ("src_x0", ctypes.c_int32), ("src_y0", ctypes.c_int32),
+                ("src_nx", ctypes.c_int32), ("src_ny", ctypes.c_int32),
+                ("reflect", ctypes.c_int32), ("w_min", ctypes.c_double), ("seed", ctypes.c_uint64)]
+
+
+def _transport_sigs(L):
+    P, I32, I64, U64, I = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_int
+    L.gmc_world_footprint.argtypes = [I64, I32, I64, ctypes.POINTER(ctypes.c_size_t)]
+    L.gmc_world_create.argtypes = [I64, I32, I64, ctypes.POINTER(P)]
+    L.gmc_world_destroy.argtypes = [P]
+    L.gmc_problem_add.argtypes = [P, ctypes.POINTER(_ProblemDesc), ctypes.POINTER(I32), P]
+    L.gmc_problem_remove.argtypes = [P, I32]
+    L.gmc_world_inject.argtypes = [P, I32, U64, I64, P, ctypes.POINTER(I64)]
+    L.gmc_transport_step.argtypes = [P, I, P, I, P, ctypes.POINTER(I64)]
+    L.gmc_problem_alive.argtypes = [P, I32, ctypes.POINTER(I64)]
+    L.gmc_problem_tally.argtypes = [P, I32, P, P, P, P, P]
+    for name in ("gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
+                 "gmc_problem_remove", "gmc_world_inject", "gmc_transport_step",
+                 "gmc_problem_alive", "gmc_problem_tally"):
+        getattr(L, name).restype = ctypes.c_int
+
+
+def world_footprint(capacity: int, max_problems: int, max_cells: int) -> int:
+    L = lib()
+    _transport_sigs(L)
+    b = ctypes.c_size_t()
+    _check(L.gmc_world_footprint(capacity, max_problems, max_cells, ctypes.byref(b)))
+    return int(b.value)
+
+
+class World:
+    """Device particle bank + problem slots (gmc_world_create / gmc_world_destroy)."""
+
+    def __init__(self, capacity: int, max_problems: int = 1, max_cells: int = 1 << 16):
+        self._L = lib()
+        _transport_sigs(self._L)
+        h = ctypes.c_void_p()
+        _check(self._L.gmc_world_create(capacity, max_problems, max_cells, ctypes.byref(h)))
+        self._h = h
+        self.capacity = capacity
+        self._shapes = {}
+
+    def add_problem(self, problem, seed: int, stream=None) -> int:
+        import numpy as np
+        tau = np.ascontiguousarray(problem.tau, np.float64)
+        c = np.ascontiguousarray(problem.c, np.float64)
+        d = _ProblemDesc(problem.nx, problem.ny, problem.L, tau.ctypes.data, c.ctypes.data,
+                         problem.src_x0, problem.src_y0, problem.src_nx, problem.src_ny,
+                         int(problem.reflect), problem.w_min, seed)
+        pid = ctypes.c_int32()
+        _check(self._L.gmc_problem_add(self._h, ctypes.byref(d), ctypes.byref(pid), _stream(stream)))
+        self._shapes[pid.value] = problem.n_cells
+        return pid.value
+
+    def remove(self, pid: int):
+        _check(self._L.gmc_problem_remove(self._h, pid))
+        self._shapes.pop(pid, None)
+
+    def inject(self, pid: int, h_begin: int, count: int, stream=None) -> int:
+        n = ctypes.c_int64()
+        _check(self._L.gmc_world_inject(self._h, pid, h_begin, count, _stream(stream), ctypes.byref(n)))
+        return n.value
+
+    def step(self, sampler: int, model: Model | None = None, K: int = 16, stream=None) -> int:
+        n = ctypes.c_int64()
+        _check(self._L.gmc_transport_step(self._h, sampler, None if model is None else model.handle,
+                                          K, _stream(stream), ctypes.byref(n)))
+        return n.value
+
+    def alive(self, pid: int) -> int:
+        n = ctypes.c_int64()
+        _check(self._L.gmc_problem_alive(self._h, pid, ctypes.byref(n)))
+        return n.value
+
+    def tally(self, pid: int, stream=None) -> dict:
+        import numpy as np
+        m = self._shapes[pid]
+        out = {k: np.zeros(m) for k in ("flux", "absorbed", "leak", "cutoff")}
+        _check(self._L.gmc_problem_tally(self._h, pid, out["flux"].ctypes.data,
+                                         out["absorbed"].ctypes.data, out["leak"].ctypes.data,
+                                         out["cutoff"].ctypes.data, _stream(stream)))
+        return out
+
+    def close(self):
+        if self._h:
+            _check(self._L.gmc_world_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -122,13 +122,10 @@ unsigned long long *device_queue_counter()
 
 }  // namespace gmc
 
-struct gmc_model {
-    int precision = 0;
-    int hidden = 0;
-    int device = 0;
-    void *dev_mem = nullptr;
-    gmc::MlpParams tmpl{};   // weight / bias pointers and scales
-};
+namespace gmc {
+int set_error(int code, const char *msg) { return fail(code, msg); }
+int set_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
+}  // namespace gmc
 
 extern "C" {
 

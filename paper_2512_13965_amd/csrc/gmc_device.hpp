@@ -78,6 +78,94 @@ __device__ __forceinline__ void normal5(uint64_t seed, uint64_t id, float z[5])
     }
 }
 
+// State of one analog walk inside the unit cell (paper section "Monte Carlo Method", eq. 4),
+// advanced one flight at a time so a persistent kernel can refill lanes between flights.
+struct Walker {
+    float x, y, u, v, len, inv_sig, cs;
+    uint32_t flight, ncoll;
+    bool scatter, analog;
+};
+
+// mode 0 (continuous absorption): flights ~ Exp(c tau); mode 1 (analog): flights ~ Exp(tau)
+// and a collision absorbs when xi > c.  Start at (x, y) with direction (u, v).
+__device__ __forceinline__ void walker_init(Walker &w, float tau, float c, int mode, float x, float y,
+                                            float u, float v)
+{
+    w.analog = (mode == 1);
+    const float sig = w.analog ? tau : c * tau;
+    w.scatter = sig > 1e-30f;            // below this 1/sig would overflow
+    w.inv_sig = w.scatter ? 1.0f / sig : 0.0f;
+    w.cs = c;
+    w.x = x;
+    w.y = y;
+    w.u = u;
+    w.v = v;
+    w.len = 0.0f;
+    w.flight = 0;
+    w.ncoll = 0;
+}
+
+constexpr int kInside = -3;
+
+// One flight: distance to the boundary, sampled flight length, then scatter or leave.
+// Flight j draws Philox(key, counter (stream lo, stream hi, j, walk tag)): word 0 -> length,
+// word 1 -> new direction, word 2 -> absorption test.  Returns kInside while the particle is
+// still in the cell, else the exit face 0..3 (pos = counter-clockwise position along it),
+// -1 absorbed, -2 capped.
+__device__ __forceinline__ int walker_flight(Walker &w, uint64_t key, uint64_t stream, float &pos)
+{
+    const float kInf = __builtin_inff();
+    float tx = kInf, ty = kInf;
+    if (w.u > 0.0f) tx = (1.0f - w.x) * fast_rcp(w.u);
+    else if (w.u < 0.0f) tx = -w.x * fast_rcp(w.u);
+    if (w.v > 0.0f) ty = (1.0f - w.y) * fast_rcp(w.v);
+    else if (w.v < 0.0f) ty = -w.y * fast_rcp(w.v);
+    const bool xface = tx <= ty;
+    const float db = fmaxf(xface ? tx : ty, 0.0f);
+    const U4 r = draw4(key, stream, w.flight, kTagWalk);
+    const float ds = w.scatter ? neg_log(u01(r.a)) * w.inv_sig : kInf;
+    int face = kInside;
+    if (ds >= db) {
+        w.len += db;
+        if (xface) {
+            const float ye = fminf(fmaxf(w.y + db * w.v, 0.0f), 1.0f);
+            face = w.u > 0.0f ? 1 : 3;
+            pos = w.u > 0.0f ? ye : 1.0f - ye;
+        } else {
+            const float xe = fminf(fmaxf(w.x + db * w.u, 0.0f), 1.0f);
+            face = w.v > 0.0f ? 2 : 0;
+            pos = w.v > 0.0f ? 1.0f - xe : xe;
+        }
+    } else {
+        w.x += ds * w.u;
+        w.y += ds * w.v;
+        w.len += ds;
+        w.ncoll += 1;
+        if (w.analog && u01(r.c) > w.cs) {
+            face = -1;
+        } else {
+            const float ph = u01(r.b);
+            w.u = cos_turns(ph);
+            w.v = sin_turns(ph);
+        }
+    }
+    w.flight += 1;
+    if (face == kInside && w.flight >= kMaxFlights) face = -2;
+    if (face < 0 && face != kInside) pos = 0.0f;
+    return face;
+}
+
+// Rotation of a direction by k quarter turns counter-clockwise.
+__device__ __forceinline__ void rot_quarter(int k, float a, float b, float &ra, float &rb)
+{
+    switch (k & 3) {
+    case 0: ra = a; rb = b; break;
+    case 1: ra = -b; rb = a; break;
+    case 2: ra = -a; rb = -b; break;
+    default: ra = b; rb = -a; break;
+    }
+}
+
 // Exit record from x_K (paper eq. 11 in the 5-dim reading): face = number of the thresholds
 // -1, 0, 1 reached by a4; pos = clamp((a0 + 1) / 2); direction (a1, a2) normalised, outward
 // normal if its norm is below 1e-6, normal component reflected if it points inward;

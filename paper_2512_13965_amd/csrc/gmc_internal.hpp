@@ -63,6 +63,8 @@ struct MlpParams {
     const float *log_tau, *c, *y_in, *sin_th;
     const float *noise;       // optional [5][n]
     float *raw;               // optional [5][n]
+    const uint64_t *ids;      // optional per-sample random stream ids (else id_base + i)
+    const uint64_t *keys;     // optional per-sample Philox keys (else seed)
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
     int64_t n;
@@ -78,6 +80,8 @@ struct WalkParams {
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
     uint32_t *ncoll;          // optional
+    const uint64_t *ids;      // optional per-particle random stream ids (else id_base + i)
+    const uint64_t *keys;     // optional per-particle Philox keys (else seed)
     int64_t n;
     int mode;
     uint64_t seed, id_base;
@@ -91,4 +95,16 @@ hipError_t launch_decode(const float *raw, int64_t n, int32_t *face, float *pos,
 int device_cu_count();
 unsigned long long *device_queue_counter();
 
+// Record a thread-local error message (returned by gmc_last_error) and return `code`.
+int set_error(int code, const char *msg);
+int set_hip_error(hipError_t e, const char *what);
+
 }  // namespace gmc
+
+struct gmc_model {
+    int precision = 0;
+    int hidden = 0;
+    int device = 0;
+    void *dev_mem = nullptr;
+    gmc::MlpParams tmpl{};   // weight / bias pointers and scales
+};

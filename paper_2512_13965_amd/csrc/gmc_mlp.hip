@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
 #pragma unroll
                     for (int d = 0; d < 5; ++d) z[d] = p.noise[d * p.n + i];
                 } else {
-                    normal5(p.seed, p.id_base + (uint64_t)i, z);
+                    normal5(p.keys ? p.keys[i] : p.seed, p.ids ? p.ids[i] : p.id_base + (uint64_t)i, z);
                 }
             }
 #pragma unroll

@@ -1,0 +1,636 @@
+// Cell-to-cell transport on gfx950 (paper: section "Transport Algorithm", its four stages; the
+// track-length flux estimator of eqs. 5-7).
+//
+// A "world" holds a structure-of-arrays particle bank shared by any number of problems (each a
+// grid of square cells with its own materials, source, seed and FP64 tallies), so one sampler
+// launch serves particles of different problems and cells together.  One transport step:
+//   gather  (stage 1)  bank -> canonical left-entry conditions, per-particle random stream ids;
+//   sample  (stage 2)  the generative sampler (gmc_transmit kernels) or the analog walk;
+//   apply   (stages 3-4)  FP64 rescale of the path to physical units, weight attenuation and
+//            flux / absorption tallies (FP64 atomics), rotation back to the global frame, move
+//            to the neighbour cell or leave / cut off, and compaction of the survivors into the
+//            other bank with one atomic per wave (ballot + mbcnt).
+// Births draw a source particle and walk its first leg inside the birth cell with the analog
+// walk (the paper's separate volumetric-source network is not part of this library).
+// Random numbers depend only on (problem seed, history id, cell-visit index): a history's
+// result does not depend on which other problems share the bank or on its slot.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/gmc.h"
+#include "gmc_device.hpp"
+#include "gmc_internal.hpp"
+
+namespace gmc {
+namespace {
+
+struct ProblemDev {
+    int32_t nx, ny;
+    double L;
+    int64_t cell0;                 // first global cell index of this problem
+    int32_t sx0, sy0, snx, sny;    // source block
+    int32_t reflect;
+    double w_min;
+    uint64_t seed;
+};
+
+struct BankDev {
+    int32_t *cell, *pid, *entry;
+    float *yin, *gx, *gy;
+    double *w;
+    uint32_t *hist, *event;
+};
+
+struct CellsDev {
+    const double *tau, *c;         // per global cell (FP64: tallies)
+    const float *ltau, *cf;        // per global cell (FP32: sampler conditions)
+    double *flux, *absorbed, *leak, *cutoff;
+    const ProblemDev *prob;
+};
+
+__device__ __forceinline__ int lane_rank(uint64_t mask)
+{
+    return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Stage 3 for one cell visit: w_out = w e^{-sigma_a l} (eq. 5), deposit dw (eq. 6) and flux
+// dw / (V sigma_a) (eq. 7; w l / V when sigma_a = 0), all in FP64 with the physical path.
+__device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemDev &P, int cell,
+                                              double w, float path_units)
+{
+    const double L = P.L;
+    const double sig_a = (1.0 - cd.c[cell]) * cd.tau[cell] / L;
+    const double ls = (double)path_units * L;
+    const double dw = w * (-expm1(-sig_a * ls));
+    const double V = L * L;
+    const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
+    atomicAdd(&cd.flux[cell], phi);
+    atomicAdd(&cd.absorbed[cell], dw);
+    return w - dw;
+}
+
+struct Next {
+    int32_t cell, entry;
+    float yin, gx, gy;
+    bool alive;
+};
+
+// Stage 4: after leaving `cell` through local face `face` at counter-clockwise position pos
+// with global direction (gx, gy) and weight w_out: cut off, leak, reflect or enter the
+// neighbour (whose entry face is the opposite one, entered at position 1 - pos in its own
+// counter-clockwise orientation, i.e. canonical height y = pos).
+__device__ __forceinline__ Next move_on(const CellsDev &cd, const ProblemDev &P, int cell, int face,
+                                        float pos, float gx, float gy, double w_out)
+{
+    Next nx{cell, 0, 0.0f, gx, gy, false};
+    if (face < 0 || face > 3) {              // capped walk: drop its weight with the cutoff
+        atomicAdd(&cd.cutoff[cell], w_out);
+        return nx;
+    }
+    if (w_out < P.w_min) {
+        atomicAdd(&cd.cutoff[cell], w_out);
+        return nx;
+    }
+    const int64_t local = cell - P.cell0;
+    const int ci = (int)(local % P.nx), cj = (int)(local / P.nx);
+    int ni = ci, nj = cj;
+    if (face == 0) nj -= 1;
+    else if (face == 1) ni += 1;
+    else if (face == 2) nj += 1;
+    else ni -= 1;
+    if (ni < 0 || nj < 0 || ni >= P.nx || nj >= P.ny) {
+        if (!P.reflect) {
+            atomicAdd(&cd.leak[cell], w_out);
+            return nx;
+        }
+        nx.entry = face;                     // specular reflection back into the same cell
+        nx.yin = 1.0f - pos;
+        if (face == 0 || face == 2) nx.gy = -gy;
+        else nx.gx = -gx;
+    } else {
+        nx.cell = (int32_t)(P.cell0 + (int64_t)nj * P.nx + ni);
+        nx.entry = (face + 2) & 3;
+        nx.yin = pos;
+    }
+    nx.alive = true;
+    return nx;
+}
+
+// Append the alive lanes' particles to `out` (one atomic per wave) and count them per problem.
+__device__ __forceinline__ void append(bool alive, const Next &nx, int32_t pid, double w,
+                                       uint32_t hist, uint32_t event, BankDev out,
+                                       unsigned long long *counter, unsigned long long *pcount)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t mask = __ballot(alive);
+    if (!mask) return;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long b = 0;
+    if (lane == leader) b = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    const unsigned long long base = (unsigned long long)__shfl((long long)b, leader);
+    if (alive) {
+        const int64_t j = (int64_t)(base + (unsigned long long)lane_rank(mask));
+        out.cell[j] = nx.cell;
+        out.pid[j] = pid;
+        out.entry[j] = nx.entry;
+        out.yin[j] = nx.yin;
+        out.gx[j] = nx.gx;
+        out.gy[j] = nx.gy;
+        out.w[j] = w;
+        out.hist[j] = hist;
+        out.event[j] = event;
+    }
+    // per-problem alive counts: one atomic per distinct problem among the wave's survivors
+    uint64_t m = mask;
+    while (m) {
+        const int l0 = __ffsll((unsigned long long)m) - 1;
+        const int p0 = __shfl(pid, l0);
+        const uint64_t same = __ballot(alive && pid == p0);
+        if (lane == l0) atomicAdd(&pcount[p0], (unsigned long long)__popcll(same));
+        m &= ~same;
+    }
+}
+
+// Births of histories [h0, h0 + count) of problem pid: source sampling, analog first leg in the
+// birth cell (global orientation), tally, move; survivors appended after the alive particles.
+__global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, uint32_t h0,
+                                                    int64_t count, BankDev out,
+                                                    unsigned long long *counter,
+                                                    unsigned long long *pcount)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool alive = false;
+    Next nx{};
+    double w_out = 0.0;
+    uint32_t h = 0;
+    if (t < count) {
+        const ProblemDev P = cd.prob[pid];
+        h = h0 + (uint32_t)t;
+        const U4 r = draw4(P.seed, (uint64_t)h, 0u, kTagSource);
+        const uint32_t nsrc = (uint32_t)(P.snx * P.sny);
+        const uint32_t pick = __umulhi(r.a, nsrc);
+        const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
+        const int cell = (int)(P.cell0 + (int64_t)cj * P.nx + ci);
+        const float ph = u01(r.d);
+        Walker W;
+        walker_init(W, (float)cd.tau[cell], (float)cd.c[cell], 0, u01_open(r.b), u01_open(r.c),
+                    cos_turns(ph), sin_turns(ph));
+        float pos = 0.0f;
+        int face;
+        do {
+            face = walker_flight(W, P.seed, (uint64_t)h, pos);
+        } while (face == kInside);
+        w_out = visit_tally(cd, P, cell, 1.0, W.len);
+        nx = move_on(cd, P, cell, face, pos, W.u, W.v, w_out);
+        alive = nx.alive;
+    }
+    append(alive, nx, pid, w_out, h, 1u, out, counter, pcount);
+}
+
+// Stage 1: canonical conditions of every alive particle.  Entry face e maps to the canonical
+// left face by the rotation of k = (e + 1) mod 4 quarter turns (canonical -> local).
+__global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n, CellsDev cd,
+                                                     float *ltau, float *cc, float *yin, float *sth,
+                                                     uint64_t *ids, uint64_t *keys)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int cell = b.cell[i];
+    const int k = (b.entry[i] + 1) & 3;
+    float U, V;
+    rot_quarter((4 - k) & 3, b.gx[i], b.gy[i], U, V);
+    ltau[i] = cd.ltau[cell];
+    cc[i] = cd.cf[cell];
+    yin[i] = b.yin[i];
+    sth[i] = fminf(fmaxf(V, -1.0f), 1.0f);
+    ids[i] = (uint64_t)b.hist[i] | ((uint64_t)b.event[i] << 32);
+    keys[i] = cd.prob[b.pid[i]].seed;
+}
+
+// Stages 3-4 for every alive particle, survivors compacted into `out`.
+__global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n, const int32_t *face_c,
+                                                    const float *pos, const float *dcos,
+                                                    const float *dsin, const float *path,
+                                                    CellsDev cd, BankDev out,
+                                                    unsigned long long *counter,
+                                                    unsigned long long *pcount)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool alive = false;
+    Next nx{};
+    double w_out = 0.0;
+    int32_t pid = 0;
+    uint32_t hist = 0, event = 0;
+    if (i < n) {
+        pid = in.pid[i];
+        const ProblemDev P = cd.prob[pid];
+        const int cell = in.cell[i];
+        const int k = (in.entry[i] + 1) & 3;
+        hist = in.hist[i];
+        event = in.event[i] + 1;
+        w_out = visit_tally(cd, P, cell, in.w[i], path[i]);
+        const int fc = face_c[i];
+        float gx, gy;
+        rot_quarter(k, dcos[i], dsin[i], gx, gy);
+        nx = move_on(cd, P, cell, fc >= 0 ? (fc + k) & 3 : fc, pos[i], gx, gy, w_out);
+        alive = nx.alive;
+    }
+    append(alive, nx, pid, w_out, hist, event, out, counter, pcount);
+}
+
+__global__ void set_u64_kernel(unsigned long long *p, unsigned long long v, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = (i == 0) ? v : 0ull;
+}
+
+__global__ void zero_f64_kernel(double *p, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+int blocks_for(int64_t n) { return (int)((n + 255) / 256); }
+
+}  // namespace
+}  // namespace gmc
+
+using namespace gmc;
+
+struct gmc_world {
+    int device = 0;
+    int64_t cap = 0;
+    int32_t max_problems = 0;
+    int64_t max_cells = 0;
+    void *mem = nullptr;
+    BankDev bank[2]{};
+    int cur = 0;
+    // sampler staging
+    float *c_ltau = nullptr, *c_c = nullptr, *c_yin = nullptr, *c_sth = nullptr;
+    uint64_t *ids = nullptr, *keys = nullptr;
+    int32_t *e_face = nullptr;
+    float *e_pos = nullptr, *e_dcos = nullptr, *e_dsin = nullptr, *e_path = nullptr;
+    // cells and tallies
+    double *tau = nullptr, *c = nullptr;
+    float *ltau = nullptr, *cf = nullptr;
+    double *flux = nullptr, *absorbed = nullptr, *leak = nullptr, *cutoff = nullptr;
+    ProblemDev *prob = nullptr;
+    unsigned long long *counters = nullptr;   // [2][1 + max_problems]: n_alive, per-problem
+    unsigned long long *host_counters = nullptr;
+    // host bookkeeping
+    int64_t n_alive = 0;
+    std::vector<int64_t> alive_pp;
+    std::vector<ProblemDev> prob_host;
+    std::vector<char> in_use;
+    std::vector<std::pair<int64_t, int64_t>> free_cells;   // [begin, end) ranges
+    std::mutex mu;
+
+    unsigned long long *cnt(int which) { return counters + (size_t)which * (1 + max_problems); }
+    CellsDev cells() const { return CellsDev{tau, c, ltau, cf, flux, absorbed, leak, cutoff, prob}; }
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Byte layout of one world allocation (also used to report the footprint).
+struct Layout {
+    size_t total = 0;
+    std::vector<std::pair<void **, size_t>> parts;
+    void add(void **p, size_t bytes) { parts.push_back({p, total}); total += align256(bytes); }
+};
+
+void plan(gmc_world *w, Layout &L)
+{
+    const size_t C = (size_t)w->cap, P = (size_t)w->max_problems, N = (size_t)w->max_cells;
+    for (int b = 0; b < 2; ++b) {
+        BankDev &k = w->bank[b];
+        L.add((void **)&k.cell, 4 * C);
+        L.add((void **)&k.pid, 4 * C);
+        L.add((void **)&k.entry, 4 * C);
+        L.add((void **)&k.yin, 4 * C);
+        L.add((void **)&k.gx, 4 * C);
+        L.add((void **)&k.gy, 4 * C);
+        L.add((void **)&k.w, 8 * C);
+        L.add((void **)&k.hist, 4 * C);
+        L.add((void **)&k.event, 4 * C);
+    }
+    L.add((void **)&w->c_ltau, 4 * C);
+    L.add((void **)&w->c_c, 4 * C);
+    L.add((void **)&w->c_yin, 4 * C);
+    L.add((void **)&w->c_sth, 4 * C);
+    L.add((void **)&w->ids, 8 * C);
+    L.add((void **)&w->keys, 8 * C);
+    L.add((void **)&w->e_face, 4 * C);
+    L.add((void **)&w->e_pos, 4 * C);
+    L.add((void **)&w->e_dcos, 4 * C);
+    L.add((void **)&w->e_dsin, 4 * C);
+    L.add((void **)&w->e_path, 4 * C);
+    L.add((void **)&w->tau, 8 * N);
+    L.add((void **)&w->c, 8 * N);
+    L.add((void **)&w->ltau, 4 * N);
+    L.add((void **)&w->cf, 4 * N);
+    L.add((void **)&w->flux, 8 * N);
+    L.add((void **)&w->absorbed, 8 * N);
+    L.add((void **)&w->leak, 8 * N);
+    L.add((void **)&w->cutoff, 8 * N);
+    L.add((void **)&w->prob, sizeof(ProblemDev) * P);
+    L.add((void **)&w->counters, 8 * 2 * (1 + P));
+}
+
+int sync_counters(gmc_world *w, int which, hipStream_t s)
+{
+    const size_t bytes = 8 * (size_t)(1 + w->max_problems);
+    hipError_t e = hipMemcpyAsync(w->host_counters, w->cnt(which), bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_hip_error(e, "transport: reading counters");
+    w->n_alive = (int64_t)w->host_counters[0];
+    for (int p = 0; p < w->max_problems; ++p) w->alive_pp[p] = (int64_t)w->host_counters[1 + p];
+    return GMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmc_world_footprint(int64_t bank_capacity, int32_t max_problems, int64_t max_cells, size_t *bytes)
+{
+    if (!bytes || bank_capacity <= 0 || max_problems <= 0 || max_cells <= 0)
+        return set_error(GMC_EINVAL, "gmc_world_footprint: bad argument");
+    gmc_world w;
+    w.cap = bank_capacity;
+    w.max_problems = max_problems;
+    w.max_cells = max_cells;
+    Layout L;
+    plan(&w, L);
+    *bytes = L.total;
+    return GMC_OK;
+}
+
+int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_cells, gmc_world **out)
+{
+    if (!out) return set_error(GMC_EINVAL, "gmc_world_create: null output");
+    *out = nullptr;
+    if (bank_capacity <= 0 || bank_capacity > ((int64_t)1 << 31) || max_problems <= 0 ||
+        max_problems > 65536 || max_cells <= 0 || max_cells > ((int64_t)1 << 31))
+        return set_error(GMC_EINVAL, "gmc_world_create: capacity out of range");
+    gmc_world *w = new gmc_world();
+    w->cap = bank_capacity;
+    w->max_problems = max_problems;
+    w->max_cells = max_cells;
+    Layout L;
+    plan(w, L);
+    hipError_t e = hipGetDevice(&w->device);
+    if (e != hipSuccess) { delete w; return set_hip_error(e, "gmc_world_create: hipGetDevice"); }
+    e = hipMalloc(&w->mem, L.total);
+    if (e != hipSuccess) { delete w; return set_error(GMC_ENOMEM, "gmc_world_create: device allocation failed"); }
+    for (auto &pr : L.parts) *pr.first = (char *)w->mem + pr.second;
+    e = hipHostMalloc((void **)&w->host_counters, 8 * (size_t)(1 + max_problems), hipHostMallocDefault);
+    if (e != hipSuccess) {
+        (void)hipFree(w->mem);
+        delete w;
+        return set_error(GMC_ENOMEM, "gmc_world_create: pinned host allocation failed");
+    }
+    e = hipMemset(w->counters, 0, 8 * 2 * (size_t)(1 + max_problems));
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipHostFree(w->host_counters);
+        (void)hipFree(w->mem);
+        delete w;
+        return set_hip_error(e, "gmc_world_create: clearing counters");
+    }
+    w->alive_pp.assign(max_problems, 0);
+    w->prob_host.assign(max_problems, ProblemDev{});
+    w->in_use.assign(max_problems, 0);
+    w->free_cells.push_back({0, max_cells});
+    *out = w;
+    return GMC_OK;
+}
+
+int gmc_world_destroy(gmc_world *w)
+{
+    if (!w) return set_error(GMC_EINVAL, "gmc_world_destroy: null world");
+    hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    if (w->host_counters) e1 = hipHostFree(w->host_counters);
+    if (w->mem) e2 = hipFree(w->mem);
+    delete w;
+    if (e1 != hipSuccess) return set_hip_error(e1, "gmc_world_destroy");
+    if (e2 != hipSuccess) return set_hip_error(e2, "gmc_world_destroy");
+    return GMC_OK;
+}
+
+int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, void *stream)
+{
+    if (!w || !d || !pid_out) return set_error(GMC_EINVAL, "gmc_problem_add: null pointer");
+    if (d->nx <= 0 || d->ny <= 0 || !(d->L > 0.0) || !d->tau || !d->c)
+        return set_error(GMC_EINVAL, "gmc_problem_add: bad grid or materials");
+    if (d->src_nx <= 0 || d->src_ny <= 0 || d->src_x0 < 0 || d->src_y0 < 0 ||
+        d->src_x0 + d->src_nx > d->nx || d->src_y0 + d->src_ny > d->ny)
+        return set_error(GMC_EINVAL, "gmc_problem_add: source block outside the grid");
+    const int64_t n = (int64_t)d->nx * d->ny;
+    for (int64_t i = 0; i < n; ++i)
+        if (!(d->tau[i] >= 0.0) || !std::isfinite(d->tau[i]) || !(d->c[i] >= 0.0) || !(d->c[i] <= 1.0))
+            return set_error(GMC_EINVAL, "gmc_problem_add: tau must be finite >= 0 and c in [0, 1]");
+    std::lock_guard<std::mutex> lk(w->mu);
+    int pid = -1;
+    for (int p = 0; p < w->max_problems; ++p)
+        if (!w->in_use[p]) { pid = p; break; }
+    if (pid < 0) return set_error(GMC_ENOMEM, "gmc_problem_add: no free problem slot");
+    int64_t cell0 = -1;
+    for (auto &r : w->free_cells)
+        if (r.second - r.first >= n) {
+            cell0 = r.first;
+            r.first += n;
+            break;
+        }
+    if (cell0 < 0) return set_error(GMC_ENOMEM, "gmc_problem_add: no room for the cells");
+    w->free_cells.erase(std::remove_if(w->free_cells.begin(), w->free_cells.end(),
+                                       [](const std::pair<int64_t, int64_t> &r) { return r.first >= r.second; }),
+                        w->free_cells.end());
+    std::vector<float> lt(n), cf(n);
+    for (int64_t i = 0; i < n; ++i) {
+        lt[i] = d->tau[i] > 0.0 ? (float)std::log(d->tau[i]) : -1.0e4f;
+        cf[i] = (float)d->c[i];
+    }
+    ProblemDev P{d->nx, d->ny, d->L, cell0, d->src_x0, d->src_y0, d->src_nx, d->src_ny,
+                 d->reflect ? 1 : 0, d->w_min, d->seed};
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync(w->tau + cell0, d->tau, 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w->c + cell0, d->c, 8 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w->ltau + cell0, lt.data(), 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w->cf + cell0, cf.data(), 4 * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(w->prob + pid, &P, sizeof P, hipMemcpyHostToDevice, s);
+    double *tallies[4] = {w->flux, w->absorbed, w->leak, w->cutoff};
+    for (double *t : tallies) {
+        if (e != hipSuccess) break;
+        hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks_for(n)), dim3(256), 0, s, t + cell0, n);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);      // the host staging vectors go away
+    if (e != hipSuccess) {
+        w->free_cells.push_back({cell0, cell0 + n});
+        return set_hip_error(e, "gmc_problem_add: upload");
+    }
+    w->in_use[pid] = 1;
+    w->prob_host[pid] = P;
+    w->alive_pp[pid] = 0;
+    *pid_out = pid;
+    return GMC_OK;
+}
+
+int gmc_problem_remove(gmc_world *w, int32_t pid)
+{
+    if (!w || pid < 0 || pid >= (w ? w->max_problems : 0) || !w->in_use[pid])
+        return set_error(GMC_EINVAL, "gmc_problem_remove: no such problem");
+    std::lock_guard<std::mutex> lk(w->mu);
+    if (w->alive_pp[pid] != 0)
+        return set_error(GMC_EINVAL, "gmc_problem_remove: the problem still has particles in flight");
+    const ProblemDev &P = w->prob_host[pid];
+    w->free_cells.push_back({P.cell0, P.cell0 + (int64_t)P.nx * P.ny});
+    std::sort(w->free_cells.begin(), w->free_cells.end());
+    std::vector<std::pair<int64_t, int64_t>> merged;
+    for (auto &r : w->free_cells) {
+        if (!merged.empty() && merged.back().second >= r.first) merged.back().second = std::max(merged.back().second, r.second);
+        else merged.push_back(r);
+    }
+    w->free_cells.swap(merged);
+    w->in_use[pid] = 0;
+    return GMC_OK;
+}
+
+int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count, void *stream,
+                     int64_t *n_alive_out)
+{
+    if (!w || pid < 0 || pid >= w->max_problems || !w->in_use[pid])
+        return set_error(GMC_EINVAL, "gmc_world_inject: no such problem");
+    if (count < 0 || h_begin + (uint64_t)count > ((uint64_t)1 << 32))
+        return set_error(GMC_EINVAL, "gmc_world_inject: history ids must stay below 2^32");
+    if (count > w->cap - w->n_alive)
+        return set_error(GMC_ENOMEM, "gmc_world_inject: not enough free bank slots");
+    hipStream_t s = (hipStream_t)stream;
+    if (count > 0) {
+        const int which = w->cur;
+        unsigned long long *ctr = w->cnt(which);
+        // the bank's particle counter restarts at the number alive; per-problem counts continue
+        hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(1), 0, s, ctr, (unsigned long long)w->n_alive, 1);
+        hipLaunchKernelGGL(birth_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
+                           (uint32_t)h_begin, count, w->bank[which], ctr, ctr + 1);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "gmc_world_inject: launch");
+        const int rc = sync_counters(w, which, s);
+        if (rc != GMC_OK) return rc;
+    }
+    if (n_alive_out) *n_alive_out = w->n_alive;
+    return GMC_OK;
+}
+
+int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
+                       int64_t *n_alive_out)
+{
+    if (!w) return set_error(GMC_EINVAL, "gmc_transport_step: null world");
+    if (sampler != GMC_SAMPLER_GMC && sampler != GMC_SAMPLER_MC)
+        return set_error(GMC_EINVAL, "gmc_transport_step: sampler must be GMC or MC");
+    if (sampler == GMC_SAMPLER_GMC && (!m || K < 1 || K > 1024))
+        return set_error(GMC_EINVAL, "gmc_transport_step: GMC needs a model and K in 1..1024");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n = w->n_alive;
+    if (n > 0) {
+        const int cur = w->cur, nxt = 1 - cur;
+        hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n)), dim3(256), 0, s, w->bank[cur], n,
+                           w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->ids, w->keys);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: gather");
+        const int cu = device_cu_count();
+        if (cu <= 0) return set_error(GMC_EDEVICE, "gmc_transport_step: cannot query the device");
+        if (sampler == GMC_SAMPLER_GMC) {
+            MlpParams p = m->tmpl;
+            p.log_tau = w->c_ltau;
+            p.c = w->c_c;
+            p.y_in = w->c_yin;
+            p.sin_th = w->c_sth;
+            p.noise = nullptr;
+            p.raw = nullptr;
+            p.ids = w->ids;
+            p.keys = w->keys;
+            p.face = w->e_face;
+            p.pos = w->e_pos;
+            p.dcos = w->e_dcos;
+            p.dsin = w->e_dsin;
+            p.path = w->e_path;
+            p.n = n;
+            p.K = K;
+            p.seed = 0;
+            p.id_base = 0;
+            const int64_t ntiles = (n + kTileM - 1) / kTileM;
+            e = launch_mlp_ode(m->precision, m->hidden, p, (int)std::min<int64_t>(ntiles, cu), s);
+        } else {
+            WalkParams p{};
+            p.log_tau = w->c_ltau;
+            p.c = w->c_c;
+            p.y_in = w->c_yin;
+            p.sin_th = w->c_sth;
+            p.face = w->e_face;
+            p.pos = w->e_pos;
+            p.dcos = w->e_dcos;
+            p.dsin = w->e_dsin;
+            p.path = w->e_path;
+            p.ncoll = nullptr;
+            p.ids = w->ids;
+            p.keys = w->keys;
+            p.n = n;
+            p.mode = GMC_MODE_CONTINUOUS;
+            p.queue = device_queue_counter();
+            if (!p.queue) return set_error(GMC_ENOMEM, "gmc_transport_step: work counter");
+            e = launch_walk(p, (int)std::min<int64_t>((n + 255) / 256, (int64_t)cu * 8), s);
+        }
+        if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: sampler");
+        unsigned long long *ctr = w->cnt(nxt);
+        hipLaunchKernelGGL(set_u64_kernel, dim3(blocks_for(1 + w->max_problems)), dim3(256), 0, s,
+                           ctr, 0ull, 1 + w->max_problems);
+        hipLaunchKernelGGL(apply_kernel, dim3(blocks_for(n)), dim3(256), 0, s, w->bank[cur], n,
+                           w->e_face, w->e_pos, w->e_dcos, w->e_dsin, w->e_path, w->cells(),
+                           w->bank[nxt], ctr, ctr + 1);
+        e = hipGetLastError();
+        if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: apply");
+        w->cur = nxt;
+        const int rc = sync_counters(w, nxt, s);
+        if (rc != GMC_OK) return rc;
+    }
+    if (n_alive_out) *n_alive_out = w->n_alive;
+    return GMC_OK;
+}
+
+int gmc_problem_alive(const gmc_world *w, int32_t pid, int64_t *n_alive)
+{
+    if (!w || !n_alive || pid < 0 || pid >= w->max_problems || !w->in_use[pid])
+        return set_error(GMC_EINVAL, "gmc_problem_alive: no such problem");
+    *n_alive = w->alive_pp[pid];
+    return GMC_OK;
+}
+
+int gmc_problem_tally(gmc_world *w, int32_t pid, double *flux, double *absorbed, double *leak,
+                      double *cutoff, void *stream)
+{
+    if (!w || pid < 0 || pid >= w->max_problems || !w->in_use[pid])
+        return set_error(GMC_EINVAL, "gmc_problem_tally: no such problem");
+    const ProblemDev &P = w->prob_host[pid];
+    const int64_t n = (int64_t)P.nx * P.ny;
+    hipStream_t s = (hipStream_t)stream;
+    double *dst[4] = {flux, absorbed, leak, cutoff};
+    const double *src[4] = {w->flux, w->absorbed, w->leak, w->cutoff};
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < 4 && e == hipSuccess; ++t)
+        if (dst[t]) e = hipMemcpyAsync(dst[t], src[t] + P.cell0, 8 * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_hip_error(e, "gmc_problem_tally: copy");
+    return GMC_OK;
+}
+
+}  // extern "C"

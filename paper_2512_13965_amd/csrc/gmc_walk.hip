@@ -21,15 +21,12 @@ __device__ __forceinline__ int lane_rank(uint64_t mask)
 __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
 {
     const int lane = threadIdx.x & 63;
-    const float kInf = __builtin_inff();
-
     bool alive = false;
     bool exhausted = false;     // wave-uniform: the work counter has passed n
     int64_t idx = 0;
-    float x = 0.f, y = 0.f, u = 1.f, v = 0.f, len = 0.f, inv_sig = 0.f, cs = 0.f;
-    bool scatter = false;
-    uint32_t flight = 0, ncoll = 0;
-    const bool analog = (p.mode == 1);
+    uint64_t key = p.seed, stream = 0;
+    Walker w;
+    walker_init(w, 0.0f, 0.0f, 0, 0.0f, 0.0f, 1.0f, 0.0f);
 
     for (;;) {
         const bool need = !alive && !exhausted;
@@ -44,19 +41,11 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
                 const int64_t i = (int64_t)(base + (unsigned long long)lane_rank(needmask));
                 if (i < p.n) {
                     idx = i;
-                    const float tau = expf(p.log_tau[i]);
-                    cs = p.c[i];
-                    const float sig = analog ? tau : cs * tau;
-                    scatter = sig > 1e-30f;      // below this 1/sig would overflow
-                    inv_sig = scatter ? 1.0f / sig : 0.0f;
                     const float s = p.sin_th[i];
-                    x = 0.0f;
-                    y = p.y_in[i];
-                    u = sqrtf(fmaxf(1.0f - s * s, 0.0f));
-                    v = s;
-                    len = 0.0f;
-                    flight = 0;
-                    ncoll = 0;
+                    walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, 0.0f, p.y_in[i],
+                                sqrtf(fmaxf(1.0f - s * s, 0.0f)), s);
+                    stream = p.ids ? p.ids[i] : p.id_base + (uint64_t)i;
+                    key = p.keys ? p.keys[i] : p.seed;
                     alive = true;
                 }
             }
@@ -68,51 +57,15 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
         }
         if (!alive) continue;
 
-        // one flight (eq. 4): distance to the cell boundary, sampled flight, scatter or leave
-        float tx = kInf, ty = kInf;
-        if (u > 0.0f) tx = (1.0f - x) * fast_rcp(u);
-        else if (u < 0.0f) tx = -x * fast_rcp(u);
-        if (v > 0.0f) ty = (1.0f - y) * fast_rcp(v);
-        else if (v < 0.0f) ty = -y * fast_rcp(v);
-        const bool xface = tx <= ty;
-        const float db = fmaxf(xface ? tx : ty, 0.0f);
-        const U4 r = draw4(p.seed, p.id_base + (uint64_t)idx, flight, kTagWalk);
-        const float ds = scatter ? neg_log(u01(r.a)) * inv_sig : kInf;
-        int face = -3;   // still inside
         float pos = 0.0f;
-        if (ds >= db) {
-            len += db;
-            if (xface) {
-                const float ye = fminf(fmaxf(y + db * v, 0.0f), 1.0f);
-                face = u > 0.0f ? 1 : 3;
-                pos = u > 0.0f ? ye : 1.0f - ye;
-            } else {
-                const float xe = fminf(fmaxf(x + db * u, 0.0f), 1.0f);
-                face = v > 0.0f ? 2 : 0;
-                pos = v > 0.0f ? 1.0f - xe : xe;
-            }
-        } else {
-            x += ds * u;
-            y += ds * v;
-            len += ds;
-            ncoll += 1;
-            if (analog && u01(r.c) > cs) {
-                face = -1;   // absorbed at this collision
-            } else {
-                const float ph = u01(r.b);
-                u = cos_turns(ph);
-                v = sin_turns(ph);
-            }
-        }
-        flight += 1;
-        if (face == -3 && flight >= kMaxFlights) face = -2;
-        if (face != -3) {
+        const int face = walker_flight(w, key, stream, pos);
+        if (face != kInside) {
             p.face[idx] = face;
             p.pos[idx] = pos;
-            p.dcos[idx] = u;
-            p.dsin[idx] = v;
-            p.path[idx] = len;
-            if (p.ncoll) p.ncoll[idx] = ncoll;
+            p.dcos[idx] = w.u;
+            p.dsin[idx] = w.v;
+            p.path[idx] = w.len;
+            if (p.ncoll) p.ncoll[idx] = w.ncoll;
             alive = false;
         }
     }

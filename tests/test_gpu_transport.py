@@ -1,0 +1,153 @@
+"""GPU transport (paper section "Transport Algorithm"; track-length tallies of eqs. 5-7)
+against the FP64 oracle transport, the conservation laws and the statistical behaviour of
+eq. 12.
+
+With the analog sampler both sides draw the same Philox words for every history, so a history
+takes the same path on both sides unless an FP32 near-tie sends the GPU walk the other way (see
+test_gpu_walk.py); flux maps then agree far inside their statistical error.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_13965_amd import inputs
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(binding, prob, n, seed, sampler, model=None, K=16, capacity=1 << 18):
+    from paper_2512_13965_amd import transport
+    w = binding.World(capacity, 2, max(prob.n_cells, 1 << 12))
+    out = transport.run_problem(w, prob, n, seed, sampler, model, K)
+    w.close()
+    return out
+
+
+@pytest.mark.parametrize("name,prob", [
+    ("checkerboard8", inputs.checkerboard_problem(8, src=2)),
+    ("hetero3", inputs.Problem(3, 3, 0.7, np.array([0.3, 2.0, 0.7, 1.5, 0.5, 3.0, 0.9, 0.2, 1.1]),
+                               np.array([0.9, 0.5, 0.99, 0.7, 0.8, 0.95, 0.3, 1.0, 0.6]), 1, 1, 1, 1)),
+])
+def test_mc_transport_matches_oracle(orc, name, prob):
+    binding = require_gpu()
+    n = 20_000
+    g = _gpu(binding, prob, n, seed=11, sampler=binding.SAMPLER_MC)
+    o = orc.transport(prob, seed=11, h_begin=0, h_end=n, nthreads=8)
+    rel = np.abs(g["flux"] - o["flux"]).sum() / np.abs(o["flux"]).sum()
+    print(f"{name}: flux L1 rel diff {rel:.2e}; leak {g['leak'].sum():.6f} vs {o['leak']:.6f}; "
+          f"absorbed {g['absorbed'].sum():.6f} vs {o['absorbed'].sum():.6f}")
+    assert rel < 5e-5          # measured <= 3e-6
+    assert abs(g["leak"].sum() - o["leak"]) <= 1e-3 * n
+    assert abs(g["absorbed"].sum() - o["absorbed"].sum()) <= 1e-3 * n
+
+
+@pytest.mark.parametrize("sampler", ["mc", "gmc"])
+def test_weight_balance(sampler):
+    # every unit of source weight leaks, is absorbed or is cut off -- for any sampler, since
+    # the tally is the weight lost along the sampled path
+    binding = require_gpu()
+    prob = inputs.checkerboard_problem(16, src=2)
+    n = 50_000
+    model = None
+    if sampler == "gmc":
+        model = binding.Model(inputs.pack_blob(inputs.random_weights(256, 1)), "bf16")
+    g = _gpu(binding, prob, n, 3, binding.SAMPLER_MC if sampler == "mc" else binding.SAMPLER_GMC, model)
+    total = g["leak"].sum() + g["absorbed"].sum() + g["cutoff"].sum()
+    assert abs(total - n) < 1e-9 * n
+    assert np.all(g["flux"] >= 0) and g["transmissions"] >= n
+
+
+def test_reflecting_box_flux_equals_source_over_sigma_a():
+    # P7: reflecting homogeneous box with a uniform source: E[phi_i] = N / (sigma_a V n_cells)
+    binding = require_gpu()
+    tau, c, L = 2.0, 0.8, 0.5
+    prob = inputs.homogeneous_problem(6, tau, c, reflect=True, L=L)
+    n = 200_000
+    g = _gpu(binding, prob, n, 5, binding.SAMPLER_MC)
+    sig_a, V = (1 - c) * tau / L, L * L
+    assert g["leak"].sum() == 0.0
+    assert abs(g["absorbed"].sum() + g["cutoff"].sum() - n) < 1e-9 * n
+    np.testing.assert_allclose((g["flux"] * sig_a * V).sum(), g["absorbed"].sum(), rtol=1e-12)
+    phi = n / (sig_a * V * prob.n_cells)
+    assert abs(g["flux"].mean() - phi) / phi < 2e-3
+    assert np.abs(g["flux"] / phi - 1).max() < 0.05
+
+
+@pytest.mark.parametrize("sampler", ["mc", "gmc"])
+def test_alone_and_in_mix_agree(sampler):
+    # a problem's tallies do not depend on the other problems sharing the bank
+    binding = require_gpu()
+    from paper_2512_13965_amd import transport
+    a = inputs.checkerboard_problem(8, src=2)
+    b, _ = inputs.random_problem(7, side_range=(16, 24))
+    model = None
+    if sampler == "gmc":
+        model = binding.Model(inputs.pack_blob(inputs.random_weights(256, 2)), "fp32")
+    smp = binding.SAMPLER_MC if sampler == "mc" else binding.SAMPLER_GMC
+    na, nb = 20_000, 30_000
+    w = binding.World(1 << 17, 4, 1 << 12)
+    alone = transport.run_problem(w, a, na, 21, smp, model)
+    # the mix: b first (other slot and cells), then a, injected and stepped together
+    pb = w.add_problem(b, 99)
+    pa = w.add_problem(a, 21)
+    w.inject(pb, 0, nb)
+    w.inject(pa, 0, na)
+    alive = 1
+    while alive:
+        alive = w.step(smp, model)
+    mix = w.tally(pa)
+    w.close()
+    for k in ("flux", "absorbed", "leak", "cutoff"):
+        np.testing.assert_allclose(mix[k], alone[k], rtol=1e-12, atol=1e-12 * na)
+
+
+def test_cfg3_checkerboard_gpu_vs_oracle(orc):
+    # 32 x 32 unit cells, checkerboard (0.5, 0.5) / (50, 0.99), central 4 x 4 source, vacuum
+    binding = require_gpu()
+    prob = inputs.checkerboard_problem(32)
+    n = 100_000
+    g = _gpu(binding, prob, n, 1, binding.SAMPLER_MC, capacity=1 << 20)
+    o = orc.transport(prob, seed=1, h_begin=0, h_end=n, nthreads=8)
+    rel = np.abs(g["flux"] - o["flux"]).sum() / np.abs(o["flux"]).sum()
+    print(f"cfg3: flux L1 rel diff {rel:.2e}, transmissions {g['transmissions']}, steps {g['steps']}")
+    assert rel < 5e-5          # measured <= 3e-6
+    assert abs(g["absorbed"].sum() + g["leak"].sum() + g["cutoff"].sum() - n) < 1e-9 * n
+
+
+def test_eq12_error_decays_as_inverse_sqrt_n():
+    # eq. 12: cell-averaged standard deviation over K = 5 independent runs, log-log slope -1/2
+    binding = require_gpu()
+    prob = inputs.checkerboard_problem(16, src=2)
+    Ns = [10_000, 40_000, 160_000]
+    sig = []
+    for N in Ns:
+        runs = np.array([_gpu(binding, prob, N, 1000 + 17 * k, binding.SAMPLER_MC)["flux"] / N
+                         for k in range(5)])
+        sig.append(np.mean(runs.std(0, ddof=1)))
+    slope = np.polyfit(np.log(Ns), np.log(sig), 1)[0]
+    print("eq12 sigma", sig, "slope", slope)
+    assert abs(slope + 0.5) < 0.1
+
+
+def test_world_errors():
+    binding = require_gpu()
+    w = binding.World(1000, 1, 100)
+    with pytest.raises(binding.GmcError):
+        w.add_problem(inputs.checkerboard_problem(16), 1)          # 256 cells > 100
+    pid = w.add_problem(inputs.checkerboard_problem(8, src=2), 1)
+    with pytest.raises(binding.GmcError):
+        w.add_problem(inputs.checkerboard_problem(4, src=2), 2)     # no free slot
+    with pytest.raises(binding.GmcError):
+        w.inject(pid, 0, 2000)                                       # more than the bank holds
+    n = w.inject(pid, 0, 500)
+    assert 0 <= n <= 500
+    if n:
+        with pytest.raises(binding.GmcError):
+            w.remove(pid)                                            # still in flight
+    while n:
+        n = w.step(binding.SAMPLER_MC)
+    w.remove(pid)
+    w.close()
