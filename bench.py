@@ -92,6 +92,67 @@ def cpu_baseline_analog(tau=100.0, budget_s=8.0):
             "sample": f"{n} analog transmissions at tau={tau:g}, c=1, {dt:.1f} s"}
 
 
+def bench_transport(binding, inputs, w512):
+    """Full 2-D transport: 32 x 32 unit cells, checkerboard (tau, c) = (0.5, 0.5) / (50, 0.99),
+    isotropic unit source in the central 4 x 4 cells, vacuum boundaries, 10^6 histories, FP64
+    tallies; analog sampler and generative sampler (BF16, H = 512, K = 16)."""
+    import torch
+    from paper_2512_13965_amd import transport
+    prob = inputs.checkerboard_problem(32)
+    n = 1_000_000
+    out = {"workload": "32x32 checkerboard (0.5,0.5)/(50,0.99), central 4x4 source, vacuum, 1e6 histories"}
+    world = binding.World(1 << 20, 2, 1 << 12)
+    model = binding.Model(inputs.pack_blob(w512), "bf16")
+    for name, smp, m in (("analog", binding.SAMPLER_MC, None), ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, model)):
+        transport.run_problem(world, prob, 20_000, 7, smp, m, 16)          # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = transport.run_problem(world, prob, n, 1, smp, m, 16)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bal = r["absorbed"].sum() + r["leak"].sum() + r["cutoff"].sum()
+        out[name] = {"seconds": dt, "histories_per_s": n / dt, "transmissions": int(r["transmissions"]),
+                     "transmissions_per_s": r["transmissions"] / dt, "steps": r["steps"],
+                     "balance_error": abs(bal - n) / n}
+    model.close()
+    world.close()
+    out["note"] = ("the generative run uses seeded random-init weights: it measures the throughput "
+                   "of the path, not a physical flux")
+    return out
+
+
+def bench_serving(binding, inputs, w512, n_req):
+    """Continuous batching of a Poisson stream of transport requests of the config-3 kind
+    (grids 16^2..128^2, per-cell tau log-uniform in [0.1, 200], c ~ U[0, 1]); histories per
+    request log-uniform in [1e4, 10^5.5] (scaled down from 1e4..1e7 so the stream completes in
+    tens of seconds); generative sampler BF16, H = 512, K = 16."""
+    from paper_2512_13965_amd import serving
+    model = binding.Model(inputs.pack_blob(w512), "bf16")
+    world = binding.World(1 << 20, 16, 1 << 18)
+    make = lambda i: inputs.random_problem(1000 + i, hist_log10_range=(4.0, 5.5))
+
+    def serve(reqs):
+        return serving.Server(world, binding.SAMPLER_GMC, model, K=16,
+                              cell_budget=(1 << 18) * serving.CELL_BYTES).run(reqs)
+
+    # capacity: a burst of 48 requests all arriving at t = 0
+    burst = serving.poisson_requests(48, rate_hz=1e9, seed=12, make_problem=make)
+    cap = serve(burst)
+    capacity_hz = len(cap.requests) / cap.wall
+    rate = 0.7 * capacity_hz
+    st = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make))
+    model.close()
+    world.close()
+    lat = st.latency_percentiles((50, 90, 99))
+    return {"requests": len(st.requests), "capacity_req_per_s": capacity_hz,
+            "arrival_rate_hz": rate, "wall_s": st.wall, "steps": st.steps,
+            "transmissions": st.transmissions, "transmissions_per_s": st.throughput,
+            "latency_s": lat, "histories": int(sum(r.n_hist for r in st.requests)),
+            "workload": "Poisson stream at 70% of the measured capacity; grids 16^2-128^2, "
+                        "tau log-U[0.1,200], c U[0,1], 1e4-10^5.5 histories/request, "
+                        "GMC BF16 H=512 K=16 random-init weights"}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +160,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="only the timed steps (for profiling)")
+    ap.add_argument("--no-transport", action="store_true", help="skip transport and serving runs")
+    ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving stream")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -204,6 +267,10 @@ def main():
     res["wide_sampler"] = wide
     for s in sweep:
         s["gmc_bf16_h512_k16_tps"] = next(x["tps"] for x in wide if x["precision"] == "bf16" and x["K"] == 16)
+
+    if not args.no_transport:
+        res["transport"] = bench_transport(binding, inputs, w5)
+        res["serving"] = bench_serving(binding, inputs, w5, args.serve_requests)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, K)
