@@ -162,9 +162,34 @@ def main():
     ap.add_argument("--quick", action="store_true", help="only the timed steps (for profiling)")
     ap.add_argument("--no-transport", action="store_true", help="skip transport and serving runs")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving stream")
+    ap.add_argument("--profile", default=None,
+                    help="only launch one kernel --steps times: fp32 | bf16 | fp8 (sampler, "
+                         "H=256 / 512 / 512) or walk:TAU (analog, 2^20 transmissions)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.profile:
+        # a few launches of one kernel configuration, for counter collection
+        import torch
+        from paper_2512_13965_amd import binding, inputs
+        kind, prec, H, K, N = args.profile.split(":")[0], None, 512, 16, 1 << 20
+        if kind in ("fp32", "bf16", "fp8"):
+            prec, H = kind, (256 if kind == "fp32" else 512)
+            N = 65536 if kind == "fp32" else N
+            m = binding.Model(inputs.pack_blob(inputs.random_weights(H, 1)), prec)
+            c = binding.DeviceCond.from_host(inputs.transmission_conditions(N, 3))
+            o = binding.DeviceExit.empty(N)
+            for _ in range(args.steps):
+                binding.gmc_transmit(m, c, K, 2, 0, out=o)
+        else:
+            tau = float(args.profile.split(":")[1]) if ":" in args.profile else 100.0
+            c = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(N, tau, 1.0, 9))
+            o = binding.DeviceExit.empty(N)
+            for _ in range(args.steps):
+                binding.mc_transmit(c, binding.MODE_CONTINUOUS, 2, 0, out=o)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile": args.profile, "launches": args.steps, "batch": N}))
+        return
     if args.copy_ref:
         import torch
         src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")

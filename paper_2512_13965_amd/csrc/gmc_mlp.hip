@@ -19,6 +19,18 @@
 #include "gmc_device.hpp"
 #include "gmc_internal.hpp"
 
+// MFMA / epilogue interleave: vector instructions placed after each MFMA in the overlapped
+// k-loops (0 = leave the order to the scheduler).
+#ifndef GMC_VPM_A
+#define GMC_VPM_A 0
+#endif
+#ifndef GMC_VPM_P
+#define GMC_VPM_P 0
+#endif
+#ifndef GMC_VPM_5
+#define GMC_VPM_5 0
+#endif
+
 namespace gmc {
 namespace {
 
@@ -308,6 +320,93 @@ __device__ __forceinline__ void dense_silu(Rsrc wA, Rsrc bias, int T0, const cha
     });
 }
 
+// k-block visiting orders.  The activation tile's k-blocks split into two halves: those holding
+// the outputs of the producing layer's first row pass ("half 0") and those of its second
+// ("half 1"); G consecutive k-blocks belong to one pass of one wave.
+struct MapAll {
+    static constexpr int kb(int j) { return j; }
+};
+template <int G>
+struct MapHalf0 {
+    static constexpr int kb(int j) { return (j / G) * 2 * G + j % G; }
+};
+template <int G>
+struct MapHalf1 {
+    static constexpr int kb(int j) { return (j / G) * 2 * G + G + j % G; }
+};
+
+// acc[r][c] += W[T0 + r] x act[column tile col0 + c] over the NJ k-blocks Map::kb(0..NJ-1) of
+// a layer with NKB k-blocks (same fragment layout and prefetch scheme as mma_pass).
+template <int P, int RP, int CT, int NKB, int NJ, typename Map, int VPM = 0, typename Hook>
+__device__ __forceinline__ void mma_seq(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, const char *act,
+                                        int stride, int col0, int lane, Hook &&hook)
+{
+    constexpr int MFMA_PER_RUN = (P == kF32) ? 4 : 1;
+    using M = Mma<P>;
+    using Frag = typename M::Frag;
+    constexpr int FB = frag_bytes(P);
+    constexpr int KBB = kb_width(P) * elem_bytes(P);
+    const int h = lane >> 5, n = lane & 31;
+    const int t0 = __builtin_amdgcn_readfirstlane(T0);
+    const int voff = lane * FB;
+    const char *sb = act + (col0 * 32 + n) * stride + h * (KBB / 2);
+    Frag a[3][RP], b[2][CT];
+    auto loadA = [&](int slot, int kb) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) a[slot][r] = M::load_g(wA, voff, ((t0 + r) * NKB + kb) * 64 * FB);
+    };
+    auto loadB = [&](int slot, int kb) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[slot][c] = M::load_s(sb + c * 32 * stride + kb * KBB);
+    };
+    loadA(0, Map::kb(0));
+    if constexpr (NJ > 1) loadA(1, Map::kb(1));
+    loadB(0, Map::kb(0));
+    sfor<NJ>([&](auto JJ) {
+        constexpr int j = decltype(JJ)::value;
+        if constexpr (j + 2 < NJ) loadA((j + 2) % 3, Map::kb(j + 2));
+        if constexpr (j + 1 < NJ) loadB((j + 1) % 2, Map::kb(j + 1));
+#pragma unroll
+        for (int r = 0; r < RP; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[j % 3][r], b[j % 2][c]);
+        hook(JJ);
+        if constexpr (VPM > 0) {
+            // interleave the hook's epilogue arithmetic between the MFMAs: one MFMA, then up
+            // to VPM vector instructions, so transcendental latencies hide behind matrix work
+            sfor<RP * CT * MFMA_PER_RUN>([&](auto) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, VPM, 0);
+            });
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
+}
+
+// Part J of NJ of draining accumulator tiles src[RP][4] through the epilogue into packed words.
+template <int PO, bool SCALE, int RP, int NJ, int J>
+__device__ __forceinline__ void drain_step(const f32x16 (&src)[RP][4], uint32_t *pk, float osc, float inv)
+{
+    constexpr int UNITS = RP * 16;
+    constexpr int UPK = (UNITS + NJ - 1) / NJ;
+    constexpr int WPU = words_per_unit(PO);
+    sfor<UPK>([&](auto U) {
+        constexpr int u = J * UPK + decltype(U)::value;
+        if constexpr (u < UNITS) epi_unit<PO, SCALE>(src[u / 16][(u / 4) % 4], u % 4, osc, inv, &pk[u * WPU]);
+    });
+}
+
+// Store the packed outputs of one row pass (row tiles Tb .. Tb + RP - 1, all column tiles).
+template <int PO, int RP>
+__device__ __forceinline__ void store_pass(const uint32_t *pk, int Tb, char *act, int stride, int lane)
+{
+    constexpr int WPU = words_per_unit(PO);
+    sfor<RP * 4>([&](auto TC) {
+        constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
+        store_tile<PO>(&pk[(r * 4 + c) * 4 * WPU], Tb + r, c, act, stride, lane);
+    });
+}
+
 template <int MP, int H>
 struct Cfg {
     static constexpr int P1 = layer_prec(MP, 0);            // layer 1 operand precision
@@ -321,6 +420,13 @@ struct Cfg {
     static constexpr int NKB1 = 16 / kb_width(P1);
     static constexpr int NKBH = H / kb_width(PH);
     static constexpr int NKB5 = H / kb_width(P5);
+    static constexpr int RP = RTW >= 4 ? RTW / 2 : 1;       // row tiles per pass
+    static constexpr int NP = RTW / RP;                     // row passes per layer
+    // cross-layer pipelining needs each pass's output to fill whole k-blocks of the consumer
+    static constexpr bool PIPE = NP == 2 && RP * 32 >= kb_width(PH) && RP * 32 >= kb_width(P5);
+    static constexpr int GH = PIPE ? RP * 32 / kb_width(PH) : 1;
+    static constexpr int G5 = PIPE ? RP * 32 / kb_width(P5) : 1;
+    static constexpr int WPK = words_per_unit(PH) > words_per_unit(P5) ? words_per_unit(PH) : words_per_unit(P5);
     static constexpr int LDS_ACT = kTileM * ACT_STRIDE;
     static constexpr int LDS_IN = kTileM * IN_STRIDE;
     static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 4) * kTileM * 4;
@@ -396,6 +502,73 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
                 }
             }
             __syncthreads();
+
+            if constexpr (C::PIPE) {
+                // Cross-layer pipeline.  X holds a layer's first row pass, Y its second.  Each
+                // layer's second-pass epilogue runs inside the next layer's MFMA loop over the
+                // k-blocks holding first-pass outputs (already in LDS); its results are stored
+                // and the remaining k-blocks follow after a barrier.
+                constexpr int RP = C::RP;
+                f32x16 X[RP][4], Y[RP][4];
+                uint32_t pk[RP * 16 * C::WPK];
+                const Rsrc w0 = make_rsrc(p.wA[0], p.wA_bytes[0]), b0 = make_rsrc(p.bias[0], p.bias_bytes[0]);
+                init_bias<RP, 4>(X, b0, T0, lane);
+                mma_seq<C::P1, RP, 4, C::NKB1, C::NKB1, MapAll>(X, w0, T0, in0, C::IN_STRIDE, 0, lane, [](auto) {});
+                init_bias<RP, 4>(Y, b0, T0 + RP, lane);
+                mma_seq<C::P1, RP, 4, C::NKB1, C::NKB1, MapAll>(Y, w0, T0 + RP, in0, C::IN_STRIDE, 0, lane, [&](auto J) {
+                    drain_step<C::PH, C::SCALE, RP, C::NKB1, decltype(J)::value>(X, pk, p.oscale[0], p.inv_in_scale[1]);
+                });
+                store_pass<C::PH, RP>(pk, T0, act, C::ACT_STRIDE, lane);
+                __syncthreads();
+                auto hidden = [&](int l, auto OUTP) {
+                    constexpr int PO = decltype(OUTP)::value;
+                    const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
+                    const float osc_prev = p.oscale[l - 1], inv_prev = p.inv_in_scale[l];
+                    const float osc = p.oscale[l], inv = (l < 3) ? p.inv_in_scale[l + 1] : 1.0f;
+                    init_bias<RP, 4>(X, bl, T0, lane);
+                    mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>, GMC_VPM_A>(
+                        X, wl, T0, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
+                            drain_step<C::PH, C::SCALE, RP, C::NKBH / 2, decltype(J)::value>(Y, pk, osc_prev, inv_prev);
+                        });
+                    store_pass<C::PH, RP>(pk, T0 + RP, act, C::ACT_STRIDE, lane);
+                    __syncthreads();
+                    mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
+                        X, wl, T0, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                    init_bias<RP, 4>(Y, bl, T0 + RP, lane);
+                    mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH, MapAll, GMC_VPM_P>(
+                        Y, wl, T0 + RP, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
+                            drain_step<PO, C::SCALE, RP, C::NKBH, decltype(J)::value>(X, pk, osc, inv);
+                        });
+                    __syncthreads();
+                    store_pass<PO, RP>(pk, T0, act, C::ACT_STRIDE, lane);
+                    __syncthreads();
+                };
+                constexpr int NSAME = (C::PH == C::P5) ? 3 : 2;
+#pragma unroll 1
+                for (int l = 1; l <= NSAME; ++l) hidden(l, std::integral_constant<int, C::PH>{});
+                if constexpr (NSAME == 2) hidden(3, std::integral_constant<int, C::P5>{});
+                // layer 5 over the first-pass k-blocks while layer 4's second pass drains
+                f32x16 out[1][1];
+                const Rsrc w4 = make_rsrc(p.wA[4], p.wA_bytes[4]);
+                init_bias<1, 1>(out, make_rsrc(p.bias[4], p.bias_bytes[4]), 0, lane);
+                mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf0<C::G5>, GMC_VPM_5>(
+                    out, w4, 0, act, C::ACT_STRIDE, wave, lane, [&](auto J) {
+                        drain_step<C::P5, C::SCALE, RP, C::NKB5 / 2, decltype(J)::value>(Y, pk, p.oscale[3], 1.0f);
+                    });
+                store_pass<C::P5, RP>(pk, T0 + RP, act, C::ACT_STRIDE, lane);
+                __syncthreads();
+                mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>>(
+                    out, w4, 0, act, C::ACT_STRIDE, wave, lane, [](auto) {});
+                const int sn = wave * 32 + (lane & 31);
+                if (lane < 32) {
+#pragma unroll
+                    for (int d = 0; d < 4; ++d) xs[d * kTileM + sn] += out[0][0][d] * dt;
+                } else {
+                    xs[4 * kTileM + sn] += out[0][0][0] * dt;
+                }
+                __syncthreads();
+                continue;
+            }
 
             // layer 1: 10 -> H (reads in0, writes the activation tile: no barrier before writing)
             dense_silu<C::P1, C::PH, C::RTW, C::NKB1, C::SCALE, false>(
