@@ -254,6 +254,11 @@ def main():
         print(json.dumps(res))
         return
 
+    # sustained MFMA throughput of each instruction on this device (diagnostic, 2 waves / SIMD)
+    peaks = {p: binding.probe_mfma_peak(p, 2) for p in ("fp32", "bf16", "fp8")}
+    res["attainable_mfma_tflops"] = peaks
+    res["roofline"]["frac_of_attainable"] = res["roofline"]["achieved"] / peaks["fp32"]
+
     # analog walk vs GMC, tau sweep (pure scattering), 2^20 transmissions per launch
     NA = 1 << 20
     sweep = []
@@ -287,7 +292,8 @@ def main():
             t = float(np.median(ms))
             fl = flops_per_sample(512, KK) * NB / (t * 1e-3)
             wide.append({"precision": prec, "hidden": 512, "K": KK, "batch": NB, "ms": t,
-                         "tps": NB / (t * 1e-3), "tflops": fl / 1e12, "frac_peak": fl / PEAK[prec]})
+                         "tps": NB / (t * 1e-3), "tflops": fl / 1e12, "frac_peak": fl / PEAK[prec],
+                         "frac_of_attainable": fl / 1e12 / peaks[prec]})
         m.close()
     res["wide_sampler"] = wide
     for s in sweep:

@@ -191,6 +191,13 @@ int gmc_problem_alive(const gmc_world *w, int32_t pid, int64_t *n_alive);
 int gmc_problem_tally(gmc_world *w, int32_t pid, double *flux, double *absorbed, double *leak,
                       double *cutoff, void *stream);
 
+/* Device diagnostic, not part of the paper's method: measures the sustained matrix-core
+ * throughput (TFLOP/s, dense) of the MFMA instruction the sampler uses for `precision`
+ * (FP32 32x32x2, BF16 32x32x16, FP8 e4m3 32x32x64) with waves_per_simd (1..4) independent
+ * waves per SIMD on the current device.  Allocates and frees a small scratch buffer and
+ * synchronises the device.  Used to read roofline fractions against what the chip sustains. */
+int gmc_probe_mfma_peak(int precision, int waves_per_simd, double *tflops);
+
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *gmc_last_error(void);
 

@@ -301,3 +301,15 @@ class World:
             self.close()
         except Exception:
             pass
+
+
+def probe_mfma_peak(precision, waves_per_simd: int = 2) -> float:
+    """Sustained dense MFMA TFLOP/s of the sampler's instruction for `precision` (diagnostic)."""
+    if isinstance(precision, str):
+        precision = PRECISIONS[precision]
+    L = lib()
+    L.gmc_probe_mfma_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    L.gmc_probe_mfma_peak.restype = ctypes.c_int
+    t = ctypes.c_double()
+    _check(L.gmc_probe_mfma_peak(int(precision), waves_per_simd, ctypes.byref(t)))
+    return t.value
