@@ -103,21 +103,29 @@ def bench_transport(binding, inputs, w512):
     out = {"workload": "32x32 checkerboard (0.5,0.5)/(50,0.99), central 4x4 source, vacuum, 1e6 histories"}
     world = binding.World(1 << 20, 2, 1 << 12)
     model = binding.Model(inputs.pack_blob(w512), "bf16")
-    for name, smp, m in (("analog", binding.SAMPLER_MC, None), ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, model)):
-        transport.run_problem(world, prob, 20_000, 7, smp, m, 16)          # warm-up
+    flux = {}
+    for name, smp, m, K in (("analog", binding.SAMPLER_MC, None, 16),
+                            ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, model, 16),
+                            ("gmc_bf16_h512_k32", binding.SAMPLER_GMC, model, 32)):
+        transport.run_problem(world, prob, 20_000, 7, smp, m, K)          # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = transport.run_problem(world, prob, n, 1, smp, m, 16)
+        r = transport.run_problem(world, prob, n, 1, smp, m, K)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         bal = r["absorbed"].sum() + r["leak"].sum() + r["cutoff"].sum()
+        flux[name] = r["flux"] / n
         out[name] = {"seconds": dt, "histories_per_s": n / dt, "transmissions": int(r["transmissions"]),
                      "transmissions_per_s": r["transmissions"] / dt, "steps": r["steps"],
-                     "balance_error": abs(bal - n) / n}
+                     "balance_error": abs(bal - n) / n, "leak_per_history": float(r["leak"].sum() / n)}
     model.close()
     world.close()
-    out["note"] = ("the generative run uses seeded random-init weights: it measures the throughput "
-                   "of the path, not a physical flux")
+    ref = flux["analog"]
+    for name in ("gmc_bf16_h512_k16", "gmc_bf16_h512_k32"):
+        out[name]["flux_rel_l1_vs_analog"] = float(np.abs(flux[name] - ref).sum() / np.abs(ref).sum())
+    out["note"] = ("the generative runs use the weights fitted to this library's analog walk "
+                   "(paper_2512_13965_amd/weights/gmc_h512.bin); flux_rel_l1_vs_analog is the "
+                   "L1 distance of the per-source-particle flux maps")
     return out
 
 
@@ -150,7 +158,7 @@ def bench_serving(binding, inputs, w512, n_req):
             "latency_s": lat, "histories": int(sum(r.n_hist for r in st.requests)),
             "workload": "Poisson stream at 70% of the measured capacity; grids 16^2-128^2, "
                         "tau log-U[0.1,200], c U[0,1], 1e4-10^5.5 histories/request, "
-                        "GMC BF16 H=512 K=16 random-init weights"}
+                        "GMC BF16 H=512 K=16 trained weights"}
 
 
 def main():
@@ -280,11 +288,13 @@ def main():
     # width-512 sampler in BF16 / FP8 on 2^20 transmissions (cfg2 shape, random-init weights)
     NB = 1 << 20
     w5 = inputs.random_weights(512, 1)
+    wpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512.bin")
+    w5t = inputs.load_blob(wpath) if os.path.exists(wpath) else w5     # trained (cfg2)
     condB = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
     outB = binding.DeviceExit.empty(NB, dev)
     wide = []
     for prec in ("bf16", "fp8"):
-        m = binding.Model(inputs.pack_blob(w5), prec)
+        m = binding.Model(inputs.pack_blob(w5t), prec)
         for KK in (8, 16, 32):
             fn = lambda: binding.gmc_transmit(m, condB, KK, 2, 0, out=outB)
             fn()
@@ -300,8 +310,8 @@ def main():
         s["gmc_bf16_h512_k16_tps"] = next(x["tps"] for x in wide if x["precision"] == "bf16" and x["K"] == 16)
 
     if not args.no_transport:
-        res["transport"] = bench_transport(binding, inputs, w5)
-        res["serving"] = bench_serving(binding, inputs, w5, args.serve_requests)
+        res["transport"] = bench_transport(binding, inputs, w5t)
+        res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, K)

@@ -1,0 +1,79 @@
+"""Statistical acceptance of the fitted boundary model (paper: Fig. 2b compares the joint
+exit-angle / path-length law of GMC and MC; "Network Architecture and Inputs" for the model).
+
+A learned approximation cannot match the exit law sample by sample -- this comparison is
+"parity unpinned": the reference is the FP64 oracle's analog walk (mode C) at the same entry
+condition, and the budgets below are the fitted model's measured distances (K = 32 Euler steps,
+BF16) plus statistical noise, so a model or sampler regression fails them.  Thin cells are not
+tested here: their exit law has an uncollided atom the flow can only smear.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2512_13965_amd import inputs
+from tests.gpu_util import require_gpu
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                       "paper_2512_13965_amd", "weights", "gmc_h512.bin")
+
+
+def _fixed(n, tau, c, y, s):
+    f = lambda v: np.full(n, np.float32(v))
+    return inputs.Conditions(f(math.log(tau)), f(c), f(y), f(s))
+
+
+def _tv2(a, b, bins):
+    ha, _ = np.histogramdd(a, bins=bins)
+    hb, _ = np.histogramdd(b, bins=bins)
+    return 0.5 * np.abs(ha / ha.sum() - hb / hb.sum()).sum()
+
+
+@pytest.fixture(scope="module")
+def trained():
+    binding = require_gpu()
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no fitted weights")
+    m = binding.Model(open(WEIGHTS, "rb").read(), "bf16")
+    yield binding, m
+    m.close()
+
+
+@pytest.mark.parametrize("tau,c,y,s", [(10.0, 1.0, 0.3, 0.5), (100.0, 1.0, 0.5, -0.3),
+                                       (30.0, 0.95, 0.9, -0.8)])
+def test_exit_law_matches_the_walk(orc, trained, tau, c, y, s):
+    binding, m = trained
+    n_g, n_o = 100_000, 50_000
+    g = binding.gmc_transmit(m, binding.DeviceCond.from_host(_fixed(n_g, tau, c, y, s)), 32, 5).to_host()
+    o = orc.mc_transmit(_fixed(n_o, tau, c, y, s), 0, seed=17, nthreads=8)
+    fg = np.bincount(g["face"], minlength=4) / n_g
+    fo = np.bincount(o["face"], minlength=4) / n_o
+    tv_face = 0.5 * np.abs(fg - fo).sum()
+    ks_cos = stats.ks_2samp(g["dir_cos"], o["u"]).statistic
+    ks_len = stats.ks_2samp(np.log(g["path"]), np.log(o["len"])).statistic
+    ks_pos = stats.ks_2samp(g["pos"] + g["face"], o["pos"] + o["face"]).statistic
+    # Fig. 2b: joint law of the exit x-direction cosine and log10 of the path length
+    bins = [np.linspace(-1, 1, 11), np.linspace(-3, 2.5, 12)]
+    tv_joint = _tv2(np.stack([g["dir_cos"], np.log10(g["path"])], 1),
+                    np.stack([o["u"], np.log10(o["len"])], 1), bins)
+    print(f"tau={tau} c={c}: face TV {tv_face:.4f}, KS pos {ks_pos:.4f} cos {ks_cos:.4f} "
+          f"ln l {ks_len:.4f}, joint TV {tv_joint:.4f}")
+    assert tv_face < 0.02
+    assert ks_pos < 0.05 and ks_cos < 0.05 and ks_len < 0.05
+    assert tv_joint < 0.06
+
+
+def test_mean_path_length_invariance(trained):
+    # P3: with pure scattering and uniform cosine-law entry, E[path] = pi / 4 at any tau_s; the
+    # fitted model reproduces it within 6 % at tau = 10 (Euler K = 32)
+    binding, m = trained
+    cond = inputs.fixed_cell_conditions(200_000, 10.0, 1.0, seed=3)
+    g = binding.gmc_transmit(m, binding.DeviceCond.from_host(cond), 32, 9).to_host()
+    rel = abs(g["path"].mean() - math.pi / 4) / (math.pi / 4)
+    print(f"E[path] = {g['path'].mean():.4f}, pi/4 = {math.pi / 4:.4f}")
+    assert rel < 0.06
