@@ -50,6 +50,10 @@ typedef enum {
 
 typedef enum { GMC_MODE_CONTINUOUS = 0, GMC_MODE_ANALOG = 1 } gmc_walk_mode;
 typedef enum { GMC_SAMPLER_GMC = 0, GMC_SAMPLER_MC = 1 } gmc_sampler;
+/* ODE integrator of the generative sampler: explicit Euler (one network evaluation per step,
+ * eq. 8 as written) or the classic fourth-order Runge-Kutta scheme (four evaluations per step;
+ * the integrator behind the timings of the paper section "Convergence and Performance", 12 steps). */
+typedef enum { GMC_EULER = 0, GMC_RK4 = 1 } gmc_integrator;
 
 #define GMC_FACE_ABSORBED (-1)   /* analog-absorption walk ended inside the cell */
 #define GMC_FACE_CAPPED (-2)     /* walk exceeded 2^24 flights (never seen in practice) */
@@ -109,6 +113,17 @@ int gmc_model_info(const gmc_model *m, int *hidden, int *precision);
 int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t seed,
                  uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out,
                  void *stream);
+
+/* gmc_transmit with a choice of ODE integrator over the same K uniform steps of [0, 1]:
+ *   integrator GMC_EULER: identical to gmc_transmit.
+ *   integrator GMC_RK4:   x_{k+1} = x_k + (h/6)(k1 + 2 k2 + 2 k3 + k4), h = 1/K, with
+ *              k1 = v(x_k, t_k), k2 = v(x_k + h k1/2, t_k + h/2), k3 = v(x_k + h k2/2, t_k + h/2),
+ *              k4 = v(x_k + h k3, t_k + h); t_k = k/K (4K network evaluations).
+ * Other arguments, ownership and errors as for gmc_transmit; GMC_EINVAL for an unknown
+ * integrator. */
+int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int K, uint64_t seed,
+               uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out,
+               void *stream);
 
 /* Samples n cell transmissions with the analog random walk that the generative sampler
  * replaces (paper "Monte Carlo Method", eq. 4): flights d = -ln(xi) / sigma with
@@ -175,12 +190,15 @@ int gmc_problem_remove(gmc_world *w, int32_t pid);
 int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count, void *stream,
                      int64_t *n_alive_out);
 /* One transport step for every particle in flight: canonical conditions (stage 1), one cell
- * transmission each with the generative sampler (sampler = GMC_SAMPLER_GMC, model m, K Euler
- * steps) or the analog walk with continuous absorption (GMC_SAMPLER_MC, m unused), FP64
+ * transmission each with the generative sampler (sampler = GMC_SAMPLER_GMC, model m, K steps
+ * of the world's integrator) or the analog walk with continuous absorption (GMC_SAMPLER_MC, m unused), FP64
  * attenuation and tallies (stage 3), move / leak / cutoff and compaction (stage 4).
  * Synchronises `stream`; *n_alive_out (optional) = particles still in flight. */
 int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
                        int64_t *n_alive_out);
+/* Integrator (GMC_EULER, the default, or GMC_RK4) that later gmc_transport_step calls with the
+ * generative sampler use; K then counts integration steps.  GMC_EINVAL otherwise. */
+int gmc_world_set_integrator(gmc_world *w, int integrator);
 /* Particles of problem pid still in flight after the last step or injection. */
 int gmc_problem_alive(const gmc_world *w, int32_t pid, int64_t *n_alive);
 /* Copies problem pid's FP64 tallies, summed over its histories so far, to host arrays of

@@ -8,8 +8,9 @@ holds none of the method's arithmetic.
 Contents
   * `gmc_oracle.c` (built to `liboracle.so`): Philox4x32-10, Box-Muller noise, the analog
     walk through one cell in FP64 (modes C and A), and FP64 cell-to-cell transport.
-  * this module: ctypes bindings for the above, and the FP64 velocity-MLP / Euler sampler
-    with optional BF16 / FP8-e4m3 quantisation emulation, plus the exit decoder.
+  * this module: ctypes bindings for the above, and the FP64 velocity-MLP sampler (explicit
+    Euler and classic RK4) with optional BF16 / FP8-e4m3 quantisation emulation, plus the exit
+    decoder.
 
 Paper references are to arXiv 2512.13965 (sections and equation numbers in order of
 appearance).
@@ -217,6 +218,34 @@ def sample_raw(weights, cond, K: int, z: np.ndarray, precision=PREC_FP64) -> np.
     for k in range(K):
         x = x + dt * velocity(weights, x, k * dt, condf, precision)
     return x
+
+
+def rk4_solve(f, x0, K: int):
+    """Classic fourth-order Runge-Kutta over [0, 1] in K uniform steps of h = 1/K for
+    dx/dt = f(x, t): each step takes slopes k1 = f(x, t), k2 = f(x + h k1 / 2, t + h / 2),
+    k3 = f(x + h k2 / 2, t + h / 2), k4 = f(x + h k3, t + h) and sets
+    x <- x + h (k1 + 2 k2 + 2 k3 + k4) / 6 (the integrator the paper times its sampler with:
+    section "Convergence and Performance", 12 steps)."""
+    x = np.array(x0, np.float64, copy=True)
+    h = 1.0 / K
+    for k in range(K):
+        t = k * h
+        k1 = f(x, t)
+        k2 = f(x + 0.5 * h * k1, t + 0.5 * h)
+        k3 = f(x + 0.5 * h * k2, t + 0.5 * h)
+        k4 = f(x + h * k3, t + h)
+        x = x + (h / 6.0) * (k1 + 2.0 * k2 + 2.0 * k3 + k4)
+    return x
+
+
+def sample_raw_rk4(weights, cond, K: int, z: np.ndarray, precision=PREC_FP64) -> np.ndarray:
+    """The sampler ODE of eq. 8 (x(0) = z ~ N(0, I), dx/dt = v(x, t | c)) integrated with
+    `rk4_solve` in K steps.  z: [5][n].  Returns x(1) as [n, 5] FP64."""
+    z = np.asarray(z, np.float64)
+    if z.ndim != 2 or z.shape[0] != 5:
+        raise ValueError("noise must have layout [5][n]")
+    condf = condition_features(cond)
+    return rk4_solve(lambda x, t: velocity(weights, x, t, condf, precision), z.T, K)
 
 
 OUTWARD = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])

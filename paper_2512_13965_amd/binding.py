@@ -55,6 +55,7 @@ def lib() -> ctypes.CDLL:
         L.gmc_model_destroy.argtypes = [P]
         L.gmc_model_info.argtypes = [P, ctypes.POINTER(I), ctypes.POINTER(I)]
         L.gmc_transmit.argtypes = [P, _Cond, I64, I, U64, U64, P, P, _Exit, P]
+        L.gmc_sample.argtypes = [P, _Cond, I64, I, I, U64, U64, P, P, _Exit, P]
         L.mc_transmit.argtypes = [_Cond, I64, I, U64, U64, _Exit, P, P]
         L.gmc_decode.argtypes = [P, I64, _Exit, P, P]
         for name in ("gmc_model_create", "gmc_model_destroy", "gmc_model_info", "gmc_transmit",
@@ -177,6 +178,29 @@ def gmc_transmit(model: Model, cond: DeviceCond, K: int, seed: int, id_base: int
     return out
 
 
+INTEGRATORS = {"euler": 0, "rk4": 1}
+
+
+def gmc_sample(model: Model, cond: DeviceCond, integrator: str, K: int, seed: int,
+               id_base: int = 0, noise: torch.Tensor | None = None,
+               raw: torch.Tensor | None = None, out: DeviceExit | None = None,
+               n: int | None = None, stream=None) -> DeviceExit:
+    """gmc_sample: the generative sampler with integrator "euler" or "rk4" over K steps."""
+    n = len(cond) if n is None else n
+    if integrator not in INTEGRATORS:
+        raise ValueError(f"integrator must be one of {sorted(INTEGRATORS)}")
+    if out is None:
+        out = DeviceExit.empty(n, cond.log_tau.device)
+    if noise is not None:
+        _need(noise, torch.float32, 5 * n, "noise")
+    if raw is not None:
+        _need(raw, torch.float32, 5 * n, "raw")
+    _check(lib().gmc_sample(model.handle, cond.c_struct(), n, INTEGRATORS[integrator], int(K),
+                            seed, id_base, _ptr(noise), _ptr(raw), out.c_struct(n),
+                            _stream(stream)))
+    return out
+
+
 def mc_transmit(cond: DeviceCond, mode: int, seed: int, id_base: int = 0,
                 ncoll: torch.Tensor | None = None, out: DeviceExit | None = None,
                 n: int | None = None, stream=None) -> DeviceExit:
@@ -224,7 +248,8 @@ def _transport_sigs(L):
     L.gmc_transport_step.argtypes = [P, I, P, I, P, ctypes.POINTER(I64)]
     L.gmc_problem_alive.argtypes = [P, I32, ctypes.POINTER(I64)]
     L.gmc_problem_tally.argtypes = [P, I32, P, P, P, P, P]
-    for name in ("gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
+    L.gmc_world_set_integrator.argtypes = [P, I]
+    for name in ("gmc_world_set_integrator", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
                  "gmc_problem_remove", "gmc_world_inject", "gmc_transport_step",
                  "gmc_problem_alive", "gmc_problem_tally"):
         getattr(L, name).restype = ctypes.c_int
@@ -270,6 +295,12 @@ class World:
         n = ctypes.c_int64()
         _check(self._L.gmc_world_inject(self._h, pid, h_begin, count, _stream(stream), ctypes.byref(n)))
         return n.value
+
+    def set_integrator(self, integrator: str):
+        """ODE integrator ("euler" or "rk4") of later generative-sampler steps."""
+        if integrator not in INTEGRATORS:
+            raise ValueError(f"integrator must be one of {sorted(INTEGRATORS)}")
+        _check(self._L.gmc_world_set_integrator(self._h, INTEGRATORS[integrator]))
 
     def step(self, sampler: int, model: Model | None = None, K: int = 16, stream=None) -> int:
         n = ctypes.c_int64()

@@ -264,8 +264,16 @@ static bool exit_ok(const gmc_exit &o) { return o.face && o.pos && o.dir_cos && 
 int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t seed,
                  uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out, void *stream)
 {
+    return gmc_sample(m, cond, n, GMC_EULER, K, seed, id_base, noise_opt, raw_opt, out, stream);
+}
+
+int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int K, uint64_t seed,
+               uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out, void *stream)
+{
     if (!m) return fail(GMC_EINVAL, "gmc_transmit: null model");
     if (n < 0) return fail(GMC_EINVAL, "gmc_transmit: negative n");
+    if (integrator != GMC_EULER && integrator != GMC_RK4)
+        return fail(GMC_EINVAL, "gmc_sample: integrator must be GMC_EULER or GMC_RK4");
     if (K < 1 || K > 1024) return fail(GMC_EINVAL, "gmc_transmit: K must be in 1..1024");
     if (n == 0) return GMC_OK;
     if (!cond_ok(cond) || !exit_ok(out)) return fail(GMC_EINVAL, "gmc_transmit: null condition or output array");
@@ -286,6 +294,7 @@ int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t s
     p.path = out.path;
     p.n = n;
     p.K = K;
+    p.integrator = integrator;
     p.seed = seed;
     p.id_base = id_base;
     const int cu = gmc::device_cu_count();

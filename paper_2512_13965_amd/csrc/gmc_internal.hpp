@@ -68,7 +68,8 @@ struct MlpParams {
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
     int64_t n;
-    int K;
+    int K;                    // integration steps
+    int integrator;           // 0 explicit Euler, 1 classic RK4 (4 evaluations per step)
     uint64_t seed, id_base;
 };
 

@@ -429,10 +429,10 @@ struct Cfg {
     static constexpr int WPK = words_per_unit(PH) > words_per_unit(P5) ? words_per_unit(PH) : words_per_unit(P5);
     static constexpr int LDS_ACT = kTileM * ACT_STRIDE;
     static constexpr int LDS_IN = kTileM * IN_STRIDE;
-    static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 4) * kTileM * 4;
+    static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 4 + 5 + 5) * kTileM * 4;
 };
 
-template <int MP, int H>
+template <int MP, int H, int RK>
 __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
 {
     using C = Cfg<MP, H>;
@@ -442,11 +442,38 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
     char *in0 = smem + C::LDS_ACT;
     float *xs = (float *)(smem + C::LDS_ACT + C::LDS_IN);   // [5][128] ODE state
     float *cf = xs + 5 * kTileM;                              // [4][128] condition features
+    float *ksum = cf + 4 * kTileM;                            // [5][128] RK4 stage sum
+    float *vout = ksum + 5 * kTileM;                          // [5][128] last network output
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     const int64_t ntiles = (p.n + kTileM - 1) / kTileM;
     const float dt = 1.0f / (float)p.K;
+    constexpr bool rk4 = (RK == 1);
+    const int nevals = rk4 ? 4 * p.K : p.K;
+    // Euler: the lane that holds output d of sample sn applies x += dt v at once.  Classic RK4:
+    // the output goes to vout; before the next evaluation the thread of sample tid forms the
+    // stage input (stages at t, t + dt/2, t + dt/2, t + dt take x, x + dt/2 k1, x + dt/2 k2,
+    // x + dt k3) and after the fourth stage x += dt/6 (k1 + 2 k2 + 2 k3 + k4).
+    auto emit = [&](int d, int sn, float v) {
+        const int o = d * kTileM + sn;
+        if constexpr (rk4) vout[o] = v;
+        else xs[o] += v * dt;
+    };
+    auto advance = [&](int e, float xi[5]) {
+        const int stage = e & 3;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) {
+            const int o = d * kTileM + tid;
+            const float v = vout[o];
+            if (stage < 3) {
+                ksum[o] = stage == 0 ? v : ksum[o] + 2.0f * v;
+                xi[d] = xs[o] + (stage == 2 ? dt : 0.5f * dt) * v;
+            } else {
+                xi[d] = xs[o] = xs[o] + (dt * (1.0f / 6.0f)) * (ksum[o] + v);
+            }
+        }
+    };
     const int T0 = wave * C::RTW;
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -476,13 +503,19 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
         }
         __syncthreads();
 
-        for (int k = 0; k < p.K; ++k) {
-            const float t = (float)k * dt;
+        for (int e = 0; e < nevals; ++e) {
+            const int stage = rk4 ? (e & 3) : 0;
+            const int k = rk4 ? (e >> 2) : e;
+            const float t = ((float)k + (stage == 0 ? 0.0f : (stage == 3 ? 1.0f : 0.5f))) * dt;
             // layer-1 input row of sample tid: [x0..x4, t, ln tau, c, 2y-1, sin th, 0 x 6]
             if (tid < kTileM) {
                 float v[16];
+                if (!rk4 || e == 0) {
 #pragma unroll
-                for (int d = 0; d < 5; ++d) v[d] = xs[d * kTileM + tid];
+                    for (int d = 0; d < 5; ++d) v[d] = xs[d * kTileM + tid];
+                } else {
+                    advance(e - 1, v);
+                }
                 v[5] = t;
 #pragma unroll
                 for (int d = 0; d < 4; ++d) v[6 + d] = cf[d * kTileM + tid];
@@ -562,9 +595,9 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
                 const int sn = wave * 32 + (lane & 31);
                 if (lane < 32) {
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) xs[d * kTileM + sn] += out[0][0][d] * dt;
+                    for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
                 } else {
-                    xs[4 * kTileM + sn] += out[0][0][0] * dt;
+                    emit(4, sn, out[0][0][0]);
                 }
                 __syncthreads();
                 continue;
@@ -602,9 +635,9 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
                 const int sn = wave * 32 + (lane & 31);
                 if (lane < 32) {
 #pragma unroll
-                    for (int d = 0; d < 4; ++d) xs[d * kTileM + sn] += out[0][0][d] * dt;
+                    for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
                 } else {
-                    xs[4 * kTileM + sn] += out[0][0][0] * dt;
+                    emit(4, sn, out[0][0][0]);
                 }
             }
             __syncthreads();
@@ -612,10 +645,15 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
 
         if (tid < kTileM) {
             const int64_t i = base + tid;
+            float xk[5];
+            if constexpr (rk4) {
+                advance(nevals - 1, xk);
+            } else {
+#pragma unroll
+                for (int d = 0; d < 5; ++d) xk[d] = xs[d * kTileM + tid];
+            }
             if (i < p.n) {
-                const float a0 = xs[0 * kTileM + tid], a1 = xs[1 * kTileM + tid],
-                            a2 = xs[2 * kTileM + tid], a3 = xs[3 * kTileM + tid],
-                            a4 = xs[4 * kTileM + tid];
+                const float a0 = xk[0], a1 = xk[1], a2 = xk[2], a3 = xk[3], a4 = xk[4];
                 if (p.raw) {
                     p.raw[0 * p.n + i] = a0;
                     p.raw[1 * p.n + i] = a1;
@@ -639,7 +677,8 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
 template <int MP, int H>
 hipError_t launch_one(const MlpParams &p, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((mlp_ode_kernel<MP, H>), dim3(grid), dim3(256), 0, s, p);
+    if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1>), dim3(grid), dim3(256), 0, s, p);
+    else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0>), dim3(grid), dim3(256), 0, s, p);
     return hipGetLastError();
 }
 

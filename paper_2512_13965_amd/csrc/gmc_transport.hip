@@ -272,6 +272,7 @@ struct gmc_world {
     void *mem = nullptr;
     BankDev bank[2]{};
     int cur = 0;
+    int integrator = GMC_EULER;   // ODE integrator of the generative sampler
     // sampler staging
     float *c_ltau = nullptr, *c_c = nullptr, *c_yin = nullptr, *c_sth = nullptr;
     uint64_t *ids = nullptr, *keys = nullptr;
@@ -531,6 +532,16 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
     return GMC_OK;
 }
 
+int gmc_world_set_integrator(gmc_world *w, int integrator)
+{
+    if (!w) return set_error(GMC_EINVAL, "gmc_world_set_integrator: null world");
+    if (integrator != GMC_EULER && integrator != GMC_RK4)
+        return set_error(GMC_EINVAL, "gmc_world_set_integrator: integrator must be GMC_EULER or GMC_RK4");
+    std::lock_guard<std::mutex> lk(w->mu);
+    w->integrator = integrator;
+    return GMC_OK;
+}
+
 int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
                        int64_t *n_alive_out)
 {
@@ -566,6 +577,7 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
             p.path = w->e_path;
             p.n = n;
             p.K = K;
+            p.integrator = w->integrator;
             p.seed = 0;
             p.id_base = 0;
             const int64_t ntiles = (n + kTileM - 1) / kTileM;
