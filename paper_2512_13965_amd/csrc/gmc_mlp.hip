@@ -30,6 +30,14 @@
 #ifndef GMC_VPM_5
 #define GMC_VPM_5 0
 #endif
+#ifndef GMC_PFA
+#define GMC_PFA 2
+#endif
+// 8: BF16 / FP8 models of width >= 256 use the two-group schedule (eight waves); 4: they use
+// the single-group cross-layer pipeline (four waves).  Both give bit-identical results.
+#ifndef GMC_WIDE_WAVES
+#define GMC_WIDE_WAVES 8
+#endif
 
 namespace gmc {
 namespace {
@@ -337,7 +345,7 @@ struct MapHalf1 {
 
 // acc[r][c] += W[T0 + r] x act[column tile col0 + c] over the NJ k-blocks Map::kb(0..NJ-1) of
 // a layer with NKB k-blocks (same fragment layout and prefetch scheme as mma_pass).
-template <int P, int RP, int CT, int NKB, int NJ, typename Map, int VPM = 0, typename Hook>
+template <int P, int RP, int CT, int NKB, int NJ, typename Map, int VPM = 0, int SWAPB = 0, typename Hook>
 __device__ __forceinline__ void mma_seq(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, const char *act,
                                         int stride, int col0, int lane, Hook &&hook)
 {
@@ -350,26 +358,30 @@ __device__ __forceinline__ void mma_seq(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, 
     const int t0 = __builtin_amdgcn_readfirstlane(T0);
     const int voff = lane * FB;
     const char *sb = act + (col0 * 32 + n) * stride + h * (KBB / 2);
-    Frag a[3][RP], b[2][CT];
+    // k-blocks the weight loads run ahead (an FP8 k-block is four times the matrix work of a
+    // BF16 one, and its fragments twice the registers)
+    constexpr int PA = (P == kFP8) ? 1 : GMC_PFA;
+    Frag a[PA + 1][RP], b[2][CT];
     auto loadA = [&](int slot, int kb) {
 #pragma unroll
         for (int r = 0; r < RP; ++r) a[slot][r] = M::load_g(wA, voff, ((t0 + r) * NKB + kb) * 64 * FB);
     };
     auto loadB = [&](int slot, int kb) {
 #pragma unroll
-        for (int c = 0; c < CT; ++c) b[slot][c] = M::load_s(sb + c * 32 * stride + kb * KBB);
+        for (int c = 0; c < CT; ++c) b[slot][c] = M::load_s(sb + c * 32 * stride + (kb ^ SWAPB) * KBB);
     };
-    loadA(0, Map::kb(0));
-    if constexpr (NJ > 1) loadA(1, Map::kb(1));
+    sfor<PA>([&](auto I) {
+        if constexpr (decltype(I)::value < NJ) loadA(decltype(I)::value, Map::kb(decltype(I)::value));
+    });
     loadB(0, Map::kb(0));
     sfor<NJ>([&](auto JJ) {
         constexpr int j = decltype(JJ)::value;
-        if constexpr (j + 2 < NJ) loadA((j + 2) % 3, Map::kb(j + 2));
+        if constexpr (j + PA < NJ) loadA((j + PA) % (PA + 1), Map::kb(j + PA));
         if constexpr (j + 1 < NJ) loadB((j + 1) % 2, Map::kb(j + 1));
 #pragma unroll
         for (int r = 0; r < RP; ++r)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[j % 3][r], b[j % 2][c]);
+            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[j % (PA + 1)][r], b[j % 2][c]);
         hook(JJ);
         if constexpr (VPM > 0) {
             // interleave the hook's epilogue arithmetic between the MFMAs: one MFMA, then up
@@ -416,16 +428,27 @@ struct Cfg {
     static constexpr int ACT_ELEM = (MP == kF32) ? 4 : 2;   // widest type stored in the tile
     static constexpr int ACT_STRIDE = H * ACT_ELEM + 16;    // +16 B: conflict-free row reads
     static constexpr int IN_STRIDE = 16 * elem_bytes(P1) + 16;
-    static constexpr int RTW = H / (32 * kWaves);           // row tiles per wave
+    // Two-group schedule (BF16 / FP8, H >= 256): eight waves, two per SIMD.  Group 0 owns the
+    // first half of every layer's output rows, group 1 the second half; while one group's
+    // waves run the matrix k-loop, the other group's waves run the SiLU epilogue on the same
+    // SIMDs, so vector and matrix work overlap across waves.
+    static constexpr bool GROUPS = (MP != kF32 && H >= 256 && GMC_WIDE_WAVES == 8);
+    static constexpr int W = GROUPS ? 8 : kWaves;
+    static constexpr int THREADS = 64 * W;
+    static constexpr int NT = H / 32;                       // row tiles of a hidden layer
+    static constexpr int RTW = NT / W;                      // row tiles per wave
+    static constexpr int RPG = NT / 8;                      // row tiles per wave (two-group schedule)
     static constexpr int NKB1 = 16 / kb_width(P1);
     static constexpr int NKBH = H / kb_width(PH);
     static constexpr int NKB5 = H / kb_width(P5);
     static constexpr int RP = RTW >= 4 ? RTW / 2 : 1;       // row tiles per pass
     static constexpr int NP = RTW / RP;                     // row passes per layer
-    // cross-layer pipelining needs each pass's output to fill whole k-blocks of the consumer
-    static constexpr bool PIPE = NP == 2 && RP * 32 >= kb_width(PH) && RP * 32 >= kb_width(P5);
-    static constexpr int GH = PIPE ? RP * 32 / kb_width(PH) : 1;
-    static constexpr int G5 = PIPE ? RP * 32 / kb_width(P5) : 1;
+    // Cross-layer pipelining: pass p of wave w computes row tiles p * NT / 2 + w * RP + r, so
+    // the first passes of all waves fill the first half of the consumer's k-blocks and the
+    // second passes the other half; each half must be whole k-blocks.
+    static constexpr bool PIPE = !GROUPS && NP == 2 && NKBH % 2 == 0 && NKB5 % 2 == 0;
+    static constexpr int GH = (PIPE || GROUPS) ? NKBH / 2 : 1;
+    static constexpr int G5 = (PIPE || GROUPS) ? NKB5 / 2 : 1;
     static constexpr int WPK = words_per_unit(PH) > words_per_unit(P5) ? words_per_unit(PH) : words_per_unit(P5);
     static constexpr int LDS_ACT = kTileM * ACT_STRIDE;
     static constexpr int LDS_IN = kTileM * IN_STRIDE;
@@ -433,10 +456,15 @@ struct Cfg {
 };
 
 template <int MP, int H, int RK>
-__global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
+__global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpParams p)
 {
     using C = Cfg<MP, H>;
     static_assert(C::LDS_BYTES <= 160 * 1024, "LDS budget");
+    static_assert(C::RTW >= 1 && C::NT % C::W == 0, "row tiles must split evenly over the waves");
+    static_assert(C::GROUPS || C::PIPE || C::W == kTileM / 32,
+                  "the layer-by-layer path maps one wave per column tile in layer 5");
+    static_assert(!C::GROUPS || (C::RPG >= 1 && C::NKBH % 2 == 0 && C::NKB5 % 2 == 0),
+                  "two-group schedule: each group's rows fill whole k-blocks of the consumer");
     __shared__ __attribute__((aligned(16))) char smem[C::LDS_BYTES];
     char *act = smem;
     char *in0 = smem + C::LDS_ACT;
@@ -474,7 +502,8 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
             }
         }
     };
-    const int T0 = wave * C::RTW;
+    const int T0 = wave * C::RTW;                    // first row tile (layer-by-layer path)
+    const int TX = wave * C::RP, TY = C::NT / 2 + wave * C::RP;   // pass row tiles (pipelined path)
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         const int64_t base = tile * kTileM;
@@ -536,6 +565,102 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
             }
             __syncthreads();
 
+            if constexpr (C::GROUPS) {
+                // Two-group schedule.  Per hidden layer, three barrier-separated phases:
+                //   P1: group 0 multiplies over the k-blocks of the first half of the input
+                //       features; group 1 runs the epilogue of its previous-layer rows (layer 1
+                //       included) and writes them over the second half (nobody reads it in P1)
+                //   P2: group 0 over the second half; group 1 over the first half
+                //   P3: group 0 runs its epilogue into the first half; group 1 over the
+                //       second half
+                // Every accumulator sums its k-blocks in natural order.
+                constexpr int RG = C::RPG;
+                // FP8 models: the last hidden layer writes BF16, two bytes per feature, whose
+                // first half would cover the FP8 second half that group 1 still reads in P3.
+                // Its outputs are therefore stored with the two halves swapped (row tile
+                // T -> T ^ NT/2) and layer 5 reads k-block kb from position kb ^ NKB5/2.
+                constexpr int XT = (C::PH != C::P5) ? C::NT / 2 : 0;
+                constexpr int SW5 = (C::PH != C::P5) ? C::NKB5 / 2 : 0;
+                const int grp = wave >> 2, wg = wave & 3;
+                const int TB = grp * (C::NT / 2) + wg * RG;       // first row tile of this wave
+                f32x16 acc[RG][4];
+                auto drain = [&](auto POC, float osc, float inv, int xt = 0) {
+                    constexpr int PO = decltype(POC)::value;
+                    constexpr int WPU = words_per_unit(PO);
+                    sfor<RG * 4>([&](auto TC) {
+                        constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
+                        uint32_t wd[4 * WPU];
+#pragma unroll
+                        for (int g = 0; g < 4; ++g) epi_unit<PO, C::SCALE>(acc[r][c], g, osc, inv, &wd[g * WPU]);
+                        store_tile<PO>(wd, (TB + r) ^ xt, c, act, C::ACT_STRIDE, lane);
+                    });
+                };
+                // layer 1 (10 -> H): both groups multiply; group 0 writes its rows now, group 1
+                // during the first hidden layer's P1
+                init_bias<RG, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), TB, lane);
+                mma_seq<C::P1, RG, 4, C::NKB1, C::NKB1, MapAll>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), TB, in0,
+                                                                C::IN_STRIDE, 0, lane, [](auto) {});
+                if (grp == 0) drain(std::integral_constant<int, C::PH>{}, p.oscale[0], p.inv_in_scale[1]);
+                __syncthreads();
+                auto hidden = [&](int l, auto OUTP) {
+                    const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
+                    if (grp == 0) {
+                        init_bias<RG, 4>(acc, bl, TB, lane);
+                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                    } else {
+                        drain(std::integral_constant<int, C::PH>{}, p.oscale[l - 1], p.inv_in_scale[l]);
+                    }
+                    __syncthreads();
+                    if (grp == 0) {
+                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                    } else {
+                        init_bias<RG, 4>(acc, bl, TB, lane);
+                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                    }
+                    __syncthreads();
+                    if (grp == 0) {
+                        drain(OUTP, p.oscale[l], (l < 3) ? p.inv_in_scale[l + 1] : 1.0f,
+                              decltype(OUTP)::value != C::PH ? XT : 0);
+                    } else {
+                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                    }
+                    __syncthreads();
+                };
+                constexpr int NSAME = (C::PH == C::P5) ? 3 : 2;
+#pragma unroll 1
+                for (int l = 1; l <= NSAME; ++l) hidden(l, std::integral_constant<int, C::PH>{});
+                if constexpr (NSAME == 2) hidden(3, std::integral_constant<int, C::P5>{});
+                f32x16 out[1][1];
+                const Rsrc w4 = make_rsrc(p.wA[4], p.wA_bytes[4]);
+                // layer 5 (5 x H): group 0 wave w owns sample column tile w; group 1 writes
+                // its layer-4 rows meanwhile
+                if (grp == 0) {
+                    init_bias<1, 1>(out, make_rsrc(p.bias[4], p.bias_bytes[4]), 0, lane);
+                    mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf0<C::G5>, 0, SW5>(
+                        out, w4, 0, act, C::ACT_STRIDE, wg, lane, [](auto) {});
+                } else {
+                    drain(std::integral_constant<int, C::P5>{}, p.oscale[3], 1.0f, XT);
+                }
+                __syncthreads();
+                if (grp == 0) {
+                    mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>, 0, SW5>(
+                        out, w4, 0, act, C::ACT_STRIDE, wg, lane, [](auto) {});
+                    const int sn = wg * 32 + (lane & 31);
+                    if (lane < 32) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
+                    } else {
+                        emit(4, sn, out[0][0][0]);
+                    }
+                }
+                __syncthreads();
+                continue;
+            }
+
             if constexpr (C::PIPE) {
                 // Cross-layer pipeline.  X holds a layer's first row pass, Y its second.  Each
                 // layer's second-pass epilogue runs inside the next layer's MFMA loop over the
@@ -545,59 +670,69 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
                 f32x16 X[RP][4], Y[RP][4];
                 uint32_t pk[RP * 16 * C::WPK];
                 const Rsrc w0 = make_rsrc(p.wA[0], p.wA_bytes[0]), b0 = make_rsrc(p.bias[0], p.bias_bytes[0]);
-                init_bias<RP, 4>(X, b0, T0, lane);
-                mma_seq<C::P1, RP, 4, C::NKB1, C::NKB1, MapAll>(X, w0, T0, in0, C::IN_STRIDE, 0, lane, [](auto) {});
-                init_bias<RP, 4>(Y, b0, T0 + RP, lane);
-                mma_seq<C::P1, RP, 4, C::NKB1, C::NKB1, MapAll>(Y, w0, T0 + RP, in0, C::IN_STRIDE, 0, lane, [&](auto J) {
+                init_bias<RP, 4>(X, b0, TX, lane);
+                mma_seq<C::P1, RP, 4, C::NKB1, C::NKB1, MapAll>(X, w0, TX, in0, C::IN_STRIDE, 0, lane, [](auto) {});
+                init_bias<RP, 4>(Y, b0, TY, lane);
+                mma_seq<C::P1, RP, 4, C::NKB1, C::NKB1, MapAll>(Y, w0, TY, in0, C::IN_STRIDE, 0, lane, [&](auto J) {
                     drain_step<C::PH, C::SCALE, RP, C::NKB1, decltype(J)::value>(X, pk, p.oscale[0], p.inv_in_scale[1]);
                 });
-                store_pass<C::PH, RP>(pk, T0, act, C::ACT_STRIDE, lane);
+                store_pass<C::PH, RP>(pk, TX, act, C::ACT_STRIDE, lane);
                 __syncthreads();
                 auto hidden = [&](int l, auto OUTP) {
                     constexpr int PO = decltype(OUTP)::value;
                     const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
                     const float osc_prev = p.oscale[l - 1], inv_prev = p.inv_in_scale[l];
                     const float osc = p.oscale[l], inv = (l < 3) ? p.inv_in_scale[l + 1] : 1.0f;
-                    init_bias<RP, 4>(X, bl, T0, lane);
+                    init_bias<RP, 4>(X, bl, TX, lane);
                     mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>, GMC_VPM_A>(
-                        X, wl, T0, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
+                        X, wl, TX, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
                             drain_step<C::PH, C::SCALE, RP, C::NKBH / 2, decltype(J)::value>(Y, pk, osc_prev, inv_prev);
                         });
-                    store_pass<C::PH, RP>(pk, T0 + RP, act, C::ACT_STRIDE, lane);
+                    store_pass<C::PH, RP>(pk, TY, act, C::ACT_STRIDE, lane);
                     __syncthreads();
                     mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
-                        X, wl, T0, act, C::ACT_STRIDE, 0, lane, [](auto) {});
-                    init_bias<RP, 4>(Y, bl, T0 + RP, lane);
+                        X, wl, TX, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                    init_bias<RP, 4>(Y, bl, TY, lane);
                     mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH, MapAll, GMC_VPM_P>(
-                        Y, wl, T0 + RP, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
+                        Y, wl, TY, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
                             drain_step<PO, C::SCALE, RP, C::NKBH, decltype(J)::value>(X, pk, osc, inv);
                         });
                     __syncthreads();
-                    store_pass<PO, RP>(pk, T0, act, C::ACT_STRIDE, lane);
+                    store_pass<PO, RP>(pk, TX, act, C::ACT_STRIDE, lane);
                     __syncthreads();
                 };
                 constexpr int NSAME = (C::PH == C::P5) ? 3 : 2;
 #pragma unroll 1
                 for (int l = 1; l <= NSAME; ++l) hidden(l, std::integral_constant<int, C::PH>{});
                 if constexpr (NSAME == 2) hidden(3, std::integral_constant<int, C::P5>{});
-                // layer 5 over the first-pass k-blocks while layer 4's second pass drains
+                // layer 5 (5 x H, rows padded to one tile) over the first-pass k-blocks while
+                // layer 4's second pass drains; wave w < 4 owns sample column tile w, further
+                // waves only drain
+                constexpr int CT5 = kTileM / 32;
                 f32x16 out[1][1];
                 const Rsrc w4 = make_rsrc(p.wA[4], p.wA_bytes[4]);
-                init_bias<1, 1>(out, make_rsrc(p.bias[4], p.bias_bytes[4]), 0, lane);
-                mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf0<C::G5>, GMC_VPM_5>(
-                    out, w4, 0, act, C::ACT_STRIDE, wave, lane, [&](auto J) {
-                        drain_step<C::P5, C::SCALE, RP, C::NKB5 / 2, decltype(J)::value>(Y, pk, p.oscale[3], 1.0f);
-                    });
-                store_pass<C::P5, RP>(pk, T0 + RP, act, C::ACT_STRIDE, lane);
-                __syncthreads();
-                mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>>(
-                    out, w4, 0, act, C::ACT_STRIDE, wave, lane, [](auto) {});
-                const int sn = wave * 32 + (lane & 31);
-                if (lane < 32) {
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
+                auto drain4 = [&](auto J) {
+                    drain_step<C::P5, C::SCALE, RP, C::NKB5 / 2, decltype(J)::value>(Y, pk, p.oscale[3], 1.0f);
+                };
+                if (C::W == CT5 || wave < CT5) {
+                    init_bias<1, 1>(out, make_rsrc(p.bias[4], p.bias_bytes[4]), 0, lane);
+                    mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf0<C::G5>, GMC_VPM_5>(
+                        out, w4, 0, act, C::ACT_STRIDE, wave, lane, drain4);
                 } else {
-                    emit(4, sn, out[0][0][0]);
+                    sfor<C::NKB5 / 2>(drain4);
+                }
+                store_pass<C::P5, RP>(pk, TY, act, C::ACT_STRIDE, lane);
+                __syncthreads();
+                if (C::W == CT5 || wave < CT5) {
+                    mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>>(
+                        out, w4, 0, act, C::ACT_STRIDE, wave, lane, [](auto) {});
+                    const int sn = wave * 32 + (lane & 31);
+                    if (lane < 32) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
+                    } else {
+                        emit(4, sn, out[0][0][0]);
+                    }
                 }
                 __syncthreads();
                 continue;
@@ -677,8 +812,9 @@ __global__ __launch_bounds__(256, 1) void mlp_ode_kernel(MlpParams p)
 template <int MP, int H>
 hipError_t launch_one(const MlpParams &p, int grid, hipStream_t s)
 {
-    if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1>), dim3(grid), dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0>), dim3(grid), dim3(256), 0, s, p);
+    constexpr int threads = Cfg<MP, H>::THREADS;
+    if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1>), dim3(grid), dim3(threads), 0, s, p);
+    else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0>), dim3(grid), dim3(threads), 0, s, p);
     return hipGetLastError();
 }
 

@@ -3,8 +3,9 @@ exit-angle / path-length law of GMC and MC; "Network Architecture and Inputs" fo
 
 A learned approximation cannot match the exit law sample by sample -- this comparison is
 "parity unpinned": the reference is the FP64 oracle's analog walk (mode C) at the same entry
-condition, and the budgets below are the fitted model's measured distances (K = 32 Euler steps,
-BF16) plus statistical noise, so a model or sampler regression fails them.  Thin cells are not
+condition, and the budgets below are the fitted model's measured distances (BF16; K = 32 Euler
+steps, and the paper's classic RK4 with 12 steps) plus statistical noise, so a model or sampler
+regression fails them.  Thin cells are not
 tested here: their exit law has an uncollided atom the flow can only smear.
 """
 import math
@@ -77,3 +78,41 @@ def test_mean_path_length_invariance(trained):
     rel = abs(g["path"].mean() - math.pi / 4) / (math.pi / 4)
     print(f"E[path] = {g['path'].mean():.4f}, pi/4 = {math.pi / 4:.4f}")
     assert rel < 0.06
+
+
+@pytest.mark.parametrize("tau,c,y,s", [(10.0, 1.0, 0.3, 0.5), (100.0, 1.0, 0.5, -0.3),
+                                       (30.0, 0.95, 0.9, -0.8)])
+def test_rk4_exit_law_matches_the_walk(orc, trained, tau, c, y, s):
+    # the paper's integrator (classic RK4, 12 steps): measured face TV <= 0.004, KS cos / ln l
+    # <= 0.01, KS pos <= 0.07 (the position law is the loosest fit of this model)
+    binding, m = trained
+    n_g, n_o = 100_000, 50_000
+    g = binding.gmc_sample(m, binding.DeviceCond.from_host(_fixed(n_g, tau, c, y, s)), "rk4", 12,
+                           5).to_host()
+    o = orc.mc_transmit(_fixed(n_o, tau, c, y, s), 0, seed=17, nthreads=8)
+    fg = np.bincount(g["face"], minlength=4) / n_g
+    fo = np.bincount(o["face"], minlength=4) / n_o
+    tv_face = 0.5 * np.abs(fg - fo).sum()
+    ks_cos = stats.ks_2samp(g["dir_cos"], o["u"]).statistic
+    ks_len = stats.ks_2samp(np.log(g["path"]), np.log(o["len"])).statistic
+    ks_pos = stats.ks_2samp(g["pos"] + g["face"], o["pos"] + o["face"]).statistic
+    print(f"rk4x12 tau={tau} c={c}: face TV {tv_face:.4f}, KS pos {ks_pos:.4f} cos {ks_cos:.4f} "
+          f"ln l {ks_len:.4f}")
+    assert tv_face < 0.02
+    assert ks_cos < 0.03 and ks_len < 0.03 and ks_pos < 0.1
+
+
+def test_rk4_removes_the_euler_path_length_bias(trained):
+    # P3 (E[path] = pi / 4 at c = 1 for every tau): explicit Euler at K = 32 undershoots long
+    # diffusive paths (measured 0.66 at tau = 100); RK4 with 12 steps holds it within 1.5 %
+    # at tau = 1, 10 and 100 (measured <= 0.4 %)
+    binding, m = trained
+    for tau in (1.0, 10.0, 100.0):
+        cond = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(200_000, tau, 1.0, seed=3))
+        g = binding.gmc_sample(m, cond, "rk4", 12, 9).to_host()
+        rel = abs(g["path"].mean() - math.pi / 4) / (math.pi / 4)
+        print(f"rk4x12 tau={tau}: E[path] = {g['path'].mean():.4f}")
+        assert rel < 0.015
+    cond = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(200_000, 100.0, 1.0, seed=3))
+    e = binding.gmc_transmit(m, cond, 32, 9).to_host()
+    assert abs(e["path"].mean() - math.pi / 4) / (math.pi / 4) > 0.1
