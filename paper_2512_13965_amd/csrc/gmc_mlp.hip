@@ -49,6 +49,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 using Rsrc = __amdgpu_buffer_rsrc_t;
 
@@ -532,12 +533,15 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
         }
         __syncthreads();
 
+        // Two-group Euler: the layer-5 lanes apply the step and write the next input row
+        // themselves, so the input row is assembled here only for the first evaluation.
+        constexpr bool fold = C::GROUPS && !rk4;
         for (int e = 0; e < nevals; ++e) {
             const int stage = rk4 ? (e & 3) : 0;
             const int k = rk4 ? (e >> 2) : e;
             const float t = ((float)k + (stage == 0 ? 0.0f : (stage == 3 ? 1.0f : 0.5f))) * dt;
             // layer-1 input row of sample tid: [x0..x4, t, ln tau, c, 2y-1, sin th, 0 x 6]
-            if (tid < kTileM) {
+            if ((!fold || e == 0) && tid < kTileM) {
                 float v[16];
                 if (!rk4 || e == 0) {
 #pragma unroll
@@ -563,7 +567,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                                   pack_bf16(v[8 * q + 4], v[8 * q + 5]), pack_bf16(v[8 * q + 6], v[8 * q + 7])};
                 }
             }
-            __syncthreads();
+            if (!fold || e == 0) __syncthreads();
 
             if constexpr (C::GROUPS) {
                 // Two-group schedule.  Per hidden layer, three barrier-separated phases:
@@ -650,7 +654,23 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>, 0, SW5>(
                         out, w4, 0, act, C::ACT_STRIDE, wg, lane, [](auto) {});
                     const int sn = wg * 32 + (lane & 31);
-                    if (lane < 32) {
+                    if constexpr (fold) {
+                        // x += dt v, then the next input row's x (and t) in BF16
+                        char *row = in0 + sn * C::IN_STRIDE;
+                        if (lane < 32) {
+                            float x[4];
+#pragma unroll
+                            for (int d = 0; d < 4; ++d) {
+                                x[d] = xs[d * kTileM + sn] + out[0][0][d] * dt;
+                                xs[d * kTileM + sn] = x[d];
+                            }
+                            *(u32x2 *)row = u32x2{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3])};
+                        } else {
+                            const float x4 = xs[4 * kTileM + sn] + out[0][0][0] * dt;
+                            xs[4 * kTileM + sn] = x4;
+                            *(uint32_t *)(row + 8) = pack_bf16(x4, (float)(e + 1) * dt);
+                        }
+                    } else if (lane < 32) {
 #pragma unroll
                         for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
                     } else {
