@@ -10,14 +10,17 @@ inputs resident in HBM.
 Beside the timed steps the same run measures, with HIP events on the launch stream:
   * the analog random-walk kernel that the sampler replaces, on 2^20 transmissions per
     optical thickness tau = 1 .. 100 (c = 1, pure scattering) and the GMC/analog ratio;
-  * the width-512 sampler in BF16 and FP8 (2^20 transmissions, K = 8 / 16 / 32);
+  * the width-512 sampler in BF16 and FP8 (2^20 transmissions, Euler K = 8 / 16 / 32 and
+    classic RK4 with 12 steps);
   * the FP64 CPU oracle on a bounded sample of the same workload (cpu_baseline).
 Prints ONE JSON line.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
+import re
 import math
 import os
 import sys
@@ -31,6 +34,31 @@ sys.path.insert(0, ROOT)
 METRIC = "cell transmissions/sec GMC vs analog MC at tau=1..100; p50/p99 request latency"
 TAUS = [1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0]
 PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
+KERNEL_SOURCES = ["gmc_mlp.hip", "gmc_device.hpp", "gmc_internal.hpp"]
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mlp_ode_fp32_h256_k16_b65536.md")
+
+
+def kernel_source_hash() -> str:
+    """SHA-256 over the sources the sampler kernel is built from."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2512_13965_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the headline kernel from the committed counter summary, or None
+    when the kernel sources changed since those counters were taken."""
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    m_hash = re.search(r"traffic_source_sha256:\s*([0-9a-f]{64})", text)
+    m_bytes = re.search(r"traffic_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m_hash or not m_bytes or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_bytes.group(1))
 
 
 def flops_per_sample(H: int, K: int) -> float:
@@ -172,7 +200,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving stream")
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: fp32 | bf16 | fp8 (sampler, "
-                         "H=256 / 512 / 512) or walk:TAU (analog, 2^20 transmissions)")
+                         "H=256 / 512 / 512, Euler K=16), rk4 (BF16 H=512, RK4 x 12) or "
+                         "walk:TAU (analog, 2^20 transmissions)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -181,14 +210,15 @@ def main():
         import torch
         from paper_2512_13965_amd import binding, inputs
         kind, prec, H, K, N = args.profile.split(":")[0], None, 512, 16, 1 << 20
-        if kind in ("fp32", "bf16", "fp8"):
-            prec, H = kind, (256 if kind == "fp32" else 512)
+        if kind in ("fp32", "bf16", "fp8", "rk4"):
+            prec, H = ("bf16" if kind == "rk4" else kind), (256 if kind == "fp32" else 512)
+            integ, K = ("rk4", 12) if kind == "rk4" else ("euler", K)
             N = 65536 if kind == "fp32" else N
             m = binding.Model(inputs.pack_blob(inputs.random_weights(H, 1)), prec)
             c = binding.DeviceCond.from_host(inputs.transmission_conditions(N, 3))
             o = binding.DeviceExit.empty(N)
             for _ in range(args.steps):
-                binding.gmc_transmit(m, c, K, 2, 0, out=o)
+                binding.gmc_sample(m, c, integ, K, 2, 0, out=o)
         else:
             tau = float(args.profile.split(":")[1]) if ":" in args.profile else 100.0
             c = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(N, tau, 1.0, 9))
@@ -254,7 +284,7 @@ def main():
                                "seeded random-init weights, Philox noise",
                    "hidden": H, "K": K, "batch": N, "precision": "fp32"},
         "roofline": {"bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK["f32"] / 1e12,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK["f32"], "traffic": measured_traffic(),
                      "kernel": "mlp_ode_kernel<fp32,256>", "avg_launch_ms": float(kms.mean())},
         "launch_ms_p50": float(np.median(kms)), "launch_ms_p99": float(np.quantile(kms, 0.99)),
     }
