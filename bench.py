@@ -167,8 +167,9 @@ def bench_serving(binding, inputs, w512, n_req):
     world = binding.World(1 << 20, 16, 1 << 18)
     make = lambda i: inputs.random_problem(1000 + i, hist_log10_range=(4.0, 5.5))
 
-    def serve(reqs):
-        return serving.Server(world, binding.SAMPLER_GMC, model, K=16,
+    def serve(reqs, graphs=True):
+        world.set_graphs(graphs)
+        return serving.Server(world, binding.SAMPLER_GMC, model, K=16, graphs=graphs,
                               cell_budget=(1 << 18) * serving.CELL_BYTES).run(reqs)
 
     # capacity: a burst of 48 requests all arriving at t = 0
@@ -177,6 +178,8 @@ def bench_serving(binding, inputs, w512, n_req):
     capacity_hz = len(cap.requests) / cap.wall
     rate = 0.7 * capacity_hz
     st = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make))
+    # the same stream with direct kernel launches instead of the captured per-bucket step graphs
+    direct = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make), graphs=False)
     model.close()
     world.close()
     lat = st.latency_percentiles((50, 90, 99))
@@ -184,6 +187,9 @@ def bench_serving(binding, inputs, w512, n_req):
             "arrival_rate_hz": rate, "wall_s": st.wall, "steps": st.steps,
             "transmissions": st.transmissions, "transmissions_per_s": st.throughput,
             "latency_s": lat, "histories": int(sum(r.n_hist for r in st.requests)),
+            "step_graphs": "captured per power-of-two particle-count bucket",
+            "direct_launches": {"latency_s": direct.latency_percentiles((50, 90, 99)),
+                                "transmissions_per_s": direct.throughput, "wall_s": direct.wall},
             "workload": "Poisson stream at 70% of the measured capacity; grids 16^2-128^2, "
                         "tau log-U[0.1,200], c U[0,1], 1e4-10^5.5 histories/request, "
                         "GMC BF16 H=512 K=16 trained weights"}

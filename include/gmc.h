@@ -199,6 +199,14 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
 /* Integrator (GMC_EULER, the default, or GMC_RK4) that later gmc_transport_step calls with the
  * generative sampler use; K then counts integration steps.  GMC_EINVAL otherwise. */
 int gmc_world_set_integrator(gmc_world *w, int integrator);
+/* enable != 0: later gmc_transport_step calls replay a HIP graph of the step (gather, sampler,
+ * counter reset, apply) captured once per (sampler, model, K, integrator, bank parity) and per
+ * particle-count bucket (the next power of two >= 1024, capped at the bank capacity); the captured
+ * kernels read the particle count from the device, so one graph serves every count in its bucket.
+ * Graphs are captured on a stream the world owns and replayed on the caller's stream; they are
+ * released with the world.  Results equal those of the uncaptured step (FP64 tallies up to the
+ * order of their atomic additions).  enable = 0 returns to direct launches. */
+int gmc_world_set_graphs(gmc_world *w, int enable);
 /* Particles of problem pid still in flight after the last step or injection. */
 int gmc_problem_alive(const gmc_world *w, int32_t pid, int64_t *n_alive);
 /* Copies problem pid's FP64 tallies, summed over its histories so far, to host arrays of

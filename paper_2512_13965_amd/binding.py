@@ -249,7 +249,8 @@ def _transport_sigs(L):
     L.gmc_problem_alive.argtypes = [P, I32, ctypes.POINTER(I64)]
     L.gmc_problem_tally.argtypes = [P, I32, P, P, P, P, P]
     L.gmc_world_set_integrator.argtypes = [P, I]
-    for name in ("gmc_world_set_integrator", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
+    L.gmc_world_set_graphs.argtypes = [P, I]
+    for name in ("gmc_world_set_integrator", "gmc_world_set_graphs", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
                  "gmc_problem_remove", "gmc_world_inject", "gmc_transport_step",
                  "gmc_problem_alive", "gmc_problem_tally"):
         getattr(L, name).restype = ctypes.c_int
@@ -301,6 +302,10 @@ class World:
         if integrator not in INTEGRATORS:
             raise ValueError(f"integrator must be one of {sorted(INTEGRATORS)}")
         _check(self._L.gmc_world_set_integrator(self._h, INTEGRATORS[integrator]))
+
+    def set_graphs(self, enable: bool = True):
+        """Replay captured HIP graphs of the transport step per particle-count bucket."""
+        _check(self._L.gmc_world_set_graphs(self._h, 1 if enable else 0))
 
     def step(self, sampler: int, model: Model | None = None, K: int = 16, stream=None) -> int:
         n = ctypes.c_int64()

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -172,6 +173,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     std::vector<std::vector<uint8_t>> frag(5);
     std::vector<std::vector<float>> bias(5);
     gmc_model *m = new gmc_model();
+    static std::atomic<uint64_t> next_serial{1};
+    m->serial = next_serial++;
     m->precision = precision;
     m->hidden = H;
     for (int l = 0; l < 5; ++l) {

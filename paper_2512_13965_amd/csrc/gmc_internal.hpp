@@ -67,7 +67,8 @@ struct MlpParams {
     const uint64_t *keys;     // optional per-sample Philox keys (else seed)
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
-    int64_t n;
+    int64_t n;                // samples (also the row stride of noise / raw)
+    const unsigned long long *n_dev;   // optional: sample count read on the device (<= n)
     int K;                    // integration steps
     int integrator;           // 0 explicit Euler, 1 classic RK4 (4 evaluations per step)
     uint64_t seed, id_base;
@@ -84,6 +85,7 @@ struct WalkParams {
     const uint64_t *ids;      // optional per-particle random stream ids (else id_base + i)
     const uint64_t *keys;     // optional per-particle Philox keys (else seed)
     int64_t n;
+    const unsigned long long *n_dev;   // optional: particle count read on the device (<= n)
     int mode;
     uint64_t seed, id_base;
     unsigned long long *queue;  // device work counter, zeroed by the launcher
@@ -103,6 +105,7 @@ int set_hip_error(hipError_t e, const char *what);
 }  // namespace gmc
 
 struct gmc_model {
+    uint64_t serial = 0;     // unique per created model (keys captured launches)
     int precision = 0;
     int hidden = 0;
     int device = 0;

@@ -476,7 +476,10 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int64_t ntiles = (p.n + kTileM - 1) / kTileM;
+    // samples to process: the launch's own count, or one the device holds (a captured graph
+    // sized for a bucket of counts); noise and raw keep the row stride p.n
+    const int64_t n_items = p.n_dev ? (int64_t)*p.n_dev : p.n;
+    const int64_t ntiles = (n_items + kTileM - 1) / kTileM;
     const float dt = 1.0f / (float)p.K;
     constexpr bool rk4 = (RK == 1);
     const int nevals = rk4 ? 4 * p.K : p.K;
@@ -512,7 +515,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             const int64_t i = base + tid;
             float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
             float lt = 0.f, cc = 0.f, yy = 0.5f, ss = 0.f;
-            if (i < p.n) {
+            if (i < n_items) {
                 lt = p.log_tau[i];
                 cc = p.c[i];
                 yy = p.y_in[i];
@@ -807,7 +810,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
 #pragma unroll
                 for (int d = 0; d < 5; ++d) xk[d] = xs[d * kTileM + tid];
             }
-            if (i < p.n) {
+            if (i < n_items) {
                 const float a0 = xk[0], a1 = xk[1], a2 = xk[2], a3 = xk[3], a4 = xk[4];
                 if (p.raw) {
                     p.raw[0 * p.n + i] = a0;

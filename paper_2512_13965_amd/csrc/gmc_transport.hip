@@ -196,10 +196,12 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
 
 // Stage 1: canonical conditions of every alive particle.  Entry face e maps to the canonical
 // left face by the rotation of k = (e + 1) mod 4 quarter turns (canonical -> local).
-__global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n, CellsDev cd,
+__global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
+                                                     const unsigned long long *n_dev, CellsDev cd,
                                                      float *ltau, float *cc, float *yin, float *sth,
                                                      uint64_t *ids, uint64_t *keys)
 {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int cell = b.cell[i];
@@ -215,13 +217,15 @@ __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n, Cells
 }
 
 // Stages 3-4 for every alive particle, survivors compacted into `out`.
-__global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n, const int32_t *face_c,
+__global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
+                                                    const unsigned long long *n_dev, const int32_t *face_c,
                                                     const float *pos, const float *dcos,
                                                     const float *dsin, const float *path,
                                                     CellsDev cd, BankDev out,
                                                     unsigned long long *counter,
                                                     unsigned long long *pcount)
 {
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool alive = false;
     Next nx{};
@@ -285,6 +289,18 @@ struct gmc_world {
     ProblemDev *prob = nullptr;
     unsigned long long *counters = nullptr;   // [2][1 + max_problems]: n_alive, per-problem
     unsigned long long *host_counters = nullptr;
+    unsigned long long *queue = nullptr;      // the analog walk's work counter (this world's own)
+    // captured transport steps, one per (sampler, model, K, integrator, bank parity, bucket)
+    struct StepGraph {
+        int sampler, K, integrator, cur;
+        uint64_t model;        // serial of the model (0 for the analog walk)
+        int64_t bucket;
+        hipGraph_t graph;
+        hipGraphExec_t exec;
+    };
+    bool graphs = false;
+    hipStream_t capture_stream = nullptr;
+    std::vector<StepGraph> step_graphs;
     // host bookkeeping
     int64_t n_alive = 0;
     std::vector<int64_t> alive_pp;
@@ -344,6 +360,7 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->cutoff, 8 * N);
     L.add((void **)&w->prob, sizeof(ProblemDev) * P);
     L.add((void **)&w->counters, 8 * 2 * (1 + P));
+    L.add((void **)&w->queue, 8);
 }
 
 int sync_counters(gmc_world *w, int which, hipStream_t s)
@@ -419,6 +436,11 @@ int gmc_world_destroy(gmc_world *w)
 {
     if (!w) return set_error(GMC_EINVAL, "gmc_world_destroy: null world");
     hipError_t e1 = hipSuccess, e2 = hipSuccess;
+    for (auto &g : w->step_graphs) {
+        (void)hipGraphExecDestroy(g.exec);
+        (void)hipGraphDestroy(g.graph);
+    }
+    if (w->capture_stream) (void)hipStreamDestroy(w->capture_stream);
     if (w->host_counters) e1 = hipHostFree(w->host_counters);
     if (w->mem) e2 = hipFree(w->mem);
     delete w;
@@ -542,6 +564,136 @@ int gmc_world_set_integrator(gmc_world *w, int integrator)
     return GMC_OK;
 }
 
+int gmc_world_set_graphs(gmc_world *w, int enable)
+{
+    if (!w) return set_error(GMC_EINVAL, "gmc_world_set_graphs: null world");
+    std::lock_guard<std::mutex> lk(w->mu);
+    if (enable && !w->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&w->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            w->capture_stream = nullptr;
+            return set_hip_error(e, "gmc_world_set_graphs: capture stream");
+        }
+    }
+    w->graphs = enable != 0;
+    return GMC_OK;
+}
+
+namespace {
+
+// Enqueue one transport step on `s`: gather, sampler, counter reset, apply.  Grids are sized for
+// `n_launch` particles; the kernels process n_dev[0] of them when n_dev is given (a captured step
+// serves every count up to its bucket), else n_launch.
+int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream_t s, int64_t n_launch,
+                 const unsigned long long *n_dev)
+{
+    const int cur = w->cur, nxt = 1 - cur;
+    hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
+                       n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->ids, w->keys);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: gather");
+    const int cu = device_cu_count();
+    if (cu <= 0) return set_error(GMC_EDEVICE, "gmc_transport_step: cannot query the device");
+    if (sampler == GMC_SAMPLER_GMC) {
+        MlpParams p = m->tmpl;
+        p.log_tau = w->c_ltau;
+        p.c = w->c_c;
+        p.y_in = w->c_yin;
+        p.sin_th = w->c_sth;
+        p.noise = nullptr;
+        p.raw = nullptr;
+        p.ids = w->ids;
+        p.keys = w->keys;
+        p.face = w->e_face;
+        p.pos = w->e_pos;
+        p.dcos = w->e_dcos;
+        p.dsin = w->e_dsin;
+        p.path = w->e_path;
+        p.n = n_launch;
+        p.n_dev = n_dev;
+        p.K = K;
+        p.integrator = w->integrator;
+        p.seed = 0;
+        p.id_base = 0;
+        const int64_t ntiles = (n_launch + kTileM - 1) / kTileM;
+        e = launch_mlp_ode(m->precision, m->hidden, p, (int)std::min<int64_t>(ntiles, cu), s);
+    } else {
+        WalkParams p{};
+        p.log_tau = w->c_ltau;
+        p.c = w->c_c;
+        p.y_in = w->c_yin;
+        p.sin_th = w->c_sth;
+        p.face = w->e_face;
+        p.pos = w->e_pos;
+        p.dcos = w->e_dcos;
+        p.dsin = w->e_dsin;
+        p.path = w->e_path;
+        p.ncoll = nullptr;
+        p.ids = w->ids;
+        p.keys = w->keys;
+        p.n = n_launch;
+        p.n_dev = n_dev;
+        p.mode = GMC_MODE_CONTINUOUS;
+        p.queue = w->queue;
+        e = launch_walk(p, (int)std::min<int64_t>((n_launch + 255) / 256, (int64_t)cu * 8), s);
+    }
+    if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: sampler");
+    unsigned long long *ctr = w->cnt(nxt);
+    hipLaunchKernelGGL(set_u64_kernel, dim3(blocks_for(1 + w->max_problems)), dim3(256), 0, s,
+                       ctr, 0ull, 1 + w->max_problems);
+    hipLaunchKernelGGL(apply_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
+                       n_dev, w->e_face, w->e_pos, w->e_dcos, w->e_dsin, w->e_path, w->cells(),
+                       w->bank[nxt], ctr, ctr + 1);
+    e = hipGetLastError();
+    if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: apply");
+    return GMC_OK;
+}
+
+// Bucket of a particle count: the next power of two (at least 1024), capped at the capacity.
+int64_t step_bucket(const gmc_world *w, int64_t n)
+{
+    int64_t b = 1024;
+    while (b < n) b <<= 1;
+    return std::min<int64_t>(b, w->cap);
+}
+
+// The captured step for this configuration and bucket, captured (and instantiated) on first use.
+// The captured kernels read the particle count from the current bank's device counter.
+int step_graph(gmc_world *w, int sampler, const gmc_model *m, int K, int64_t bucket, hipGraphExec_t *exec)
+{
+    const int integ = (sampler == GMC_SAMPLER_GMC) ? w->integrator : 0;
+    const uint64_t mm = (sampler == GMC_SAMPLER_GMC) ? m->serial : 0;
+    const int KK = (sampler == GMC_SAMPLER_GMC) ? K : 0;
+    for (auto &g : w->step_graphs)
+        if (g.sampler == sampler && g.model == mm && g.K == KK && g.integrator == integ && g.cur == w->cur &&
+            g.bucket == bucket) {
+            *exec = g.exec;
+            return GMC_OK;
+        }
+    hipStream_t cs = w->capture_stream;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: begin capture");
+    const int rc = enqueue_step(w, sampler, m, K, cs, bucket, w->cnt(w->cur));
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cs, &graph);
+    if (rc != GMC_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return rc;
+    }
+    if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: end capture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return set_hip_error(e, "gmc_transport_step: instantiate");
+    }
+    w->step_graphs.push_back({sampler, KK, integ, w->cur, mm, bucket, graph, x});
+    *exec = x;
+    return GMC_OK;
+}
+
+}  // namespace
+
 int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
                        int64_t *n_alive_out)
 {
@@ -553,66 +705,20 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = w->n_alive;
     if (n > 0) {
-        const int cur = w->cur, nxt = 1 - cur;
-        hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n)), dim3(256), 0, s, w->bank[cur], n,
-                           w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->ids, w->keys);
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: gather");
-        const int cu = device_cu_count();
-        if (cu <= 0) return set_error(GMC_EDEVICE, "gmc_transport_step: cannot query the device");
-        if (sampler == GMC_SAMPLER_GMC) {
-            MlpParams p = m->tmpl;
-            p.log_tau = w->c_ltau;
-            p.c = w->c_c;
-            p.y_in = w->c_yin;
-            p.sin_th = w->c_sth;
-            p.noise = nullptr;
-            p.raw = nullptr;
-            p.ids = w->ids;
-            p.keys = w->keys;
-            p.face = w->e_face;
-            p.pos = w->e_pos;
-            p.dcos = w->e_dcos;
-            p.dsin = w->e_dsin;
-            p.path = w->e_path;
-            p.n = n;
-            p.K = K;
-            p.integrator = w->integrator;
-            p.seed = 0;
-            p.id_base = 0;
-            const int64_t ntiles = (n + kTileM - 1) / kTileM;
-            e = launch_mlp_ode(m->precision, m->hidden, p, (int)std::min<int64_t>(ntiles, cu), s);
+        int rc;
+        if (w->graphs) {
+            hipGraphExec_t x = nullptr;
+            rc = step_graph(w, sampler, m, K, step_bucket(w, n), &x);
+            if (rc != GMC_OK) return rc;
+            const hipError_t e = hipGraphLaunch(x, s);
+            if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: graph launch");
         } else {
-            WalkParams p{};
-            p.log_tau = w->c_ltau;
-            p.c = w->c_c;
-            p.y_in = w->c_yin;
-            p.sin_th = w->c_sth;
-            p.face = w->e_face;
-            p.pos = w->e_pos;
-            p.dcos = w->e_dcos;
-            p.dsin = w->e_dsin;
-            p.path = w->e_path;
-            p.ncoll = nullptr;
-            p.ids = w->ids;
-            p.keys = w->keys;
-            p.n = n;
-            p.mode = GMC_MODE_CONTINUOUS;
-            p.queue = device_queue_counter();
-            if (!p.queue) return set_error(GMC_ENOMEM, "gmc_transport_step: work counter");
-            e = launch_walk(p, (int)std::min<int64_t>((n + 255) / 256, (int64_t)cu * 8), s);
+            rc = enqueue_step(w, sampler, m, K, s, n, nullptr);
+            if (rc != GMC_OK) return rc;
         }
-        if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: sampler");
-        unsigned long long *ctr = w->cnt(nxt);
-        hipLaunchKernelGGL(set_u64_kernel, dim3(blocks_for(1 + w->max_problems)), dim3(256), 0, s,
-                           ctr, 0ull, 1 + w->max_problems);
-        hipLaunchKernelGGL(apply_kernel, dim3(blocks_for(n)), dim3(256), 0, s, w->bank[cur], n,
-                           w->e_face, w->e_pos, w->e_dcos, w->e_dsin, w->e_path, w->cells(),
-                           w->bank[nxt], ctr, ctr + 1);
-        e = hipGetLastError();
-        if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: apply");
+        const int nxt = 1 - w->cur;
         w->cur = nxt;
-        const int rc = sync_counters(w, nxt, s);
+        rc = sync_counters(w, nxt, s);
         if (rc != GMC_OK) return rc;
     }
     if (n_alive_out) *n_alive_out = w->n_alive;

@@ -27,6 +27,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
     uint64_t key = p.seed, stream = 0;
     Walker w;
     walker_init(w, 0.0f, 0.0f, 0, 0.0f, 0.0f, 1.0f, 0.0f);
+    const int64_t n = p.n_dev ? (int64_t)*p.n_dev : p.n;
 
     for (;;) {
         const bool need = !alive && !exhausted;
@@ -39,7 +40,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
             const unsigned long long base = (unsigned long long)__shfl((long long)b, leader);
             if (need) {
                 const int64_t i = (int64_t)(base + (unsigned long long)lane_rank(needmask));
-                if (i < p.n) {
+                if (i < n) {
                     idx = i;
                     const float s = p.sin_th[i];
                     walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, 0.0f, p.y_in[i],
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
                     alive = true;
                 }
             }
-            if (base + (unsigned long long)cnt >= (unsigned long long)p.n) exhausted = true;
+            if (base + (unsigned long long)cnt >= (unsigned long long)n) exhausted = true;
         }
         if (!__ballot(alive)) {
             if (exhausted) break;

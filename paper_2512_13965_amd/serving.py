@@ -74,8 +74,11 @@ class Server:
     add_problem / inject / step / alive / tally / remove / capacity interface)."""
 
     def __init__(self, world, sampler: int, model=None, K: int = 16, cell_budget: int | None = None,
-                 chunk: int | None = None, clock=time.perf_counter, sleep=time.sleep):
+                 chunk: int | None = None, clock=time.perf_counter, sleep=time.sleep,
+                 graphs: bool = True):
         self.world = world
+        if graphs and hasattr(world, "set_graphs"):
+            world.set_graphs(True)      # replay captured steps per batch-size bucket
         self.sampler, self.model, self.K = sampler, model, K
         self.cell_budget = cell_budget            # bytes of cell pool usable by requests
         self.chunk = chunk or max(1, world.capacity // 4)
