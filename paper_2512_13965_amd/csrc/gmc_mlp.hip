@@ -30,6 +30,12 @@
 #ifndef GMC_VPM_5
 #define GMC_VPM_5 0
 #endif
+#ifndef GMC_DRAIN_STAGED
+#define GMC_DRAIN_STAGED 1
+#endif
+#ifndef GMC_DRAIN_W
+#define GMC_DRAIN_W 16
+#endif
 #ifndef GMC_PFA
 #define GMC_PFA 2
 #endif
@@ -597,8 +603,44 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     sfor<RG * 4>([&](auto TC) {
                         constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
                         uint32_t wd[4 * WPU];
+#if GMC_DRAIN_STAGED
+                        // the same operations as epi_unit, issued stage by stage over 8 values so
+                        // that independent transcendentals follow each other
+                        constexpr int DW = GMC_DRAIN_W;
+                        sfor<16 / DW>([&](auto HH) {
+                            constexpr int h0 = decltype(HH)::value * DW;
+                            float a[DW], t[DW];
+#pragma unroll
+                            for (int i = 0; i < DW; ++i) {
+                                a[i] = C::SCALE ? acc[r][c][h0 + i] * osc : acc[r][c][h0 + i];
+                                t[i] = -1.4426950408889634f * a[i];
+                            }
+                            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                            for (int i = 0; i < DW; ++i) t[i] = __builtin_amdgcn_exp2f(t[i]);
+                            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                            for (int i = 0; i < DW; ++i) t[i] = __builtin_amdgcn_rcpf(1.0f + t[i]);
+                            __builtin_amdgcn_sched_barrier(0);
+                            float y[DW];
+#pragma unroll
+                            for (int i = 0; i < DW; ++i) y[i] = C::SCALE ? (a[i] * t[i]) * inv : a[i] * t[i];
+                            if constexpr (PO == kF32) {
+#pragma unroll
+                                for (int i = 0; i < DW; ++i) wd[h0 + i] = __builtin_bit_cast(uint32_t, y[i]);
+                            } else if constexpr (PO == kBF16) {
+#pragma unroll
+                                for (int i = 0; i < DW / 2; ++i) wd[h0 / 2 + i] = pack_bf16(y[2 * i], y[2 * i + 1]);
+                            } else {
+#pragma unroll
+                                for (int i = 0; i < DW / 4; ++i)
+                                    wd[h0 / 4 + i] = pack_fp8x4(y[4 * i], y[4 * i + 1], y[4 * i + 2], y[4 * i + 3]);
+                            }
+                        });
+#else
 #pragma unroll
                         for (int g = 0; g < 4; ++g) epi_unit<PO, C::SCALE>(acc[r][c], g, osc, inv, &wd[g * WPU]);
+#endif
                         store_tile<PO>(wd, (TB + r) ^ xt, c, act, C::ACT_STRIDE, lane);
                     });
                 };
