@@ -253,6 +253,49 @@ __device__ __forceinline__ void epi_unit(const f32x16 &acc, int g, float oscale,
     }
 }
 
+// The epilogue of a whole accumulator tile (16 values per lane): the operations of epi_unit,
+// issued stage by stage over DW values so that independent transcendentals follow each other.
+template <int PO, bool SCALE>
+__device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float inv_next, uint32_t *w)
+{
+#if GMC_DRAIN_STAGED
+    constexpr int DW = GMC_DRAIN_W;
+    sfor<16 / DW>([&](auto HH) {
+        constexpr int h0 = decltype(HH)::value * DW;
+        float a[DW], t[DW];
+#pragma unroll
+        for (int i = 0; i < DW; ++i) {
+            a[i] = SCALE ? acc[h0 + i] * oscale : acc[h0 + i];
+            t[i] = -1.4426950408889634f * a[i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < DW; ++i) t[i] = __builtin_amdgcn_exp2f(t[i]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < DW; ++i) t[i] = __builtin_amdgcn_rcpf(1.0f + t[i]);
+        __builtin_amdgcn_sched_barrier(0);
+        float y[DW];
+#pragma unroll
+        for (int i = 0; i < DW; ++i) y[i] = SCALE ? (a[i] * t[i]) * inv_next : a[i] * t[i];
+        if constexpr (PO == kF32) {
+#pragma unroll
+            for (int i = 0; i < DW; ++i) w[h0 + i] = __builtin_bit_cast(uint32_t, y[i]);
+        } else if constexpr (PO == kBF16) {
+#pragma unroll
+            for (int i = 0; i < DW / 2; ++i) w[h0 / 2 + i] = pack_bf16(y[2 * i], y[2 * i + 1]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < DW / 4; ++i) w[h0 / 4 + i] = pack_fp8x4(y[4 * i], y[4 * i + 1], y[4 * i + 2], y[4 * i + 3]);
+        }
+    });
+#else
+    constexpr int WPU = words_per_unit(PO);
+#pragma unroll
+    for (int g = 0; g < 4; ++g) epi_unit<PO, SCALE>(acc, g, oscale, inv_next, &w[g * WPU]);
+#endif
+}
+
 // Store the packed epilogue of accumulator tile (row tile T, column tile c) into the LDS
 // activation tile in the column order that a consumer with operand precision PO reads
 // (see phys_to_feature()).
@@ -597,59 +640,57 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 const int grp = wave >> 2, wg = wave & 3;
                 const int TB = grp * (C::NT / 2) + wg * RG;       // first row tile of this wave
                 f32x16 acc[RG][4];
+                // SiLU epilogue of accumulator tiles a[r][c] (row tile T0 + r, column tile c0 + c)
+                // into the activation tile, row tile index xor xt
+                auto drain_tiles = [&](auto POC, auto &a, int T0, int c0, float osc, float inv, int xt) {
+                    constexpr int PO = decltype(POC)::value;
+                    using A = std::remove_reference_t<decltype(a)>;
+                    constexpr int RX = std::extent_v<A, 0>, CX = std::extent_v<A, 1>;
+                    sfor<RX * CX>([&](auto TC) {
+                        constexpr int r = decltype(TC)::value / CX, c = decltype(TC)::value % CX;
+                        uint32_t wd[4 * words_per_unit(PO)];
+                        epi_tile<PO, C::SCALE>(a[r][c], osc, inv, wd);
+                        store_tile<PO>(wd, (T0 + r) ^ xt, c0 + c, act, C::ACT_STRIDE, lane);
+                    });
+                };
                 auto drain = [&](auto POC, float osc, float inv, int xt = 0) {
                     constexpr int PO = decltype(POC)::value;
                     constexpr int WPU = words_per_unit(PO);
                     sfor<RG * 4>([&](auto TC) {
                         constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
                         uint32_t wd[4 * WPU];
-#if GMC_DRAIN_STAGED
-                        // the same operations as epi_unit, issued stage by stage over 8 values so
-                        // that independent transcendentals follow each other
-                        constexpr int DW = GMC_DRAIN_W;
-                        sfor<16 / DW>([&](auto HH) {
-                            constexpr int h0 = decltype(HH)::value * DW;
-                            float a[DW], t[DW];
-#pragma unroll
-                            for (int i = 0; i < DW; ++i) {
-                                a[i] = C::SCALE ? acc[r][c][h0 + i] * osc : acc[r][c][h0 + i];
-                                t[i] = -1.4426950408889634f * a[i];
-                            }
-                            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                            for (int i = 0; i < DW; ++i) t[i] = __builtin_amdgcn_exp2f(t[i]);
-                            __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                            for (int i = 0; i < DW; ++i) t[i] = __builtin_amdgcn_rcpf(1.0f + t[i]);
-                            __builtin_amdgcn_sched_barrier(0);
-                            float y[DW];
-#pragma unroll
-                            for (int i = 0; i < DW; ++i) y[i] = C::SCALE ? (a[i] * t[i]) * inv : a[i] * t[i];
-                            if constexpr (PO == kF32) {
-#pragma unroll
-                                for (int i = 0; i < DW; ++i) wd[h0 + i] = __builtin_bit_cast(uint32_t, y[i]);
-                            } else if constexpr (PO == kBF16) {
-#pragma unroll
-                                for (int i = 0; i < DW / 2; ++i) wd[h0 / 2 + i] = pack_bf16(y[2 * i], y[2 * i + 1]);
-                            } else {
-#pragma unroll
-                                for (int i = 0; i < DW / 4; ++i)
-                                    wd[h0 / 4 + i] = pack_fp8x4(y[4 * i], y[4 * i + 1], y[4 * i + 2], y[4 * i + 3]);
-                            }
-                        });
-#else
-#pragma unroll
-                        for (int g = 0; g < 4; ++g) epi_unit<PO, C::SCALE>(acc[r][c], g, osc, inv, &wd[g * WPU]);
-#endif
+                        epi_tile<PO, C::SCALE>(acc[r][c], osc, inv, wd);
                         store_tile<PO>(wd, (TB + r) ^ xt, c, act, C::ACT_STRIDE, lane);
                     });
                 };
-                // layer 1 (10 -> H): both groups multiply; group 0 writes its rows now, group 1
-                // during the first hidden layer's P1
-                init_bias<RG, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), TB, lane);
-                mma_seq<C::P1, RG, 4, C::NKB1, C::NKB1, MapAll>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), TB, in0,
-                                                                C::IN_STRIDE, 0, lane, [](auto) {});
-                if (grp == 0) drain(std::integral_constant<int, C::PH>{}, p.oscale[0], p.inv_in_scale[1]);
+                // layer 1 (10 -> H): both groups multiply their own rows; group 0 writes them now,
+                // group 1 during the first hidden layer's P1.  FP8 models (whose epilogue has
+                // the most vector work) split group 0's rows between the two waves of each SIMD
+                // instead: group 1 recomputes the second half of them (a single k-block of
+                // MFMAs) and runs that half's epilogue.
+                if constexpr (MP != kFP8) {
+                    init_bias<RG, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), TB, lane);
+                    mma_seq<C::P1, RG, 4, C::NKB1, C::NKB1, MapAll>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), TB,
+                                                                    in0, C::IN_STRIDE, 0, lane, [](auto) {});
+                    if (grp == 0) drain(std::integral_constant<int, C::PH>{}, p.oscale[0], p.inv_in_scale[1]);
+                } else {
+                    constexpr int RS = RG >= 2 ? RG / 2 : 1;       // row tiles of each share
+                    constexpr int CS = RG >= 2 ? 4 : 2;            // column tiles of each share
+                    constexpr int R_OFF = RG >= 2 ? RG / 2 : 0, C_OFF = RG >= 2 ? 0 : 2;
+                    const Rsrc w0 = make_rsrc(p.wA[0], p.wA_bytes[0]), b0 = make_rsrc(p.bias[0], p.bias_bytes[0]);
+                    f32x16 part[RS][CS];
+                    const int TS0 = wg * RG + (grp == 0 ? 0 : R_OFF), CS0 = (grp == 0) ? 0 : C_OFF;
+                    if (grp != 0) {
+                        init_bias<RG, 4>(acc, b0, TB, lane);
+                        mma_seq<C::P1, RG, 4, C::NKB1, C::NKB1, MapAll>(acc, w0, TB, in0, C::IN_STRIDE, 0, lane,
+                                                                        [](auto) {});
+                    }
+                    init_bias<RS, CS>(part, b0, TS0, lane);
+                    mma_seq<C::P1, RS, CS, C::NKB1, C::NKB1, MapAll>(part, w0, TS0, in0, C::IN_STRIDE, CS0, lane,
+                                                                     [](auto) {});
+                    drain_tiles(std::integral_constant<int, C::PH>{}, part, TS0, CS0, p.oscale[0],
+                                p.inv_in_scale[1], 0);
+                }
                 __syncthreads();
                 auto hidden = [&](int l, auto OUTP) {
                     const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
