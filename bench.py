@@ -245,7 +245,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the sampler shards by "
-              f"particle id with no communication, see DESIGN.md", file=sys.stderr)
+              f"particle id with no communication between GPUs", file=sys.stderr)
         sys.exit(2)
 
     import torch

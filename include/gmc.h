@@ -69,6 +69,17 @@ typedef struct {
     const float *log_tau, *c, *y_in, *sin_th;
 } gmc_cond;
 
+/* Birth conditions of n particles born inside a cell (the internal, volumetric-source model of
+ * the paper section "Network Architecture and Inputs": the condition holds the two-dimensional
+ * birth position and the birth direction), device SoA, float32 [n] each, in the cell's own
+ * frame (no canonical rotation: the exit face is reported in the cell's orientation):
+ *   log_tau, c         as in gmc_cond
+ *   x, y               birth position in the unit cell, (0, 1) each
+ *   cos_phi, sin_phi   birth direction (unit vector) */
+typedef struct {
+    const float *log_tau, *c, *x, *y, *cos_phi, *sin_phi;
+} gmc_cond_internal;
+
 /* Exit records of n transmissions, device SoA, [n] each (paper eq. 11):
  *   face     int32 exit face 0..3 (GMC_FACE_* for walks that did not exit)
  *   pos      float32 counter-clockwise position along the exit face, [0, 1]
@@ -94,6 +105,10 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
 int gmc_model_destroy(gmc_model *m);
 /* Reports the hidden width and precision of a model (either pointer may be NULL). */
 int gmc_model_info(const gmc_model *m, int *hidden, int *precision);
+/* Reports the network's input width: 10 for a boundary model (gmc_cond), 12 for an internal
+ * model (gmc_cond_internal).  A blob with n_in = 12 has a 12-wide first layer; the network input
+ * order is then [x0..x4, t, ln tau, c, 2x - 1, 2y - 1, cos phi, sin phi]. */
+int gmc_model_inputs(const gmc_model *m, int *n_in);
 
 /* Samples n cell transmissions with the generative sampler (paper "Transport Algorithm",
  * second stage; eq. 8): x(0) = z ~ N(0, I_5); K explicit Euler steps x += v(x, k/K | c) / K;
@@ -125,6 +140,13 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
                uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out,
                void *stream);
 
+/* The generative sampler for particles born inside cells (internal model, n_in = 12): the
+ * same ODE, integrators, noise streams, decoding and errors as gmc_sample, with the birth
+ * condition in place of the entry condition.  GMC_EINVAL if m is not an internal model. */
+int gmc_sample_internal(const gmc_model *m, gmc_cond_internal cond, int64_t n, int integrator, int K,
+                        uint64_t seed, uint64_t id_base, const float *noise_opt, float *raw_opt,
+                        gmc_exit out, void *stream);
+
 /* Samples n cell transmissions with the analog random walk that the generative sampler
  * replaces (paper "Monte Carlo Method", eq. 4): flights d = -ln(xi) / sigma with
  * xi = ((w >> 8) + 1) * 2^-24 in (0, 1], isotropic flatland scattering phi = 2 pi xi'.
@@ -138,6 +160,11 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
  * Errors: GMC_EINVAL, GMC_EDEVICE. */
 int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
                 gmc_exit out, uint32_t *ncoll_opt, void *stream);
+/* The analog walk of mc_transmit started inside the cell at (x, y) with direction
+ * (cos_phi, sin_phi) (the walk the internal model replaces); same modes, random streams,
+ * outputs and errors.  The first flight starts at the birth point. */
+int mc_transmit_internal(gmc_cond_internal cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
+                         gmc_exit out, uint32_t *ncoll_opt, void *stream);
 
 /* Decodes raw network outputs (device float32 [5][n]) into exit records with the rule of
  * gmc_transmit.  flags_opt: NULL or device int32 [n]: bit0 position clamped, bit1 direction
@@ -184,8 +211,8 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid, void 
 /* Frees a problem's slot and cells; GMC_EINVAL while it still has particles in flight. */
 int gmc_problem_remove(gmc_world *w, int32_t pid);
 /* Births of histories [h_begin, h_begin + count) of problem pid (ids below 2^32): source
- * sampling, the first leg in the birth cell by the analog walk (continuous absorption), its
- * tally, and the move to the neighbour.  Survivors join the bank.  GMC_ENOMEM if count exceeds
+ * sampling, the first leg in the birth cell (the analog walk with continuous absorption, or the
+ * internal model set by gmc_world_set_source_model), its tally, and the move to the neighbour.  Survivors join the bank.  GMC_ENOMEM if count exceeds
  * the free bank slots.  Synchronises `stream`; *n_alive_out (optional) = particles in flight. */
 int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count, void *stream,
                      int64_t *n_alive_out);
@@ -193,9 +220,16 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
  * transmission each with the generative sampler (sampler = GMC_SAMPLER_GMC, model m, K steps
  * of the world's integrator) or the analog walk with continuous absorption (GMC_SAMPLER_MC, m unused), FP64
  * attenuation and tallies (stage 3), move / leak / cutoff and compaction (stage 4).
- * Synchronises `stream`; *n_alive_out (optional) = particles still in flight. */
+ * Synchronises `stream`; *n_alive_out (optional) = particles still in flight.  GMC_EINVAL for
+ * an unknown sampler, or for GMC without a boundary model (n_in = 10) or with K outside 1..1024. */
 int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
                        int64_t *n_alive_out);
+/* Source births of later gmc_world_inject calls: m = NULL (the default) walks each birth's first
+ * leg with the analog walk; an internal model (n_in = 12) samples it with the generative sampler
+ * instead (K steps of the world's integrator; paper "Transport Algorithm", first stage, and
+ * Fig. 1a's separate network for particles born inside cells).  The model must outlive its use.
+ * GMC_EINVAL if m is not an internal model or K is outside 1..1024. */
+int gmc_world_set_source_model(gmc_world *w, const gmc_model *m, int K);
 /* Integrator (GMC_EULER, the default, or GMC_RK4) that later gmc_transport_step calls with the
  * generative sampler use; K then counts integration steps.  GMC_EINVAL otherwise. */
 int gmc_world_set_integrator(gmc_world *w, int integrator);

@@ -58,6 +58,9 @@ def lib():
         L.orc_noise_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P]
         L.orc_mc_transmit.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
                                       ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_int]
+        L.orc_mc_transmit_internal.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int,
+                                               ctypes.c_uint64, ctypes.c_uint64, P, P, P, P, P, P,
+                                               ctypes.c_int]
         L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
@@ -111,6 +114,20 @@ def mc_transmit(cond, mode: int, seed: int, id_base: int = 0, nthreads: int = 1)
     lib().orc_mc_transmit(_p(lt), _p(cc), _p(yy), _p(ss), n, mode, seed, id_base,
                           _p(out["face"]), _p(out["pos"]), _p(out["u"]), _p(out["v"]),
                           _p(out["len"]), _p(out["ncoll"]), nthreads)
+    return out
+
+
+def mc_transmit_internal(cond, mode: int, seed: int, id_base: int = 0, nthreads: int = 1) -> dict:
+    """FP64 analog walks started inside the cell: particle i born at (x, y) with direction
+    (cos_phi, sin_phi) in the cell's own frame.  Same modes and outputs as mc_transmit."""
+    n = len(cond)
+    arr = [np.ascontiguousarray(a, np.float32) for a in (cond.log_tau, cond.c, cond.x, cond.y,
+                                                          cond.cos_phi, cond.sin_phi)]
+    out = dict(face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n), v=np.zeros(n),
+               len=np.zeros(n), ncoll=np.zeros(n, np.uint32))
+    lib().orc_mc_transmit_internal(*(_p(a) for a in arr), n, mode, seed, id_base,
+                                   _p(out["face"]), _p(out["pos"]), _p(out["u"]), _p(out["v"]),
+                                   _p(out["len"]), _p(out["ncoll"]), nthreads)
     return out
 
 
@@ -177,10 +194,14 @@ def silu(a):
 
 
 def condition_features(cond) -> np.ndarray:
-    """Condition part of the network input: (ln tau, c, 2*y_in - 1, sin theta_in), [n, 4]."""
-    return np.stack([np.asarray(cond.log_tau, np.float64), np.asarray(cond.c, np.float64),
-                     2.0 * np.asarray(cond.y_in, np.float64) - 1.0,
-                     np.asarray(cond.sin_th, np.float64)], axis=1)
+    """Condition part of the network input.  Boundary model (entry conditions):
+    (ln tau, c, 2*y_in - 1, sin theta_in), [n, 4].  Internal model (birth conditions, which carry
+    the birth position x, y and direction): (ln tau, c, 2x - 1, 2y - 1, cos phi, sin phi), [n, 6]."""
+    f = lambda a: np.asarray(a, np.float64)
+    if hasattr(cond, "x"):
+        return np.stack([f(cond.log_tau), f(cond.c), 2.0 * f(cond.x) - 1.0, 2.0 * f(cond.y) - 1.0,
+                         f(cond.cos_phi), f(cond.sin_phi)], axis=1)
+    return np.stack([f(cond.log_tau), f(cond.c), 2.0 * f(cond.y_in) - 1.0, f(cond.sin_th)], axis=1)
 
 
 def velocity(weights, x, t, condf, precision=PREC_FP64):

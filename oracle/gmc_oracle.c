@@ -176,6 +176,7 @@ void orc_walk(double tau, double c, int mode, double x, double y, double u, doub
  * scattering ratio c[i]; random stream id_base + i.  Outputs are [n] arrays. */
 typedef struct {
     const float *log_tau, *c, *y_in, *sin_th;
+    const float *x_in, *cos_phi;   /* births inside the cell (internal model), else NULL */
     int64_t n;
     int mode;
     uint64_t seed, id_base;
@@ -190,9 +191,13 @@ static void *walk_worker(void *arg)
     walk_job *j = (walk_job *)arg;
     for (int64_t i = j->begin; i < j->end; ++i) {
         double s = (double)j->sin_th[i];
-        double u0 = sqrt(1.0 - s * s);
+        double x0 = 0.0, u0 = sqrt(1.0 - s * s);
+        if (j->x_in) {            /* birth at (x, y) with direction (cos phi, sin phi) */
+            x0 = (double)j->x_in[i];
+            u0 = (double)j->cos_phi[i];
+        }
         orc_exit e;
-        orc_walk(exp((double)j->log_tau[i]), (double)j->c[i], j->mode, 0.0, (double)j->y_in[i],
+        orc_walk(exp((double)j->log_tau[i]), (double)j->c[i], j->mode, x0, (double)j->y_in[i],
                  u0, s, j->seed, j->id_base + (uint64_t)i, &e);
         j->face[i] = e.face; j->pos[i] = e.pos; j->u[i] = e.u; j->v[i] = e.v;
         j->len[i] = e.len; j->ncoll[i] = e.ncoll;
@@ -200,22 +205,42 @@ static void *walk_worker(void *arg)
     return NULL;
 }
 
-void orc_mc_transmit(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
-                     int64_t n, int mode, uint64_t seed, uint64_t id_base, int32_t *face,
-                     double *pos, double *u, double *v, double *len, uint32_t *ncoll, int nthreads)
+static void run_walks(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
+                      const float *x_in, const float *cos_phi, int64_t n, int mode, uint64_t seed,
+                      uint64_t id_base, int32_t *face, double *pos, double *u, double *v, double *len,
+                      uint32_t *ncoll, int nthreads)
 {
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;
     walk_job jobs[256];
     pthread_t th[256];
     for (int t = 0; t < nthreads; ++t) {
-        walk_job j = {log_tau, c, y_in, sin_th, n, mode, seed, id_base, face, pos, u, v, len, ncoll,
-                      n * t / nthreads, n * (t + 1) / nthreads};
+        walk_job j = {log_tau, c, y_in, sin_th, x_in, cos_phi, n, mode, seed, id_base, face, pos, u, v,
+                      len, ncoll, n * t / nthreads, n * (t + 1) / nthreads};
         jobs[t] = j;
     }
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, walk_worker, &jobs[t]);
     walk_worker(&jobs[0]);
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+}
+
+void orc_mc_transmit(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
+                     int64_t n, int mode, uint64_t seed, uint64_t id_base, int32_t *face,
+                     double *pos, double *u, double *v, double *len, uint32_t *ncoll, int nthreads)
+{
+    run_walks(log_tau, c, y_in, sin_th, NULL, NULL, n, mode, seed, id_base, face, pos, u, v, len, ncoll,
+              nthreads);
+}
+
+/* Batch of walks started inside the cell: particle i is born at (x[i], y[i]) with direction
+ * (cos_phi[i], sin_phi[i]) (the walk that the internal, volumetric-source model replaces). */
+void orc_mc_transmit_internal(const float *log_tau, const float *c, const float *x, const float *y,
+                              const float *cos_phi, const float *sin_phi, int64_t n, int mode,
+                              uint64_t seed, uint64_t id_base, int32_t *face, double *pos, double *u,
+                              double *v, double *len, uint32_t *ncoll, int nthreads)
+{
+    run_walks(log_tau, c, y, sin_phi, x, cos_phi, n, mode, seed, id_base, face, pos, u, v, len, ncoll,
+              nthreads);
 }
 
 /* ------------------------------------------------------------------------------------ */

@@ -33,6 +33,11 @@ class _Cond(ctypes.Structure):
                 ("y_in", ctypes.c_void_p), ("sin_th", ctypes.c_void_p)]
 
 
+class _CondInternal(ctypes.Structure):
+    _fields_ = [("log_tau", ctypes.c_void_p), ("c", ctypes.c_void_p), ("x", ctypes.c_void_p),
+                ("y", ctypes.c_void_p), ("cos_phi", ctypes.c_void_p), ("sin_phi", ctypes.c_void_p)]
+
+
 class _Exit(ctypes.Structure):
     _fields_ = [("face", ctypes.c_void_p), ("pos", ctypes.c_void_p),
                 ("dir_cos", ctypes.c_void_p), ("dir_sin", ctypes.c_void_p),
@@ -58,8 +63,12 @@ def lib() -> ctypes.CDLL:
         L.gmc_sample.argtypes = [P, _Cond, I64, I, I, U64, U64, P, P, _Exit, P]
         L.mc_transmit.argtypes = [_Cond, I64, I, U64, U64, _Exit, P, P]
         L.gmc_decode.argtypes = [P, I64, _Exit, P, P]
+        L.gmc_model_inputs.argtypes = [P, ctypes.POINTER(I)]
+        L.gmc_sample_internal.argtypes = [P, _CondInternal, I64, I, I, U64, U64, P, P, _Exit, P]
+        L.mc_transmit_internal.argtypes = [_CondInternal, I64, I, U64, U64, _Exit, P, P]
         for name in ("gmc_model_create", "gmc_model_destroy", "gmc_model_info", "gmc_transmit",
-                     "mc_transmit", "gmc_decode"):
+                     "mc_transmit", "gmc_decode", "gmc_sample", "gmc_model_inputs",
+                     "gmc_sample_internal", "mc_transmit_internal"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -109,6 +118,32 @@ class DeviceCond:
 
 
 @dataclass
+class DeviceCondInternal:
+    """Device SoA of internal-model birth conditions (float32 tensors of equal length)."""
+    log_tau: torch.Tensor
+    c: torch.Tensor
+    x: torch.Tensor
+    y: torch.Tensor
+    cos_phi: torch.Tensor
+    sin_phi: torch.Tensor
+
+    @classmethod
+    def from_host(cls, cond, device="cuda"):
+        f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
+        return cls(f(cond.log_tau), f(cond.c), f(cond.x), f(cond.y), f(cond.cos_phi), f(cond.sin_phi))
+
+    def __len__(self):
+        return int(self.log_tau.numel())
+
+    def c_struct(self) -> _CondInternal:
+        n = len(self)
+        names = ("log_tau", "c", "x", "y", "cos_phi", "sin_phi")
+        for nm in names:
+            _need(getattr(self, nm), torch.float32, n, nm)
+        return _CondInternal(*(getattr(self, nm).data_ptr() for nm in names))
+
+
+@dataclass
 class DeviceExit:
     face: torch.Tensor
     pos: torch.Tensor
@@ -146,6 +181,9 @@ class Model:
         hid, prec = ctypes.c_int(), ctypes.c_int()
         _check(lib().gmc_model_info(h, ctypes.byref(hid), ctypes.byref(prec)))
         self.hidden, self.precision = hid.value, prec.value
+        nin = ctypes.c_int()
+        _check(lib().gmc_model_inputs(h, ctypes.byref(nin)))
+        self.n_in = nin.value          # 10: boundary model, 12: internal model
 
     @property
     def handle(self):
@@ -201,6 +239,40 @@ def gmc_sample(model: Model, cond: DeviceCond, integrator: str, K: int, seed: in
     return out
 
 
+def gmc_sample_internal(model: Model, cond: DeviceCondInternal, integrator: str, K: int, seed: int,
+                        id_base: int = 0, noise: torch.Tensor | None = None,
+                        raw: torch.Tensor | None = None, out: DeviceExit | None = None,
+                        n: int | None = None, stream=None) -> DeviceExit:
+    """gmc_sample_internal: the internal (volumetric-source) model's sampler."""
+    n = len(cond) if n is None else n
+    if integrator not in INTEGRATORS:
+        raise ValueError(f"integrator must be one of {sorted(INTEGRATORS)}")
+    if out is None:
+        out = DeviceExit.empty(n, cond.log_tau.device)
+    if noise is not None:
+        _need(noise, torch.float32, 5 * n, "noise")
+    if raw is not None:
+        _need(raw, torch.float32, 5 * n, "raw")
+    _check(lib().gmc_sample_internal(model.handle, cond.c_struct(), n, INTEGRATORS[integrator], int(K),
+                                     seed, id_base, _ptr(noise), _ptr(raw), out.c_struct(n),
+                                     _stream(stream)))
+    return out
+
+
+def mc_transmit_internal(cond: DeviceCondInternal, mode: int, seed: int, id_base: int = 0,
+                         ncoll: torch.Tensor | None = None, out: DeviceExit | None = None,
+                         n: int | None = None, stream=None) -> DeviceExit:
+    """mc_transmit_internal: the analog walk from a birth point inside the cell."""
+    n = len(cond) if n is None else n
+    if out is None:
+        out = DeviceExit.empty(n, cond.log_tau.device)
+    if ncoll is not None:
+        _need(ncoll, torch.int32, n, "ncoll")
+    _check(lib().mc_transmit_internal(cond.c_struct(), n, int(mode), seed, id_base, out.c_struct(n),
+                                      _ptr(ncoll), _stream(stream)))
+    return out
+
+
 def mc_transmit(cond: DeviceCond, mode: int, seed: int, id_base: int = 0,
                 ncoll: torch.Tensor | None = None, out: DeviceExit | None = None,
                 n: int | None = None, stream=None) -> DeviceExit:
@@ -250,7 +322,8 @@ def _transport_sigs(L):
     L.gmc_problem_tally.argtypes = [P, I32, P, P, P, P, P]
     L.gmc_world_set_integrator.argtypes = [P, I]
     L.gmc_world_set_graphs.argtypes = [P, I]
-    for name in ("gmc_world_set_integrator", "gmc_world_set_graphs", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
+    L.gmc_world_set_source_model.argtypes = [P, P, I]
+    for name in ("gmc_world_set_integrator", "gmc_world_set_graphs", "gmc_world_set_source_model", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
                  "gmc_problem_remove", "gmc_world_inject", "gmc_transport_step",
                  "gmc_problem_alive", "gmc_problem_tally"):
         getattr(L, name).restype = ctypes.c_int
@@ -302,6 +375,10 @@ class World:
         if integrator not in INTEGRATORS:
             raise ValueError(f"integrator must be one of {sorted(INTEGRATORS)}")
         _check(self._L.gmc_world_set_integrator(self._h, INTEGRATORS[integrator]))
+
+    def set_source_model(self, model: Model | None, K: int = 16):
+        """Births sampled by an internal model (None: analog first leg)."""
+        _check(self._L.gmc_world_set_source_model(self._h, None if model is None else model.handle, int(K)))
 
     def set_graphs(self, enable: bool = True):
         """Replay captured HIP graphs of the transport step per particle-count bucket."""

@@ -144,13 +144,14 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     std::memcpy(&hd, host_blob, sizeof hd);
     if (std::memcmp(hd.magic, "GMCW0001", 8) != 0 || hd.version != 1)
         return fail(GMC_EINVAL, "gmc_model_create: bad magic or version");
-    if (hd.n_in != 10 || hd.n_out != 5 || hd.n_layers != 5)
-        return fail(GMC_EINVAL, "gmc_model_create: network must be 10 -> H x4 -> 5");
+    if ((hd.n_in != 10 && hd.n_in != 12) || hd.n_out != 5 || hd.n_layers != 5)
+        return fail(GMC_EINVAL, "gmc_model_create: network must be 10 (or 12) -> H x4 -> 5");
     const int H = (int)hd.hidden;
     if (!mlp_supported(precision, H))
         return fail(GMC_EUNSUPPORTED, "gmc_model_create: hidden width " + std::to_string(H) +
                                           " not built for this precision");
-    const int dims[5][2] = {{H, 10}, {H, H}, {H, H}, {H, H}, {5, H}};
+    const int NI = (int)hd.n_in;
+    const int dims[5][2] = {{H, NI}, {H, H}, {H, H}, {H, H}, {5, H}};
     size_t need = sizeof(BlobHeader);
     for (auto &d : dims) need += sizeof(float) * (size_t)(d[0] * d[1] + d[0]);
     if (nbytes != need) return fail(GMC_EINVAL, "gmc_model_create: blob size does not match header");
@@ -176,6 +177,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     static std::atomic<uint64_t> next_serial{1};
     m->serial = next_serial++;
     m->precision = precision;
+    m->n_in = NI;
+    m->tmpl.n_cond = NI - 6;
     m->hidden = H;
     for (int l = 0; l < 5; ++l) {
         const int P = layer_prec(precision, l);
@@ -261,7 +264,18 @@ int gmc_model_info(const gmc_model *m, int *hidden, int *precision)
     return GMC_OK;
 }
 
+int gmc_model_inputs(const gmc_model *m, int *n_in)
+{
+    if (!m || !n_in) return fail(GMC_EINVAL, "gmc_model_inputs: null pointer");
+    *n_in = m->n_in;
+    return GMC_OK;
+}
+
 static bool cond_ok(const gmc_cond &c) { return c.log_tau && c.c && c.y_in && c.sin_th; }
+static bool cond_ok(const gmc_cond_internal &c)
+{
+    return c.log_tau && c.c && c.x && c.y && c.cos_phi && c.sin_phi;
+}
 static bool exit_ok(const gmc_exit &o) { return o.face && o.pos && o.dir_cos && o.dir_sin && o.path; }
 
 int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t seed,
@@ -270,24 +284,25 @@ int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t s
     return gmc_sample(m, cond, n, GMC_EULER, K, seed, id_base, noise_opt, raw_opt, out, stream);
 }
 
-int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int K, uint64_t seed,
-               uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Common part of gmc_sample / gmc_sample_internal: checks, then one fused sampler launch with the
+// condition pointers already in p.
+int launch_sampler(const gmc_model *m, gmc::MlpParams p, int64_t n, int integrator, int K, uint64_t seed,
+                   uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out, void *stream,
+                   const char *who)
 {
-    if (!m) return fail(GMC_EINVAL, "gmc_transmit: null model");
-    if (n < 0) return fail(GMC_EINVAL, "gmc_transmit: negative n");
+    const std::string w(who);
     if (integrator != GMC_EULER && integrator != GMC_RK4)
-        return fail(GMC_EINVAL, "gmc_sample: integrator must be GMC_EULER or GMC_RK4");
-    if (K < 1 || K > 1024) return fail(GMC_EINVAL, "gmc_transmit: K must be in 1..1024");
+        return fail(GMC_EINVAL, w + ": integrator must be GMC_EULER or GMC_RK4");
+    if (K < 1 || K > 1024) return fail(GMC_EINVAL, w + ": K must be in 1..1024");
     if (n == 0) return GMC_OK;
-    if (!cond_ok(cond) || !exit_ok(out)) return fail(GMC_EINVAL, "gmc_transmit: null condition or output array");
+    if (!exit_ok(out)) return fail(GMC_EINVAL, w + ": null output array");
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev != m->device)
-        return fail(GMC_EINVAL, "gmc_transmit: model lives on another device");
-    gmc::MlpParams p = m->tmpl;
-    p.log_tau = cond.log_tau;
-    p.c = cond.c;
-    p.y_in = cond.y_in;
-    p.sin_th = cond.sin_th;
+        return fail(GMC_EINVAL, w + ": model lives on another device");
     p.noise = noise_opt;
     p.raw = raw_opt;
     p.face = out.face;
@@ -296,32 +311,28 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
     p.dsin = out.dir_sin;
     p.path = out.path;
     p.n = n;
+    p.n_dev = nullptr;
     p.K = K;
     p.integrator = integrator;
     p.seed = seed;
     p.id_base = id_base;
     const int cu = gmc::device_cu_count();
-    if (cu <= 0) return fail(GMC_EDEVICE, "gmc_transmit: cannot query the device");
+    if (cu <= 0) return fail(GMC_EDEVICE, w + ": cannot query the device");
     const int64_t ntiles = (n + gmc::kTileM - 1) / gmc::kTileM;
     const int grid = (int)std::min<int64_t>(ntiles, cu);
     hipError_t e = gmc::launch_mlp_ode(m->precision, m->hidden, p, grid, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "gmc_transmit: launch");
+    if (e != hipSuccess) return hip_fail(e, (w + ": launch").c_str());
     return GMC_OK;
 }
 
-int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base, gmc_exit out,
-                uint32_t *ncoll_opt, void *stream)
+int launch_walk_api(gmc::WalkParams p, int64_t n, int mode, uint64_t seed, uint64_t id_base, gmc_exit out,
+                    uint32_t *ncoll_opt, void *stream, const char *who)
 {
-    if (n < 0) return fail(GMC_EINVAL, "mc_transmit: negative n");
+    const std::string w(who);
     if (mode != GMC_MODE_CONTINUOUS && mode != GMC_MODE_ANALOG)
-        return fail(GMC_EINVAL, "mc_transmit: mode must be 0 (continuous) or 1 (analog)");
+        return fail(GMC_EINVAL, w + ": mode must be 0 (continuous) or 1 (analog)");
     if (n == 0) return GMC_OK;
-    if (!cond_ok(cond) || !exit_ok(out)) return fail(GMC_EINVAL, "mc_transmit: null condition or output array");
-    gmc::WalkParams p{};
-    p.log_tau = cond.log_tau;
-    p.c = cond.c;
-    p.y_in = cond.y_in;
-    p.sin_th = cond.sin_th;
+    if (!exit_ok(out)) return fail(GMC_EINVAL, w + ": null output array");
     p.face = out.face;
     p.pos = out.pos;
     p.dcos = out.dir_cos;
@@ -329,17 +340,86 @@ int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_b
     p.path = out.path;
     p.ncoll = ncoll_opt;
     p.n = n;
+    p.n_dev = nullptr;
     p.mode = mode;
     p.seed = seed;
     p.id_base = id_base;
     p.queue = gmc::device_queue_counter();
-    if (!p.queue) return fail(GMC_ENOMEM, "mc_transmit: cannot allocate the work counter");
+    if (!p.queue) return fail(GMC_ENOMEM, w + ": cannot allocate the work counter");
     const int cu = gmc::device_cu_count();
-    if (cu <= 0) return fail(GMC_EDEVICE, "mc_transmit: cannot query the device");
+    if (cu <= 0) return fail(GMC_EDEVICE, w + ": cannot query the device");
     const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)cu * 8);
     hipError_t e = gmc::launch_walk(p, grid, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "mc_transmit: launch");
+    if (e != hipSuccess) return hip_fail(e, (w + ": launch").c_str());
     return GMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int K, uint64_t seed,
+               uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out, void *stream)
+{
+    if (!m) return fail(GMC_EINVAL, "gmc_transmit: null model");
+    if (n < 0) return fail(GMC_EINVAL, "gmc_transmit: negative n");
+    if (m->n_in != 10) return fail(GMC_EINVAL, "gmc_transmit: the model is not a boundary model (10 inputs)");
+    if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "gmc_transmit: null condition array");
+    gmc::MlpParams p = m->tmpl;
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.y_in = cond.y_in;
+    p.sin_th = cond.sin_th;
+    p.x_in = nullptr;
+    p.cos_phi = nullptr;
+    return launch_sampler(m, p, n, integrator, K, seed, id_base, noise_opt, raw_opt, out, stream, "gmc_sample");
+}
+
+int gmc_sample_internal(const gmc_model *m, gmc_cond_internal cond, int64_t n, int integrator, int K,
+                        uint64_t seed, uint64_t id_base, const float *noise_opt, float *raw_opt,
+                        gmc_exit out, void *stream)
+{
+    if (!m) return fail(GMC_EINVAL, "gmc_sample_internal: null model");
+    if (n < 0) return fail(GMC_EINVAL, "gmc_sample_internal: negative n");
+    if (m->n_in != 12) return fail(GMC_EINVAL, "gmc_sample_internal: the model is not an internal model (12 inputs)");
+    if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "gmc_sample_internal: null condition array");
+    gmc::MlpParams p = m->tmpl;
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.x_in = cond.x;
+    p.y_in = cond.y;
+    p.cos_phi = cond.cos_phi;
+    p.sin_th = cond.sin_phi;
+    return launch_sampler(m, p, n, integrator, K, seed, id_base, noise_opt, raw_opt, out, stream,
+                          "gmc_sample_internal");
+}
+
+int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base, gmc_exit out,
+                uint32_t *ncoll_opt, void *stream)
+{
+    if (n < 0) return fail(GMC_EINVAL, "mc_transmit: negative n");
+    if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "mc_transmit: null condition array");
+    gmc::WalkParams p{};
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.y_in = cond.y_in;
+    p.sin_th = cond.sin_th;
+    return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit");
+}
+
+int mc_transmit_internal(gmc_cond_internal cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
+                         gmc_exit out, uint32_t *ncoll_opt, void *stream)
+{
+    if (n < 0) return fail(GMC_EINVAL, "mc_transmit_internal: negative n");
+    if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "mc_transmit_internal: null condition array");
+    gmc::WalkParams p{};
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.x_in = cond.x;
+    p.y_in = cond.y;
+    p.cos_phi = cond.cos_phi;
+    p.sin_th = cond.sin_phi;
+    return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit_internal");
 }
 
 int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, void *stream)

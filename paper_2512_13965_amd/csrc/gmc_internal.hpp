@@ -61,6 +61,8 @@ struct MlpParams {
     float oscale[5];          // accumulator multiplier per layer (FP8 hidden layers: sw * sa)
     float inv_in_scale[5];    // 1 / activation scale of the input of layer l (FP8 hidden layers)
     const float *log_tau, *c, *y_in, *sin_th;
+    const float *x_in, *cos_phi;   // internal model only: birth x and direction cosine
+    int n_cond;               // condition features: 4 (boundary model) or 6 (internal model)
     const float *noise;       // optional [5][n]
     float *raw;               // optional [5][n]
     const uint64_t *ids;      // optional per-sample random stream ids (else id_base + i)
@@ -79,6 +81,8 @@ bool mlp_supported(int prec, int hidden);
 
 struct WalkParams {
     const float *log_tau, *c, *y_in, *sin_th;
+    const float *x_in, *cos_phi;   // optional: start inside the cell at (x_in, y_in), direction
+                                   // (cos_phi, sin_th); else on the left face, cosine from sin_th
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
     uint32_t *ncoll;          // optional
@@ -108,6 +112,7 @@ struct gmc_model {
     uint64_t serial = 0;     // unique per created model (keys captured launches)
     int precision = 0;
     int hidden = 0;
+    int n_in = 10;           // 10: boundary model, 12: internal model
     int device = 0;
     void *dev_mem = nullptr;
     gmc::MlpParams tmpl{};   // weight / bias pointers and scales

@@ -502,7 +502,7 @@ struct Cfg {
     static constexpr int WPK = words_per_unit(PH) > words_per_unit(P5) ? words_per_unit(PH) : words_per_unit(P5);
     static constexpr int LDS_ACT = kTileM * ACT_STRIDE;
     static constexpr int LDS_IN = kTileM * IN_STRIDE;
-    static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 4 + 5 + 5) * kTileM * 4;
+    static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 6 + 5 + 5) * kTileM * 4;
 };
 
 template <int MP, int H, int RK>
@@ -519,8 +519,8 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
     char *act = smem;
     char *in0 = smem + C::LDS_ACT;
     float *xs = (float *)(smem + C::LDS_ACT + C::LDS_IN);   // [5][128] ODE state
-    float *cf = xs + 5 * kTileM;                              // [4][128] condition features
-    float *ksum = cf + 4 * kTileM;                            // [5][128] RK4 stage sum
+    float *cf = xs + 5 * kTileM;                              // [6][128] condition features
+    float *ksum = cf + 6 * kTileM;                            // [5][128] RK4 stage sum
     float *vout = ksum + 5 * kTileM;                          // [5][128] last network output
 
     const int tid = threadIdx.x;
@@ -563,12 +563,16 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
         if (tid < kTileM) {
             const int64_t i = base + tid;
             float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            float lt = 0.f, cc = 0.f, yy = 0.5f, ss = 0.f;
+            float lt = 0.f, cc = 0.f, yy = 0.5f, ss = 0.f, xx = 0.5f, co = 1.f;
             if (i < n_items) {
                 lt = p.log_tau[i];
                 cc = p.c[i];
                 yy = p.y_in[i];
                 ss = p.sin_th[i];
+                if (p.n_cond == 6) {
+                    xx = p.x_in[i];
+                    co = p.cos_phi[i];
+                }
                 if (p.noise) {
 #pragma unroll
                     for (int d = 0; d < 5; ++d) z[d] = p.noise[d * p.n + i];
@@ -578,10 +582,21 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             }
 #pragma unroll
             for (int d = 0; d < 5; ++d) xs[d * kTileM + tid] = z[d];
+            // boundary model: (ln tau, c, 2 y_in - 1, sin th); internal model:
+            // (ln tau, c, 2 x - 1, 2 y - 1, cos phi, sin phi)
             cf[0 * kTileM + tid] = lt;
             cf[1 * kTileM + tid] = cc;
-            cf[2 * kTileM + tid] = 2.0f * yy - 1.0f;
-            cf[3 * kTileM + tid] = ss;
+            if (p.n_cond == 6) {
+                cf[2 * kTileM + tid] = 2.0f * xx - 1.0f;
+                cf[3 * kTileM + tid] = 2.0f * yy - 1.0f;
+                cf[4 * kTileM + tid] = co;
+                cf[5 * kTileM + tid] = ss;
+            } else {
+                cf[2 * kTileM + tid] = 2.0f * yy - 1.0f;
+                cf[3 * kTileM + tid] = ss;
+                cf[4 * kTileM + tid] = 0.0f;
+                cf[5 * kTileM + tid] = 0.0f;
+            }
         }
         __syncthreads();
 
@@ -603,9 +618,9 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 }
                 v[5] = t;
 #pragma unroll
-                for (int d = 0; d < 4; ++d) v[6 + d] = cf[d * kTileM + tid];
+                for (int d = 0; d < 6; ++d) v[6 + d] = cf[d * kTileM + tid];   // zero past n_cond
 #pragma unroll
-                for (int d = 10; d < 16; ++d) v[d] = 0.0f;
+                for (int d = 12; d < 16; ++d) v[d] = 0.0f;
                 char *row = in0 + tid * C::IN_STRIDE;
                 if constexpr (C::P1 == kF32) {
 #pragma unroll

@@ -194,6 +194,62 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
     append(alive, nx, pid, w_out, h, 1u, out, counter, pcount);
 }
 
+// Source births for the generative internal model: birth cell, position and direction of
+// histories [h0, h0 + count) (the same Philox draw as birth_kernel) as internal-model
+// conditions in the cell's own frame; the birth event uses random stream id h.
+__global__ __launch_bounds__(256) void source_kernel(CellsDev cd, int32_t pid, uint32_t h0, int64_t count,
+                                                     float *ltau, float *cc, float *xb, float *yb,
+                                                     float *cosb, float *sinb, uint64_t *ids, uint64_t *keys)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    const ProblemDev P = cd.prob[pid];
+    const uint32_t h = h0 + (uint32_t)t;
+    const U4 r = draw4(P.seed, (uint64_t)h, 0u, kTagSource);
+    const uint32_t nsrc = (uint32_t)(P.snx * P.sny);
+    const uint32_t pick = __umulhi(r.a, nsrc);
+    const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
+    const int cell = (int)(P.cell0 + (int64_t)cj * P.nx + ci);
+    const float ph = u01(r.d);
+    ltau[t] = cd.ltau[cell];
+    cc[t] = cd.cf[cell];
+    xb[t] = u01_open(r.b);
+    yb[t] = u01_open(r.c);
+    cosb[t] = cos_turns(ph);
+    sinb[t] = sin_turns(ph);
+    ids[t] = (uint64_t)h;
+    keys[t] = P.seed;
+}
+
+// Stages 3-4 of the births sampled by the internal model (exits in the cell's own frame, which
+// is the global orientation): tally, move, append.
+__global__ __launch_bounds__(256) void source_apply_kernel(CellsDev cd, int32_t pid, uint32_t h0,
+                                                           int64_t count, const int32_t *face_c,
+                                                           const float *pos, const float *dcos,
+                                                           const float *dsin, const float *path,
+                                                           BankDev out, unsigned long long *counter,
+                                                           unsigned long long *pcount)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool alive = false;
+    Next nx{};
+    double w_out = 0.0;
+    uint32_t h = 0;
+    if (t < count) {
+        const ProblemDev P = cd.prob[pid];
+        h = h0 + (uint32_t)t;
+        const U4 r = draw4(P.seed, (uint64_t)h, 0u, kTagSource);
+        const uint32_t nsrc = (uint32_t)(P.snx * P.sny);
+        const uint32_t pick = __umulhi(r.a, nsrc);
+        const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
+        const int cell = (int)(P.cell0 + (int64_t)cj * P.nx + ci);
+        w_out = visit_tally(cd, P, cell, 1.0, path[t]);
+        nx = move_on(cd, P, cell, face_c[t], pos[t], dcos[t], dsin[t], w_out);
+        alive = nx.alive;
+    }
+    append(alive, nx, pid, w_out, h, 1u, out, counter, pcount);
+}
+
 // Stage 1: canonical conditions of every alive particle.  Entry face e maps to the canonical
 // left face by the rotation of k = (e + 1) mod 4 quarter turns (canonical -> local).
 __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
@@ -277,8 +333,11 @@ struct gmc_world {
     BankDev bank[2]{};
     int cur = 0;
     int integrator = GMC_EULER;   // ODE integrator of the generative sampler
+    const gmc_model *src_model = nullptr;   // internal model for births (else analog first leg)
+    int src_K = 16;
     // sampler staging
     float *c_ltau = nullptr, *c_c = nullptr, *c_yin = nullptr, *c_sth = nullptr;
+    float *c_x = nullptr, *c_cos = nullptr;      // internal-model births
     uint64_t *ids = nullptr, *keys = nullptr;
     int32_t *e_face = nullptr;
     float *e_pos = nullptr, *e_dcos = nullptr, *e_dsin = nullptr, *e_path = nullptr;
@@ -343,6 +402,8 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->c_c, 4 * C);
     L.add((void **)&w->c_yin, 4 * C);
     L.add((void **)&w->c_sth, 4 * C);
+    L.add((void **)&w->c_x, 4 * C);
+    L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);
     L.add((void **)&w->keys, 8 * C);
     L.add((void **)&w->e_face, 4 * C);
@@ -543,14 +604,62 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
         unsigned long long *ctr = w->cnt(which);
         // the bank's particle counter restarts at the number alive; per-problem counts continue
         hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(1), 0, s, ctr, (unsigned long long)w->n_alive, 1);
-        hipLaunchKernelGGL(birth_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
-                           (uint32_t)h_begin, count, w->bank[which], ctr, ctr + 1);
+        if (!w->src_model) {
+            hipLaunchKernelGGL(birth_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
+                               (uint32_t)h_begin, count, w->bank[which], ctr, ctr + 1);
+        } else {
+            hipLaunchKernelGGL(source_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
+                               (uint32_t)h_begin, count, w->c_ltau, w->c_c, w->c_x, w->c_yin, w->c_cos,
+                               w->c_sth, w->ids, w->keys);
+            const gmc_model *m = w->src_model;
+            MlpParams p = m->tmpl;
+            p.log_tau = w->c_ltau;
+            p.c = w->c_c;
+            p.x_in = w->c_x;
+            p.y_in = w->c_yin;
+            p.cos_phi = w->c_cos;
+            p.sin_th = w->c_sth;
+            p.noise = nullptr;
+            p.raw = nullptr;
+            p.ids = w->ids;
+            p.keys = w->keys;
+            p.face = w->e_face;
+            p.pos = w->e_pos;
+            p.dcos = w->e_dcos;
+            p.dsin = w->e_dsin;
+            p.path = w->e_path;
+            p.n = count;
+            p.n_dev = nullptr;
+            p.K = w->src_K;
+            p.integrator = w->integrator;
+            p.seed = 0;
+            p.id_base = 0;
+            const int cu = device_cu_count();
+            if (cu <= 0) return set_error(GMC_EDEVICE, "gmc_world_inject: cannot query the device");
+            hipError_t e = launch_mlp_ode(m->precision, m->hidden, p,
+                                          (int)std::min<int64_t>((count + kTileM - 1) / kTileM, cu), s);
+            if (e != hipSuccess) return set_hip_error(e, "gmc_world_inject: internal sampler");
+            hipLaunchKernelGGL(source_apply_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
+                               (uint32_t)h_begin, count, w->e_face, w->e_pos, w->e_dcos, w->e_dsin,
+                               w->e_path, w->bank[which], ctr, ctr + 1);
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return set_hip_error(e, "gmc_world_inject: launch");
         const int rc = sync_counters(w, which, s);
         if (rc != GMC_OK) return rc;
     }
     if (n_alive_out) *n_alive_out = w->n_alive;
+    return GMC_OK;
+}
+
+int gmc_world_set_source_model(gmc_world *w, const gmc_model *m, int K)
+{
+    if (!w) return set_error(GMC_EINVAL, "gmc_world_set_source_model: null world");
+    if (m && (m->n_in != 12 || K < 1 || K > 1024))
+        return set_error(GMC_EINVAL, "gmc_world_set_source_model: needs an internal model (12 inputs) and K in 1..1024");
+    std::lock_guard<std::mutex> lk(w->mu);
+    w->src_model = m;
+    w->src_K = K;
     return GMC_OK;
 }
 
@@ -702,6 +811,8 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
         return set_error(GMC_EINVAL, "gmc_transport_step: sampler must be GMC or MC");
     if (sampler == GMC_SAMPLER_GMC && (!m || K < 1 || K > 1024))
         return set_error(GMC_EINVAL, "gmc_transport_step: GMC needs a model and K in 1..1024");
+    if (sampler == GMC_SAMPLER_GMC && m->n_in != 10)
+        return set_error(GMC_EINVAL, "gmc_transport_step: the model is not a boundary model (10 inputs)");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = w->n_alive;
     if (n > 0) {

@@ -7,7 +7,7 @@ into the on-disk blob that the C library parses.  Every generator takes an
 explicit integer seed and uses numpy's PCG64, so any input can be re-created
 from its seed alone.
 
-Workload recipes (sizes and laws follow the paper's workloads, see DESIGN.md):
+Workload recipes (sizes and laws follow the paper's workloads):
 
 * entry conditions of a cell transmission in the canonical left-entry frame
   (paper, "Network Architecture and Inputs", eq. 10, and "Transport
@@ -16,7 +16,13 @@ Workload recipes (sizes and laws follow the paper's workloads):
   y_in ~ U(0, 1) on the left face, and a cosine-law entry direction.  For a
   flatland cosine law the pdf of theta is cos(theta)/2 on (-pi/2, pi/2), which
   makes sin(theta_in) uniform on (-1, 1); we draw sin(theta_in) directly.
-* velocity-network weights: fully connected 10 -> H -> H -> H -> H -> 5,
+* conditions of the internal (volumetric-source) model: the same ln tau and c
+  laws, a birth point (x, y) uniform in the unit cell and an isotropic birth
+  direction phi ~ U[0, 2 pi) given as (cos phi, sin phi) (paper, "Network
+  Architecture and Inputs": the internal model is conditioned on the birth
+  position and direction instead of the entry height and angle).
+* velocity-network weights: fully connected n_in -> H -> H -> H -> H -> 5
+  (n_in = 10 for the boundary model, 12 for the internal model),
   every weight and bias U(-1/sqrt(fan_in), +1/sqrt(fan_in)) (the usual
   default initialisation of a linear layer), float32.
 * noise z ~ N(0, I_5) when a caller wants to hand the sampler its noise
@@ -30,7 +36,8 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-N_IN = 10   # x (5), t (1), condition (4)
+N_IN = 10            # boundary model: x (5), t (1), condition (4)
+N_IN_INTERNAL = 12   # internal (volumetric-source) model: x (5), t (1), condition (6)
 N_OUT = 5   # exit state: position, cos, sin, log path, face
 N_LAYERS = 5
 
@@ -92,6 +99,49 @@ def fixed_cell_conditions(n: int, tau: float, c: float, seed: int) -> Conditions
                       np.full(n, np.float32(c), np.float32), y_in, sin_th)
 
 
+@dataclass
+class InternalConditions:
+    """Structure-of-arrays batch of birth conditions for the internal (volumetric-source) model:
+    optical side ln tau, scattering ratio c, birth position (x, y) in the unit cell and birth
+    direction (cos phi, sin phi) in the cell's own frame (all float32, length n)."""
+    log_tau: np.ndarray
+    c: np.ndarray
+    x: np.ndarray
+    y: np.ndarray
+    cos_phi: np.ndarray
+    sin_phi: np.ndarray
+
+    def __len__(self) -> int:
+        return int(self.log_tau.shape[0])
+
+    def subset(self, idx) -> "InternalConditions":
+        return InternalConditions(*(a[idx].copy() for a in (self.log_tau, self.c, self.x, self.y,
+                                                             self.cos_phi, self.sin_phi)))
+
+
+def internal_conditions(n: int, seed: int, log_tau_range=(LOG_TAU_MIN, LOG_TAU_MAX),
+                        c_range=(0.0, 1.0)) -> InternalConditions:
+    """Mixed-cell births: ln tau, c uniform on their ranges, position uniform in the cell,
+    isotropic direction (phi uniform on [0, 2 pi))."""
+    g = rng(seed)
+    lo, hi = log_tau_range
+    log_tau = (lo + (hi - lo) * g.random(n)).astype(np.float32)
+    c = (c_range[0] + (c_range[1] - c_range[0]) * g.random(n)).astype(np.float32)
+    x = _open01(g, n)
+    y = _open01(g, n)
+    phi = 2.0 * math.pi * g.random(n)
+    return InternalConditions(log_tau, c, x, y, np.cos(phi).astype(np.float32),
+                              np.sin(phi).astype(np.float32))
+
+
+def fixed_internal_conditions(n: int, tau: float, c: float, seed: int) -> InternalConditions:
+    """One material for every birth; uniform position, isotropic direction."""
+    b = internal_conditions(n, seed)
+    b.log_tau[:] = np.float32(math.log(tau))
+    b.c[:] = np.float32(c)
+    return b
+
+
 def normal_incidence_conditions(n: int, tau: float, c: float, seed: int) -> Conditions:
     """A beam along +x (sin theta = 0) at uniform entry height."""
     g = rng(seed)
@@ -109,8 +159,8 @@ def noise(n: int, seed: int) -> np.ndarray:
 # velocity-network weights
 # --------------------------------------------------------------------------------------
 
-def layer_dims(hidden: int):
-    return [(hidden, N_IN), (hidden, hidden), (hidden, hidden), (hidden, hidden), (N_OUT, hidden)]
+def layer_dims(hidden: int, n_in: int = N_IN):
+    return [(hidden, n_in), (hidden, hidden), (hidden, hidden), (hidden, hidden), (N_OUT, hidden)]
 
 
 @dataclass
@@ -122,6 +172,7 @@ class Weights:
     act_scale: np.ndarray = field(default_factory=lambda: np.ones(N_LAYERS, np.float32))
     w_scale: np.ndarray = field(default_factory=lambda: np.ones(N_LAYERS, np.float32))
     seed: int = 0
+    n_in: int = N_IN          # 10: boundary model, 12: internal model
 
     def n_params(self) -> int:
         return int(sum(w.size + bb.size for w, bb in zip(self.W, self.b)))
@@ -134,7 +185,7 @@ def pow2_ceil_scale(amax: float, fmax: float = 448.0) -> float:
     return float(2.0 ** math.ceil(math.log2(amax / fmax)))
 
 
-def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5) -> Weights:
+def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5, n_in: int = N_IN) -> Weights:
     """Seeded random-init network, U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for W and b.
 
     The per-layer FP8 scales are stored with the weights: the weight scale is the
@@ -145,18 +196,18 @@ def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5) -> Weig
     """
     g = rng(seed)
     W, b = [], []
-    for (o, i) in layer_dims(hidden):
+    for (o, i) in layer_dims(hidden, n_in):
         bound = 1.0 / math.sqrt(i)
         W.append(g.uniform(-bound, bound, size=(o, i)).astype(np.float32))
         b.append(g.uniform(-bound, bound, size=(o,)).astype(np.float32))
     w_scale = np.array([pow2_ceil_scale(float(np.abs(w).max())) for w in W], np.float32)
     a_scale = np.full(N_LAYERS, np.float32(act_scale), np.float32)
-    return Weights(hidden, W, b, a_scale, w_scale, seed)
+    return Weights(hidden, W, b, a_scale, w_scale, seed, n_in)
 
 
 def pack_blob(w: Weights) -> bytes:
     """Serialise to the versioned little-endian blob read by gmc_model_create()."""
-    hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, N_IN, w.hidden, N_OUT, N_LAYERS, 0,
+    hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, w.n_in, w.hidden, N_OUT, N_LAYERS, 0,
                     int(w.seed) & 0xFFFFFFFF, 0,
                     *[float(x) for x in w.act_scale], *[float(x) for x in w.w_scale])
     parts = [hdr]
@@ -169,21 +220,21 @@ def pack_blob(w: Weights) -> bytes:
 def unpack_blob(blob: bytes) -> Weights:
     fields = _HDR.unpack_from(blob, 0)
     magic, version, n_in, hidden, n_out, n_layers, _flags, seed, _res = fields[:9]
-    if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in != N_IN or n_out != N_OUT \
-            or n_layers != N_LAYERS:
+    if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in not in (N_IN, N_IN_INTERNAL) \
+            or n_out != N_OUT or n_layers != N_LAYERS:
         raise ValueError("not a GMC weights blob of a supported version")
     act = np.array(fields[9:14], np.float32)
     wsc = np.array(fields[14:19], np.float32)
     off = _HDR.size
     W, b = [], []
-    for (o, i) in layer_dims(hidden):
+    for (o, i) in layer_dims(hidden, n_in):
         W.append(np.frombuffer(blob, np.float32, o * i, off).reshape(o, i).copy())
         off += 4 * o * i
         b.append(np.frombuffer(blob, np.float32, o, off).copy())
         off += 4 * o
     if off != len(blob):
         raise ValueError("weights blob has trailing or missing bytes")
-    return Weights(hidden, W, b, act, wsc, seed)
+    return Weights(hidden, W, b, act, wsc, seed, n_in)
 
 
 def save_blob(w: Weights, path: str) -> None:

@@ -8,10 +8,11 @@ from . import binding
 
 def run_problem(world: binding.World, problem, n_hist: int, seed: int, sampler: int,
                 model: binding.Model | None = None, K: int = 16, chunk: int | None = None,
-                stream=None, integrator: str = "euler") -> dict:
+                stream=None, integrator: str = "euler", source_model=None, source_K: int = 16) -> dict:
     """Runs histories [0, n_hist) of `problem` to completion.  Returns the tallies summed over
     histories (divide by n_hist for per-source-particle values) and step statistics."""
     world.set_integrator(integrator)
+    world.set_source_model(source_model, source_K)
     pid = world.add_problem(problem, seed, stream)
     chunk = world.capacity // 2 if chunk is None else chunk
     injected, steps, transmissions = 0, 0, 0

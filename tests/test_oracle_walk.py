@@ -1,7 +1,7 @@
 """Pins for the oracle's analog walk through one square cell (paper section "Monte Carlo
 Method": flight lengths of eq. 4, implicit capture of eqs. 5-6).
 
-Closed forms used (derived from eq. 4 for a unit square, see DESIGN.md):
+Closed forms used (derived from eq. 4 for a unit square):
   P1  normal incidence, no scattering: P(right) = exp(-tau), path 1.
   P2  cosine-law entry, no scattering: face fractions by 1-D quadrature.
   P3  pure-scattering flights, uniform cosine-law entry on one face: E[path] = pi/4 for
