@@ -120,10 +120,11 @@ def cpu_baseline_analog(tau=100.0, budget_s=8.0):
             "sample": f"{n} analog transmissions at tau={tau:g}, c=1, {dt:.1f} s"}
 
 
-def bench_transport(binding, inputs, w512):
+def bench_transport(binding, inputs, w512, w512_internal=None):
     """Full 2-D transport: 32 x 32 unit cells, checkerboard (tau, c) = (0.5, 0.5) / (50, 0.99),
     isotropic unit source in the central 4 x 4 cells, vacuum boundaries, 10^6 histories, FP64
-    tallies; analog sampler and generative sampler (BF16, H = 512, K = 16)."""
+    tallies; analog sampler and generative sampler (BF16, H = 512: Euler K = 16 and 32, RK4 with
+    12 steps, and RK4 with births sampled by the internal model when its weights exist)."""
     import torch
     from paper_2512_13965_amd import transport
     prob = inputs.checkerboard_problem(32)
@@ -131,14 +132,20 @@ def bench_transport(binding, inputs, w512):
     out = {"workload": "32x32 checkerboard (0.5,0.5)/(50,0.99), central 4x4 source, vacuum, 1e6 histories"}
     world = binding.World(1 << 20, 2, 1 << 12)
     model = binding.Model(inputs.pack_blob(w512), "bf16")
+    src = None if w512_internal is None else binding.Model(inputs.pack_blob(w512_internal), "bf16")
     flux = {}
-    for name, smp, m, K in (("analog", binding.SAMPLER_MC, None, 16),
-                            ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, model, 16),
-                            ("gmc_bf16_h512_k32", binding.SAMPLER_GMC, model, 32)):
-        transport.run_problem(world, prob, 20_000, 7, smp, m, K)          # warm-up
+    runs = [("analog", binding.SAMPLER_MC, None, 16, "euler", None),
+            ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, model, 16, "euler", None),
+            ("gmc_bf16_h512_k32", binding.SAMPLER_GMC, model, 32, "euler", None),
+            ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, model, 12, "rk4", None)]
+    if src is not None:
+        runs.append(("gmc_bf16_h512_rk4x12_internal_births", binding.SAMPLER_GMC, model, 12, "rk4", src))
+    for name, smp, m, K, integ, sm in runs:
+        kw = dict(integrator=integ, source_model=sm, source_K=K)
+        transport.run_problem(world, prob, 20_000, 7, smp, m, K, **kw)          # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = transport.run_problem(world, prob, n, 1, smp, m, K)
+        r = transport.run_problem(world, prob, n, 1, smp, m, K, **kw)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         bal = r["absorbed"].sum() + r["leak"].sum() + r["cutoff"].sum()
@@ -147,13 +154,17 @@ def bench_transport(binding, inputs, w512):
                      "transmissions_per_s": r["transmissions"] / dt, "steps": r["steps"],
                      "balance_error": abs(bal - n) / n, "leak_per_history": float(r["leak"].sum() / n)}
     model.close()
+    if src is not None:
+        src.close()
     world.close()
     ref = flux["analog"]
-    for name in ("gmc_bf16_h512_k16", "gmc_bf16_h512_k32"):
-        out[name]["flux_rel_l1_vs_analog"] = float(np.abs(flux[name] - ref).sum() / np.abs(ref).sum())
+    for name in flux:
+        if name != "analog":
+            out[name]["flux_rel_l1_vs_analog"] = float(np.abs(flux[name] - ref).sum() / np.abs(ref).sum())
     out["note"] = ("the generative runs use the weights fitted to this library's analog walk "
-                   "(paper_2512_13965_amd/weights/gmc_h512.bin); flux_rel_l1_vs_analog is the "
-                   "L1 distance of the per-source-particle flux maps")
+                   "(paper_2512_13965_amd/weights/gmc_h512.bin, and gmc_h512_internal.bin for the "
+                   "births); flux_rel_l1_vs_analog is the L1 distance of the per-source-particle "
+                   "flux maps")
     return out
 
 
@@ -326,6 +337,8 @@ def main():
     w5 = inputs.random_weights(512, 1)
     wpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512.bin")
     w5t = inputs.load_blob(wpath) if os.path.exists(wpath) else w5     # trained (cfg2)
+    ipath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512_internal.bin")
+    w5i = inputs.load_blob(ipath) if os.path.exists(ipath) else None
     condB = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
     outB = binding.DeviceExit.empty(NB, dev)
     wide = []
@@ -353,7 +366,7 @@ def main():
                                              and x["integrator"] == "rk4")
 
     if not args.no_transport:
-        res["transport"] = bench_transport(binding, inputs, w5t)
+        res["transport"] = bench_transport(binding, inputs, w5t, w5i)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests)
 
     if not args.no_cpu:

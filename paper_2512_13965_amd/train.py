@@ -1,9 +1,12 @@
-"""One-time fit of the boundary velocity network by conditional flow matching (paper section
-"Conditional Flow Matching", eq. 9; training data as in "Network Architecture and Inputs":
-pure-scattering Monte Carlo exits over a range of optical dimensions and entry states).
+"""One-time fit of a velocity network by conditional flow matching (paper section "Conditional
+Flow Matching", eq. 9; training data as in "Network Architecture and Inputs": pure-scattering
+Monte Carlo exits over a range of optical dimensions and entry states).  Two models: the
+boundary model (condition: ln tau, c, entry height, sin of the entry angle) and the internal
+model for particles born inside a cell (condition: ln tau, c, birth point, birth direction).
 
-Data come from this library's own analog walk (`mc_transmit`, continuous-absorption mode: the
-exit law of a walk whose flights are drawn from sigma_s = c tau), on the GPU.  Targets are the
+Data come from this library's own analog walk (`mc_transmit` / `mc_transmit_internal`,
+continuous-absorption mode: the exit law of a walk whose flights are drawn from
+sigma_s = c tau), on the GPU.  Targets are the
 5-dim exit encoding the sampler decodes:
   a0 = 2 pos - 1, (a1, a2) = exit direction, a3 = ln(path / L), a4 = face - 1.5 + u,
   u ~ U(-1/2, 1/2) (dequantisation: the face is recovered exactly by the decoder's thresholds
@@ -12,6 +15,8 @@ Loss (eq. 9, sigma_min = 0): E || v(x_t, t | c) - (x1 - x0) ||^2, x_t = (1 - t) 
 x0 ~ N(0, I), t ~ U[0, 1].  The fit itself is offline PyTorch (autograd), not the hot path.
 
 Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_amd/weights/gmc_h512.bin
+       python -m paper_2512_13965_amd.train --model internal --hidden 512 \
+           --out paper_2512_13965_amd/weights/gmc_h512_internal.bin
 """
 from __future__ import annotations
 
@@ -27,27 +32,36 @@ from . import binding, inputs
 LOG_TAU_TRAIN = (math.log(0.05), math.log(300.0))
 
 
-def make_dataset(n: int, seed: int, device="cuda"):
-    """(conditions [n, 4], targets [n, 5]) on `device`, from the GPU analog walk."""
-    cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
-    dc = binding.DeviceCond.from_host(cond, device)
-    ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
+def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
+    """(conditions [n, 4] (boundary) or [n, 6] (internal), targets [n, 5]) on `device`, from
+    the GPU analog walk."""
+    if kind == "internal":
+        cond = inputs.internal_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
+        dc = binding.DeviceCondInternal.from_host(cond, device)
+        ex = binding.mc_transmit_internal(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
+        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.x - 1.0, 2.0 * dc.y - 1.0,
+                             dc.cos_phi, dc.sin_phi], dim=1)
+    else:
+        cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
+        dc = binding.DeviceCond.from_host(cond, device)
+        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
+        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th], dim=1)
     torch.cuda.synchronize()
     g = torch.Generator(device=device).manual_seed(seed + 1)
     u = torch.rand(n, device=device, generator=g) - 0.5
     tgt = torch.stack([2.0 * ex.pos - 1.0, ex.dir_cos, ex.dir_sin,
                        torch.log(torch.clamp(ex.path, min=1e-6)),
                        ex.face.float() - 1.5 + u], dim=1)
-    feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th], dim=1)
     return feats, tgt
 
 
 class VelocityMLP(torch.nn.Module):
-    """Same network as the sampler kernels: 10 -> H (SiLU) x4 -> 5, input [x, t, condition]."""
+    """Same network as the sampler kernels: n_in -> H (SiLU) x4 -> 5, input [x, t, condition]
+    (n_in = 10 boundary, 12 internal)."""
 
-    def __init__(self, hidden: int):
+    def __init__(self, hidden: int, n_in: int = inputs.N_IN):
         super().__init__()
-        dims = inputs.layer_dims(hidden)
+        dims = inputs.layer_dims(hidden, n_in)
         self.layers = torch.nn.ModuleList([torch.nn.Linear(i, o) for (o, i) in dims])
 
     def forward(self, x, t, c):
@@ -62,7 +76,8 @@ class VelocityMLP(torch.nn.Module):
         W = [l.weight.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
         b = [l.bias.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
         w_scale = np.array([inputs.pow2_ceil_scale(float(np.abs(x).max())) for x in W], np.float32)
-        return inputs.Weights(W[0].shape[0], W, b, np.asarray(act_scale, np.float32), w_scale, seed)
+        return inputs.Weights(W[0].shape[0], W, b, np.asarray(act_scale, np.float32), w_scale, seed,
+                              n_in=W[0].shape[1])
 
 
 @torch.no_grad()
@@ -86,12 +101,12 @@ def activation_scales(model: VelocityMLP, feats, tgt, n=65536, seed=0):
 
 
 def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=20251213,
-          log_every=1000, device="cuda"):
+          log_every=1000, device="cuda", kind="boundary"):
     torch.manual_seed(seed)
     t0 = time.time()
-    feats, tgt = make_dataset(n_data, seed, device)
-    print(f"data: {n_data} exits in {time.time() - t0:.1f}s", flush=True)
-    model = VelocityMLP(hidden).to(device)
+    feats, tgt = make_dataset(n_data, seed, device, kind)
+    print(f"data: {n_data} {kind} exits in {time.time() - t0:.1f}s", flush=True)
+    model = VelocityMLP(hidden, 5 + 1 + feats.shape[1]).to(device)
     opt = torch.optim.AdamW(model.parameters(), lr=lr, weight_decay=1e-4)
     sched = torch.optim.lr_scheduler.OneCycleLR(opt, max_lr=lr, total_steps=steps, pct_start=0.05)
     g = torch.Generator(device=device).manual_seed(seed + 2)
@@ -122,9 +137,10 @@ def main():
     ap.add_argument("--data", type=int, default=4_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--model", choices=("boundary", "internal"), default="boundary")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    w = train(a.hidden, a.data, a.steps, a.batch, a.lr)
+    w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)
     inputs.save_blob(w, a.out)
     print("saved", a.out, "act scales", list(w.act_scale), "w scales", list(w.w_scale), flush=True)
 
