@@ -168,6 +168,55 @@ def bench_transport(binding, inputs, w512, w512_internal=None):
     return out
 
 
+def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000):
+    """The paper's two benchmark problems at its mesh size and cross sections ("Benchmark
+    Performance"; layouts defined by inputs.lattice_problem / inputs.hohlraum_problem): the
+    7 x 7 cm lattice (112^2 cells, central volumetric source) and the 1.3 x 1.3 cm hohlraum
+    (112^2 cells, isotropic incident flux on the left side).  Analog MC, and the generative
+    sampler (BF16, H = 512) with Euler K = 16 and RK4 x 12; for the lattice also RK4 x 12 with
+    births from the internal model.  flux_rel_l1_vs_mc is the L1 distance of the flux maps to
+    the analog run; mc_noise_rel_l1 is the same distance between two analog runs with
+    different seeds (the statistical floor at this history count)."""
+    import torch
+    from paper_2512_13965_amd import transport
+    out = {"histories": n}
+    model = binding.Model(inputs.pack_blob(w512), "bf16")
+    src = None if w512_internal is None else binding.Model(inputs.pack_blob(w512_internal), "bf16")
+    world = binding.World(1 << 20, 2, 1 << 14)
+    for pname, prob in (("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))):
+        runs = [("analog", binding.SAMPLER_MC, None, 16, "euler", None),
+                ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, model, 16, "euler", None),
+                ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, model, 12, "rk4", None)]
+        if src is not None and prob.src_face < 0:
+            runs.append(("gmc_bf16_h512_rk4x12_internal_births", binding.SAMPLER_GMC, model, 12, "rk4", src))
+        res, flux = {}, {}
+        for name, smp, m, K, integ, sm in runs:
+            kw = dict(integrator=integ, source_model=sm, source_K=K)
+            transport.run_problem(world, prob, 5_000, 7, smp, m, K, **kw)          # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = transport.run_problem(world, prob, n, 1, smp, m, K, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            flux[name] = r["flux"] / n
+            res[name] = {"seconds": dt, "histories_per_s": n / dt, "transmissions": int(r["transmissions"]),
+                         "transmissions_per_s": r["transmissions"] / dt,
+                         "transmissions_per_history": r["transmissions"] / n,
+                         "leak_per_history": float(r["leak"].sum() / n)}
+        ref = flux["analog"]
+        l1 = lambda a: float(np.abs(a - ref).sum() / np.abs(ref).sum())
+        for name in flux:
+            if name != "analog":
+                res[name]["flux_rel_l1_vs_mc"] = l1(flux[name])
+        res["mc_noise_rel_l1"] = l1(transport.run_problem(world, prob, n, 2, binding.SAMPLER_MC)["flux"] / n)
+        out[pname] = res
+    world.close()
+    model.close()
+    if src is not None:
+        src.close()
+    return out
+
+
 def bench_serving(binding, inputs, w512, n_req):
     """Continuous batching of a Poisson stream of transport requests of the config-3 kind
     (grids 16^2..128^2, per-cell tau log-uniform in [0.1, 200], c ~ U[0, 1]); histories per
@@ -367,6 +416,7 @@ def main():
 
     if not args.no_transport:
         res["transport"] = bench_transport(binding, inputs, w5t, w5i)
+        res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests)
 
     if not args.no_cpu:

@@ -181,12 +181,23 @@ typedef struct gmc_world gmc_world;
 
 /* One transport problem: nx * ny square cells of side L (physical length), cell (i, j) at
  * index j * nx + i (i along x).  tau[cell] = sigma_t * L (>= 0) and c[cell] = sigma_s / sigma_t
- * (in [0, 1]) are host FP64 arrays read during gmc_problem_add.  An isotropic unit source is
- * uniform over the cells [src_x0, src_x0 + src_nx) x [src_y0, src_y0 + src_ny).  Boundaries are
- * vacuum (reflect = 0) or specular (reflect = 1).  A history ends when it leaves the domain or
- * when its weight drops below w_min after a cell visit (the weight is then tallied as cutoff).
+ * (in [0, 1]) are host FP64 arrays read during gmc_problem_add.  Boundaries are vacuum
+ * (reflect = 0) or specular (reflect = 1).  A history ends when it leaves the domain or when its
+ * weight drops below w_min after a cell visit (the weight is then tallied as cutoff).
+ * Sources (one unit-weight particle per history):
+ *   src_face = -1: isotropic volumetric source, uniform over the cells
+ *     [src_x0, src_x0 + src_nx) x [src_y0, src_y0 + src_ny) (a birth picks the cell with the
+ *     first Philox word, the point with the next two, the angle with the fourth);
+ *   src_face = f in 0..3 (bottom, right, top, left): surface source of isotropic incident flux
+ *     on that side of the domain (the hohlraum drive of the paper's second benchmark): the
+ *     source cells must be a strip along that side (f = 3: src_x0 = 0, src_nx = 1; f = 1:
+ *     src_x0 = nx - 1, src_nx = 1; f = 0: src_y0 = 0, src_ny = 1; f = 2: src_y0 = ny - 1,
+ *     src_ny = 1) and the boundaries vacuum.  A birth enters a uniformly picked source cell
+ *     through face f at a uniform height (canonical y_in) with a cosine-law direction
+ *     (canonical sin theta = 2 u - 1), and its first transmission is that cell's.
  * History h draws its birth from Philox key = seed, counter (h, 0, 0, 3); the k-th cell it
- * visits (k = 0 for the birth cell) uses random stream id h + 2^32 k for its transmission. */
+ * visits (k = 0 for a volumetric birth cell; a surface birth starts at k = 1) uses random
+ * stream id h + 2^32 k for its transmission. */
 typedef struct {
     int32_t nx, ny;
     double L;
@@ -195,6 +206,7 @@ typedef struct {
     int32_t reflect;
     double w_min;
     uint64_t seed;
+    int32_t src_face;
 } gmc_problem_desc;
 
 /* Device bytes gmc_world_create would allocate for these capacities (admission control). */
@@ -206,13 +218,15 @@ int gmc_world_footprint(int64_t bank_capacity, int32_t max_problems, int64_t max
 int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_cells, gmc_world **out);
 int gmc_world_destroy(gmc_world *w);
 /* Adds a problem: takes a slot and nx * ny cells, uploads the materials, zeroes its tallies.
- * Synchronises `stream`.  GMC_ENOMEM when no slot or not enough contiguous free cells. */
+ * Synchronises `stream`.  GMC_EINVAL for a bad grid, material or source description (see
+ * gmc_problem_desc); GMC_ENOMEM when no slot or not enough contiguous free cells. */
 int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid, void *stream);
 /* Frees a problem's slot and cells; GMC_EINVAL while it still has particles in flight. */
 int gmc_problem_remove(gmc_world *w, int32_t pid);
 /* Births of histories [h_begin, h_begin + count) of problem pid (ids below 2^32): source
- * sampling, the first leg in the birth cell (the analog walk with continuous absorption, or the
- * internal model set by gmc_world_set_source_model), its tally, and the move to the neighbour.  Survivors join the bank.  GMC_ENOMEM if count exceeds
+ * sampling, and for a volumetric source the first leg in the birth cell (the analog walk with
+ * continuous absorption, or the internal model set by gmc_world_set_source_model), its tally,
+ * and the move to the neighbour (a surface source's births enter their cell directly).  Survivors join the bank.  GMC_ENOMEM if count exceeds
  * the free bank slots.  Synchronises `stream`; *n_alive_out (optional) = particles in flight. */
 int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count, void *stream,
                      int64_t *n_alive_out);

@@ -63,7 +63,7 @@ def lib():
                                                ctypes.c_int]
         L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                    ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                     ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int]
         _lib = L
     return _lib
@@ -141,8 +141,8 @@ def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -
     sc = np.zeros(3)
     lib().orc_transport(problem.nx, problem.ny, problem.L, _p(tau), _p(c), problem.src_x0,
                         problem.src_y0, problem.src_nx, problem.src_ny, int(problem.reflect),
-                        problem.w_min, seed, h_begin, h_end, _p(flux), _p(absorbed), _p(sc),
-                        nthreads)
+                        int(getattr(problem, "src_face", -1)), problem.w_min, seed, h_begin, h_end,
+                        _p(flux), _p(absorbed), _p(sc), nthreads)
     return dict(flux=flux, absorbed=absorbed, leak=sc[0], cutoff=sc[1], events=sc[2])
 
 

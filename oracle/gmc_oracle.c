@@ -266,6 +266,7 @@ typedef struct {
     int32_t src_x0, src_y0, src_nx, src_ny;
     int32_t reflect;            /* 0 vacuum, 1 specular reflection at the domain boundary */
     double w_min;               /* weight cutoff */
+    int32_t src_face;           /* -1 volumetric source; 0..3 isotropic incident flux on that side */
 } orc_problem;
 
 typedef struct {
@@ -291,53 +292,80 @@ static double visit_tally(const orc_problem *p, int cell, double w_in, double le
     return w_in - dw;
 }
 
+/* Inward direction through side f of a cell for an entry angle theta measured from the
+ * inward normal, counter-clockwise positive (the canonical frame of entry side f, turned
+ * back to the global frame): written out per side rather than through rot(). */
+static void inward_direction(int f, double cth, double sth, double *gx, double *gy)
+{
+    switch (f) {
+    case 3: *gx = cth; *gy = sth; break;      /* left side: normal +x */
+    case 0: *gx = -sth; *gy = cth; break;     /* bottom side: normal +y */
+    case 1: *gx = -cth; *gy = -sth; break;    /* right side: normal -x */
+    default: *gx = sth; *gy = -cth; break;    /* top side: normal -y */
+    }
+}
+
 static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tally *t)
 {
-    /* birth: uniform cell of the source block, uniform point, isotropic direction */
+    /* birth: uniform cell of the source block (or strip) */
     uint32_t r[4];
     draw4(seed, (uint64_t)h, 0u, ORC_TAG_SOURCE, r);
     uint32_t nsrc = (uint32_t)(p->src_nx * p->src_ny);
     uint32_t pick = (uint32_t)(((uint64_t)r[0] * nsrc) >> 32);
     int ci = p->src_x0 + (int)(pick % (uint32_t)p->src_nx);
     int cj = p->src_y0 + (int)(pick / (uint32_t)p->src_nx);
-    double x = u01_open(r[1]), y = u01_open(r[2]);
-    double phi = 2.0 * ORC_PI * orc_u01(r[3]);
-    double gx = cos(phi), gy = sin(phi);
-    double w = 1.0;
-    uint32_t event = 0;
     int cell = cj * p->nx + ci;
-
-    /* first leg: analog walk from the interior birth point (global orientation) */
+    double gx, gy, w = 1.0, pos = 0.0, y_in = 0.0;
+    uint32_t event = 0;
+    int face = 0, entry = 0;
     orc_exit e;
-    orc_walk(p->tau[cell], p->c[cell], 0, x, y, gx, gy, seed,
-             (uint64_t)h | ((uint64_t)event << 32), &e);
-    t->events += 1.0;
-    int face = e.face;
-    double pos = e.pos;
-    gx = e.u; gy = e.v;
-    w = visit_tally(p, cell, w, e.len, t);
 
+    if (p->src_face >= 0) {
+        /* surface source: enter through side src_face at a uniform canonical height with the
+         * cosine law for the angle to the inward normal (sin theta uniform on (-1, 1)); the
+         * first transmission is this cell's, cell visit 1 */
+        entry = p->src_face;
+        y_in = u01_open(r[1]);
+        double s = 2.0 * u01_open(r[2]) - 1.0;
+        inward_direction(entry, sqrt(1.0 - s * s), s, &gx, &gy);
+        event = 1;
+    } else {
+        /* volumetric source: uniform point, isotropic direction; first leg by the analog walk
+         * from the interior birth point (global orientation), cell visit 0 */
+        double x = u01_open(r[1]), y = u01_open(r[2]);
+        double phi = 2.0 * ORC_PI * orc_u01(r[3]);
+        orc_walk(p->tau[cell], p->c[cell], 0, x, y, cos(phi), sin(phi), seed,
+                 (uint64_t)h | ((uint64_t)event << 32), &e);
+        t->events += 1.0;
+        face = e.face;
+        pos = e.pos;
+        gx = e.u; gy = e.v;
+        w = visit_tally(p, cell, w, e.len, t);
+    }
+
+    int entering = (p->src_face >= 0);      /* already at the entry of its first cell */
     for (;;) {
-        if (w < p->w_min) { t->cutoff += w; return; }
-        /* stage 4: move to the neighbour through `face` */
-        int ni = ci, nj = cj;
-        if (face == 0) nj -= 1; else if (face == 1) ni += 1; else if (face == 2) nj += 1; else ni -= 1;
-        int entry;
-        double y_in;
-        if (ni < 0 || nj < 0 || ni >= p->nx || nj >= p->ny) {
-            if (!p->reflect) { t->leak += w; return; }
-            /* specular reflection: re-enter the same cell through the same face */
-            ni = ci; nj = cj;
-            entry = face;
-            y_in = 1.0 - pos;
-            if (face == 0 || face == 2) gy = -gy; else gx = -gx;
-        } else {
-            entry = (face + 2) & 3;
-            y_in = pos;
+        if (!entering) {
+            if (w < p->w_min) { t->cutoff += w; return; }
+            /* stage 4: move to the neighbour through `face` */
+            int ni = ci, nj = cj;
+            if (face == 0) nj -= 1; else if (face == 1) ni += 1; else if (face == 2) nj += 1; else ni -= 1;
+            if (ni < 0 || nj < 0 || ni >= p->nx || nj >= p->ny) {
+                if (!p->reflect) { t->leak += w; return; }
+                /* specular reflection: re-enter the same cell through the same face */
+                ni = ci; nj = cj;
+                entry = face;
+                y_in = 1.0 - pos;
+                if (face == 0 || face == 2) gy = -gy; else gx = -gx;
+            } else {
+                entry = (face + 2) & 3;
+                y_in = pos;
+            }
+            ci = ni; cj = nj;
+            cell = cj * p->nx + ci;
+            event += 1;
         }
-        ci = ni; cj = nj;
-        cell = cj * p->nx + ci;
-        event += 1;
+        entering = 0;
         /* stage 1: rotate into the canonical left-entry frame */
         int k = (entry + 1) & 3;
         double U, Vc;
@@ -378,10 +406,10 @@ static void *tr_worker(void *arg)
  * number of source particles).  out_scalars = {leak, cutoff, events}. */
 void orc_transport(int32_t nx, int32_t ny, double L, const double *tau, const double *c,
                    int32_t src_x0, int32_t src_y0, int32_t src_nx, int32_t src_ny, int32_t reflect,
-                   double w_min, uint64_t seed, uint32_t h_begin, uint32_t h_end, double *flux,
-                   double *absorbed, double *out_scalars, int nthreads)
+                   int32_t src_face, double w_min, uint64_t seed, uint32_t h_begin, uint32_t h_end,
+                   double *flux, double *absorbed, double *out_scalars, int nthreads)
 {
-    orc_problem p = {nx, ny, L, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min};
+    orc_problem p = {nx, ny, L, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face};
     int ncell = nx * ny;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;

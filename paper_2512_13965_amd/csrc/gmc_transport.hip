@@ -10,8 +10,9 @@
 //            flux / absorption tallies (FP64 atomics), rotation back to the global frame, move
 //            to the neighbour cell or leave / cut off, and compaction of the survivors into the
 //            other bank with one atomic per wave (ballot + mbcnt).
-// Births draw a source particle and walk its first leg inside the birth cell with the analog
-// walk (the paper's separate volumetric-source network is not part of this library).
+// Volumetric births draw a source particle and take its first leg inside the birth cell with the
+// analog walk or the internal (volumetric-source) model; surface-source births enter their
+// boundary cell directly.
 // Random numbers depend only on (problem seed, history id, cell-visit index): a history's
 // result does not depend on which other problems share the bank or on its slot.
 #include <hip/hip_runtime.h>
@@ -38,6 +39,7 @@ struct ProblemDev {
     int32_t reflect;
     double w_min;
     uint64_t seed;
+    int32_t src_face;              // -1 volumetric, else the domain side of a surface source
 };
 
 struct BankDev {
@@ -192,6 +194,38 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
         alive = nx.alive;
     }
     append(alive, nx, pid, w_out, h, 1u, out, counter, pcount);
+}
+
+// Surface-source births of histories [h0, h0 + count): a uniformly picked cell of the source
+// strip, entered through side f of the domain at a uniform canonical height with a cosine-law
+// canonical direction (sin theta = 2u - 1), rotated to the global frame; no tally yet, the
+// first transmission (cell visit 1) is the next transport step's.
+__global__ __launch_bounds__(256) void surface_birth_kernel(CellsDev cd, int32_t pid, uint32_t h0,
+                                                            int64_t count, BankDev out,
+                                                            unsigned long long *counter,
+                                                            unsigned long long *pcount)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool alive = false;
+    Next nx{};
+    uint32_t h = 0;
+    if (t < count) {
+        const ProblemDev P = cd.prob[pid];
+        h = h0 + (uint32_t)t;
+        const U4 r = draw4(P.seed, (uint64_t)h, 0u, kTagSource);
+        const uint32_t nsrc = (uint32_t)(P.snx * P.sny);
+        const uint32_t pick = __umulhi(r.a, nsrc);
+        const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
+        const int f = P.src_face;
+        const float s = 2.0f * u01_open(r.c) - 1.0f;
+        const float cth = sqrtf(fmaxf(1.0f - s * s, 0.0f));
+        nx.cell = (int32_t)(P.cell0 + (int64_t)cj * P.nx + ci);
+        nx.entry = f;
+        nx.yin = u01_open(r.b);
+        rot_quarter((f + 1) & 3, cth, s, nx.gx, nx.gy);
+        alive = true;
+    }
+    append(alive, nx, pid, 1.0, h, 1u, out, counter, pcount);
 }
 
 // Source births for the generative internal model: birth cell, position and direction of
@@ -365,6 +399,7 @@ struct gmc_world {
     std::vector<int64_t> alive_pp;
     std::vector<ProblemDev> prob_host;
     std::vector<char> in_use;
+    std::vector<int32_t> src_face;      // per problem slot: -1 volumetric, else a surface side
     std::vector<std::pair<int64_t, int64_t>> free_cells;   // [begin, end) ranges
     std::mutex mu;
 
@@ -488,6 +523,7 @@ int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_ce
     w->alive_pp.assign(max_problems, 0);
     w->prob_host.assign(max_problems, ProblemDev{});
     w->in_use.assign(max_problems, 0);
+    w->src_face.assign(max_problems, -1);
     w->free_cells.push_back({0, max_cells});
     *out = w;
     return GMC_OK;
@@ -518,6 +554,18 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     if (d->src_nx <= 0 || d->src_ny <= 0 || d->src_x0 < 0 || d->src_y0 < 0 ||
         d->src_x0 + d->src_nx > d->nx || d->src_y0 + d->src_ny > d->ny)
         return set_error(GMC_EINVAL, "gmc_problem_add: source block outside the grid");
+    if (d->src_face < -1 || d->src_face > 3)
+        return set_error(GMC_EINVAL, "gmc_problem_add: src_face must be -1 (volumetric) or a side 0..3");
+    if (d->src_face >= 0) {
+        const int f = d->src_face;
+        const bool strip = (f == 3) ? (d->src_x0 == 0 && d->src_nx == 1)
+                         : (f == 1) ? (d->src_x0 == d->nx - 1 && d->src_nx == 1)
+                         : (f == 0) ? (d->src_y0 == 0 && d->src_ny == 1)
+                                    : (d->src_y0 == d->ny - 1 && d->src_ny == 1);
+        if (!strip || d->reflect)
+            return set_error(GMC_EINVAL, "gmc_problem_add: a surface source needs a one-cell strip "
+                                         "along its side of the domain and vacuum boundaries");
+    }
     const int64_t n = (int64_t)d->nx * d->ny;
     for (int64_t i = 0; i < n; ++i)
         if (!(d->tau[i] >= 0.0) || !std::isfinite(d->tau[i]) || !(d->c[i] >= 0.0) || !(d->c[i] <= 1.0))
@@ -544,7 +592,7 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
         cf[i] = (float)d->c[i];
     }
     ProblemDev P{d->nx, d->ny, d->L, cell0, d->src_x0, d->src_y0, d->src_nx, d->src_ny,
-                 d->reflect ? 1 : 0, d->w_min, d->seed};
+                 d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(w->tau + cell0, d->tau, 8 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(w->c + cell0, d->c, 8 * n, hipMemcpyHostToDevice, s);
@@ -563,6 +611,7 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
         return set_hip_error(e, "gmc_problem_add: upload");
     }
     w->in_use[pid] = 1;
+    w->src_face[pid] = d->src_face;
     w->prob_host[pid] = P;
     w->alive_pp[pid] = 0;
     *pid_out = pid;
@@ -604,7 +653,10 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
         unsigned long long *ctr = w->cnt(which);
         // the bank's particle counter restarts at the number alive; per-problem counts continue
         hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(1), 0, s, ctr, (unsigned long long)w->n_alive, 1);
-        if (!w->src_model) {
+        if (w->src_face[pid] >= 0) {
+            hipLaunchKernelGGL(surface_birth_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(),
+                               pid, (uint32_t)h_begin, count, w->bank[which], ctr, ctr + 1);
+        } else if (!w->src_model) {
             hipLaunchKernelGGL(birth_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
                                (uint32_t)h_begin, count, w->bank[which], ctr, ctr + 1);
         } else {

@@ -253,10 +253,12 @@ def load_blob(path: str) -> Weights:
 
 @dataclass
 class Problem:
-    """A 2-D grid of nx * ny square cells of side L, per-cell (tau, c), a central source block.
+    """A 2-D grid of nx * ny square cells of side L, per-cell (tau, c), a source.
 
     Cell (i, j) has linear index j * nx + i (i along x).  tau = sigma_t * L.
-    The isotropic unit source is uniform over the source block's cells.
+    src_face = -1: isotropic unit source uniform over the source block's cells; src_face = f in
+    0..3 (bottom, right, top, left): isotropic incident flux on that side of the domain over the
+    source strip's cells (the block must be one cell thick along that side).
     """
     nx: int
     ny: int
@@ -269,6 +271,7 @@ class Problem:
     src_ny: int
     reflect: bool = False
     w_min: float = 1e-6
+    src_face: int = -1
 
     @property
     def n_cells(self) -> int:
@@ -313,3 +316,64 @@ def random_problem(seed: int, side_range=(16, 128), log_tau_range=(math.log(0.1)
     nh = int(round(10.0 ** (hist_log10_range[0] + (hist_log10_range[1] - hist_log10_range[0])
                             * g.random())))
     return Problem(n, n, 1.0, tau, c, s0, s0, s, s), nh
+
+
+def _from_sigmas(sig_a: np.ndarray, sig_s: np.ndarray, L: float):
+    """Per-cell (tau = sigma_t L, c = sigma_s / sigma_t) from cross sections in 1/cm."""
+    sig_t = sig_a + sig_s
+    return sig_t * L, np.where(sig_t > 0, sig_s / np.where(sig_t > 0, sig_t, 1.0), 1.0)
+
+
+def lattice_problem(cells_per_cm: int = 16) -> Problem:
+    """Heterogeneous lattice with the cross sections of the paper's first benchmark ("Benchmark
+    Performance"): a 7 x 7 cm square, 112 x 112 cells at 16 cells per cm; scattering background
+    sigma_a = 0, sigma_s = 1 /cm; absorbing blocks sigma_a = 9.5, sigma_s = 0.5 /cm; an
+    isotropic volumetric source in the central 1 x 1 cm block; vacuum boundaries.
+
+    The paper's figure with the layout is not part of its text; the layout here is defined by
+    this library: the 1 x 1 cm blocks (I, J), I, J in 1..5 with I + J even, other than the
+    central source block (3, 3), are absorbers (a periodic array, twelve blocks)."""
+    m = cells_per_cm
+    n = 7 * m
+    L = 1.0 / m
+    I = np.arange(n)[None, :] // m
+    J = np.arange(n)[:, None] // m
+    absorber = (I >= 1) & (I <= 5) & (J >= 1) & (J <= 5) & ((I + J) % 2 == 0) & ~((I == 3) & (J == 3))
+    sig_a = np.where(absorber, 9.5, 0.0).reshape(-1)
+    sig_s = np.where(absorber, 0.5, 1.0).reshape(-1)
+    tau, c = _from_sigmas(sig_a, sig_s, L)
+    return Problem(n, n, L, tau, c, 3 * m, 3 * m, m, m)
+
+
+HOHLRAUM_MATERIALS = {          # (sigma_a, sigma_s) in 1/cm, from the paper's second benchmark
+    "black": (50.0, 50.0),      # absorbing walls
+    "red": (5.0, 95.0),         # stripes
+    "green": (10.0, 90.0),      # framing regions
+    "blue": (95.0, 5.0),        # central absorber
+    "white": (0.0, 5.0),        # near vacuum
+}
+
+
+def hohlraum_problem(n: int = 112) -> Problem:
+    """Linearized hohlraum with the cross sections of the paper's second benchmark: a 1.3 x 1.3
+    cm square on an n x n mesh (112 in the paper), driven by isotropic incident flux on the
+    left side (x = 0), vacuum elsewhere.
+
+    The layout (the paper's figure is not part of its text) is defined by this library, in cm:
+    black walls along the right side (x > 1.25), the top (y > 1.25) and the bottom (y < 0.05);
+    red stripes y in [0.25, 0.30] and [1.00, 1.05] for x in [0.45, 1.25]; a central blue
+    absorber [0.45, 0.85]^2 inside a green frame [0.40, 0.90]^2; white elsewhere.  A cell takes
+    the material at its centre."""
+    L = 1.3 / n
+    xc = (np.arange(n)[None, :] + 0.5) * L + np.zeros((n, 1))
+    yc = (np.arange(n)[:, None] + 0.5) * L + np.zeros((1, n))
+    mat = np.full((n, n), "white", dtype=object)
+    inside = lambda x0, x1, y0, y1: (xc >= x0) & (xc < x1) & (yc >= y0) & (yc < y1)
+    mat[inside(0.40, 0.90, 0.40, 0.90)] = "green"
+    mat[inside(0.45, 0.85, 0.45, 0.85)] = "blue"
+    mat[inside(0.45, 1.25, 0.25, 0.30) | inside(0.45, 1.25, 1.00, 1.05)] = "red"
+    mat[(xc > 1.25) | (yc > 1.25) | (yc < 0.05)] = "black"
+    sig_a = np.array([HOHLRAUM_MATERIALS[k][0] for k in mat.reshape(-1)])
+    sig_s = np.array([HOHLRAUM_MATERIALS[k][1] for k in mat.reshape(-1)])
+    tau, c = _from_sigmas(sig_a, sig_s, L)
+    return Problem(n, n, L, tau, c, 0, 0, 1, n, False, 1e-6, 3)
