@@ -89,7 +89,7 @@ def cpu_baseline(H, K, budget_s=15.0):
     t0 = time.perf_counter()
     oracle.sample_raw(w, cond, K, z)
     dt = time.perf_counter() - t0
-    n = int(min(65536, max(probe, probe * budget_s / max(dt, 1e-6))))
+    n = int(min(1 << 18, max(probe, probe * budget_s / max(dt, 1e-6))))
     cond = inputs.transmission_conditions(n, 3)
     t0 = time.perf_counter()
     z = oracle.noise(2, 0, n)
@@ -99,7 +99,20 @@ def cpu_baseline(H, K, budget_s=15.0):
     threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     return {"value": n / dt, "unit": "transmissions/s", "cores": int(threads), "kind": "oracle",
             "sample": f"{n} transmissions of the same workload (FP64 numpy MLP + Philox/Box-Muller "
-                      f"noise + decode), {dt:.1f} s"}
+                      f"noise + decode), {dt:.1f} s", "host": host_cpu()}
+
+
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"model": model, "logical_cpus": os.cpu_count()}
 
 
 def cpu_baseline_analog(tau=100.0, budget_s=8.0):
@@ -116,8 +129,14 @@ def cpu_baseline_analog(tau=100.0, budget_s=8.0):
     t0 = time.perf_counter()
     oracle.mc_transmit(cond, 0, 2, nthreads=nt)
     dt = time.perf_counter() - t0
+    n1 = 1 << 16
+    c1 = inputs.fixed_cell_conditions(n1, tau, 1.0, 9)
+    t0 = time.perf_counter()
+    oracle.mc_transmit(c1, 0, 2, nthreads=1)
+    dt1 = time.perf_counter() - t0
     return {"value": n / dt, "unit": "transmissions/s", "cores": nt, "kind": "oracle",
-            "sample": f"{n} analog transmissions at tau={tau:g}, c=1, {dt:.1f} s"}
+            "sample": f"{n} analog transmissions at tau={tau:g}, c=1, {dt:.1f} s",
+            "single_thread_value": n1 / dt1, "host": host_cpu()}
 
 
 def bench_transport(binding, inputs, w512, w512_internal=None):
@@ -267,7 +286,8 @@ def main():
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: fp32 | bf16 | fp8 (sampler, "
                          "H=256 / 512 / 512, Euler K=16), rk4 (BF16 H=512, RK4 x 12) or "
-                         "walk:TAU (analog, 2^20 transmissions)")
+                         "walk:TAU (analog, 2^20 transmissions), transport (cfg3 checkerboard, "
+                         "2e5 analog histories per step)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -285,6 +305,13 @@ def main():
             o = binding.DeviceExit.empty(N)
             for _ in range(args.steps):
                 binding.gmc_sample(m, c, integ, K, 2, 0, out=o)
+        elif kind == "transport":
+            # the 32 x 32 checkerboard with the analog sampler: births, gather, walk, apply
+            from paper_2512_13965_amd import transport
+            w = binding.World(1 << 20, 1, 1 << 12)
+            for _ in range(args.steps):
+                transport.run_problem(w, inputs.checkerboard_problem(32), 200_000, 1, binding.SAMPLER_MC)
+            w.close()
         else:
             tau = float(args.profile.split(":")[1]) if ":" in args.profile else 100.0
             c = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(N, tau, 1.0, 9))
@@ -372,9 +399,24 @@ def main():
         fn = lambda: binding.mc_transmit(c, binding.MODE_CONTINUOUS, 2, 0, out=outA)
         fn()
         ms = time_launches(fn, 3, stream)
+        c9 = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(NA, tau, 0.9, 9), dev)
+        fn9 = lambda: binding.mc_transmit(c9, binding.MODE_CONTINUOUS, 2, 0, out=outA)
+        fn9()
+        ms9 = time_launches(fn9, 3, stream)
         sweep.append({"tau": tau, "analog_tps": NA / (np.median(ms) * 1e-3),
                       "analog_ms": float(np.median(ms)),
-                      "mean_flights_expected": 1 + math.pi * tau / 4})
+                      "mean_flights_expected": 1 + math.pi * tau / 4,
+                      "analog_tps_c0.9": NA / (np.median(ms9) * 1e-3)})
+    # one launch of 2^20 walks at tau = 100 waits for its longest walk (~10^4 flights, serial
+    # per lane); 2^23 walks per launch show the kernel's throughput with that tail amortised
+    NL = 1 << 23
+    cL = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(NL, 100.0, 1.0, 9), dev)
+    oL = binding.DeviceExit.empty(NL, dev)
+    fnL = lambda: binding.mc_transmit(cL, binding.MODE_CONTINUOUS, 2, 0, out=oL)
+    fnL()
+    msL = float(np.median(time_launches(fnL, 3, stream)))
+    res["analog_tau100_batch_2^23"] = {"ms": msL, "tps": NL / (msL * 1e-3)}
+    del cL, oL
     gmc_tps = N / (kms.mean() * 1e-3)
     for s in sweep:
         s["gmc_fp32_h256_tps"] = gmc_tps
@@ -408,6 +450,19 @@ def main():
                          "frac_of_attainable": fl / 1e12 / peaks[prec]})
         m.close()
     res["wide_sampler"] = wide
+    # width 256 in BF16 / FP8 (random-init weights), Euler K = 16, 2^20 transmissions
+    h256 = []
+    w2 = inputs.random_weights(256, 1)
+    for prec in ("bf16", "fp8"):
+        m = binding.Model(inputs.pack_blob(w2), prec)
+        fn = lambda: binding.gmc_sample(m, condB, "euler", 16, 2, 0, out=outB)
+        fn()
+        t = float(np.median(time_launches(fn, 3, stream)))
+        fl = flops_per_sample(256, 16) * NB / (t * 1e-3)
+        h256.append({"precision": prec, "hidden": 256, "integrator": "euler", "K": 16, "batch": NB,
+                     "ms": t, "tps": NB / (t * 1e-3), "tflops": fl / 1e12, "frac_peak": fl / PEAK[prec]})
+        m.close()
+    res["h256_sampler"] = h256
     for s in sweep:
         s["gmc_bf16_h512_k16_tps"] = next(x["tps"] for x in wide if x["precision"] == "bf16"
                                           and x["integrator"] == "euler" and x["K"] == 16)
