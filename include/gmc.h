@@ -59,14 +59,20 @@ typedef enum { GMC_EULER = 0, GMC_RK4 = 1 } gmc_integrator;
 #define GMC_FACE_CAPPED (-2)     /* walk exceeded 2^24 flights (never seen in practice) */
 
 /* Canonical entry conditions of n transmissions, device SoA, float32 [n] each
- * (paper eq. 10 in the reading ln tau = ln(sigma_t L), c = sigma_s / sigma_t):
- *   log_tau  natural log of the optical side tau = sigma_t * L
- *   c        scattering ratio sigma_s / sigma_t in [0, 1]
- *   y_in     entry height on the left face, in [0, 1]
- *   sin_th   sine of the entry angle from +x, in (-1, 1) (the direction is
- *            (sqrt(1 - sin_th^2), sin_th)) */
+ * (paper eq. 10 in the reading ln tau = ln(sigma_t L), c = sigma_s / sigma_t, with the
+ * rectangle's optical width and height W~, H~ given as H~ = tau and W~ / H~ = A):
+ *   log_tau     natural log of the optical length tau = sigma_t * L of the entry face
+ *   c           scattering ratio sigma_s / sigma_t in [0, 1]
+ *   y_in        entry height on the left face, as a fraction of its length, in [0, 1]
+ *   sin_th      sine of the entry angle from +x, in (-1, 1) (the direction is
+ *               (sqrt(1 - sin_th^2), sin_th))
+ *   log_aspect  optional (NULL: square cells): ln A, A = cell width along +x over the entry
+ *               face's length; the canonical cell is [0, A] x [0, 1] in units of the entry
+ *               face, exit positions are fractions of the exit face's length and path lengths
+ *               are in units of the entry face */
 typedef struct {
     const float *log_tau, *c, *y_in, *sin_th;
+    const float *log_aspect;
 } gmc_cond;
 
 /* Birth conditions of n particles born inside a cell (the internal, volumetric-source model of
@@ -105,9 +111,10 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
 int gmc_model_destroy(gmc_model *m);
 /* Reports the hidden width and precision of a model (either pointer may be NULL). */
 int gmc_model_info(const gmc_model *m, int *hidden, int *precision);
-/* Reports the network's input width: 10 for a boundary model (gmc_cond), 12 for an internal
- * model (gmc_cond_internal).  A blob with n_in = 12 has a 12-wide first layer; the network input
- * order is then [x0..x4, t, ln tau, c, 2x - 1, 2y - 1, cos phi, sin phi]. */
+/* Reports the network's input width: 10 for a boundary model of square cells (gmc_cond
+ * without log_aspect), 11 for a boundary model of rectangular cells (input order [x0..x4, t,
+ * ln tau, c, 2 y_in - 1, sin th, ln A]), 12 for an internal model (gmc_cond_internal; input
+ * order [x0..x4, t, ln tau, c, 2x - 1, 2y - 1, cos phi, sin phi]). */
 int gmc_model_inputs(const gmc_model *m, int *n_in);
 
 /* Samples n cell transmissions with the generative sampler (paper "Transport Algorithm",
@@ -125,6 +132,8 @@ int gmc_model_inputs(const gmc_model *m, int *n_in);
  *   raw_opt    NULL, or device float32 [5][n] receiving x_K before decoding
  *   out        device exit record (all five arrays required)
  * n = 0 is a no-op.  Errors: GMC_EINVAL (null pointers, K out of range), GMC_EDEVICE. */
+/* m must be a boundary model: n_in = 10 takes no log_aspect (GMC_EINVAL if one is given);
+ * n_in = 11 reads it (NULL: ln A = 0). */
 int gmc_transmit(const gmc_model *m, gmc_cond cond, int64_t n, int K, uint64_t seed,
                  uint64_t id_base, const float *noise_opt, float *raw_opt, gmc_exit out,
                  void *stream);
@@ -148,7 +157,8 @@ int gmc_sample_internal(const gmc_model *m, gmc_cond_internal cond, int64_t n, i
                         gmc_exit out, void *stream);
 
 /* Samples n cell transmissions with the analog random walk that the generative sampler
- * replaces (paper "Monte Carlo Method", eq. 4): flights d = -ln(xi) / sigma with
+ * replaces (paper "Monte Carlo Method", eq. 4) through the canonical cell [0, A] x [0, 1]
+ * (A = 1 without log_aspect; lengths in units of the entry face): flights d = -ln(xi) / sigma with
  * xi = ((w >> 8) + 1) * 2^-24 in (0, 1], isotropic flatland scattering phi = 2 pi xi'.
  *   mode GMC_MODE_CONTINUOUS: sigma = c * tau (implicit capture: the caller attenuates the
  *        weight by exp(-(1 - c) tau path), eqs. 5-6); every walk ends on a face.

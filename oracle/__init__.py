@@ -56,12 +56,12 @@ def lib():
         L.orc_u01.argtypes = [ctypes.c_uint32]
         L.orc_u01.restype = ctypes.c_double
         L.orc_noise_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P]
-        L.orc_mc_transmit.argtypes = [P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
+        L.orc_mc_transmit.argtypes = [P, P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
                                       ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_int]
         L.orc_mc_transmit_internal.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int,
                                                ctypes.c_uint64, ctypes.c_uint64, P, P, P, P, P, P,
                                                ctypes.c_int]
-        L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, P, P,
+        L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
                                     ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int]
@@ -102,16 +102,20 @@ def noise(seed: int, id_base: int, n: int) -> np.ndarray:
 
 def mc_transmit(cond, mode: int, seed: int, id_base: int = 0, nthreads: int = 1) -> dict:
     """FP64 analog transmissions of a canonical batch.  mode 0 = C (continuous absorption,
-    flights from sigma_s = c*tau), 1 = A (analog absorption).  Returns numpy arrays:
-    face (int32; -1 absorbed), pos, u, v, len (float64, units of L), ncoll (uint32)."""
+    flights from sigma_s = c*tau), 1 = A (analog absorption); rectangular cells [0, A] x [0, 1]
+    when cond.log_aspect is given.  Returns numpy arrays: face (int32; -1 absorbed), pos (a
+    fraction of the exit face), u, v, len (float64, units of the entry face), ncoll (uint32)."""
     n = len(cond)
     lt = np.ascontiguousarray(cond.log_tau, np.float32)
     cc = np.ascontiguousarray(cond.c, np.float32)
     yy = np.ascontiguousarray(cond.y_in, np.float32)
     ss = np.ascontiguousarray(cond.sin_th, np.float32)
+    la = getattr(cond, "log_aspect", None)
+    la = None if la is None else np.ascontiguousarray(la, np.float32)
     out = dict(face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n), v=np.zeros(n),
                len=np.zeros(n), ncoll=np.zeros(n, np.uint32))
-    lib().orc_mc_transmit(_p(lt), _p(cc), _p(yy), _p(ss), n, mode, seed, id_base,
+    lib().orc_mc_transmit(_p(lt), _p(cc), _p(yy), _p(ss), None if la is None else _p(la), n, mode,
+                          seed, id_base,
                           _p(out["face"]), _p(out["pos"]), _p(out["u"]), _p(out["v"]),
                           _p(out["len"]), _p(out["ncoll"]), nthreads)
     return out
@@ -139,7 +143,8 @@ def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -
     flux = np.zeros(problem.n_cells)
     absorbed = np.zeros(problem.n_cells)
     sc = np.zeros(3)
-    lib().orc_transport(problem.nx, problem.ny, problem.L, _p(tau), _p(c), problem.src_x0,
+    lib().orc_transport(problem.nx, problem.ny, problem.L, float(getattr(problem, "Ly", 0.0)),
+                        _p(tau), _p(c), problem.src_x0,
                         problem.src_y0, problem.src_nx, problem.src_ny, int(problem.reflect),
                         int(getattr(problem, "src_face", -1)), problem.w_min, seed, h_begin, h_end,
                         _p(flux), _p(absorbed), _p(sc), nthreads)
@@ -195,13 +200,17 @@ def silu(a):
 
 def condition_features(cond) -> np.ndarray:
     """Condition part of the network input.  Boundary model (entry conditions):
-    (ln tau, c, 2*y_in - 1, sin theta_in), [n, 4].  Internal model (birth conditions, which carry
+    (ln tau, c, 2*y_in - 1, sin theta_in), [n, 4], and for rectangular cells (conditions with a
+    log_aspect) ln A as a fifth column, [n, 5].  Internal model (birth conditions, which carry
     the birth position x, y and direction): (ln tau, c, 2x - 1, 2y - 1, cos phi, sin phi), [n, 6]."""
     f = lambda a: np.asarray(a, np.float64)
     if hasattr(cond, "x"):
         return np.stack([f(cond.log_tau), f(cond.c), 2.0 * f(cond.x) - 1.0, 2.0 * f(cond.y) - 1.0,
                          f(cond.cos_phi), f(cond.sin_phi)], axis=1)
-    return np.stack([f(cond.log_tau), f(cond.c), 2.0 * f(cond.y_in) - 1.0, f(cond.sin_th)], axis=1)
+    cols = [f(cond.log_tau), f(cond.c), 2.0 * f(cond.y_in) - 1.0, f(cond.sin_th)]
+    if getattr(cond, "log_aspect", None) is not None:
+        cols.append(f(cond.log_aspect))
+    return np.stack(cols, axis=1)
 
 
 def velocity(weights, x, t, condf, precision=PREC_FP64):

@@ -103,21 +103,24 @@ void orc_noise_batch(uint64_t seed, uint64_t id_base, int64_t n, double *z /* [5
 }
 
 /* ------------------------------------------------------------------------------------ */
-/* Analog walk through one unit cell (section "Monte Carlo Method", eq. 4).                */
+/* Analog walk through one cell (section "Monte Carlo Method", eq. 4).                     */
 /* ------------------------------------------------------------------------------------ */
 typedef struct {
     int32_t face;    /* 0..3, or ORC_FACE_ABSORBED / ORC_FACE_CAPPED */
-    double pos;      /* counter-clockwise position along the exit face, [0,1] */
+    double pos;      /* counter-clockwise position along the exit face, as a fraction of
+                        that face's length, [0,1] */
     double u, v;     /* exit direction (cos, sin) in the frame of the walk */
-    double len;      /* total track length in the cell, units of L */
+    double len;      /* total track length in the cell, in units of the cell's height */
     uint32_t ncoll;  /* collisions (scatterings) inside the cell */
 } orc_exit;
 
-/* mode 0 ("C", continuous absorption): flights ~ Exp(sig_s) with sig_s = c * tau; the weight
+/* The cell is the rectangle [0, a] x [0, 1] (a = 1: the unit square), lengths in units of its
+ * height, tau = sigma_t * height.
+ * mode 0 ("C", continuous absorption): flights ~ Exp(sig_s) with sig_s = c * tau; the weight
  *          is attenuated analytically afterwards (eqs. 5-6), so every walk ends on a face.
  * mode 1 ("A", analog absorption): flights ~ Exp(tau); each collision absorbs with
  *          probability 1 - c (xi > c), otherwise scatters. */
-void orc_walk(double tau, double c, int mode, double x, double y, double u, double v,
+void orc_walk(double tau, double c, int mode, double a, double x, double y, double u, double v,
               uint64_t seed, uint64_t stream, orc_exit *e)
 {
     const double sig = (mode == 0) ? c * tau : tau;
@@ -130,7 +133,7 @@ void orc_walk(double tau, double c, int mode, double x, double y, double u, doub
         }
         /* distance to the cell boundary along (u, v) */
         double tx = INFINITY, ty = INFINITY;
-        if (u > 0.0) tx = (1.0 - x) / u; else if (u < 0.0) tx = -x / u;
+        if (u > 0.0) tx = (a - x) / u; else if (u < 0.0) tx = -x / u;
         if (v > 0.0) ty = (1.0 - y) / v; else if (v < 0.0) ty = -y / v;
         int xface = (tx <= ty);
         double db = xface ? tx : ty;
@@ -150,8 +153,9 @@ void orc_walk(double tau, double c, int mode, double x, double y, double u, doub
                 if (u > 0.0) { face = 1; pos = ye; } else { face = 3; pos = 1.0 - ye; }
             } else {
                 double xe = x + db * u;
-                xe = xe < 0.0 ? 0.0 : (xe > 1.0 ? 1.0 : xe);
-                if (v > 0.0) { face = 2; pos = 1.0 - xe; } else { face = 0; pos = xe; }
+                xe = xe < 0.0 ? 0.0 : (xe > a ? a : xe);
+                /* bottom and top faces have length a: position as a fraction of it */
+                if (v > 0.0) { face = 2; pos = (a - xe) / a; } else { face = 0; pos = xe / a; }
             }
             e->face = face; e->pos = pos; e->u = u; e->v = v; e->len = len; e->ncoll = n;
             return;
@@ -177,6 +181,7 @@ void orc_walk(double tau, double c, int mode, double x, double y, double u, doub
 typedef struct {
     const float *log_tau, *c, *y_in, *sin_th;
     const float *x_in, *cos_phi;   /* births inside the cell (internal model), else NULL */
+    const float *log_aspect;        /* rectangular cells [0, A] x [0, 1], else NULL */
     int64_t n;
     int mode;
     uint64_t seed, id_base;
@@ -196,8 +201,9 @@ static void *walk_worker(void *arg)
             x0 = (double)j->x_in[i];
             u0 = (double)j->cos_phi[i];
         }
+        double a = j->log_aspect ? exp((double)j->log_aspect[i]) : 1.0;
         orc_exit e;
-        orc_walk(exp((double)j->log_tau[i]), (double)j->c[i], j->mode, x0, (double)j->y_in[i],
+        orc_walk(exp((double)j->log_tau[i]), (double)j->c[i], j->mode, a, x0, (double)j->y_in[i],
                  u0, s, j->seed, j->id_base + (uint64_t)i, &e);
         j->face[i] = e.face; j->pos[i] = e.pos; j->u[i] = e.u; j->v[i] = e.v;
         j->len[i] = e.len; j->ncoll[i] = e.ncoll;
@@ -206,7 +212,8 @@ static void *walk_worker(void *arg)
 }
 
 static void run_walks(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
-                      const float *x_in, const float *cos_phi, int64_t n, int mode, uint64_t seed,
+                      const float *x_in, const float *cos_phi, const float *log_aspect, int64_t n,
+                      int mode, uint64_t seed,
                       uint64_t id_base, int32_t *face, double *pos, double *u, double *v, double *len,
                       uint32_t *ncoll, int nthreads)
 {
@@ -215,8 +222,8 @@ static void run_walks(const float *log_tau, const float *c, const float *y_in, c
     walk_job jobs[256];
     pthread_t th[256];
     for (int t = 0; t < nthreads; ++t) {
-        walk_job j = {log_tau, c, y_in, sin_th, x_in, cos_phi, n, mode, seed, id_base, face, pos, u, v,
-                      len, ncoll, n * t / nthreads, n * (t + 1) / nthreads};
+        walk_job j = {log_tau, c, y_in, sin_th, x_in, cos_phi, log_aspect, n, mode, seed, id_base, face,
+                      pos, u, v, len, ncoll, n * t / nthreads, n * (t + 1) / nthreads};
         jobs[t] = j;
     }
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, walk_worker, &jobs[t]);
@@ -224,12 +231,14 @@ static void run_walks(const float *log_tau, const float *c, const float *y_in, c
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
 }
 
+/* log_aspect may be NULL (square cells). */
 void orc_mc_transmit(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
-                     int64_t n, int mode, uint64_t seed, uint64_t id_base, int32_t *face,
-                     double *pos, double *u, double *v, double *len, uint32_t *ncoll, int nthreads)
+                     const float *log_aspect, int64_t n, int mode, uint64_t seed, uint64_t id_base,
+                     int32_t *face, double *pos, double *u, double *v, double *len, uint32_t *ncoll,
+                     int nthreads)
 {
-    run_walks(log_tau, c, y_in, sin_th, NULL, NULL, n, mode, seed, id_base, face, pos, u, v, len, ncoll,
-              nthreads);
+    run_walks(log_tau, c, y_in, sin_th, NULL, NULL, log_aspect, n, mode, seed, id_base, face, pos, u, v,
+              len, ncoll, nthreads);
 }
 
 /* Batch of walks started inside the cell: particle i is born at (x[i], y[i]) with direction
@@ -239,8 +248,8 @@ void orc_mc_transmit_internal(const float *log_tau, const float *c, const float 
                               uint64_t seed, uint64_t id_base, int32_t *face, double *pos, double *u,
                               double *v, double *len, uint32_t *ncoll, int nthreads)
 {
-    run_walks(log_tau, c, y, sin_phi, x, cos_phi, n, mode, seed, id_base, face, pos, u, v, len, ncoll,
-              nthreads);
+    run_walks(log_tau, c, y, sin_phi, x, cos_phi, NULL, n, mode, seed, id_base, face, pos, u, v, len,
+              ncoll, nthreads);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -261,8 +270,8 @@ static void rot(int k, double a, double b, double *ra, double *rb)
 
 typedef struct {
     int32_t nx, ny;
-    double L;
-    const double *tau, *c;      /* per cell, index j * nx + i */
+    double L, Ly;               /* cell width (along x) and height (along y) */
+    const double *tau, *c;      /* per cell, index j * nx + i; tau = sigma_t * L (the width) */
     int32_t src_x0, src_y0, src_nx, src_ny;
     int32_t reflect;            /* 0 vacuum, 1 specular reflection at the domain boundary */
     double w_min;               /* weight cutoff */
@@ -276,15 +285,16 @@ typedef struct {
     double events;              /* number of cell transmissions sampled (incl. birth legs) */
 } orc_tally;
 
-/* Stage 3 of the transport loop for one cell visit: attenuate and tally. Returns w_out. */
+/* Stage 3 of the transport loop for one cell visit: attenuate and tally. Returns w_out.
+ * len_units is the track length in units of `unit` (the length of the face the walk's frame
+ * took as its height). */
 static double visit_tally(const orc_problem *p, int cell, double w_in, double len_units,
-                          orc_tally *t)
+                          double unit, orc_tally *t)
 {
-    double L = p->L;
-    double sig_a = (1.0 - p->c[cell]) * p->tau[cell] / L;
-    double ls = len_units * L;                       /* physical track length */
+    double sig_a = (1.0 - p->c[cell]) * p->tau[cell] / p->L;
+    double ls = len_units * unit;                    /* physical track length */
     double dw = w_in * (-expm1(-sig_a * ls));        /* eq. 6 */
-    double V = L * L;
+    double V = p->L * p->Ly;
     double phi = (sig_a > 0.0) ? dw / (V * sig_a)    /* eq. 7 */
                                : w_in * ls / V;      /* sigma_a -> 0 limit of eq. 7 */
     t->flux[cell] += phi;
@@ -331,16 +341,19 @@ static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tal
         event = 1;
     } else {
         /* volumetric source: uniform point, isotropic direction; first leg by the analog walk
-         * from the interior birth point (global orientation), cell visit 0 */
-        double x = u01_open(r[1]), y = u01_open(r[2]);
+         * from the interior birth point in the cell's own frame [0, L / Ly] x [0, 1] (lengths
+         * in units of the height Ly), cell visit 0 */
+        double ry = p->Ly / p->L;                        /* 1 for square cells */
+        double a = p->L / p->Ly;
+        double x = a * u01_open(r[1]), y = u01_open(r[2]);
         double phi = 2.0 * ORC_PI * orc_u01(r[3]);
-        orc_walk(p->tau[cell], p->c[cell], 0, x, y, cos(phi), sin(phi), seed,
+        orc_walk(p->tau[cell] * ry, p->c[cell], 0, a, x, y, cos(phi), sin(phi), seed,
                  (uint64_t)h | ((uint64_t)event << 32), &e);
         t->events += 1.0;
         face = e.face;
         pos = e.pos;
         gx = e.u; gy = e.v;
-        w = visit_tally(p, cell, w, e.len, t);
+        w = visit_tally(p, cell, w, e.len, p->Ly, t);
     }
 
     int entering = (p->src_face >= 0);      /* already at the entry of its first cell */
@@ -375,12 +388,16 @@ static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tal
         if (s < -1.0) s = -1.0;
         double U0 = sqrt(1.0 - s * s);
         (void)U;
+        /* the canonical cell: the entry face as height, the other side as width; left and
+         * right faces have length Ly, bottom and top length L */
+        double h_e = (entry & 1) ? p->Ly : p->L, w_e = (entry & 1) ? p->L : p->Ly;
+        double rh = (entry & 1) ? p->Ly / p->L : 1.0;     /* tau scale: h_e / L */
         /* stage 2: sample the cell transmission (analog stand-in for the network) */
-        orc_walk(p->tau[cell], p->c[cell], 0, 0.0, y_in, U0, s, seed,
+        orc_walk(p->tau[cell] * rh, p->c[cell], 0, w_e / h_e, 0.0, y_in, U0, s, seed,
                  (uint64_t)h | ((uint64_t)event << 32), &e);
         t->events += 1.0;
         /* stage 3: absorption and tally */
-        w = visit_tally(p, cell, w, e.len, t);
+        w = visit_tally(p, cell, w, e.len, h_e, t);
         /* back to the global frame */
         face = (e.face + k) & 3;
         pos = e.pos;
@@ -404,12 +421,13 @@ static void *tr_worker(void *arg)
 
 /* Runs histories [h_begin, h_end).  Tallies are sums over histories (the caller divides by the
  * number of source particles).  out_scalars = {leak, cutoff, events}. */
-void orc_transport(int32_t nx, int32_t ny, double L, const double *tau, const double *c,
+void orc_transport(int32_t nx, int32_t ny, double L, double Ly, const double *tau, const double *c,
                    int32_t src_x0, int32_t src_y0, int32_t src_nx, int32_t src_ny, int32_t reflect,
                    int32_t src_face, double w_min, uint64_t seed, uint32_t h_begin, uint32_t h_end,
                    double *flux, double *absorbed, double *out_scalars, int nthreads)
 {
-    orc_problem p = {nx, ny, L, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face};
+    if (!(Ly > 0.0)) Ly = L;                          /* square cells */
+    orc_problem p = {nx, ny, L, Ly, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face};
     int ncell = nx * ny;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;

@@ -30,7 +30,8 @@ class GmcError(RuntimeError):
 
 class _Cond(ctypes.Structure):
     _fields_ = [("log_tau", ctypes.c_void_p), ("c", ctypes.c_void_p),
-                ("y_in", ctypes.c_void_p), ("sin_th", ctypes.c_void_p)]
+                ("y_in", ctypes.c_void_p), ("sin_th", ctypes.c_void_p),
+                ("log_aspect", ctypes.c_void_p)]
 
 
 class _CondInternal(ctypes.Structure):
@@ -95,16 +96,20 @@ def _need(t, dtype, n, name):
 
 @dataclass
 class DeviceCond:
-    """Device SoA of entry conditions (float32 tensors of equal length)."""
+    """Device SoA of entry conditions (float32 tensors of equal length); log_aspect is
+    optional (rectangular cells)."""
     log_tau: torch.Tensor
     c: torch.Tensor
     y_in: torch.Tensor
     sin_th: torch.Tensor
+    log_aspect: torch.Tensor | None = None
 
     @classmethod
     def from_host(cls, cond, device="cuda"):
         f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
-        return cls(f(cond.log_tau), f(cond.c), f(cond.y_in), f(cond.sin_th))
+        la = getattr(cond, "log_aspect", None)
+        return cls(f(cond.log_tau), f(cond.c), f(cond.y_in), f(cond.sin_th),
+                   None if la is None else f(la))
 
     def __len__(self):
         return int(self.log_tau.numel())
@@ -113,8 +118,11 @@ class DeviceCond:
         n = len(self)
         for nm in ("log_tau", "c", "y_in", "sin_th"):
             _need(getattr(self, nm), torch.float32, n, nm)
+        if self.log_aspect is not None:
+            _need(self.log_aspect, torch.float32, n, "log_aspect")
         return _Cond(self.log_tau.data_ptr(), self.c.data_ptr(), self.y_in.data_ptr(),
-                     self.sin_th.data_ptr())
+                     self.sin_th.data_ptr(),
+                     None if self.log_aspect is None else self.log_aspect.data_ptr())
 
 
 @dataclass

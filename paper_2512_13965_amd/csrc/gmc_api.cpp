@@ -144,8 +144,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     std::memcpy(&hd, host_blob, sizeof hd);
     if (std::memcmp(hd.magic, "GMCW0001", 8) != 0 || hd.version != 1)
         return fail(GMC_EINVAL, "gmc_model_create: bad magic or version");
-    if ((hd.n_in != 10 && hd.n_in != 12) || hd.n_out != 5 || hd.n_layers != 5)
-        return fail(GMC_EINVAL, "gmc_model_create: network must be 10 (or 12) -> H x4 -> 5");
+    if (hd.n_in < 10 || hd.n_in > 12 || hd.n_out != 5 || hd.n_layers != 5)
+        return fail(GMC_EINVAL, "gmc_model_create: network must be 10, 11 or 12 -> H x4 -> 5");
     const int H = (int)hd.hidden;
     if (!mlp_supported(precision, H))
         return fail(GMC_EUNSUPPORTED, "gmc_model_create: hidden width " + std::to_string(H) +
@@ -363,7 +363,10 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
 {
     if (!m) return fail(GMC_EINVAL, "gmc_transmit: null model");
     if (n < 0) return fail(GMC_EINVAL, "gmc_transmit: negative n");
-    if (m->n_in != 10) return fail(GMC_EINVAL, "gmc_transmit: the model is not a boundary model (10 inputs)");
+    if (m->n_in != 10 && m->n_in != 11)
+        return fail(GMC_EINVAL, "gmc_transmit: the model is not a boundary model (10 or 11 inputs)");
+    if (m->n_in == 10 && cond.log_aspect)
+        return fail(GMC_EINVAL, "gmc_transmit: a square-cell model (10 inputs) takes no aspect ratio");
     if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "gmc_transmit: null condition array");
     gmc::MlpParams p = m->tmpl;
     p.log_tau = cond.log_tau;
@@ -372,6 +375,7 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
     p.sin_th = cond.sin_th;
     p.x_in = nullptr;
     p.cos_phi = nullptr;
+    p.log_aspect = cond.log_aspect;
     return launch_sampler(m, p, n, integrator, K, seed, id_base, noise_opt, raw_opt, out, stream, "gmc_sample");
 }
 
@@ -404,6 +408,7 @@ int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_b
     p.c = cond.c;
     p.y_in = cond.y_in;
     p.sin_th = cond.sin_th;
+    p.log_aspect = cond.log_aspect;
     return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit");
 }
 

@@ -84,15 +84,18 @@ __device__ __forceinline__ void normal5(uint64_t seed, uint64_t id, float z[5])
 // advanced one flight at a time so a persistent kernel can refill lanes between flights.
 struct Walker {
     float x, y, u, v, len, inv_sig, cs;
+    float wa;                            // cell width in units of its height (1: square)
     uint32_t flight, ncoll;
     bool scatter, analog;
 };
 
 // mode 0 (continuous absorption): flights ~ Exp(c tau); mode 1 (analog): flights ~ Exp(tau)
-// and a collision absorbs when xi > c.  Start at (x, y) with direction (u, v).
+// and a collision absorbs when xi > c.  Start at (x, y) with direction (u, v) in the cell
+// [0, wa] x [0, 1]; lengths and tau are in units of the cell height.
 __device__ __forceinline__ void walker_init(Walker &w, float tau, float c, int mode, float x, float y,
-                                            float u, float v)
+                                            float u, float v, float wa = 1.0f)
 {
+    w.wa = wa;
     w.analog = (mode == 1);
     const float sig = w.analog ? tau : c * tau;
     w.scatter = sig > 1e-30f;            // below this 1/sig would overflow
@@ -112,13 +115,13 @@ constexpr int kInside = -3;
 // One flight: distance to the boundary, sampled flight length, then scatter or leave.
 // Flight j draws Philox(key, counter (stream lo, stream hi, j, walk tag)): word 0 -> length,
 // word 1 -> new direction, word 2 -> absorption test.  Returns kInside while the particle is
-// still in the cell, else the exit face 0..3 (pos = counter-clockwise position along it),
-// -1 absorbed, -2 capped.
+// still in the cell, else the exit face 0..3 (pos = counter-clockwise position along it, as a
+// fraction of that face's length), -1 absorbed, -2 capped.
 __device__ __forceinline__ int walker_flight(Walker &w, uint64_t key, uint64_t stream, float &pos)
 {
     const float kInf = __builtin_inff();
     float tx = kInf, ty = kInf;
-    if (w.u > 0.0f) tx = (1.0f - w.x) * fast_rcp(w.u);
+    if (w.u > 0.0f) tx = (w.wa - w.x) * fast_rcp(w.u);
     else if (w.u < 0.0f) tx = -w.x * fast_rcp(w.u);
     if (w.v > 0.0f) ty = (1.0f - w.y) * fast_rcp(w.v);
     else if (w.v < 0.0f) ty = -w.y * fast_rcp(w.v);
@@ -134,9 +137,9 @@ __device__ __forceinline__ int walker_flight(Walker &w, uint64_t key, uint64_t s
             face = w.u > 0.0f ? 1 : 3;
             pos = w.u > 0.0f ? ye : 1.0f - ye;
         } else {
-            const float xe = fminf(fmaxf(w.x + db * w.u, 0.0f), 1.0f);
+            const float xe = fminf(fmaxf(w.x + db * w.u, 0.0f), w.wa);
             face = w.v > 0.0f ? 2 : 0;
-            pos = w.v > 0.0f ? 1.0f - xe : xe;
+            pos = w.v > 0.0f ? (w.wa - xe) / w.wa : xe / w.wa;
         }
     } else {
         w.x += ds * w.u;

@@ -62,7 +62,8 @@ struct MlpParams {
     float inv_in_scale[5];    // 1 / activation scale of the input of layer l (FP8 hidden layers)
     const float *log_tau, *c, *y_in, *sin_th;
     const float *x_in, *cos_phi;   // internal model only: birth x and direction cosine
-    int n_cond;               // condition features: 4 (boundary model) or 6 (internal model)
+    const float *log_aspect;  // rectangular boundary model: ln(width / entry-face length), or NULL
+    int n_cond;               // condition features: 4 (boundary), 5 (rectangular), 6 (internal)
     const float *noise;       // optional [5][n]
     float *raw;               // optional [5][n]
     const uint64_t *ids;      // optional per-sample random stream ids (else id_base + i)
@@ -83,6 +84,7 @@ struct WalkParams {
     const float *log_tau, *c, *y_in, *sin_th;
     const float *x_in, *cos_phi;   // optional: start inside the cell at (x_in, y_in), direction
                                    // (cos_phi, sin_th); else on the left face, cosine from sin_th
+    const float *log_aspect;  // optional: cell [0, A] x [0, 1], A = exp(log_aspect); else square
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
     uint32_t *ncoll;          // optional

@@ -563,7 +563,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
         if (tid < kTileM) {
             const int64_t i = base + tid;
             float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-            float lt = 0.f, cc = 0.f, yy = 0.5f, ss = 0.f, xx = 0.5f, co = 1.f;
+            float lt = 0.f, cc = 0.f, yy = 0.5f, ss = 0.f, xx = 0.5f, co = 1.f, la = 0.f;
             if (i < n_items) {
                 lt = p.log_tau[i];
                 cc = p.c[i];
@@ -573,6 +573,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     xx = p.x_in[i];
                     co = p.cos_phi[i];
                 }
+                if (p.log_aspect) la = p.log_aspect[i];
                 if (p.noise) {
 #pragma unroll
                     for (int d = 0; d < 5; ++d) z[d] = p.noise[d * p.n + i];
@@ -582,8 +583,8 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             }
 #pragma unroll
             for (int d = 0; d < 5; ++d) xs[d * kTileM + tid] = z[d];
-            // boundary model: (ln tau, c, 2 y_in - 1, sin th); internal model:
-            // (ln tau, c, 2 x - 1, 2 y - 1, cos phi, sin phi)
+            // boundary model: (ln tau, c, 2 y_in - 1, sin th), rectangular cells add ln A;
+            // internal model: (ln tau, c, 2 x - 1, 2 y - 1, cos phi, sin phi)
             cf[0 * kTileM + tid] = lt;
             cf[1 * kTileM + tid] = cc;
             if (p.n_cond == 6) {
@@ -594,7 +595,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             } else {
                 cf[2 * kTileM + tid] = 2.0f * yy - 1.0f;
                 cf[3 * kTileM + tid] = ss;
-                cf[4 * kTileM + tid] = 0.0f;
+                cf[4 * kTileM + tid] = la;
                 cf[5 * kTileM + tid] = 0.0f;
             }
         }

@@ -43,12 +43,13 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
                 if (i < n) {
                     idx = i;
                     const float s = p.sin_th[i];
+                    const float wa = p.log_aspect ? expf(p.log_aspect[i]) : 1.0f;
                     if (p.x_in) {       // birth inside the cell
                         walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, p.x_in[i], p.y_in[i],
-                                    p.cos_phi[i], s);
+                                    p.cos_phi[i], s, wa);
                     } else {            // entry on the left face
                         walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, 0.0f, p.y_in[i],
-                                    sqrtf(fmaxf(1.0f - s * s, 0.0f)), s);
+                                    sqrtf(fmaxf(1.0f - s * s, 0.0f)), s, wa);
                     }
                     stream = p.ids ? p.ids[i] : p.id_base + (uint64_t)i;
                     key = p.keys ? p.keys[i] : p.seed;

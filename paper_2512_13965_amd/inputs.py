@@ -64,30 +64,40 @@ def _open01(g: np.random.Generator, n: int) -> np.ndarray:
 
 @dataclass
 class Conditions:
-    """Structure-of-arrays batch of canonical entry conditions (all float32, length n)."""
+    """Structure-of-arrays batch of canonical entry conditions (all float32, length n).
+    log_aspect (optional): ln A of rectangular cells, A = width along the flight direction
+    over the entry face's length (None: square cells)."""
     log_tau: np.ndarray
     c: np.ndarray
     y_in: np.ndarray
     sin_th: np.ndarray
+    log_aspect: np.ndarray | None = None
 
     def __len__(self) -> int:
         return int(self.log_tau.shape[0])
 
     def subset(self, idx) -> "Conditions":
         return Conditions(self.log_tau[idx].copy(), self.c[idx].copy(),
-                          self.y_in[idx].copy(), self.sin_th[idx].copy())
+                          self.y_in[idx].copy(), self.sin_th[idx].copy(),
+                          None if self.log_aspect is None else self.log_aspect[idx].copy())
 
 
 def transmission_conditions(n: int, seed: int, log_tau_range=(LOG_TAU_MIN, LOG_TAU_MAX),
-                            c_range=(0.0, 1.0)) -> Conditions:
-    """Mixed-cell batch: ln tau ~ U[range], c ~ U[range], y_in ~ U(0,1), cosine-law entry."""
+                            c_range=(0.0, 1.0), log_aspect_range=None) -> Conditions:
+    """Mixed-cell batch: ln tau ~ U[range], c ~ U[range], y_in ~ U(0,1), cosine-law entry;
+    with log_aspect_range, rectangular cells with ln A ~ U[range] (drawn after the rest, so the
+    square-cell fields are those of the same seed without it)."""
     g = rng(seed)
     lo, hi = log_tau_range
     log_tau = (lo + (hi - lo) * g.random(n)).astype(np.float32)
     c = (c_range[0] + (c_range[1] - c_range[0]) * g.random(n)).astype(np.float32)
     y_in = _open01(g, n)
     sin_th = (2.0 * _open01(g, n).astype(np.float64) - 1.0).astype(np.float32)
-    return Conditions(log_tau, c, y_in, sin_th)
+    la = None
+    if log_aspect_range is not None:
+        a0, a1 = log_aspect_range
+        la = (a0 + (a1 - a0) * g.random(n)).astype(np.float32)
+    return Conditions(log_tau, c, y_in, sin_th, la)
 
 
 def fixed_cell_conditions(n: int, tau: float, c: float, seed: int) -> Conditions:
@@ -253,7 +263,8 @@ def load_blob(path: str) -> Weights:
 
 @dataclass
 class Problem:
-    """A 2-D grid of nx * ny square cells of side L, per-cell (tau, c), a source.
+    """A 2-D grid of nx * ny cells of width L (along x) and height Ly (0: square, Ly = L),
+    per-cell (tau, c), a source.
 
     Cell (i, j) has linear index j * nx + i (i along x).  tau = sigma_t * L.
     src_face = -1: isotropic unit source uniform over the source block's cells; src_face = f in
@@ -272,6 +283,7 @@ class Problem:
     reflect: bool = False
     w_min: float = 1e-6
     src_face: int = -1
+    Ly: float = 0.0
 
     @property
     def n_cells(self) -> int:

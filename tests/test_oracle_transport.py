@@ -84,13 +84,14 @@ def _global_walk_flux(prob, n, seed):
     continuous absorption per segment, track-length tally per segment.  Pure Python."""
     g = np.random.default_rng(seed)
     L = prob.L
+    Ly = prob.Ly if prob.Ly > 0 else L
     flux = np.zeros(prob.n_cells)
     for _ in range(n):
         k = g.integers(prob.src_nx * prob.src_ny)
         ci = prob.src_x0 + k % prob.src_nx
         cj = prob.src_y0 + k // prob.src_nx
         x = (ci + g.random()) * L
-        y = (cj + g.random()) * L
+        y = (cj + g.random()) * Ly
         ph = 2 * math.pi * g.random()
         u, v = math.cos(ph), math.sin(ph)
         w = 1.0
@@ -103,11 +104,11 @@ def _global_walk_flux(prob, n, seed):
             if d_s is None:
                 d_s = -math.log(1.0 - g.random()) / sig_s if sig_s > 0 else math.inf
             tx = ((ci + 1) * L - x) / u if u > 0 else ((ci * L - x) / u if u < 0 else math.inf)
-            ty = ((cj + 1) * L - y) / v if v > 0 else ((cj * L - y) / v if v < 0 else math.inf)
+            ty = ((cj + 1) * Ly - y) / v if v > 0 else ((cj * Ly - y) / v if v < 0 else math.inf)
             db = min(tx, ty)
             seg = min(db, d_s)
             dw = w * (-math.expm1(-sig_a * seg))
-            flux[cell] += (dw / sig_a if sig_a > 0 else w * seg) / (L * L)
+            flux[cell] += (dw / sig_a if sig_a > 0 else w * seg) / (L * Ly)
             w -= dw
             x += seg * u
             y += seg * v
@@ -128,12 +129,14 @@ def _global_walk_flux(prob, n, seed):
     return flux
 
 
-def test_cell_to_cell_transport_matches_global_walk(orc):
+@pytest.mark.parametrize("Ly", [0.0, 0.35, 1.6])
+def test_cell_to_cell_transport_matches_global_walk(orc, Ly):
     # the per-cell canonical rotation (stage 1), face decoding and neighbour move (stage 4)
-    # must reproduce a plain global random walk over the same heterogeneous grid
+    # must reproduce a plain global random walk over the same heterogeneous grid, for square
+    # cells and for rectangles of either orientation (canonical frames with A = W / H and H / W)
     t = np.array([0.3, 2.0, 0.7, 1.5, 0.5, 3.0, 0.9, 0.2, 1.1])
     c = np.array([0.9, 0.5, 0.99, 0.7, 0.8, 0.95, 0.3, 1.0, 0.6])
-    prob = inputs.Problem(3, 3, 0.7, t, c, 1, 1, 1, 1)
+    prob = inputs.Problem(3, 3, 0.7, t, c, 1, 1, 1, 1, Ly=Ly)
     n, runs = 3000, 5
     ref = np.array([_global_walk_flux(prob, n, seed=s) / n for s in range(runs)])
     got = np.array([orc.transport(prob, seed=40 + s, h_begin=0, h_end=n, nthreads=NT)["flux"] / n
