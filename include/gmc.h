@@ -189,9 +189,13 @@ int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, vo
 /* ---------------------------------------------------------------------------------------- */
 typedef struct gmc_world gmc_world;
 
-/* One transport problem: nx * ny square cells of side L (physical length), cell (i, j) at
- * index j * nx + i (i along x).  tau[cell] = sigma_t * L (>= 0) and c[cell] = sigma_s / sigma_t
- * (in [0, 1]) are host FP64 arrays read during gmc_problem_add.  Boundaries are vacuum
+/* One transport problem: nx * ny cells of width L and height Ly (physical lengths; Ly = 0 means
+ * square cells, Ly = L), cell (i, j) at index j * nx + i (i along x).  tau[cell] = sigma_t * L
+ * (>= 0) and c[cell] = sigma_s / sigma_t (in [0, 1]) are host FP64 arrays read during
+ * gmc_problem_add.  A transmission is sampled in the canonical frame of its entry face (that
+ * face as the unit of length: tau * Ly / L and aspect A = L / Ly through the left and right
+ * faces, tau and A = Ly / L through the bottom and top); rectangular cells need an 11-input
+ * boundary model for the generative sampler and volumetric births by the analog walk.  Boundaries are vacuum
  * (reflect = 0) or specular (reflect = 1).  A history ends when it leaves the domain or when its
  * weight drops below w_min after a cell visit (the weight is then tallied as cutoff).
  * Sources (one unit-weight particle per history):
@@ -217,6 +221,7 @@ typedef struct {
     double w_min;
     uint64_t seed;
     int32_t src_face;
+    double Ly;
 } gmc_problem_desc;
 
 /* Device bytes gmc_world_create would allocate for these capacities (admission control). */

@@ -195,7 +195,8 @@ PREC_FP8 = "fp8"      # hidden H x H layers in e4m3 with per-layer scales, first
 
 
 def silu(a):
-    return a / (1.0 + np.exp(-a))
+    with np.errstate(over="ignore"):       # exp(-a) -> inf for a << 0 gives the limit -0
+        return a / (1.0 + np.exp(-a))
 
 
 def condition_features(cond) -> np.ndarray:

@@ -33,7 +33,8 @@ namespace {
 
 struct ProblemDev {
     int32_t nx, ny;
-    double L;
+    double L, Ly;                  // cell width (along x) and height
+    float lr;                      // ln(Ly / L): 0 for square cells
     int64_t cell0;                 // first global cell index of this problem
     int32_t sx0, sy0, snx, sny;    // source block
     int32_t reflect;
@@ -63,15 +64,15 @@ __device__ __forceinline__ int lane_rank(uint64_t mask)
 }
 
 // Stage 3 for one cell visit: w_out = w e^{-sigma_a l} (eq. 5), deposit dw (eq. 6) and flux
-// dw / (V sigma_a) (eq. 7; w l / V when sigma_a = 0), all in FP64 with the physical path.
+// dw / (V sigma_a) (eq. 7; w l / V when sigma_a = 0), all in FP64 with the physical path
+// (path_units in units of `unit`, the length of the face the walk's frame took as its height).
 __device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemDev &P, int cell,
-                                              double w, float path_units)
+                                              double w, float path_units, double unit)
 {
-    const double L = P.L;
-    const double sig_a = (1.0 - cd.c[cell]) * cd.tau[cell] / L;
-    const double ls = (double)path_units * L;
+    const double sig_a = (1.0 - cd.c[cell]) * cd.tau[cell] / P.L;
+    const double ls = (double)path_units * unit;
     const double dw = w * (-expm1(-sig_a * ls));
-    const double V = L * L;
+    const double V = P.L * P.Ly;
     const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
     atomicAdd(&cd.flux[cell], phi);
     atomicAdd(&cd.absorbed[cell], dw);
@@ -181,15 +182,17 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
         const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
         const int cell = (int)(P.cell0 + (int64_t)cj * P.nx + ci);
         const float ph = u01(r.d);
+        // the cell's own frame [0, L / Ly] x [0, 1], lengths in units of its height Ly
+        const float wa = (float)(P.L / P.Ly);
         Walker W;
-        walker_init(W, (float)cd.tau[cell], (float)cd.c[cell], 0, u01_open(r.b), u01_open(r.c),
-                    cos_turns(ph), sin_turns(ph));
+        walker_init(W, (float)(cd.tau[cell] * (P.Ly / P.L)), (float)cd.c[cell], 0, wa * u01_open(r.b),
+                    u01_open(r.c), cos_turns(ph), sin_turns(ph), wa);
         float pos = 0.0f;
         int face;
         do {
             face = walker_flight(W, P.seed, (uint64_t)h, pos);
         } while (face == kInside);
-        w_out = visit_tally(cd, P, cell, 1.0, W.len);
+        w_out = visit_tally(cd, P, cell, 1.0, W.len, P.Ly);
         nx = move_on(cd, P, cell, face, pos, W.u, W.v, w_out);
         alive = nx.alive;
     }
@@ -277,7 +280,7 @@ __global__ __launch_bounds__(256) void source_apply_kernel(CellsDev cd, int32_t 
         const uint32_t pick = __umulhi(r.a, nsrc);
         const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
         const int cell = (int)(P.cell0 + (int64_t)cj * P.nx + ci);
-        w_out = visit_tally(cd, P, cell, 1.0, path[t]);
+        w_out = visit_tally(cd, P, cell, 1.0, path[t], P.L);
         nx = move_on(cd, P, cell, face_c[t], pos[t], dcos[t], dsin[t], w_out);
         alive = nx.alive;
     }
@@ -286,19 +289,25 @@ __global__ __launch_bounds__(256) void source_apply_kernel(CellsDev cd, int32_t 
 
 // Stage 1: canonical conditions of every alive particle.  Entry face e maps to the canonical
 // left face by the rotation of k = (e + 1) mod 4 quarter turns (canonical -> local).
+// The canonical cell takes the entry face as its height: left and right faces have length Ly,
+// bottom and top length L, so entries through a vertical face see tau * Ly / L and aspect
+// A = L / Ly, entries through a horizontal face tau and A = Ly / L.
 __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
                                                      const unsigned long long *n_dev, CellsDev cd,
                                                      float *ltau, float *cc, float *yin, float *sth,
-                                                     uint64_t *ids, uint64_t *keys)
+                                                     float *laspect, uint64_t *ids, uint64_t *keys)
 {
     const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const int cell = b.cell[i];
-    const int k = (b.entry[i] + 1) & 3;
+    const int e = b.entry[i];
+    const int k = (e + 1) & 3;
     float U, V;
     rot_quarter((4 - k) & 3, b.gx[i], b.gy[i], U, V);
-    ltau[i] = cd.ltau[cell];
+    const float lr = cd.prob[b.pid[i]].lr;
+    ltau[i] = (e & 1) ? cd.ltau[cell] + lr : cd.ltau[cell];
+    laspect[i] = (e & 1) ? -lr : lr;
     cc[i] = cd.cf[cell];
     yin[i] = b.yin[i];
     sth[i] = fminf(fmaxf(V, -1.0f), 1.0f);
@@ -329,7 +338,7 @@ __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
         const int k = (in.entry[i] + 1) & 3;
         hist = in.hist[i];
         event = in.event[i] + 1;
-        w_out = visit_tally(cd, P, cell, in.w[i], path[i]);
+        w_out = visit_tally(cd, P, cell, in.w[i], path[i], (in.entry[i] & 1) ? P.Ly : P.L);
         const int fc = face_c[i];
         float gx, gy;
         rot_quarter(k, dcos[i], dsin[i], gx, gy);
@@ -372,6 +381,7 @@ struct gmc_world {
     // sampler staging
     float *c_ltau = nullptr, *c_c = nullptr, *c_yin = nullptr, *c_sth = nullptr;
     float *c_x = nullptr, *c_cos = nullptr;      // internal-model births
+    float *c_la = nullptr;                       // canonical ln aspect (rectangular cells)
     uint64_t *ids = nullptr, *keys = nullptr;
     int32_t *e_face = nullptr;
     float *e_pos = nullptr, *e_dcos = nullptr, *e_dsin = nullptr, *e_path = nullptr;
@@ -400,6 +410,7 @@ struct gmc_world {
     std::vector<ProblemDev> prob_host;
     std::vector<char> in_use;
     std::vector<int32_t> src_face;      // per problem slot: -1 volumetric, else a surface side
+    std::vector<char> rect;             // per problem slot: non-square cells
     std::vector<std::pair<int64_t, int64_t>> free_cells;   // [begin, end) ranges
     std::mutex mu;
 
@@ -438,6 +449,7 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->c_yin, 4 * C);
     L.add((void **)&w->c_sth, 4 * C);
     L.add((void **)&w->c_x, 4 * C);
+    L.add((void **)&w->c_la, 4 * C);
     L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);
     L.add((void **)&w->keys, 8 * C);
@@ -524,6 +536,7 @@ int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_ce
     w->prob_host.assign(max_problems, ProblemDev{});
     w->in_use.assign(max_problems, 0);
     w->src_face.assign(max_problems, -1);
+    w->rect.assign(max_problems, 0);
     w->free_cells.push_back({0, max_cells});
     *out = w;
     return GMC_OK;
@@ -554,6 +567,9 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     if (d->src_nx <= 0 || d->src_ny <= 0 || d->src_x0 < 0 || d->src_y0 < 0 ||
         d->src_x0 + d->src_nx > d->nx || d->src_y0 + d->src_ny > d->ny)
         return set_error(GMC_EINVAL, "gmc_problem_add: source block outside the grid");
+    if (!(d->Ly >= 0.0) || !std::isfinite(d->Ly))
+        return set_error(GMC_EINVAL, "gmc_problem_add: Ly must be 0 (square cells) or positive");
+    const double Ly = d->Ly > 0.0 ? d->Ly : d->L;
     if (d->src_face < -1 || d->src_face > 3)
         return set_error(GMC_EINVAL, "gmc_problem_add: src_face must be -1 (volumetric) or a side 0..3");
     if (d->src_face >= 0) {
@@ -591,8 +607,8 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
         lt[i] = d->tau[i] > 0.0 ? (float)std::log(d->tau[i]) : -1.0e4f;
         cf[i] = (float)d->c[i];
     }
-    ProblemDev P{d->nx, d->ny, d->L, cell0, d->src_x0, d->src_y0, d->src_nx, d->src_ny,
-                 d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face};
+    ProblemDev P{d->nx, d->ny, d->L, Ly, (float)std::log(Ly / d->L), cell0, d->src_x0, d->src_y0,
+                 d->src_nx, d->src_ny, d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(w->tau + cell0, d->tau, 8 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(w->c + cell0, d->c, 8 * n, hipMemcpyHostToDevice, s);
@@ -612,6 +628,7 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     }
     w->in_use[pid] = 1;
     w->src_face[pid] = d->src_face;
+    w->rect[pid] = Ly != d->L;
     w->prob_host[pid] = P;
     w->alive_pp[pid] = 0;
     *pid_out = pid;
@@ -635,6 +652,7 @@ int gmc_problem_remove(gmc_world *w, int32_t pid)
     }
     w->free_cells.swap(merged);
     w->in_use[pid] = 0;
+    w->rect[pid] = 0;
     return GMC_OK;
 }
 
@@ -647,6 +665,8 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
         return set_error(GMC_EINVAL, "gmc_world_inject: history ids must stay below 2^32");
     if (count > w->cap - w->n_alive)
         return set_error(GMC_ENOMEM, "gmc_world_inject: not enough free bank slots");
+    if (w->src_face[pid] < 0 && w->src_model && w->rect[pid])
+        return set_error(GMC_EINVAL, "gmc_world_inject: the internal model serves square cells only");
     hipStream_t s = (hipStream_t)stream;
     if (count > 0) {
         const int which = w->cur;
@@ -750,7 +770,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
 {
     const int cur = w->cur, nxt = 1 - cur;
     hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
-                       n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->ids, w->keys);
+                       n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la, w->ids, w->keys);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: gather");
     const int cu = device_cu_count();
@@ -761,6 +781,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.c = w->c_c;
         p.y_in = w->c_yin;
         p.sin_th = w->c_sth;
+        p.log_aspect = (m->n_in == 11) ? w->c_la : nullptr;
         p.noise = nullptr;
         p.raw = nullptr;
         p.ids = w->ids;
@@ -784,6 +805,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.c = w->c_c;
         p.y_in = w->c_yin;
         p.sin_th = w->c_sth;
+        p.log_aspect = w->c_la;
         p.face = w->e_face;
         p.pos = w->e_pos;
         p.dcos = w->e_dcos;
@@ -863,8 +885,11 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
         return set_error(GMC_EINVAL, "gmc_transport_step: sampler must be GMC or MC");
     if (sampler == GMC_SAMPLER_GMC && (!m || K < 1 || K > 1024))
         return set_error(GMC_EINVAL, "gmc_transport_step: GMC needs a model and K in 1..1024");
-    if (sampler == GMC_SAMPLER_GMC && m->n_in != 10)
-        return set_error(GMC_EINVAL, "gmc_transport_step: the model is not a boundary model (10 inputs)");
+    if (sampler == GMC_SAMPLER_GMC && m->n_in != 10 && m->n_in != 11)
+        return set_error(GMC_EINVAL, "gmc_transport_step: the model is not a boundary model (10 or 11 inputs)");
+    if (sampler == GMC_SAMPLER_GMC && m->n_in == 10 &&
+        std::any_of(w->rect.begin(), w->rect.end(), [](char r) { return r != 0; }))
+        return set_error(GMC_EINVAL, "gmc_transport_step: rectangular cells need an 11-input boundary model");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = w->n_alive;
     if (n > 0) {

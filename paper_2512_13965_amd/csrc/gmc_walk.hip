@@ -43,7 +43,8 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
                 if (i < n) {
                     idx = i;
                     const float s = p.sin_th[i];
-                    const float wa = p.log_aspect ? expf(p.log_aspect[i]) : 1.0f;
+                    const float la = p.log_aspect ? p.log_aspect[i] : 0.0f;
+                    const float wa = la == 0.0f ? 1.0f : expf(la);
                     if (p.x_in) {       // birth inside the cell
                         walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, p.x_in[i], p.y_in[i],
                                     p.cos_phi[i], s, wa);

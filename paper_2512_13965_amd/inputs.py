@@ -336,7 +336,7 @@ def _from_sigmas(sig_a: np.ndarray, sig_s: np.ndarray, L: float):
     return sig_t * L, np.where(sig_t > 0, sig_s / np.where(sig_t > 0, sig_t, 1.0), 1.0)
 
 
-def lattice_problem(cells_per_cm: int = 16) -> Problem:
+def lattice_problem(cells_per_cm: int = 16, cells_per_cm_y: int | None = None) -> Problem:
     """Heterogeneous lattice with the cross sections of the paper's first benchmark ("Benchmark
     Performance"): a 7 x 7 cm square, 112 x 112 cells at 16 cells per cm; scattering background
     sigma_a = 0, sigma_s = 1 /cm; absorbing blocks sigma_a = 9.5, sigma_s = 0.5 /cm; an
@@ -344,17 +344,20 @@ def lattice_problem(cells_per_cm: int = 16) -> Problem:
 
     The paper's figure with the layout is not part of its text; the layout here is defined by
     this library: the 1 x 1 cm blocks (I, J), I, J in 1..5 with I + J even, other than the
-    central source block (3, 3), are absorbers (a periodic array, twelve blocks)."""
+    central source block (3, 3), are absorbers (a periodic array, twelve blocks).
+    cells_per_cm_y (default: cells_per_cm) gives rectangular cells of 1 / cells_per_cm by
+    1 / cells_per_cm_y cm."""
     m = cells_per_cm
-    n = 7 * m
-    L = 1.0 / m
+    my = m if cells_per_cm_y is None else cells_per_cm_y
+    n, ny = 7 * m, 7 * my
+    L, Ly = 1.0 / m, 1.0 / my
     I = np.arange(n)[None, :] // m
-    J = np.arange(n)[:, None] // m
+    J = np.arange(ny)[:, None] // my
     absorber = (I >= 1) & (I <= 5) & (J >= 1) & (J <= 5) & ((I + J) % 2 == 0) & ~((I == 3) & (J == 3))
     sig_a = np.where(absorber, 9.5, 0.0).reshape(-1)
     sig_s = np.where(absorber, 0.5, 1.0).reshape(-1)
     tau, c = _from_sigmas(sig_a, sig_s, L)
-    return Problem(n, n, L, tau, c, 3 * m, 3 * m, m, m)
+    return Problem(n, ny, L, tau, c, 3 * m, 3 * my, m, my, Ly=0.0 if my == m else Ly)
 
 
 HOHLRAUM_MATERIALS = {          # (sigma_a, sigma_s) in 1/cm, from the paper's second benchmark

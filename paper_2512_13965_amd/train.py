@@ -1,8 +1,10 @@
 """One-time fit of a velocity network by conditional flow matching (paper section "Conditional
 Flow Matching", eq. 9; training data as in "Network Architecture and Inputs": pure-scattering
-Monte Carlo exits over a range of optical dimensions and entry states).  Two models: the
-boundary model (condition: ln tau, c, entry height, sin of the entry angle) and the internal
-model for particles born inside a cell (condition: ln tau, c, birth point, birth direction).
+Monte Carlo exits over a range of optical dimensions and entry states).  Three models: the
+boundary model (condition: ln tau, c, entry height, sin of the entry angle), the boundary model
+of rectangular cells (the same plus ln A, A = width over entry-face length, ln A ~ U[ln 1/4,
+ln 4]) and the internal model for particles born inside a cell (condition: ln tau, c, birth
+point, birth direction).
 
 Data come from this library's own analog walk (`mc_transmit` / `mc_transmit_internal`,
 continuous-absorption mode: the exit law of a walk whose flights are drawn from
@@ -17,6 +19,8 @@ x0 ~ N(0, I), t ~ U[0, 1].  The fit itself is offline PyTorch (autograd), not th
 Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_amd/weights/gmc_h512.bin
        python -m paper_2512_13965_amd.train --model internal --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_internal.bin
+       python -m paper_2512_13965_amd.train --model rect --hidden 512 \
+           --out paper_2512_13965_amd/weights/gmc_h512_rect.bin
 """
 from __future__ import annotations
 
@@ -30,11 +34,12 @@ import torch
 from . import binding, inputs
 
 LOG_TAU_TRAIN = (math.log(0.05), math.log(300.0))
+LOG_ASPECT_TRAIN = (math.log(0.25), math.log(4.0))
 
 
 def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
-    """(conditions [n, 4] (boundary) or [n, 6] (internal), targets [n, 5]) on `device`, from
-    the GPU analog walk."""
+    """(conditions [n, 4] (boundary), [n, 5] (rect) or [n, 6] (internal), targets [n, 5]) on
+    `device`, from the GPU analog walk."""
     if kind == "internal":
         cond = inputs.internal_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
         dc = binding.DeviceCondInternal.from_host(cond, device)
@@ -42,10 +47,14 @@ def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
         feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.x - 1.0, 2.0 * dc.y - 1.0,
                              dc.cos_phi, dc.sin_phi], dim=1)
     else:
-        cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
+        la = LOG_ASPECT_TRAIN if kind == "rect" else None
+        cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
         dc = binding.DeviceCond.from_host(cond, device)
         ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
-        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th], dim=1)
+        cols = [dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th]
+        if kind == "rect":
+            cols.append(dc.log_aspect)
+        feats = torch.stack(cols, dim=1)
     torch.cuda.synchronize()
     g = torch.Generator(device=device).manual_seed(seed + 1)
     u = torch.rand(n, device=device, generator=g) - 0.5
@@ -137,7 +146,7 @@ def main():
     ap.add_argument("--data", type=int, default=4_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--model", choices=("boundary", "internal"), default="boundary")
+    ap.add_argument("--model", choices=("boundary", "rect", "internal"), default="boundary")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)

@@ -35,3 +35,12 @@ def test_hohlraum_problem():
     assert m[56, 56] == 5.0 and sig_t.reshape(112, 112)[56, 56] == 100.0    # blue centre
     assert m[56, 10] == 5.0 and sig_t.reshape(112, 112)[56, 10] == 5.0      # white, near the source
     assert m[0, 56] == 50.0 and m[111, 56] == 50.0 and m[56, 111] == 50.0   # black walls
+
+
+def test_lattice_problem_with_rectangular_cells():
+    p = inputs.lattice_problem(16, 8)
+    sq = inputs.lattice_problem(16)
+    assert (p.nx, p.ny, p.L, p.Ly) == (112, 56, 1.0 / 16, 1.0 / 8)
+    # the same material map sampled at every other row
+    np.testing.assert_array_equal((p.c.reshape(56, 112) < 0.5), (sq.c.reshape(112, 112)[::2] < 0.5))
+    assert (p.src_x0, p.src_y0, p.src_nx, p.src_ny) == (48, 24, 16, 8)
