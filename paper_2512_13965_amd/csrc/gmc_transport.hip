@@ -63,19 +63,62 @@ __device__ __forceinline__ int lane_rank(uint64_t mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// Per-workgroup tally staging: the flux and deposit of a workgroup's particles are summed per
+// cell in an LDS hash table and flushed with one pair of FP64 global atomics per distinct cell.
+// Particles near a source crowd into few cells, whose same-address global atomics would
+// otherwise serialise in L2.  A block holds at most 256 particles, so at most 256 of the 512
+// slots fill and linear probing always ends.
+constexpr int kTallySlots = 512;
+struct TallyLds {
+    int32_t key[kTallySlots];
+    double flux[kTallySlots], dep[kTallySlots];
+};
+
+__device__ __forceinline__ void tally_init(TallyLds &tl)
+{
+    for (int s = threadIdx.x; s < kTallySlots; s += blockDim.x) {
+        tl.key[s] = -1;
+        tl.flux[s] = 0.0;
+        tl.dep[s] = 0.0;
+    }
+}
+
+__device__ __forceinline__ void tally_add(TallyLds &tl, int cell, double phi, double dw)
+{
+    uint32_t s = ((uint32_t)cell * 2654435761u) >> 23;     // 9-bit multiplicative hash
+    for (;;) {
+        const int prev = atomicCAS(&tl.key[s], -1, cell);
+        if (prev == -1 || prev == cell) break;
+        s = (s + 1) & (kTallySlots - 1);
+    }
+    atomicAdd(&tl.flux[s], phi);
+    atomicAdd(&tl.dep[s], dw);
+}
+
+__device__ __forceinline__ void tally_flush(TallyLds &tl, const CellsDev &cd)
+{
+    for (int s = threadIdx.x; s < kTallySlots; s += blockDim.x) {
+        const int cell = tl.key[s];
+        if (cell >= 0) {
+            atomicAdd(&cd.flux[cell], tl.flux[s]);
+            atomicAdd(&cd.absorbed[cell], tl.dep[s]);
+        }
+    }
+}
+
 // Stage 3 for one cell visit: w_out = w e^{-sigma_a l} (eq. 5), deposit dw (eq. 6) and flux
 // dw / (V sigma_a) (eq. 7; w l / V when sigma_a = 0), all in FP64 with the physical path
-// (path_units in units of `unit`, the length of the face the walk's frame took as its height).
+// (path_units in units of `unit`, the length of the face the walk's frame took as its height),
+// staged in the workgroup's table.
 __device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemDev &P, int cell,
-                                              double w, float path_units, double unit)
+                                              double w, float path_units, double unit, TallyLds &tl)
 {
     const double sig_a = (1.0 - cd.c[cell]) * cd.tau[cell] / P.L;
     const double ls = (double)path_units * unit;
     const double dw = w * (-expm1(-sig_a * ls));
     const double V = P.L * P.Ly;
     const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
-    atomicAdd(&cd.flux[cell], phi);
-    atomicAdd(&cd.absorbed[cell], dw);
+    tally_add(tl, cell, phi, dw);
     return w - dw;
 }
 
@@ -168,6 +211,9 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
                                                     unsigned long long *counter,
                                                     unsigned long long *pcount)
 {
+    __shared__ TallyLds tl;
+    tally_init(tl);
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool alive = false;
     Next nx{};
@@ -192,11 +238,13 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
         do {
             face = walker_flight(W, P.seed, (uint64_t)h, pos);
         } while (face == kInside);
-        w_out = visit_tally(cd, P, cell, 1.0, W.len, P.Ly);
+        w_out = visit_tally(cd, P, cell, 1.0, W.len, P.Ly, tl);
         nx = move_on(cd, P, cell, face, pos, W.u, W.v, w_out);
         alive = nx.alive;
     }
     append(alive, nx, pid, w_out, h, 1u, out, counter, pcount);
+    __syncthreads();
+    tally_flush(tl, cd);
 }
 
 // Surface-source births of histories [h0, h0 + count): a uniformly picked cell of the source
@@ -267,6 +315,9 @@ __global__ __launch_bounds__(256) void source_apply_kernel(CellsDev cd, int32_t 
                                                            BankDev out, unsigned long long *counter,
                                                            unsigned long long *pcount)
 {
+    __shared__ TallyLds tl;
+    tally_init(tl);
+    __syncthreads();
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool alive = false;
     Next nx{};
@@ -280,11 +331,13 @@ __global__ __launch_bounds__(256) void source_apply_kernel(CellsDev cd, int32_t 
         const uint32_t pick = __umulhi(r.a, nsrc);
         const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
         const int cell = (int)(P.cell0 + (int64_t)cj * P.nx + ci);
-        w_out = visit_tally(cd, P, cell, 1.0, path[t], P.L);
+        w_out = visit_tally(cd, P, cell, 1.0, path[t], P.L, tl);
         nx = move_on(cd, P, cell, face_c[t], pos[t], dcos[t], dsin[t], w_out);
         alive = nx.alive;
     }
     append(alive, nx, pid, w_out, h, 1u, out, counter, pcount);
+    __syncthreads();
+    tally_flush(tl, cd);
 }
 
 // Stage 1: canonical conditions of every alive particle.  Entry face e maps to the canonical
@@ -324,6 +377,9 @@ __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
                                                     unsigned long long *counter,
                                                     unsigned long long *pcount)
 {
+    __shared__ TallyLds tl;
+    tally_init(tl);
+    __syncthreads();
     const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool alive = false;
@@ -338,7 +394,7 @@ __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
         const int k = (in.entry[i] + 1) & 3;
         hist = in.hist[i];
         event = in.event[i] + 1;
-        w_out = visit_tally(cd, P, cell, in.w[i], path[i], (in.entry[i] & 1) ? P.Ly : P.L);
+        w_out = visit_tally(cd, P, cell, in.w[i], path[i], (in.entry[i] & 1) ? P.Ly : P.L, tl);
         const int fc = face_c[i];
         float gx, gy;
         rot_quarter(k, dcos[i], dsin[i], gx, gy);
@@ -346,6 +402,8 @@ __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
         alive = nx.alive;
     }
     append(alive, nx, pid, w_out, hist, event, out, counter, pcount);
+    __syncthreads();
+    tally_flush(tl, cd);
 }
 
 __global__ void set_u64_kernel(unsigned long long *p, unsigned long long v, int n)
