@@ -37,6 +37,7 @@ from dataclasses import dataclass, field
 import numpy as np
 
 N_IN = 10            # boundary model: x (5), t (1), condition (4)
+N_IN_RECT = 11       # boundary model of rectangular cells: x (5), t (1), condition (5)
 N_IN_INTERNAL = 12   # internal (volumetric-source) model: x (5), t (1), condition (6)
 N_OUT = 5   # exit state: position, cos, sin, log path, face
 N_LAYERS = 5
@@ -230,7 +231,7 @@ def pack_blob(w: Weights) -> bytes:
 def unpack_blob(blob: bytes) -> Weights:
     fields = _HDR.unpack_from(blob, 0)
     magic, version, n_in, hidden, n_out, n_layers, _flags, seed, _res = fields[:9]
-    if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in not in (N_IN, N_IN_INTERNAL) \
+    if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in not in (N_IN, N_IN_RECT, N_IN_INTERNAL) \
             or n_out != N_OUT or n_layers != N_LAYERS:
         raise ValueError("not a GMC weights blob of a supported version")
     act = np.array(fields[9:14], np.float32)

@@ -44,3 +44,12 @@ def test_lattice_problem_with_rectangular_cells():
     # the same material map sampled at every other row
     np.testing.assert_array_equal((p.c.reshape(56, 112) < 0.5), (sq.c.reshape(112, 112)[::2] < 0.5))
     assert (p.src_x0, p.src_y0, p.src_nx, p.src_ny) == (48, 24, 16, 8)
+
+
+def test_weight_blobs_of_every_model_kind_round_trip():
+    for n_in in (inputs.N_IN, inputs.N_IN_RECT, inputs.N_IN_INTERNAL):
+        w = inputs.random_weights(32, 3, n_in=n_in)
+        back = inputs.unpack_blob(inputs.pack_blob(w))
+        assert back.n_in == n_in and back.W[0].shape == (32, n_in)
+        for a, b in zip(w.W + w.b, back.W + back.b):
+            np.testing.assert_array_equal(a, b)
