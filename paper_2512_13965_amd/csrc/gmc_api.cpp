@@ -348,7 +348,7 @@ int launch_walk_api(gmc::WalkParams p, int64_t n, int mode, uint64_t seed, uint6
     if (!p.queue) return fail(GMC_ENOMEM, w + ": cannot allocate the work counter");
     const int cu = gmc::device_cu_count();
     if (cu <= 0) return fail(GMC_EDEVICE, w + ": cannot query the device");
-    const int grid = (int)std::min<int64_t>((n + 255) / 256, (int64_t)cu * 8);
+    const int grid = gmc::walk_grid(n, cu);
     hipError_t e = gmc::launch_walk(p, grid, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, (w + ": launch").c_str());
     return GMC_OK;

@@ -98,6 +98,16 @@ struct WalkParams {
 };
 
 hipError_t launch_walk(const WalkParams &p, int grid, hipStream_t s);
+#ifndef GMC_WALK_BLOCKS_PER_CU
+#define GMC_WALK_BLOCKS_PER_CU 8
+#endif
+// Grid of the persistent walk for n particles: at most GMC_WALK_BLOCKS_PER_CU blocks of 256
+// lanes per compute unit.
+inline int walk_grid(int64_t n, int cu)
+{
+    const int64_t want = (n + 255) / 256, cap = (int64_t)cu * GMC_WALK_BLOCKS_PER_CU;
+    return (int)(want < cap ? want : cap);
+}
 hipError_t launch_decode(const float *raw, int64_t n, int32_t *face, float *pos, float *dcos,
                          float *dsin, float *path, int32_t *flags, hipStream_t s);
 

@@ -876,7 +876,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.n_dev = n_dev;
         p.mode = GMC_MODE_CONTINUOUS;
         p.queue = w->queue;
-        e = launch_walk(p, (int)std::min<int64_t>((n_launch + 255) / 256, (int64_t)cu * 8), s);
+        e = launch_walk(p, walk_grid(n_launch, cu), s);
     }
     if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: sampler");
     unsigned long long *ctr = w->cnt(nxt);

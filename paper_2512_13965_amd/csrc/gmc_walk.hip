@@ -4,8 +4,9 @@
 // The walk has a heavy-tailed cost (mean 1 + pi tau_s / 4 flights, a long tail of diffusive
 // walks), so lanes are not bound to particles: the kernel is persistent, each lane walks one
 // particle at a time, and after every flight the lanes whose particle has left the cell are
-// refilled from a global work counter with one atomic per wave (ballot of the idle lanes,
-// mbcnt for each lane's rank among them).  The queue keeps every lane busy until it runs dry.
+// refilled (ballot of the idle lanes, mbcnt for each lane's rank among them) from a pool of
+// indices the wave holds, which it refills in chunks from a global work counter with one
+// atomic.  The queue keeps every lane busy until it runs dry.
 #include "gmc_device.hpp"
 #include "gmc_internal.hpp"
 
@@ -22,25 +23,44 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
 {
     const int lane = threadIdx.x & 63;
     bool alive = false;
-    bool exhausted = false;     // wave-uniform: the work counter has passed n
     int64_t idx = 0;
     uint64_t key = p.seed, stream = 0;
     Walker w;
     walker_init(w, 0.0f, 0.0f, 0, 0.0f, 0.0f, 1.0f, 0.0f);
     const int64_t n = p.n_dev ? (int64_t)*p.n_dev : p.n;
+    // Work arrives in chunks: one atomic on the global counter gives a wave `chunk` (or more)
+    // consecutive particle indices, which it hands to its idle lanes over the following
+    // iterations.  The counter then sees about n / chunk atomics instead of one per refill
+    // (same-address atomics serialise in L2 and bound a walk whose lanes free up one at a time).
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    int64_t chunk = n / (waves * 4);
+    chunk = chunk < 1 ? 1 : (chunk > 64 ? 64 : chunk);
+    int64_t pool_next = 0, pool_end = 0;   // wave-uniform: unstarted indices held by this wave
+    bool exhausted = false;                // wave-uniform: the global counter has reached n
 
     for (;;) {
-        const bool need = !alive && !exhausted;
+        const bool need = !alive && !(exhausted && pool_next >= pool_end);
         const uint64_t needmask = __ballot(need);
         if (needmask) {
-            const int cnt = __popcll(needmask);
-            const int leader = __ffsll((unsigned long long)needmask) - 1;
-            unsigned long long b = 0;
-            if (lane == leader) b = atomicAdd(p.queue, (unsigned long long)cnt);
-            const unsigned long long base = (unsigned long long)__shfl((long long)b, leader);
+            const int64_t cnt = __popcll(needmask);
+            const int64_t avail = pool_end - pool_next;
+            int64_t base2 = 0, end2 = 0;
+            if (avail < cnt && !exhausted) {
+                const int64_t take = (cnt - avail) > chunk ? (cnt - avail) : chunk;
+                const int leader = __ffsll((unsigned long long)needmask) - 1;
+                unsigned long long b = 0;
+                if (lane == leader) b = atomicAdd(p.queue, (unsigned long long)take);
+                base2 = (int64_t)__shfl((long long)b, leader);
+                end2 = base2 + take < n ? base2 + take : n;
+                if (base2 + take >= n) exhausted = true;
+                if (base2 > end2) base2 = end2;    // past the end: nothing left
+            }
             if (need) {
-                const int64_t i = (int64_t)(base + (unsigned long long)lane_rank(needmask));
-                if (i < n) {
+                const int64_t r = lane_rank(needmask);
+                int64_t i = -1;
+                if (r < avail) i = pool_next + r;
+                else if (base2 + (r - avail) < end2) i = base2 + (r - avail);
+                if (i >= 0) {
                     idx = i;
                     const float s = p.sin_th[i];
                     const float la = p.log_aspect ? p.log_aspect[i] : 0.0f;
@@ -57,10 +77,16 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
                     alive = true;
                 }
             }
-            if (base + (unsigned long long)cnt >= (unsigned long long)n) exhausted = true;
+            if (avail >= cnt) {
+                pool_next += cnt;
+            } else {                  // old pool used up; the rest of the new chunk remains
+                const int64_t used = cnt - avail;
+                pool_next = base2 + used < end2 ? base2 + used : end2;
+                pool_end = end2;
+            }
         }
         if (!__ballot(alive)) {
-            if (exhausted) break;
+            if (exhausted && pool_next >= pool_end) break;
             continue;
         }
         if (!alive) continue;
