@@ -56,15 +56,15 @@ def lib():
         L.orc_u01.argtypes = [ctypes.c_uint32]
         L.orc_u01.restype = ctypes.c_double
         L.orc_noise_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64, P]
-        L.orc_mc_transmit.argtypes = [P, P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
+        L.orc_mc_transmit.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_uint64,
                                       ctypes.c_uint64, P, P, P, P, P, P, ctypes.c_int]
         L.orc_mc_transmit_internal.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int,
                                                ctypes.c_uint64, ctypes.c_uint64, P, P, P, P, P, P,
                                                ctypes.c_int]
         L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
-                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_uint64,
-                                    ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int]
+                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int]
         _lib = L
     return _lib
 
@@ -112,10 +112,12 @@ def mc_transmit(cond, mode: int, seed: int, id_base: int = 0, nthreads: int = 1)
     ss = np.ascontiguousarray(cond.sin_th, np.float32)
     la = getattr(cond, "log_aspect", None)
     la = None if la is None else np.ascontiguousarray(la, np.float32)
+    ox = getattr(cond, "omega_x", None)
+    ox = None if ox is None else np.ascontiguousarray(ox, np.float32)
     out = dict(face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n), v=np.zeros(n),
                len=np.zeros(n), ncoll=np.zeros(n, np.uint32))
-    lib().orc_mc_transmit(_p(lt), _p(cc), _p(yy), _p(ss), None if la is None else _p(la), n, mode,
-                          seed, id_base,
+    lib().orc_mc_transmit(_p(lt), _p(cc), _p(yy), _p(ss), None if la is None else _p(la),
+                          None if ox is None else _p(ox), n, mode, seed, id_base,
                           _p(out["face"]), _p(out["pos"]), _p(out["u"]), _p(out["v"]),
                           _p(out["len"]), _p(out["ncoll"]), nthreads)
     return out
@@ -146,7 +148,8 @@ def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -
     lib().orc_transport(problem.nx, problem.ny, problem.L, float(getattr(problem, "Ly", 0.0)),
                         _p(tau), _p(c), problem.src_x0,
                         problem.src_y0, problem.src_nx, problem.src_ny, int(problem.reflect),
-                        int(getattr(problem, "src_face", -1)), problem.w_min, seed, h_begin, h_end,
+                        int(getattr(problem, "src_face", -1)), int(getattr(problem, "xy", False)),
+                        problem.w_min, seed, h_begin, h_end,
                         _p(flux), _p(absorbed), _p(sc), nthreads)
     return dict(flux=flux, absorbed=absorbed, leak=sc[0], cutoff=sc[1], events=sc[2])
 

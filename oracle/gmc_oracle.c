@@ -116,12 +116,17 @@ typedef struct {
 
 /* The cell is the rectangle [0, a] x [0, 1] (a = 1: the unit square), lengths in units of its
  * height, tau = sigma_t * height.
+ * xy = 0: flatland, directions on the unit circle, isotropic scattering phi = 2 pi xi.
+ * xy = 1: XY geometry (eq. 1 over the sphere, the problem invariant along z): (u, v) is the
+ *          projection of a unit direction on the plane, lengths are three-dimensional; a
+ *          collision draws mu = cos(polar angle) = 2 xi' - 1 and phi = 2 pi xi, giving
+ *          (u, v) = sqrt(1 - mu^2) (cos phi, sin phi).
  * mode 0 ("C", continuous absorption): flights ~ Exp(sig_s) with sig_s = c * tau; the weight
  *          is attenuated analytically afterwards (eqs. 5-6), so every walk ends on a face.
  * mode 1 ("A", analog absorption): flights ~ Exp(tau); each collision absorbs with
  *          probability 1 - c (xi > c), otherwise scatters. */
-void orc_walk(double tau, double c, int mode, double a, double x, double y, double u, double v,
-              uint64_t seed, uint64_t stream, orc_exit *e)
+void orc_walk(double tau, double c, int mode, int xy, double a, double x, double y, double u,
+              double v, uint64_t seed, uint64_t stream, orc_exit *e)
 {
     const double sig = (mode == 0) ? c * tau : tau;
     double len = 0.0;
@@ -169,9 +174,15 @@ void orc_walk(double tau, double c, int mode, double a, double x, double y, doub
             e->face = ORC_FACE_ABSORBED; e->pos = 0.0; e->u = u; e->v = v; e->len = len; e->ncoll = n;
             return;
         }
-        double phi = 2.0 * ORC_PI * orc_u01(r[1]);   /* isotropic flatland scattering */
+        double phi = 2.0 * ORC_PI * orc_u01(r[1]);   /* isotropic scattering */
         u = cos(phi);
         v = sin(phi);
+        if (xy) {                                      /* on the sphere, projected */
+            double mu = 2.0 * orc_u01(r[3]) - 1.0;
+            double st = sqrt(1.0 - mu * mu);
+            u *= st;
+            v *= st;
+        }
     }
 }
 
@@ -182,6 +193,8 @@ typedef struct {
     const float *log_tau, *c, *y_in, *sin_th;
     const float *x_in, *cos_phi;   /* births inside the cell (internal model), else NULL */
     const float *log_aspect;        /* rectangular cells [0, A] x [0, 1], else NULL */
+    const float *omega_x;           /* XY geometry: in-plane x component of the entry
+                                       direction (sin_th holds the y component), else NULL */
     int64_t n;
     int mode;
     uint64_t seed, id_base;
@@ -196,15 +209,15 @@ static void *walk_worker(void *arg)
     walk_job *j = (walk_job *)arg;
     for (int64_t i = j->begin; i < j->end; ++i) {
         double s = (double)j->sin_th[i];
-        double x0 = 0.0, u0 = sqrt(1.0 - s * s);
+        double x0 = 0.0, u0 = j->omega_x ? (double)j->omega_x[i] : sqrt(1.0 - s * s);
         if (j->x_in) {            /* birth at (x, y) with direction (cos phi, sin phi) */
             x0 = (double)j->x_in[i];
             u0 = (double)j->cos_phi[i];
         }
         double a = j->log_aspect ? exp((double)j->log_aspect[i]) : 1.0;
         orc_exit e;
-        orc_walk(exp((double)j->log_tau[i]), (double)j->c[i], j->mode, a, x0, (double)j->y_in[i],
-                 u0, s, j->seed, j->id_base + (uint64_t)i, &e);
+        orc_walk(exp((double)j->log_tau[i]), (double)j->c[i], j->mode, j->omega_x != NULL, a, x0,
+                 (double)j->y_in[i], u0, s, j->seed, j->id_base + (uint64_t)i, &e);
         j->face[i] = e.face; j->pos[i] = e.pos; j->u[i] = e.u; j->v[i] = e.v;
         j->len[i] = e.len; j->ncoll[i] = e.ncoll;
     }
@@ -212,8 +225,8 @@ static void *walk_worker(void *arg)
 }
 
 static void run_walks(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
-                      const float *x_in, const float *cos_phi, const float *log_aspect, int64_t n,
-                      int mode, uint64_t seed,
+                      const float *x_in, const float *cos_phi, const float *log_aspect,
+                      const float *omega_x, int64_t n, int mode, uint64_t seed,
                       uint64_t id_base, int32_t *face, double *pos, double *u, double *v, double *len,
                       uint32_t *ncoll, int nthreads)
 {
@@ -222,8 +235,8 @@ static void run_walks(const float *log_tau, const float *c, const float *y_in, c
     walk_job jobs[256];
     pthread_t th[256];
     for (int t = 0; t < nthreads; ++t) {
-        walk_job j = {log_tau, c, y_in, sin_th, x_in, cos_phi, log_aspect, n, mode, seed, id_base, face,
-                      pos, u, v, len, ncoll, n * t / nthreads, n * (t + 1) / nthreads};
+        walk_job j = {log_tau, c, y_in, sin_th, x_in, cos_phi, log_aspect, omega_x, n, mode, seed,
+                      id_base, face, pos, u, v, len, ncoll, n * t / nthreads, n * (t + 1) / nthreads};
         jobs[t] = j;
     }
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, walk_worker, &jobs[t]);
@@ -231,14 +244,15 @@ static void run_walks(const float *log_tau, const float *c, const float *y_in, c
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
 }
 
-/* log_aspect may be NULL (square cells). */
+/* log_aspect may be NULL (square cells); omega_x may be NULL (flatland) or give the in-plane x
+ * component of each entry direction (XY geometry; sin_th is then its y component). */
 void orc_mc_transmit(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
-                     const float *log_aspect, int64_t n, int mode, uint64_t seed, uint64_t id_base,
-                     int32_t *face, double *pos, double *u, double *v, double *len, uint32_t *ncoll,
-                     int nthreads)
+                     const float *log_aspect, const float *omega_x, int64_t n, int mode, uint64_t seed,
+                     uint64_t id_base, int32_t *face, double *pos, double *u, double *v, double *len,
+                     uint32_t *ncoll, int nthreads)
 {
-    run_walks(log_tau, c, y_in, sin_th, NULL, NULL, log_aspect, n, mode, seed, id_base, face, pos, u, v,
-              len, ncoll, nthreads);
+    run_walks(log_tau, c, y_in, sin_th, NULL, NULL, log_aspect, omega_x, n, mode, seed, id_base, face,
+              pos, u, v, len, ncoll, nthreads);
 }
 
 /* Batch of walks started inside the cell: particle i is born at (x[i], y[i]) with direction
@@ -248,8 +262,8 @@ void orc_mc_transmit_internal(const float *log_tau, const float *c, const float 
                               uint64_t seed, uint64_t id_base, int32_t *face, double *pos, double *u,
                               double *v, double *len, uint32_t *ncoll, int nthreads)
 {
-    run_walks(log_tau, c, y, sin_phi, x, cos_phi, NULL, n, mode, seed, id_base, face, pos, u, v, len,
-              ncoll, nthreads);
+    run_walks(log_tau, c, y, sin_phi, x, cos_phi, NULL, NULL, n, mode, seed, id_base, face, pos, u, v,
+              len, ncoll, nthreads);
 }
 
 /* ------------------------------------------------------------------------------------ */
@@ -276,6 +290,7 @@ typedef struct {
     int32_t reflect;            /* 0 vacuum, 1 specular reflection at the domain boundary */
     double w_min;               /* weight cutoff */
     int32_t src_face;           /* -1 volumetric source; 0..3 isotropic incident flux on that side */
+    int32_t xy;                 /* 0 flatland, 1 XY geometry (directions on the sphere) */
 } orc_problem;
 
 typedef struct {
@@ -336,8 +351,17 @@ static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tal
          * first transmission is this cell's, cell visit 1 */
         entry = p->src_face;
         y_in = u01_open(r[1]);
-        double s = 2.0 * u01_open(r[2]) - 1.0;
-        inward_direction(entry, sqrt(1.0 - s * s), s, &gx, &gy);
+        if (p->xy) {
+            /* isotropic incident flux in three dimensions: the cosine of the angle to the
+             * inward normal is sqrt(xi) (pdf 2 cos over the hemisphere), the azimuth about the
+             * normal psi = 2 pi xi'; the in-plane components are (sqrt(xi), sqrt(1 - xi) cos psi) */
+            double xi = u01_open(r[2]);
+            double psi = 2.0 * ORC_PI * orc_u01(r[3]);
+            inward_direction(entry, sqrt(xi), sqrt(1.0 - xi) * cos(psi), &gx, &gy);
+        } else {
+            double s = 2.0 * u01_open(r[2]) - 1.0;
+            inward_direction(entry, sqrt(1.0 - s * s), s, &gx, &gy);
+        }
         event = 1;
     } else {
         /* volumetric source: uniform point, isotropic direction; first leg by the analog walk
@@ -347,7 +371,14 @@ static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tal
         double a = p->L / p->Ly;
         double x = a * u01_open(r[1]), y = u01_open(r[2]);
         double phi = 2.0 * ORC_PI * orc_u01(r[3]);
-        orc_walk(p->tau[cell] * ry, p->c[cell], 0, a, x, y, cos(phi), sin(phi), seed,
+        double st = 1.0;
+        if (p->xy) {             /* isotropic on the sphere: mu from a second draw */
+            uint32_t r2[4];
+            draw4(seed, (uint64_t)h, 1u, ORC_TAG_SOURCE, r2);
+            double mu = 2.0 * orc_u01(r2[0]) - 1.0;
+            st = sqrt(1.0 - mu * mu);
+        }
+        orc_walk(p->tau[cell] * ry, p->c[cell], 0, p->xy, a, x, y, st * cos(phi), st * sin(phi), seed,
                  (uint64_t)h | ((uint64_t)event << 32), &e);
         t->events += 1.0;
         face = e.face;
@@ -383,17 +414,18 @@ static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tal
         int k = (entry + 1) & 3;
         double U, Vc;
         rot(-k & 3, gx, gy, &U, &Vc);
-        double s = Vc;
-        if (s > 1.0) s = 1.0;
-        if (s < -1.0) s = -1.0;
-        double U0 = sqrt(1.0 - s * s);
-        (void)U;
+        double s = Vc, U0 = U;
+        if (!p->xy) {            /* flatland: unit direction, the x component from the y one */
+            if (s > 1.0) s = 1.0;
+            if (s < -1.0) s = -1.0;
+            U0 = sqrt(1.0 - s * s);
+        }
         /* the canonical cell: the entry face as height, the other side as width; left and
          * right faces have length Ly, bottom and top length L */
         double h_e = (entry & 1) ? p->Ly : p->L, w_e = (entry & 1) ? p->L : p->Ly;
         double rh = (entry & 1) ? p->Ly / p->L : 1.0;     /* tau scale: h_e / L */
         /* stage 2: sample the cell transmission (analog stand-in for the network) */
-        orc_walk(p->tau[cell] * rh, p->c[cell], 0, w_e / h_e, 0.0, y_in, U0, s, seed,
+        orc_walk(p->tau[cell] * rh, p->c[cell], 0, p->xy, w_e / h_e, 0.0, y_in, U0, s, seed,
                  (uint64_t)h | ((uint64_t)event << 32), &e);
         t->events += 1.0;
         /* stage 3: absorption and tally */
@@ -423,11 +455,12 @@ static void *tr_worker(void *arg)
  * number of source particles).  out_scalars = {leak, cutoff, events}. */
 void orc_transport(int32_t nx, int32_t ny, double L, double Ly, const double *tau, const double *c,
                    int32_t src_x0, int32_t src_y0, int32_t src_nx, int32_t src_ny, int32_t reflect,
-                   int32_t src_face, double w_min, uint64_t seed, uint32_t h_begin, uint32_t h_end,
-                   double *flux, double *absorbed, double *out_scalars, int nthreads)
+                   int32_t src_face, int32_t xy, double w_min, uint64_t seed, uint32_t h_begin,
+                   uint32_t h_end, double *flux, double *absorbed, double *out_scalars, int nthreads)
 {
     if (!(Ly > 0.0)) Ly = L;                          /* square cells */
-    orc_problem p = {nx, ny, L, Ly, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face};
+    orc_problem p = {nx, ny, L, Ly, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face,
+                     xy ? 1 : 0};
     int ncell = nx * ny;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;

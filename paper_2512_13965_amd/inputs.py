@@ -67,12 +67,15 @@ def _open01(g: np.random.Generator, n: int) -> np.ndarray:
 class Conditions:
     """Structure-of-arrays batch of canonical entry conditions (all float32, length n).
     log_aspect (optional): ln A of rectangular cells, A = width along the flight direction
-    over the entry face's length (None: square cells)."""
+    over the entry face's length (None: square cells).  omega_x (optional): XY geometry, the
+    in-plane x component of the entry direction, sin_th then being its y component (None:
+    flatland, unit in-plane direction)."""
     log_tau: np.ndarray
     c: np.ndarray
     y_in: np.ndarray
     sin_th: np.ndarray
     log_aspect: np.ndarray | None = None
+    omega_x: np.ndarray | None = None
 
     def __len__(self) -> int:
         return int(self.log_tau.shape[0])
@@ -80,7 +83,8 @@ class Conditions:
     def subset(self, idx) -> "Conditions":
         return Conditions(self.log_tau[idx].copy(), self.c[idx].copy(),
                           self.y_in[idx].copy(), self.sin_th[idx].copy(),
-                          None if self.log_aspect is None else self.log_aspect[idx].copy())
+                          None if self.log_aspect is None else self.log_aspect[idx].copy(),
+                          None if self.omega_x is None else self.omega_x[idx].copy())
 
 
 def transmission_conditions(n: int, seed: int, log_tau_range=(LOG_TAU_MIN, LOG_TAU_MAX),
@@ -99,6 +103,37 @@ def transmission_conditions(n: int, seed: int, log_tau_range=(LOG_TAU_MIN, LOG_T
         a0, a1 = log_aspect_range
         la = (a0 + (a1 - a0) * g.random(n)).astype(np.float32)
     return Conditions(log_tau, c, y_in, sin_th, la)
+
+
+def _xy_entry(g, n):
+    """Entry directions of isotropic incident flux in three dimensions, projected on the plane:
+    cosine to the inward normal sqrt(xi), azimuth psi about it; (omega_x, omega_y) =
+    (sqrt(xi), sqrt(1 - xi) cos psi)."""
+    xi = _open01(g, n).astype(np.float64)
+    psi = 2.0 * math.pi * _open01(g, n).astype(np.float64)
+    return np.sqrt(xi).astype(np.float32), (np.sqrt(1.0 - xi) * np.cos(psi)).astype(np.float32)
+
+
+def xy_conditions(n: int, seed: int, log_tau_range=(LOG_TAU_MIN, LOG_TAU_MAX),
+                  c_range=(0.0, 1.0)) -> Conditions:
+    """Mixed-cell batch in XY geometry: ln tau, c and y_in as transmission_conditions, entry
+    directions of isotropic incident flux on the sphere (projected)."""
+    g = rng(seed)
+    lo, hi = log_tau_range
+    log_tau = (lo + (hi - lo) * g.random(n)).astype(np.float32)
+    c = (c_range[0] + (c_range[1] - c_range[0]) * g.random(n)).astype(np.float32)
+    y_in = _open01(g, n)
+    ox, oy = _xy_entry(g, n)
+    return Conditions(log_tau, c, y_in, oy, None, ox)
+
+
+def fixed_xy_conditions(n: int, tau: float, c: float, seed: int) -> Conditions:
+    """One material for every particle, XY geometry; y_in ~ U(0,1), isotropic incident flux."""
+    g = rng(seed)
+    y_in = _open01(g, n)
+    ox, oy = _xy_entry(g, n)
+    return Conditions(np.full(n, np.float32(math.log(tau)), np.float32),
+                      np.full(n, np.float32(c), np.float32), y_in, oy, None, ox)
 
 
 def fixed_cell_conditions(n: int, tau: float, c: float, seed: int) -> Conditions:
@@ -285,6 +320,7 @@ class Problem:
     w_min: float = 1e-6
     src_face: int = -1
     Ly: float = 0.0
+    xy: bool = False          # XY geometry: directions on the sphere (eq. 1), invariant along z
 
     @property
     def n_cells(self) -> int:

@@ -85,6 +85,12 @@ def _global_walk_flux(prob, n, seed):
     g = np.random.default_rng(seed)
     L = prob.L
     Ly = prob.Ly if prob.Ly > 0 else L
+
+    def direction():
+        # isotropic: on the circle (flatland) or on the sphere, projected (XY geometry)
+        ph = 2 * math.pi * g.random()
+        st = math.sqrt(1.0 - (2.0 * g.random() - 1.0) ** 2) if prob.xy else 1.0
+        return st * math.cos(ph), st * math.sin(ph)
     flux = np.zeros(prob.n_cells)
     for _ in range(n):
         k = g.integers(prob.src_nx * prob.src_ny)
@@ -92,8 +98,7 @@ def _global_walk_flux(prob, n, seed):
         cj = prob.src_y0 + k // prob.src_nx
         x = (ci + g.random()) * L
         y = (cj + g.random()) * Ly
-        ph = 2 * math.pi * g.random()
-        u, v = math.cos(ph), math.sin(ph)
+        u, v = direction()
         w = 1.0
         d_s = None
         while True:
@@ -113,8 +118,7 @@ def _global_walk_flux(prob, n, seed):
             x += seg * u
             y += seg * v
             if d_s < db:
-                ph = 2 * math.pi * g.random()
-                u, v = math.cos(ph), math.sin(ph)
+                u, v = direction()
                 d_s = None
                 continue
             d_s = None         # exponential flights are memoryless: redraw in the next cell
@@ -129,14 +133,15 @@ def _global_walk_flux(prob, n, seed):
     return flux
 
 
-@pytest.mark.parametrize("Ly", [0.0, 0.35, 1.6])
-def test_cell_to_cell_transport_matches_global_walk(orc, Ly):
+@pytest.mark.parametrize("Ly,xy", [(0.0, False), (0.35, False), (1.6, False), (0.0, True), (0.5, True)])
+def test_cell_to_cell_transport_matches_global_walk(orc, Ly, xy):
     # the per-cell canonical rotation (stage 1), face decoding and neighbour move (stage 4)
     # must reproduce a plain global random walk over the same heterogeneous grid, for square
-    # cells and for rectangles of either orientation (canonical frames with A = W / H and H / W)
+    # cells and for rectangles of either orientation (canonical frames with A = W / H and H / W),
+    # in flatland and in XY geometry (three-dimensional directions, projected)
     t = np.array([0.3, 2.0, 0.7, 1.5, 0.5, 3.0, 0.9, 0.2, 1.1])
     c = np.array([0.9, 0.5, 0.99, 0.7, 0.8, 0.95, 0.3, 1.0, 0.6])
-    prob = inputs.Problem(3, 3, 0.7, t, c, 1, 1, 1, 1, Ly=Ly)
+    prob = inputs.Problem(3, 3, 0.7, t, c, 1, 1, 1, 1, Ly=Ly, xy=xy)
     n, runs = 3000, 5
     ref = np.array([_global_walk_flux(prob, n, seed=s) / n for s in range(runs)])
     got = np.array([orc.transport(prob, seed=40 + s, h_begin=0, h_end=n, nthreads=NT)["flux"] / n
