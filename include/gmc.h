@@ -69,10 +69,14 @@ typedef enum { GMC_EULER = 0, GMC_RK4 = 1 } gmc_integrator;
  *   log_aspect  optional (NULL: square cells): ln A, A = cell width along +x over the entry
  *               face's length; the canonical cell is [0, A] x [0, 1] in units of the entry
  *               face, exit positions are fractions of the exit face's length and path lengths
- *               are in units of the entry face */
+ *               are in units of the entry face
+ *   omega_x     optional (NULL: flatland): XY geometry (eq. 1 over the sphere, the problem
+ *               invariant along z); the entry direction's in-plane projection is
+ *               (omega_x, sin_th), inside the unit disk, and paths are three-dimensional */
 typedef struct {
     const float *log_tau, *c, *y_in, *sin_th;
     const float *log_aspect;
+    const float *omega_x;
 } gmc_cond;
 
 /* Birth conditions of n particles born inside a cell (the internal, volumetric-source model of
@@ -158,7 +162,10 @@ int gmc_sample_internal(const gmc_model *m, gmc_cond_internal cond, int64_t n, i
 
 /* Samples n cell transmissions with the analog random walk that the generative sampler
  * replaces (paper "Monte Carlo Method", eq. 4) through the canonical cell [0, A] x [0, 1]
- * (A = 1 without log_aspect; lengths in units of the entry face): flights d = -ln(xi) / sigma with
+ * (A = 1 without log_aspect; lengths in units of the entry face).  With omega_x (XY geometry)
+ * a scattering also draws mu = 2 xi_3 - 1 from word 3 and the new in-plane direction is
+ * sqrt(1 - mu^2) (cos phi, sin phi); exit directions are then projections (norm <= 1).
+ * Flights d = -ln(xi) / sigma with
  * xi = ((w >> 8) + 1) * 2^-24 in (0, 1], isotropic flatland scattering phi = 2 pi xi'.
  *   mode GMC_MODE_CONTINUOUS: sigma = c * tau (implicit capture: the caller attenuates the
  *        weight by exp(-(1 - c) tau path), eqs. 5-6); every walk ends on a face.
@@ -195,7 +202,13 @@ typedef struct gmc_world gmc_world;
  * gmc_problem_add.  A transmission is sampled in the canonical frame of its entry face (that
  * face as the unit of length: tau * Ly / L and aspect A = L / Ly through the left and right
  * faces, tau and A = Ly / L through the bottom and top); rectangular cells need an 11-input
- * boundary model for the generative sampler and volumetric births by the analog walk.  Boundaries are vacuum
+ * boundary model for the generative sampler and volumetric births by the analog walk.
+ * xy = 1 selects XY geometry (eq. 1 over the sphere, invariant along z): directions are
+ * projections of unit directions, scattering and volumetric sources are isotropic on the sphere
+ * (mu from the next Philox block of the birth stream), a surface source is isotropic incident
+ * flux (cosine sqrt(xi) to the normal, azimuth psi), tracks are three-dimensional.  All problems
+ * of a world share one geometry (GMC_EINVAL otherwise); the generative sampler then needs a
+ * model of that geometry.  Boundaries are vacuum
  * (reflect = 0) or specular (reflect = 1).  A history ends when it leaves the domain or when its
  * weight drops below w_min after a cell visit (the weight is then tallied as cutoff).
  * Sources (one unit-weight particle per history):
@@ -222,6 +235,7 @@ typedef struct {
     uint64_t seed;
     int32_t src_face;
     double Ly;
+    int32_t xy;
 } gmc_problem_desc;
 
 /* Device bytes gmc_world_create would allocate for these capacities (admission control). */

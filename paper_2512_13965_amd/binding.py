@@ -31,7 +31,7 @@ class GmcError(RuntimeError):
 class _Cond(ctypes.Structure):
     _fields_ = [("log_tau", ctypes.c_void_p), ("c", ctypes.c_void_p),
                 ("y_in", ctypes.c_void_p), ("sin_th", ctypes.c_void_p),
-                ("log_aspect", ctypes.c_void_p)]
+                ("log_aspect", ctypes.c_void_p), ("omega_x", ctypes.c_void_p)]
 
 
 class _CondInternal(ctypes.Structure):
@@ -103,13 +103,15 @@ class DeviceCond:
     y_in: torch.Tensor
     sin_th: torch.Tensor
     log_aspect: torch.Tensor | None = None
+    omega_x: torch.Tensor | None = None
 
     @classmethod
     def from_host(cls, cond, device="cuda"):
         f = lambda a: torch.as_tensor(a, dtype=torch.float32).to(device).contiguous()
         la = getattr(cond, "log_aspect", None)
+        ox = getattr(cond, "omega_x", None)
         return cls(f(cond.log_tau), f(cond.c), f(cond.y_in), f(cond.sin_th),
-                   None if la is None else f(la))
+                   None if la is None else f(la), None if ox is None else f(ox))
 
     def __len__(self):
         return int(self.log_tau.numel())
@@ -118,11 +120,13 @@ class DeviceCond:
         n = len(self)
         for nm in ("log_tau", "c", "y_in", "sin_th"):
             _need(getattr(self, nm), torch.float32, n, nm)
-        if self.log_aspect is not None:
-            _need(self.log_aspect, torch.float32, n, "log_aspect")
+        for nm in ("log_aspect", "omega_x"):
+            if getattr(self, nm) is not None:
+                _need(getattr(self, nm), torch.float32, n, nm)
         return _Cond(self.log_tau.data_ptr(), self.c.data_ptr(), self.y_in.data_ptr(),
                      self.sin_th.data_ptr(),
-                     None if self.log_aspect is None else self.log_aspect.data_ptr())
+                     None if self.log_aspect is None else self.log_aspect.data_ptr(),
+                     None if self.omega_x is None else self.omega_x.data_ptr())
 
 
 @dataclass
@@ -315,7 +319,7 @@ class _ProblemDesc(ctypes.Structure):
                 ("src_x0", ctypes.c_int32), ("src_y0", ctypes.c_int32),
                 ("src_nx", ctypes.c_int32), ("src_ny", ctypes.c_int32),
                 ("reflect", ctypes.c_int32), ("w_min", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("src_face", ctypes.c_int32), ("Ly", ctypes.c_double)]
+                ("src_face", ctypes.c_int32), ("Ly", ctypes.c_double), ("xy", ctypes.c_int32)]
 
 
 def _transport_sigs(L):
@@ -365,7 +369,7 @@ class World:
         d = _ProblemDesc(problem.nx, problem.ny, problem.L, tau.ctypes.data, c.ctypes.data,
                          problem.src_x0, problem.src_y0, problem.src_nx, problem.src_ny,
                          int(problem.reflect), problem.w_min, seed, int(getattr(problem, "src_face", -1)),
-                         float(getattr(problem, "Ly", 0.0)))
+                         float(getattr(problem, "Ly", 0.0)), int(bool(getattr(problem, "xy", False))))
         pid = ctypes.c_int32()
         _check(self._L.gmc_problem_add(self._h, ctypes.byref(d), ctypes.byref(pid), _stream(stream)))
         self._shapes[pid.value] = problem.n_cells

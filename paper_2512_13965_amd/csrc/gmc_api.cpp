@@ -146,6 +146,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         return fail(GMC_EINVAL, "gmc_model_create: bad magic or version");
     if (hd.n_in < 10 || hd.n_in > 12 || hd.n_out != 5 || hd.n_layers != 5)
         return fail(GMC_EINVAL, "gmc_model_create: network must be 10, 11 or 12 -> H x4 -> 5");
+    if ((hd.flags & 1u) && hd.n_in != 11)
+        return fail(GMC_EINVAL, "gmc_model_create: an XY-geometry model has 11 inputs");
     const int H = (int)hd.hidden;
     if (!mlp_supported(precision, H))
         return fail(GMC_EUNSUPPORTED, "gmc_model_create: hidden width " + std::to_string(H) +
@@ -178,6 +180,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     m->serial = next_serial++;
     m->precision = precision;
     m->n_in = NI;
+    m->xy = (hd.flags & 1u) != 0;
     m->tmpl.n_cond = NI - 6;
     m->hidden = H;
     for (int l = 0; l < 5; ++l) {
@@ -367,6 +370,10 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
         return fail(GMC_EINVAL, "gmc_transmit: the model is not a boundary model (10 or 11 inputs)");
     if (m->n_in == 10 && cond.log_aspect)
         return fail(GMC_EINVAL, "gmc_transmit: a square-cell model (10 inputs) takes no aspect ratio");
+    if ((cond.omega_x != nullptr) != m->xy)
+        return fail(GMC_EINVAL, "gmc_transmit: omega_x is given exactly for XY-geometry models");
+    if (m->xy && cond.log_aspect)
+        return fail(GMC_EINVAL, "gmc_transmit: XY-geometry models serve square cells");
     if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "gmc_transmit: null condition array");
     gmc::MlpParams p = m->tmpl;
     p.log_tau = cond.log_tau;
@@ -409,6 +416,7 @@ int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_b
     p.y_in = cond.y_in;
     p.sin_th = cond.sin_th;
     p.log_aspect = cond.log_aspect;
+    p.omega_x = cond.omega_x;
     return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit");
 }
 

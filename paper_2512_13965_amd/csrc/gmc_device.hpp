@@ -85,6 +85,7 @@ __device__ __forceinline__ void normal5(uint64_t seed, uint64_t id, float z[5])
 struct Walker {
     float x, y, u, v, len, inv_sig, cs;
     float wa;                            // cell width in units of its height (1: square)
+    bool xy;                             // XY geometry: (u, v) projects a direction on the sphere
     uint32_t flight, ncoll;
     bool scatter, analog;
 };
@@ -93,9 +94,10 @@ struct Walker {
 // and a collision absorbs when xi > c.  Start at (x, y) with direction (u, v) in the cell
 // [0, wa] x [0, 1]; lengths and tau are in units of the cell height.
 __device__ __forceinline__ void walker_init(Walker &w, float tau, float c, int mode, float x, float y,
-                                            float u, float v, float wa = 1.0f)
+                                            float u, float v, float wa = 1.0f, bool xy = false)
 {
     w.wa = wa;
+    w.xy = xy;
     w.analog = (mode == 1);
     const float sig = w.analog ? tau : c * tau;
     w.scatter = sig > 1e-30f;            // below this 1/sig would overflow
@@ -152,6 +154,12 @@ __device__ __forceinline__ int walker_flight(Walker &w, uint64_t key, uint64_t s
             const float ph = u01(r.b);
             w.u = cos_turns(ph);
             w.v = sin_turns(ph);
+            if (w.xy) {                  // on the sphere: mu = 2 xi - 1 from word 3, projected
+                const float mu = 2.0f * u01(r.d) - 1.0f;
+                const float st = sqrtf(fmaxf(1.0f - mu * mu, 0.0f));
+                w.u *= st;
+                w.v *= st;
+            }
         }
     }
     w.flight += 1;

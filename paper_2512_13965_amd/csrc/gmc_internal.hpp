@@ -85,6 +85,7 @@ struct WalkParams {
     const float *x_in, *cos_phi;   // optional: start inside the cell at (x_in, y_in), direction
                                    // (cos_phi, sin_th); else on the left face, cosine from sin_th
     const float *log_aspect;  // optional: cell [0, A] x [0, 1], A = exp(log_aspect); else square
+    const float *omega_x;     // optional: XY geometry, in-plane x component of the entry direction
     int32_t *face;
     float *pos, *dcos, *dsin, *path;
     uint32_t *ncoll;          // optional
@@ -124,7 +125,8 @@ struct gmc_model {
     uint64_t serial = 0;     // unique per created model (keys captured launches)
     int precision = 0;
     int hidden = 0;
-    int n_in = 10;           // 10: boundary model, 12: internal model
+    int n_in = 10;           // 10: boundary model, 11: rectangular-cell or XY boundary model, 12: internal
+    bool xy = false;         // XY geometry (blob flags bit 0): condition carries omega_x
     int device = 0;
     void *dev_mem = nullptr;
     gmc::MlpParams tmpl{};   // weight / bias pointers and scales

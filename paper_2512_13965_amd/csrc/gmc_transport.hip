@@ -41,6 +41,7 @@ struct ProblemDev {
     double w_min;
     uint64_t seed;
     int32_t src_face;              // -1 volumetric, else the domain side of a surface source
+    int32_t xy;                    // XY geometry: directions on the sphere, projected
 };
 
 struct BankDev {
@@ -230,9 +231,15 @@ __global__ __launch_bounds__(256) void birth_kernel(CellsDev cd, int32_t pid, ui
         const float ph = u01(r.d);
         // the cell's own frame [0, L / Ly] x [0, 1], lengths in units of its height Ly
         const float wa = (float)(P.L / P.Ly);
+        float st = 1.0f;
+        if (P.xy) {                      // isotropic on the sphere: mu from a second draw
+            const U4 r2 = draw4(P.seed, (uint64_t)h, 1u, kTagSource);
+            const float mu = 2.0f * u01(r2.a) - 1.0f;
+            st = sqrtf(fmaxf(1.0f - mu * mu, 0.0f));
+        }
         Walker W;
         walker_init(W, (float)(cd.tau[cell] * (P.Ly / P.L)), (float)cd.c[cell], 0, wa * u01_open(r.b),
-                    u01_open(r.c), cos_turns(ph), sin_turns(ph), wa);
+                    u01_open(r.c), st * cos_turns(ph), st * sin_turns(ph), wa, P.xy != 0);
         float pos = 0.0f;
         int face;
         do {
@@ -268,8 +275,15 @@ __global__ __launch_bounds__(256) void surface_birth_kernel(CellsDev cd, int32_t
         const uint32_t pick = __umulhi(r.a, nsrc);
         const int ci = P.sx0 + (int)(pick % (uint32_t)P.snx), cj = P.sy0 + (int)(pick / (uint32_t)P.snx);
         const int f = P.src_face;
-        const float s = 2.0f * u01_open(r.c) - 1.0f;
-        const float cth = sqrtf(fmaxf(1.0f - s * s, 0.0f));
+        float s, cth;
+        if (P.xy) {      // isotropic incident flux on the sphere: cosine sqrt(xi), azimuth psi
+            const float xi = u01_open(r.c);
+            cth = sqrtf(xi);
+            s = sqrtf(fmaxf(1.0f - xi, 0.0f)) * cos_turns(u01(r.d));
+        } else {
+            s = 2.0f * u01_open(r.c) - 1.0f;
+            cth = sqrtf(fmaxf(1.0f - s * s, 0.0f));
+        }
         nx.cell = (int32_t)(P.cell0 + (int64_t)cj * P.nx + ci);
         nx.entry = f;
         nx.yin = u01_open(r.b);
@@ -348,7 +362,8 @@ __global__ __launch_bounds__(256) void source_apply_kernel(CellsDev cd, int32_t 
 __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
                                                      const unsigned long long *n_dev, CellsDev cd,
                                                      float *ltau, float *cc, float *yin, float *sth,
-                                                     float *laspect, uint64_t *ids, uint64_t *keys)
+                                                     float *laspect, float *omx, uint64_t *ids,
+                                                     uint64_t *keys)
 {
     const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -361,6 +376,7 @@ __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
     const float lr = cd.prob[b.pid[i]].lr;
     ltau[i] = (e & 1) ? cd.ltau[cell] + lr : cd.ltau[cell];
     laspect[i] = (e & 1) ? -lr : lr;
+    omx[i] = U;                          // read only in XY geometry
     cc[i] = cd.cf[cell];
     yin[i] = b.yin[i];
     sth[i] = fminf(fmaxf(V, -1.0f), 1.0f);
@@ -440,6 +456,7 @@ struct gmc_world {
     float *c_ltau = nullptr, *c_c = nullptr, *c_yin = nullptr, *c_sth = nullptr;
     float *c_x = nullptr, *c_cos = nullptr;      // internal-model births
     float *c_la = nullptr;                       // canonical ln aspect (rectangular cells)
+    float *c_ox = nullptr;                       // canonical in-plane x direction (XY geometry)
     uint64_t *ids = nullptr, *keys = nullptr;
     int32_t *e_face = nullptr;
     float *e_pos = nullptr, *e_dcos = nullptr, *e_dsin = nullptr, *e_path = nullptr;
@@ -469,6 +486,7 @@ struct gmc_world {
     std::vector<char> in_use;
     std::vector<int32_t> src_face;      // per problem slot: -1 volumetric, else a surface side
     std::vector<char> rect;             // per problem slot: non-square cells
+    std::vector<char> xyg;              // per problem slot: XY geometry
     std::vector<std::pair<int64_t, int64_t>> free_cells;   // [begin, end) ranges
     std::mutex mu;
 
@@ -508,6 +526,7 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->c_sth, 4 * C);
     L.add((void **)&w->c_x, 4 * C);
     L.add((void **)&w->c_la, 4 * C);
+    L.add((void **)&w->c_ox, 4 * C);
     L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);
     L.add((void **)&w->keys, 8 * C);
@@ -595,6 +614,7 @@ int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_ce
     w->in_use.assign(max_problems, 0);
     w->src_face.assign(max_problems, -1);
     w->rect.assign(max_problems, 0);
+    w->xyg.assign(max_problems, 0);
     w->free_cells.push_back({0, max_cells});
     *out = w;
     return GMC_OK;
@@ -628,6 +648,8 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     if (!(d->Ly >= 0.0) || !std::isfinite(d->Ly))
         return set_error(GMC_EINVAL, "gmc_problem_add: Ly must be 0 (square cells) or positive");
     const double Ly = d->Ly > 0.0 ? d->Ly : d->L;
+    if (d->xy != 0 && d->xy != 1)
+        return set_error(GMC_EINVAL, "gmc_problem_add: xy must be 0 (flatland) or 1 (XY geometry)");
     if (d->src_face < -1 || d->src_face > 3)
         return set_error(GMC_EINVAL, "gmc_problem_add: src_face must be -1 (volumetric) or a side 0..3");
     if (d->src_face >= 0) {
@@ -645,6 +667,9 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
         if (!(d->tau[i] >= 0.0) || !std::isfinite(d->tau[i]) || !(d->c[i] >= 0.0) || !(d->c[i] <= 1.0))
             return set_error(GMC_EINVAL, "gmc_problem_add: tau must be finite >= 0 and c in [0, 1]");
     std::lock_guard<std::mutex> lk(w->mu);
+    for (int q = 0; q < w->max_problems; ++q)
+        if (w->in_use[q] && w->xyg[q] != (d->xy ? 1 : 0))
+            return set_error(GMC_EINVAL, "gmc_problem_add: the world's problems share one geometry (flatland or XY)");
     int pid = -1;
     for (int p = 0; p < w->max_problems; ++p)
         if (!w->in_use[p]) { pid = p; break; }
@@ -666,7 +691,7 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
         cf[i] = (float)d->c[i];
     }
     ProblemDev P{d->nx, d->ny, d->L, Ly, (float)std::log(Ly / d->L), cell0, d->src_x0, d->src_y0,
-                 d->src_nx, d->src_ny, d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face};
+                 d->src_nx, d->src_ny, d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face, d->xy ? 1 : 0};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(w->tau + cell0, d->tau, 8 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(w->c + cell0, d->c, 8 * n, hipMemcpyHostToDevice, s);
@@ -687,6 +712,7 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     w->in_use[pid] = 1;
     w->src_face[pid] = d->src_face;
     w->rect[pid] = Ly != d->L;
+    w->xyg[pid] = d->xy ? 1 : 0;
     w->prob_host[pid] = P;
     w->alive_pp[pid] = 0;
     *pid_out = pid;
@@ -711,6 +737,7 @@ int gmc_problem_remove(gmc_world *w, int32_t pid)
     w->free_cells.swap(merged);
     w->in_use[pid] = 0;
     w->rect[pid] = 0;
+    w->xyg[pid] = 0;
     return GMC_OK;
 }
 
@@ -723,8 +750,8 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
         return set_error(GMC_EINVAL, "gmc_world_inject: history ids must stay below 2^32");
     if (count > w->cap - w->n_alive)
         return set_error(GMC_ENOMEM, "gmc_world_inject: not enough free bank slots");
-    if (w->src_face[pid] < 0 && w->src_model && w->rect[pid])
-        return set_error(GMC_EINVAL, "gmc_world_inject: the internal model serves square cells only");
+    if (w->src_face[pid] < 0 && w->src_model && (w->rect[pid] || w->xyg[pid]))
+        return set_error(GMC_EINVAL, "gmc_world_inject: the internal model serves flatland square cells only");
     hipStream_t s = (hipStream_t)stream;
     if (count > 0) {
         const int which = w->cur;
@@ -820,6 +847,14 @@ int gmc_world_set_graphs(gmc_world *w, int enable)
 
 namespace {
 
+// XY geometry of the world's problems (they all share one geometry)
+bool world_xy(const gmc_world *w)
+{
+    for (int p = 0; p < w->max_problems; ++p)
+        if (w->in_use[p] && w->xyg[p]) return true;
+    return false;
+}
+
 // Enqueue one transport step on `s`: gather, sampler, counter reset, apply.  Grids are sized for
 // `n_launch` particles; the kernels process n_dev[0] of them when n_dev is given (a captured step
 // serves every count up to its bucket), else n_launch.
@@ -828,7 +863,8 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
 {
     const int cur = w->cur, nxt = 1 - cur;
     hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
-                       n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la, w->ids, w->keys);
+                       n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la, w->c_ox, w->ids,
+                       w->keys);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: gather");
     const int cu = device_cu_count();
@@ -864,6 +900,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.y_in = w->c_yin;
         p.sin_th = w->c_sth;
         p.log_aspect = w->c_la;
+        p.omega_x = world_xy(w) ? w->c_ox : nullptr;
         p.face = w->e_face;
         p.pos = w->e_pos;
         p.dcos = w->e_dcos;
@@ -948,6 +985,8 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
     if (sampler == GMC_SAMPLER_GMC && m->n_in == 10 &&
         std::any_of(w->rect.begin(), w->rect.end(), [](char r) { return r != 0; }))
         return set_error(GMC_EINVAL, "gmc_transport_step: rectangular cells need an 11-input boundary model");
+    if (sampler == GMC_SAMPLER_GMC && world_xy(w) != m->xy)
+        return set_error(GMC_EINVAL, "gmc_transport_step: the model's geometry (flatland / XY) differs from the world's");
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = w->n_alive;
     if (n > 0) {

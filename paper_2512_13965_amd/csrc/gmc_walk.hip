@@ -68,6 +68,9 @@ __global__ __launch_bounds__(256) void walk_kernel(WalkParams p)
                     if (p.x_in) {       // birth inside the cell
                         walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, p.x_in[i], p.y_in[i],
                                     p.cos_phi[i], s, wa);
+                    } else if (p.omega_x) {   // entry on the left face, XY geometry
+                        walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, 0.0f, p.y_in[i],
+                                    p.omega_x[i], s, wa, true);
                     } else {            // entry on the left face
                         walker_init(w, expf(p.log_tau[i]), p.c[i], p.mode, 0.0f, p.y_in[i],
                                     sqrtf(fmaxf(1.0f - s * s, 0.0f)), s, wa);
