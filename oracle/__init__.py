@@ -205,7 +205,8 @@ def silu(a):
 def condition_features(cond) -> np.ndarray:
     """Condition part of the network input.  Boundary model (entry conditions):
     (ln tau, c, 2*y_in - 1, sin theta_in), [n, 4], and for rectangular cells (conditions with a
-    log_aspect) ln A as a fifth column, [n, 5].  Internal model (birth conditions, which carry
+    log_aspect) ln A as a fifth column, [n, 5]; in XY geometry (conditions with omega_x, sin_th
+    being the in-plane y component) omega_x as the fifth column.  Internal model (birth conditions, which carry
     the birth position x, y and direction): (ln tau, c, 2x - 1, 2y - 1, cos phi, sin phi), [n, 6]."""
     f = lambda a: np.asarray(a, np.float64)
     if hasattr(cond, "x"):
@@ -214,6 +215,8 @@ def condition_features(cond) -> np.ndarray:
     cols = [f(cond.log_tau), f(cond.c), 2.0 * f(cond.y_in) - 1.0, f(cond.sin_th)]
     if getattr(cond, "log_aspect", None) is not None:
         cols.append(f(cond.log_aspect))
+    elif getattr(cond, "omega_x", None) is not None:       # XY geometry: omega_x
+        cols.append(f(cond.omega_x))
     return np.stack(cols, axis=1)
 
 
@@ -285,15 +288,16 @@ def sample_raw_rk4(weights, cond, K: int, z: np.ndarray, precision=PREC_FP64) ->
 OUTWARD = np.array([[0.0, -1.0], [1.0, 0.0], [0.0, 1.0], [-1.0, 0.0]])
 
 
-def decode(raw) -> dict:
+def decode(raw, xy: bool = False) -> dict:
     """Exit record from the network output (paper eq. 11; the target layout is
     a0 = 2r - 1, (a1, a2) = exit direction, a3 = ln(path / L), a4 = face - 1.5).
 
     face = number of the thresholds -1, 0, 1 that a4 reaches (clamped to 0..3);
     pos = clamp((a0 + 1) / 2, 0, 1); direction = (a1, a2) normalised (outward normal of the
     face if the norm is below 1e-6), its normal component reflected if it points into the
-    cell; path = exp(a3).  Also returns per-sample flags: bit0 pos clamped, bit1 direction
-    reflected, bit2 zero-norm direction."""
+    cell; path = exp(a3).  In XY geometry (xy=True) the direction is a projection: it is kept
+    when its norm is at most 1 and scaled to norm 1 otherwise.  Also returns per-sample flags:
+    bit0 pos clamped, bit1 direction reflected, bit2 zero-norm direction."""
     raw = np.asarray(raw, np.float64)
     a0, a1, a2, a3, a4 = (raw[:, i] for i in range(5))
     face = (a4 >= -1.0).astype(np.int32) + (a4 >= 0.0) + (a4 >= 1.0)
@@ -305,6 +309,8 @@ def decode(raw) -> dict:
     small = nrm < 1e-6
     nout = OUTWARD[face]
     safe = np.where(small, 1.0, nrm)
+    if xy:
+        safe = np.where(small, 1.0, np.maximum(nrm, 1.0))
     u = np.where(small, nout[:, 0], a1 / safe)
     v = np.where(small, nout[:, 1], a2 / safe)
     dn = u * nout[:, 0] + v * nout[:, 1]

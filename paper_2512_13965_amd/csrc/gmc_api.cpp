@@ -181,6 +181,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     m->precision = precision;
     m->n_in = NI;
     m->xy = (hd.flags & 1u) != 0;
+    m->tmpl.xy = m->xy ? 1 : 0;
     m->tmpl.n_cond = NI - 6;
     m->hidden = H;
     for (int l = 0; l < 5; ++l) {
@@ -383,6 +384,7 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
     p.x_in = nullptr;
     p.cos_phi = nullptr;
     p.log_aspect = cond.log_aspect;
+    p.omega_x = cond.omega_x;
     return launch_sampler(m, p, n, integrator, K, seed, id_base, noise_opt, raw_opt, out, stream, "gmc_sample");
 }
 

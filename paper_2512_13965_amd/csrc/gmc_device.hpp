@@ -188,7 +188,10 @@ struct Exit {
     float pos, u, v, path;
 };
 
-__device__ __forceinline__ int decode_exit(float a0, float a1, float a2, float a3, float a4, Exit &e)
+// In XY geometry the exit direction is a projection: (a1, a2) is kept inside the unit disk
+// (scaled to norm 1 only when it lies outside) instead of being normalised.
+__device__ __forceinline__ int decode_exit(float a0, float a1, float a2, float a3, float a4, Exit &e,
+                                           bool xy = false)
 {
     int flags = 0;
     const int face = (a4 >= -1.0f) + (a4 >= 0.0f) + (a4 >= 1.0f);
@@ -204,10 +207,13 @@ __device__ __forceinline__ int decode_exit(float a0, float a1, float a2, float a
         u = nx;
         v = ny;
         flags |= 4;
-    } else {
+    } else if (!xy || nrm > 1.0f) {
         const float inv = 1.0f / nrm;
         u = a1 * inv;
         v = a2 * inv;
+    } else {
+        u = a1;
+        v = a2;
     }
     const float dn = u * nx + v * ny;
     if (dn < 0.0f) {

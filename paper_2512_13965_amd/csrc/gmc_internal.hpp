@@ -74,6 +74,8 @@ struct MlpParams {
     const unsigned long long *n_dev;   // optional: sample count read on the device (<= n)
     int K;                    // integration steps
     int integrator;           // 0 explicit Euler, 1 classic RK4 (4 evaluations per step)
+    const float *omega_x;     // XY boundary model: in-plane x component of the entry direction
+    int xy;                   // XY geometry: exit directions decoded into the unit disk
     uint64_t seed, id_base;
 };
 

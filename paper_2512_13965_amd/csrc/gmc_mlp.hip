@@ -574,6 +574,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     co = p.cos_phi[i];
                 }
                 if (p.log_aspect) la = p.log_aspect[i];
+                else if (p.omega_x) la = p.omega_x[i];     // XY model: fifth feature omega_x
                 if (p.noise) {
 #pragma unroll
                     for (int d = 0; d < 5; ++d) z[d] = p.noise[d * p.n + i];
@@ -583,7 +584,8 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             }
 #pragma unroll
             for (int d = 0; d < 5; ++d) xs[d * kTileM + tid] = z[d];
-            // boundary model: (ln tau, c, 2 y_in - 1, sin th), rectangular cells add ln A;
+            // boundary model: (ln tau, c, 2 y_in - 1, sin th), rectangular cells add ln A, an
+            // XY-geometry model the entry direction's in-plane x component omega_x;
             // internal model: (ln tau, c, 2 x - 1, 2 y - 1, cos phi, sin phi)
             cf[0 * kTileM + tid] = lt;
             cf[1 * kTileM + tid] = cc;
@@ -919,7 +921,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     p.raw[4 * p.n + i] = a4;
                 }
                 Exit e;
-                decode_exit(a0, a1, a2, a3, a4, e);
+                decode_exit(a0, a1, a2, a3, a4, e, p.xy != 0);
                 p.face[i] = e.face;
                 p.pos[i] = e.pos;
                 p.dcos[i] = e.u;

@@ -875,7 +875,8 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.c = w->c_c;
         p.y_in = w->c_yin;
         p.sin_th = w->c_sth;
-        p.log_aspect = (m->n_in == 11) ? w->c_la : nullptr;
+        p.log_aspect = (m->n_in == 11 && !m->xy) ? w->c_la : nullptr;
+        p.omega_x = m->xy ? w->c_ox : nullptr;
         p.noise = nullptr;
         p.raw = nullptr;
         p.ids = w->ids;

@@ -218,7 +218,8 @@ class Weights:
     act_scale: np.ndarray = field(default_factory=lambda: np.ones(N_LAYERS, np.float32))
     w_scale: np.ndarray = field(default_factory=lambda: np.ones(N_LAYERS, np.float32))
     seed: int = 0
-    n_in: int = N_IN          # 10: boundary model, 12: internal model
+    n_in: int = N_IN          # 10: boundary model, 11: rectangular / XY boundary model, 12: internal
+    flags: int = 0            # bit 0: XY geometry (11 inputs, fifth condition feature omega_x)
 
     def n_params(self) -> int:
         return int(sum(w.size + bb.size for w, bb in zip(self.W, self.b)))
@@ -231,7 +232,8 @@ def pow2_ceil_scale(amax: float, fmax: float = 448.0) -> float:
     return float(2.0 ** math.ceil(math.log2(amax / fmax)))
 
 
-def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5, n_in: int = N_IN) -> Weights:
+def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5, n_in: int = N_IN,
+                   flags: int = 0) -> Weights:
     """Seeded random-init network, U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for W and b.
 
     The per-layer FP8 scales are stored with the weights: the weight scale is the
@@ -248,12 +250,12 @@ def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5, n_in: i
         b.append(g.uniform(-bound, bound, size=(o,)).astype(np.float32))
     w_scale = np.array([pow2_ceil_scale(float(np.abs(w).max())) for w in W], np.float32)
     a_scale = np.full(N_LAYERS, np.float32(act_scale), np.float32)
-    return Weights(hidden, W, b, a_scale, w_scale, seed, n_in)
+    return Weights(hidden, W, b, a_scale, w_scale, seed, n_in, flags)
 
 
 def pack_blob(w: Weights) -> bytes:
     """Serialise to the versioned little-endian blob read by gmc_model_create()."""
-    hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, w.n_in, w.hidden, N_OUT, N_LAYERS, 0,
+    hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, w.n_in, w.hidden, N_OUT, N_LAYERS, int(w.flags),
                     int(w.seed) & 0xFFFFFFFF, 0,
                     *[float(x) for x in w.act_scale], *[float(x) for x in w.w_scale])
     parts = [hdr]
@@ -265,7 +267,7 @@ def pack_blob(w: Weights) -> bytes:
 
 def unpack_blob(blob: bytes) -> Weights:
     fields = _HDR.unpack_from(blob, 0)
-    magic, version, n_in, hidden, n_out, n_layers, _flags, seed, _res = fields[:9]
+    magic, version, n_in, hidden, n_out, n_layers, flags, seed, _res = fields[:9]
     if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in not in (N_IN, N_IN_RECT, N_IN_INTERNAL) \
             or n_out != N_OUT or n_layers != N_LAYERS:
         raise ValueError("not a GMC weights blob of a supported version")
@@ -280,7 +282,7 @@ def unpack_blob(blob: bytes) -> Weights:
         off += 4 * o
     if off != len(blob):
         raise ValueError("weights blob has trailing or missing bytes")
-    return Weights(hidden, W, b, act, wsc, seed, n_in)
+    return Weights(hidden, W, b, act, wsc, seed, n_in, flags)
 
 
 def save_blob(w: Weights, path: str) -> None:

@@ -1,10 +1,12 @@
 """One-time fit of a velocity network by conditional flow matching (paper section "Conditional
 Flow Matching", eq. 9; training data as in "Network Architecture and Inputs": pure-scattering
-Monte Carlo exits over a range of optical dimensions and entry states).  Three models: the
+Monte Carlo exits over a range of optical dimensions and entry states).  Four models: the
 boundary model (condition: ln tau, c, entry height, sin of the entry angle), the boundary model
 of rectangular cells (the same plus ln A, A = width over entry-face length, ln A ~ U[ln 1/4,
-ln 4]) and the internal model for particles born inside a cell (condition: ln tau, c, birth
-point, birth direction).
+ln 4]), the boundary model in XY geometry (entry direction a projection of a direction on the
+sphere: its in-plane components omega_y, omega_x; exit directions inside the unit disk) and the
+internal model for particles born inside a cell (condition: ln tau, c, birth point, birth
+direction).
 
 Data come from this library's own analog walk (`mc_transmit` / `mc_transmit_internal`,
 continuous-absorption mode: the exit law of a walk whose flights are drawn from
@@ -21,6 +23,8 @@ Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_
            --out paper_2512_13965_amd/weights/gmc_h512_internal.bin
        python -m paper_2512_13965_amd.train --model rect --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_rect.bin
+       python -m paper_2512_13965_amd.train --model xy --hidden 512 \
+           --out paper_2512_13965_amd/weights/gmc_h512_xy.bin
 """
 from __future__ import annotations
 
@@ -46,6 +50,11 @@ def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
         ex = binding.mc_transmit_internal(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
         feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.x - 1.0, 2.0 * dc.y - 1.0,
                              dc.cos_phi, dc.sin_phi], dim=1)
+    elif kind == "xy":
+        cond = inputs.xy_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
+        dc = binding.DeviceCond.from_host(cond, device)
+        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
+        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th, dc.omega_x], dim=1)
     else:
         la = LOG_ASPECT_TRAIN if kind == "rect" else None
         cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
@@ -81,12 +90,12 @@ class VelocityMLP(torch.nn.Module):
                 h = torch.nn.functional.silu(h)
         return h
 
-    def to_weights(self, seed: int, act_scale) -> inputs.Weights:
+    def to_weights(self, seed: int, act_scale, flags: int = 0) -> inputs.Weights:
         W = [l.weight.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
         b = [l.bias.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
         w_scale = np.array([inputs.pow2_ceil_scale(float(np.abs(x).max())) for x in W], np.float32)
         return inputs.Weights(W[0].shape[0], W, b, np.asarray(act_scale, np.float32), w_scale, seed,
-                              n_in=W[0].shape[1])
+                              n_in=W[0].shape[1], flags=flags)
 
 
 @torch.no_grad()
@@ -136,7 +145,7 @@ def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=
             print(f"step {it}/{steps} loss {run / (log_every / 50):.4f} ({time.time() - t0:.0f}s)", flush=True)
             run = 0.0
     scales = activation_scales(model, feats, tgt)
-    return model.to_weights(seed & 0xFFFFFFFF, scales)
+    return model.to_weights(seed & 0xFFFFFFFF, scales, flags=1 if kind == "xy" else 0)
 
 
 def main():
@@ -146,7 +155,7 @@ def main():
     ap.add_argument("--data", type=int, default=4_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--model", choices=("boundary", "rect", "internal"), default="boundary")
+    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal"), default="boundary")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)

@@ -78,3 +78,62 @@ def test_xy_world_geometry_checks():
         w.step(binding.SAMPLER_GMC, m, 4)                        # flatland model, XY world
     w.close()
     m.close()
+
+
+@pytest.mark.parametrize("prec,H,K", [("fp32", 256, 16), ("bf16", 512, 16)])
+def test_xy_sampler_matches_oracle(orc, prec, H, K):
+    # an XY-geometry boundary model (11 inputs, flag bit 0): condition (ln tau, c, 2 y - 1,
+    # omega_y, omega_x); exits decoded into the unit disk
+    import torch
+    binding = require_gpu()
+    n = 20_011
+    cond = inputs.xy_conditions(n, seed=73)
+    w = inputs.random_weights(H, 6, n_in=inputs.N_IN_RECT, flags=1)
+    m = binding.Model(inputs.pack_blob(w), prec)
+    raw = torch.empty(5 * n, dtype=torch.float32, device="cuda")
+    out = binding.gmc_sample(m, binding.DeviceCond.from_host(cond), "euler", K, 2, 0, raw=raw).to_host()
+    torch.cuda.synchronize()
+    m.close()
+    raw = raw.view(5, n).cpu().numpy().astype(np.float64)
+    from tests.gpu_util import sample_indices
+    idx = sample_indices(n, 200, seed=5)
+    z = np.stack([orc.noise(2, int(i), 1)[:, 0] for i in idx], axis=1)
+    ref = orc.sample_raw(w, cond.subset(idx), K, z, orc.PREC_FP64 if prec == "fp32" else orc.PREC_BF16)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    print(f"XY {prec}: p99 {np.quantile(err, .99):.2e} max {err.max():.2e}")
+    tol = (1e-5, 1e-5) if prec == "fp32" else (1e-5, 5e-5)
+    assert np.quantile(err, 0.99) < tol[0] and err.max() < tol[1]
+    # the kernel's decoder against the oracle's XY decoder on the kernel's own raw output
+    d = orc.decode(raw.T, xy=True)
+    np.testing.assert_array_equal(out["face"], d["face"])
+    np.testing.assert_allclose(out["dir_cos"], d["u"], atol=2e-6)
+    np.testing.assert_allclose(out["dir_sin"], d["v"], atol=2e-6)
+    assert np.all(out["dir_cos"] ** 2 + out["dir_sin"] ** 2 <= 1.0 + 1e-5)
+
+
+def test_xy_model_checks():
+    binding = require_gpu()
+    with pytest.raises(binding.GmcError):
+        binding.Model(inputs.pack_blob(inputs.random_weights(128, 1, flags=1)), "fp32")   # XY needs 11 inputs
+    mxy = binding.Model(inputs.pack_blob(inputs.random_weights(128, 1, n_in=11, flags=1)), "fp32")
+    flat = binding.DeviceCond.from_host(inputs.transmission_conditions(64, 1))
+    with pytest.raises(binding.GmcError):
+        binding.gmc_sample(mxy, flat, "euler", 4, 0)                 # XY model needs omega_x
+    w = binding.World(1 << 12, 1, 1 << 10)
+    w.add_problem(inputs.checkerboard_problem(4, src=2), 1)
+    with pytest.raises(binding.GmcError):
+        w.step(binding.SAMPLER_GMC, mxy, 4)                          # XY model, flatland world
+    w.close()
+    mxy.close()
+
+
+def test_xy_gmc_transport_balances():
+    binding = require_gpu()
+    from paper_2512_13965_amd import transport
+    m = binding.Model(inputs.pack_blob(inputs.random_weights(256, 3, n_in=11, flags=1)), "bf16")
+    w = binding.World(1 << 16, 1, 1 << 12)
+    for face in (-1, 3):
+        r = transport.run_problem(w, _xy_problem(0.0, face, 81), 10_000, 5, binding.SAMPLER_GMC, m, 8)
+        assert abs(r["absorbed"].sum() + r["leak"].sum() + r["cutoff"].sum() - 10_000) < 1e-6
+    w.close()
+    m.close()

@@ -82,3 +82,26 @@ def test_pure_absorber_escape_by_quadrature(orc):
     se = math.sqrt(p_q * (1 - p_q) / n)
     print(f"escape {p_mc:.5f} vs {p_q:.5f}")
     assert abs(p_mc - p_q) < 4.5 * se
+
+
+def test_xy_decoding_keeps_projected_directions_inside_the_disk(orc):
+    # a4 = -0.5 reaches only the threshold -1: face 1 (right side, outward normal +x)
+    raw = np.array([[0.0, 0.3, 0.4, 0.0, -0.5],     # norm 0.5, outward: kept as is
+                    [0.0, 1.2, 1.6, 0.0, -0.5],     # norm 2: scaled to norm 1
+                    [0.0, -0.3, 0.4, 0.0, -0.5]])   # points inward: x component reflected
+    d = orc.decode(raw, xy=True)
+    np.testing.assert_array_equal(d["face"], [1, 1, 1])
+    np.testing.assert_allclose(np.stack([d["u"], d["v"]], 1), [[0.3, 0.4], [0.6, 0.8], [0.3, 0.4]], atol=1e-15)
+    flat = orc.decode(raw)
+    np.testing.assert_allclose(np.hypot(flat["u"], flat["v"]), 1.0, atol=1e-15)
+
+
+def test_xy_condition_features_and_blob_flags(orc):
+    c = inputs.xy_conditions(5, seed=6)
+    f = orc.condition_features(c)
+    assert f.shape == (5, 5)
+    np.testing.assert_allclose(f[:, 3], c.sin_th)
+    np.testing.assert_allclose(f[:, 4], c.omega_x)
+    w = inputs.random_weights(16, 1, n_in=inputs.N_IN_RECT, flags=1)
+    back = inputs.unpack_blob(inputs.pack_blob(w))
+    assert back.flags == 1 and back.n_in == inputs.N_IN_RECT
