@@ -187,7 +187,7 @@ def bench_transport(binding, inputs, w512, w512_internal=None):
     return out
 
 
-def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512_rect=None):
+def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512_rect=None, w512_xy=None):
     """The paper's two benchmark problems at its mesh size and cross sections ("Benchmark
     Performance"; layouts defined by inputs.lattice_problem / inputs.hohlraum_problem): the
     7 x 7 cm lattice (112^2 cells, central volumetric source) and the 1.3 x 1.3 cm hohlraum
@@ -196,23 +196,32 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     births from the internal model.  flux_rel_l1_vs_mc is the L1 distance of the flux maps to
     the analog run; mc_noise_rel_l1 is the same distance between two analog runs with
     different seeds (the statistical floor at this history count).  With the rectangular-cell
-    model, also the lattice on 112 x 56 cells of 1/16 x 1/8 cm."""
+    model, also the lattice on 112 x 56 cells of 1/16 x 1/8 cm; with the XY-geometry model, the
+    lattice in XY geometry (one world per geometry)."""
     import torch
     from paper_2512_13965_amd import transport
     out = {"histories": n}
     model = binding.Model(inputs.pack_blob(w512), "bf16")
     src = None if w512_internal is None else binding.Model(inputs.pack_blob(w512_internal), "bf16")
     rect = None if w512_rect is None else binding.Model(inputs.pack_blob(w512_rect), "bf16")
+    xym = None if w512_xy is None else binding.Model(inputs.pack_blob(w512_xy), "bf16")
     world = binding.World(1 << 20, 2, 1 << 14)
     problems = [("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))]
     if rect is not None:
         problems.append(("lattice_112x56_rect", inputs.lattice_problem(16, 8)))
+    if xym is not None:
+        lx = inputs.lattice_problem(16)
+        lx.xy = True
+        problems.append(("lattice_112_xy", lx))
     for pname, prob in problems:
-        bm = rect if prob.Ly > 0 else model
+        if prob.xy:
+            world.close()
+            world = binding.World(1 << 20, 2, 1 << 14)
+        bm = xym if prob.xy else (rect if prob.Ly > 0 else model)
         runs = [("analog", binding.SAMPLER_MC, None, 16, "euler", None),
                 ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, bm, 16, "euler", None),
                 ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, bm, 12, "rk4", None)]
-        if src is not None and prob.src_face < 0 and prob.Ly == 0:
+        if src is not None and prob.src_face < 0 and prob.Ly == 0 and not prob.xy:
             runs.append(("gmc_bf16_h512_rk4x12_internal_births", binding.SAMPLER_GMC, model, 12, "rk4", src))
         res, flux = {}, {}
         for name, smp, m, K, integ, sm in runs:
@@ -237,7 +246,7 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
         out[pname] = res
     world.close()
     model.close()
-    for mm in (src, rect):
+    for mm in (src, rect, xym):
         if mm is not None:
             mm.close()
     return out
@@ -439,6 +448,8 @@ def main():
     w5i = inputs.load_blob(ipath) if os.path.exists(ipath) else None
     rpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512_rect.bin")
     w5r = inputs.load_blob(rpath) if os.path.exists(rpath) else None
+    xpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512_xy.bin")
+    w5x = inputs.load_blob(xpath) if os.path.exists(xpath) else None
     condB = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
     outB = binding.DeviceExit.empty(NB, dev)
     wide = []
@@ -480,7 +491,7 @@ def main():
 
     if not args.no_transport:
         res["transport"] = bench_transport(binding, inputs, w5t, w5i)
-        res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i, w512_rect=w5r)
+        res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i, w512_rect=w5r, w512_xy=w5x)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests)
 
     if not args.no_cpu:
