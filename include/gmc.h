@@ -2,7 +2,7 @@
  * gmc.h -- C ABI of the MI355X (gfx950) Generative Monte Carlo cell-transmission library.
  *
  * Method: Farmer, Murray, Krotz, McClarren, "Generative Monte Carlo Sampling for
- * Constant-Cost Particle Transport", arXiv 2512.13965.  A particle entering a square cell is
+ * Constant-Cost Particle Transport", arXiv 2512.13965.  A particle entering a cell is
  * "teleported" to its exit state by integrating a conditional flow-matching velocity field
  * from Gaussian noise (section "Conditional Flow Matching", eq. 8) instead of following its
  * random walk (section "Monte Carlo Method", eq. 4).  Both samplers live behind this ABI.
@@ -15,11 +15,14 @@
  *   - Return value: GMC_OK (0) or a negative gmc_status; no exceptions cross the ABI and the
  *     library never aborts.  gmc_last_error() gives a thread-local message for the last
  *     failure on the calling thread.
- *   - Lengths are in units of the cell side L and directions are in the canonical frame in
- *     which the particle enters through the left face x = 0 of the unit square (section
- *     "Transport Algorithm", first stage).  Faces: 0 bottom (y=0), 1 right (x=1), 2 top (y=1),
- *     3 left (x=0).  The position along an exit face runs counter-clockwise: bottom x,
- *     right y, top 1-x, left 1-y.
+ *   - Lengths are in units of the entry face (the cell side L for square cells) and
+ *     directions are in the canonical frame in which the particle enters through the left
+ *     face x = 0 of the cell [0, A] x [0, 1] (A = 1: the unit square; section "Transport
+ *     Algorithm", first stage).  Faces: 0 bottom (y=0), 1 right (x=A), 2 top (y=1), 3 left
+ *     (x=0).  The position along an exit face runs counter-clockwise, as a fraction of that
+ *     face's length: bottom x/A, right y, top (A-x)/A, left 1-y.  Directions are unit in-plane
+ *     vectors (flatland, the default) or projections of unit vectors on the sphere (XY
+ *     geometry, see gmc_cond.omega_x).
  *   - Results are a pure function of (weights, condition, seed, particle id, K): they do not
  *     depend on the batch size or on a particle's position in the batch.
  */
