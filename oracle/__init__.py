@@ -61,6 +61,8 @@ def lib():
         L.orc_mc_transmit_internal.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_int,
                                                ctypes.c_uint64, ctypes.c_uint64, P, P, P, P, P, P,
                                                ctypes.c_int]
+        L.orc_uncollided_split.argtypes = [P, P, P, P, P, P, ctypes.c_int64, ctypes.c_uint64,
+                                           ctypes.c_uint64, P, P, P, P, P, P]
         L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -120,6 +122,22 @@ def mc_transmit(cond, mode: int, seed: int, id_base: int = 0, nthreads: int = 1)
                           None if ox is None else _p(ox), n, mode, seed, id_base,
                           _p(out["face"]), _p(out["pos"]), _p(out["u"]), _p(out["v"]),
                           _p(out["len"]), _p(out["ncoll"]), nthreads)
+    return out
+
+
+def uncollided_split(cond, seed: int, id_base: int = 0) -> dict:
+    """First-flight split (an analytic variant beside the paper's single model): flag = 1 where
+    the particle crosses without a collision (probability exp(-c tau d_b) against Philox word 0
+    of counter (id, 0, 4)); face, pos, u, v, len of the entry ray's exit for every particle."""
+    n = len(cond)
+    f32 = lambda a: None if a is None else np.ascontiguousarray(a, np.float32)
+    arrs = [f32(cond.log_tau), f32(cond.c), f32(cond.y_in), f32(cond.sin_th),
+            f32(getattr(cond, "log_aspect", None)), f32(getattr(cond, "omega_x", None))]
+    out = dict(flag=np.zeros(n, np.int32), face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n),
+               v=np.zeros(n), len=np.zeros(n))
+    lib().orc_uncollided_split(*[None if a is None else _p(a) for a in arrs], n, seed, id_base,
+                               _p(out["flag"]), _p(out["face"]), _p(out["pos"]), _p(out["u"]),
+                               _p(out["v"]), _p(out["len"]))
     return out
 
 

@@ -32,6 +32,7 @@
 #define ORC_TAG_NOISE 1u
 #define ORC_TAG_WALK 2u
 #define ORC_TAG_SOURCE 3u
+#define ORC_TAG_SPLIT 4u
 #define ORC_MAX_FLIGHTS 16777216u /* 2^24: a walk still inside after this many flights is "capped" */
 
 #define ORC_FACE_ABSORBED (-1)
@@ -253,6 +254,32 @@ void orc_mc_transmit(const float *log_tau, const float *c, const float *y_in, co
 {
     run_walks(log_tau, c, y_in, sin_th, NULL, NULL, log_aspect, omega_x, n, mode, seed, id_base, face,
               pos, u, v, len, ncoll, nthreads);
+}
+
+/* First-flight split of a batch of canonical transmissions: particle i crosses its cell without
+ * a collision with probability exp(-c tau d_b), d_b the length of its entry ray to the boundary
+ * (flights ~ Exp(c tau), eq. 4); the decision compares it with xi = u01(word 0) of
+ * Philox(seed, (id lo, id hi, 0, 4)), id = id_base + i.  flag[i] = 1 for an uncollided crossing,
+ * whose exit is the ray's end (the straight walk through a cell without scattering). */
+void orc_uncollided_split(const float *log_tau, const float *c, const float *y_in, const float *sin_th,
+                          const float *log_aspect, const float *omega_x, int64_t n, uint64_t seed,
+                          uint64_t id_base, int32_t *flag, int32_t *face, double *pos, double *u,
+                          double *v, double *len)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double s = (double)sin_th[i];
+        double u0 = omega_x ? (double)omega_x[i] : sqrt(1.0 - s * s);
+        double a = log_aspect ? exp((double)log_aspect[i]) : 1.0;
+        double tau = exp((double)log_tau[i]);
+        orc_exit e;
+        /* no scattering: one flight to the boundary */
+        orc_walk(0.0, 0.0, 0, omega_x != NULL, a, 0.0, (double)y_in[i], u0, s, seed, id_base + (uint64_t)i, &e);
+        double pu = exp(-(double)c[i] * tau * e.len);
+        uint32_t r[4];
+        draw4(seed, id_base + (uint64_t)i, 0u, ORC_TAG_SPLIT, r);
+        flag[i] = orc_u01(r[0]) <= pu;
+        face[i] = e.face; pos[i] = e.pos; u[i] = e.u; v[i] = e.v; len[i] = e.len;
+    }
 }
 
 /* Batch of walks started inside the cell: particle i is born at (x[i], y[i]) with direction
