@@ -112,6 +112,9 @@ typedef struct gmc_model gmc_model;
  * 10->H, H->H (x3), H->5.  Network input order: [x0..x4, t, ln tau, c, 2*y_in-1, sin_th];
  * SiLU after layers 1..4 (paper section "Network Architecture and Inputs", eqs. 10-11).
  * Supported: H in {128, 256} for GMC_FP32, H in {128, 256, 512} for GMC_BF16 / GMC_FP8_E4M3.
+ * flags: bit 0 XY geometry (n_in = 11, condition ln tau, c, 2 y_in - 1, omega_y, omega_x);
+ * bit 1 a boundary model fitted on collided crossings only (the transport step then places
+ * uncollided crossings itself, see gmc_uncollided_split); other bits GMC_EINVAL.
  * The scales must be positive powers of two.  The blob is host memory owned by the caller.
  * On success *out owns device memory until gmc_model_destroy(). */
 int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_model **out);
@@ -162,6 +165,18 @@ int gmc_sample(const gmc_model *m, gmc_cond cond, int64_t n, int integrator, int
 int gmc_sample_internal(const gmc_model *m, gmc_cond_internal cond, int64_t n, int integrator, int K,
                         uint64_t seed, uint64_t id_base, const float *noise_opt, float *raw_opt,
                         gmc_exit out, void *stream);
+
+/* First-flight split of n canonical transmissions (an analytic variant beside the paper's single
+ * model; used by the transport step with a collided-only model, blob flag bit 1): the entry ray
+ * meets the cell boundary after d_b, and with flights ~ Exp(c tau) (eq. 4) the particle crosses
+ * without a collision with probability exp(-c tau d_b).  Particle i compares it with
+ * xi = ((w >> 8) + 1) 2^-24, w = word 0 of Philox4x32-10 with key = seed and counter
+ * (id lo, id hi, 0, 4), id = id_base + i.  uncollided[i] (device int32 [n]) = 1 for an
+ * uncollided crossing, whose exit record is written (face and position at the ray's end, the
+ * entry direction, path d_b); 0 otherwise, the record then left as it was.  Flatland, XY
+ * geometry and rectangular cells as for mc_transmit.  Errors: GMC_EINVAL, GMC_EDEVICE. */
+int gmc_uncollided_split(gmc_cond cond, int64_t n, uint64_t seed, uint64_t id_base, int32_t *uncollided,
+                         gmc_exit out, void *stream);
 
 /* Samples n cell transmissions with the analog random walk that the generative sampler
  * replaces (paper "Monte Carlo Method", eq. 4) through the canonical cell [0, A] x [0, 1]
@@ -266,6 +281,9 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
  * transmission each with the generative sampler (sampler = GMC_SAMPLER_GMC, model m, K steps
  * of the world's integrator) or the analog walk with continuous absorption (GMC_SAMPLER_MC, m unused), FP64
  * attenuation and tallies (stage 3), move / leak / cutoff and compaction (stage 4).
+ * With a model fitted on collided crossings (blob flag bit 1) stage 1 first draws each
+ * particle's first-flight split (gmc_uncollided_split's test and exit); only the collided
+ * particles, compacted, go through the sampler, whose exits are scattered back.
  * Synchronises `stream`; *n_alive_out (optional) = particles still in flight.  GMC_EINVAL for
  * an unknown sampler, or for GMC without a boundary model (n_in = 10) or with K outside 1..1024. */
 int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,

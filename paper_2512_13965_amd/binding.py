@@ -67,9 +67,10 @@ def lib() -> ctypes.CDLL:
         L.gmc_model_inputs.argtypes = [P, ctypes.POINTER(I)]
         L.gmc_sample_internal.argtypes = [P, _CondInternal, I64, I, I, U64, U64, P, P, _Exit, P]
         L.mc_transmit_internal.argtypes = [_CondInternal, I64, I, U64, U64, _Exit, P, P]
+        L.gmc_uncollided_split.argtypes = [_Cond, I64, U64, U64, P, _Exit, P]
         for name in ("gmc_model_create", "gmc_model_destroy", "gmc_model_info", "gmc_transmit",
                      "mc_transmit", "gmc_decode", "gmc_sample", "gmc_model_inputs",
-                     "gmc_sample_internal", "mc_transmit_internal"):
+                     "gmc_sample_internal", "mc_transmit_internal", "gmc_uncollided_split"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -296,6 +297,21 @@ def mc_transmit(cond: DeviceCond, mode: int, seed: int, id_base: int = 0,
     _check(lib().mc_transmit(cond.c_struct(), n, int(mode), seed, id_base, out.c_struct(n),
                              _ptr(ncoll), _stream(stream)))
     return out
+
+
+def uncollided_split(cond: DeviceCond, seed: int, id_base: int = 0, flag: torch.Tensor | None = None,
+                     out: DeviceExit | None = None, n: int | None = None, stream=None):
+    """gmc_uncollided_split: flag[i] = 1 where particle i crosses its cell without a collision,
+    with its exit written to out[i].  Returns (flag, out)."""
+    n = len(cond) if n is None else n
+    if out is None:
+        out = DeviceExit.empty(n, cond.log_tau.device)
+    if flag is None:
+        flag = torch.zeros(n, dtype=torch.int32, device=cond.log_tau.device)
+    _need(flag, torch.int32, n, "flag")
+    _check(lib().gmc_uncollided_split(cond.c_struct(), n, seed, id_base, _ptr(flag), out.c_struct(n),
+                                      _stream(stream)))
+    return flag, out
 
 
 def gmc_decode(raw: torch.Tensor, n: int, out: DeviceExit | None = None,

@@ -146,6 +146,9 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         return fail(GMC_EINVAL, "gmc_model_create: bad magic or version");
     if (hd.n_in < 10 || hd.n_in > 12 || hd.n_out != 5 || hd.n_layers != 5)
         return fail(GMC_EINVAL, "gmc_model_create: network must be 10, 11 or 12 -> H x4 -> 5");
+    if (hd.flags & ~3u) return fail(GMC_EINVAL, "gmc_model_create: unknown flags");
+    if ((hd.flags & 2u) && hd.n_in == 12)
+        return fail(GMC_EINVAL, "gmc_model_create: only boundary models can be fitted on collided exits");
     if ((hd.flags & 1u) && hd.n_in != 11)
         return fail(GMC_EINVAL, "gmc_model_create: an XY-geometry model has 11 inputs");
     const int H = (int)hd.hidden;
@@ -181,6 +184,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     m->precision = precision;
     m->n_in = NI;
     m->xy = (hd.flags & 1u) != 0;
+    m->collided = (hd.flags & 2u) != 0;
     m->tmpl.xy = m->xy ? 1 : 0;
     m->tmpl.n_cond = NI - 6;
     m->hidden = H;
@@ -435,6 +439,34 @@ int mc_transmit_internal(gmc_cond_internal cond, int64_t n, int mode, uint64_t s
     p.cos_phi = cond.cos_phi;
     p.sin_th = cond.sin_phi;
     return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit_internal");
+}
+
+int gmc_uncollided_split(gmc_cond cond, int64_t n, uint64_t seed, uint64_t id_base, int32_t *uncollided,
+                         gmc_exit out, void *stream)
+{
+    if (n < 0) return fail(GMC_EINVAL, "gmc_uncollided_split: negative n");
+    if (n == 0) return GMC_OK;
+    if (!cond_ok(cond) || !uncollided || !exit_ok(out))
+        return fail(GMC_EINVAL, "gmc_uncollided_split: null pointer");
+    if (n > (int64_t)0x7FFFFFFF * 256) return fail(GMC_EINVAL, "gmc_uncollided_split: n too large");
+    gmc::WalkParams p{};
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.y_in = cond.y_in;
+    p.sin_th = cond.sin_th;
+    p.log_aspect = cond.log_aspect;
+    p.omega_x = cond.omega_x;
+    p.face = out.face;
+    p.pos = out.pos;
+    p.dcos = out.dir_cos;
+    p.dsin = out.dir_sin;
+    p.path = out.path;
+    p.n = n;
+    p.seed = seed;
+    p.id_base = id_base;
+    hipError_t e = gmc::launch_split(p, uncollided, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "gmc_uncollided_split: launch");
+    return GMC_OK;
 }
 
 int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, void *stream)

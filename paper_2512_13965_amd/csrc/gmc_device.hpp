@@ -10,6 +10,7 @@ namespace gmc {
 constexpr uint32_t kTagNoise = 1u;
 constexpr uint32_t kTagWalk = 2u;
 constexpr uint32_t kTagSource = 3u;
+constexpr uint32_t kTagSplit = 4u;
 constexpr uint32_t kMaxFlights = 1u << 24;
 
 struct U4 {
@@ -227,6 +228,39 @@ __device__ __forceinline__ int decode_exit(float a0, float a1, float a2, float a
     e.v = v;
     e.path = expf(a3);
     return flags;
+}
+
+// First-flight split of a canonical transmission: the entry ray from (0, y) along (u, v) meets
+// the boundary of [0, wa] x [0, 1] after d_b; with flights ~ Exp(c tau) (eq. 4, continuous
+// absorption) the particle crosses without a collision with probability exp(-c tau d_b).  The
+// decision compares that probability with xi = u01(word 0) of Philox(key, (id lo, id hi, 0,
+// split tag)); an uncollided particle leaves at the ray's end with its entry direction and path
+// d_b (written to e).  Returns true for an uncollided crossing.
+__device__ __forceinline__ bool uncollided_exit(float tau, float c, float y, float u, float v, float wa,
+                                                uint64_t key, uint64_t id, Exit &e)
+{
+    const float kInf = __builtin_inff();
+    const float tx = u > 0.0f ? wa / u : kInf;
+    float ty = kInf;
+    if (v > 0.0f) ty = (1.0f - y) / v;
+    else if (v < 0.0f) ty = -y / v;
+    const bool xface = tx <= ty;
+    const float db = xface ? tx : ty;
+    const float pu = expf(-c * tau * db);
+    const U4 r = draw4(key, id, 0u, kTagSplit);
+    if (!(u01(r.a) <= pu)) return false;
+    e.u = u;
+    e.v = v;
+    e.path = db;
+    if (xface) {
+        e.face = 1;
+        e.pos = fminf(fmaxf(y + db * v, 0.0f), 1.0f);
+    } else {
+        const float xe = fminf(fmaxf(db * u, 0.0f), wa);
+        e.face = v > 0.0f ? 2 : 0;
+        e.pos = v > 0.0f ? (wa - xe) / wa : xe / wa;
+    }
+    return true;
 }
 
 }  // namespace gmc

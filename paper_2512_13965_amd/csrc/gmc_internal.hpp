@@ -111,6 +111,7 @@ inline int walk_grid(int64_t n, int cu)
     const int64_t want = (n + 255) / 256, cap = (int64_t)cu * GMC_WALK_BLOCKS_PER_CU;
     return (int)(want < cap ? want : cap);
 }
+hipError_t launch_split(const WalkParams &p, int32_t *flag, hipStream_t s);
 hipError_t launch_decode(const float *raw, int64_t n, int32_t *face, float *pos, float *dcos,
                          float *dsin, float *path, int32_t *flags, hipStream_t s);
 
@@ -129,6 +130,7 @@ struct gmc_model {
     int hidden = 0;
     int n_in = 10;           // 10: boundary model, 11: rectangular-cell or XY boundary model, 12: internal
     bool xy = false;         // XY geometry (blob flags bit 0): condition carries omega_x
+    bool collided = false;   // fitted on collided exits (blob flags bit 1): transport splits first flights
     int device = 0;
     void *dev_mem = nullptr;
     gmc::MlpParams tmpl{};   // weight / bias pointers and scales

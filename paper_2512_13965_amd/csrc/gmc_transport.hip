@@ -384,6 +384,90 @@ __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
     keys[i] = cd.prob[b.pid[i]].seed;
 }
 
+// Stage 1 with the first-flight split (models fitted on collided exits, blob flag bit 1):
+// canonical conditions as gather_kernel; a particle that crosses its cell without a collision
+// (uncollided_exit) gets its exit record written at its own index, the others are compacted
+// (one atomic per wave) into the sampler's staging with their bank index in sidx.
+__global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_arg,
+                                                           const unsigned long long *n_dev, CellsDev cd,
+                                                           float *ltau, float *cc, float *yin, float *sth,
+                                                           float *laspect, float *omx, uint64_t *ids,
+                                                           uint64_t *keys, int32_t *sidx,
+                                                           unsigned long long *count, int32_t *e_face,
+                                                           float *e_pos, float *e_dcos, float *e_dsin,
+                                                           float *e_path)
+{
+    const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    bool collided = false;
+    float lt = 0.f, c = 0.f, y = 0.f, s = 0.f, la = 0.f, ox = 0.f;
+    uint64_t id = 0, key = 0;
+    if (i < n) {
+        const int cell = b.cell[i];
+        const int e = b.entry[i];
+        const int k = (e + 1) & 3;
+        float U, V;
+        rot_quarter((4 - k) & 3, b.gx[i], b.gy[i], U, V);
+        const ProblemDev P = cd.prob[b.pid[i]];
+        lt = (e & 1) ? cd.ltau[cell] + P.lr : cd.ltau[cell];
+        la = (e & 1) ? -P.lr : P.lr;
+        c = cd.cf[cell];
+        y = b.yin[i];
+        s = fminf(fmaxf(V, -1.0f), 1.0f);
+        ox = U;
+        id = (uint64_t)b.hist[i] | ((uint64_t)b.event[i] << 32);
+        key = P.seed;
+        const float u = P.xy ? U : sqrtf(fmaxf(1.0f - s * s, 0.0f));
+        Exit ex;
+        if (uncollided_exit(expf(lt), c, y, u, s, la == 0.0f ? 1.0f : expf(la), key, id, ex)) {
+            e_face[i] = ex.face;
+            e_pos[i] = ex.pos;
+            e_dcos[i] = ex.u;
+            e_dsin[i] = ex.v;
+            e_path[i] = ex.path;
+        } else {
+            collided = true;
+        }
+    }
+    const uint64_t mask = __ballot(collided);
+    if (!mask) return;
+    const int leader = __ffsll((unsigned long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane == leader) base = atomicAdd(count, (unsigned long long)__popcll(mask));
+    base = (unsigned long long)__shfl((long long)base, leader);
+    if (collided) {
+        const int64_t j = (int64_t)(base + (unsigned long long)lane_rank(mask));
+        ltau[j] = lt;
+        cc[j] = c;
+        yin[j] = y;
+        sth[j] = s;
+        laspect[j] = la;
+        omx[j] = ox;
+        ids[j] = id;
+        keys[j] = key;
+        sidx[j] = (int32_t)i;
+    }
+}
+
+// The sampler's exits of the compacted collided particles back to their bank indices.
+__global__ __launch_bounds__(256) void scatter_kernel(int64_t n_arg, const unsigned long long *count,
+                                                      const int32_t *sidx, const int32_t *f2, const float *p2,
+                                                      const float *c2, const float *s2, const float *l2,
+                                                      int32_t *face, float *pos, float *dcos, float *dsin,
+                                                      float *path)
+{
+    const int64_t n = (int64_t)*count;
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n || j >= n_arg) return;
+    const int32_t i = sidx[j];
+    face[i] = f2[j];
+    pos[i] = p2[j];
+    dcos[i] = c2[j];
+    dsin[i] = s2[j];
+    path[i] = l2[j];
+}
+
 // Stages 3-4 for every alive particle, survivors compacted into `out`.
 __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
                                                     const unsigned long long *n_dev, const int32_t *face_c,
@@ -457,6 +541,10 @@ struct gmc_world {
     float *c_x = nullptr, *c_cos = nullptr;      // internal-model births
     float *c_la = nullptr;                       // canonical ln aspect (rectangular cells)
     float *c_ox = nullptr;                       // canonical in-plane x direction (XY geometry)
+    // first-flight split: bank index of each compacted collided particle, their exits, count
+    int32_t *s_idx = nullptr, *s_face = nullptr;
+    float *s_pos = nullptr, *s_dcos = nullptr, *s_dsin = nullptr, *s_path = nullptr;
+    unsigned long long *s_count = nullptr;
     uint64_t *ids = nullptr, *keys = nullptr;
     int32_t *e_face = nullptr;
     float *e_pos = nullptr, *e_dcos = nullptr, *e_dsin = nullptr, *e_path = nullptr;
@@ -527,6 +615,13 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->c_x, 4 * C);
     L.add((void **)&w->c_la, 4 * C);
     L.add((void **)&w->c_ox, 4 * C);
+    L.add((void **)&w->s_idx, 4 * C);
+    L.add((void **)&w->s_face, 4 * C);
+    L.add((void **)&w->s_pos, 4 * C);
+    L.add((void **)&w->s_dcos, 4 * C);
+    L.add((void **)&w->s_dsin, 4 * C);
+    L.add((void **)&w->s_path, 4 * C);
+    L.add((void **)&w->s_count, 8);
     L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);
     L.add((void **)&w->keys, 8 * C);
@@ -862,9 +957,18 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
                  const unsigned long long *n_dev)
 {
     const int cur = w->cur, nxt = 1 - cur;
-    hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
-                       n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la, w->c_ox, w->ids,
-                       w->keys);
+    const bool split = sampler == GMC_SAMPLER_GMC && m->collided;
+    if (split) {
+        hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(1), 0, s, w->s_count, 0ull, 1);
+        hipLaunchKernelGGL(gather_split_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur],
+                           n_launch, n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la,
+                           w->c_ox, w->ids, w->keys, w->s_idx, w->s_count, w->e_face, w->e_pos, w->e_dcos,
+                           w->e_dsin, w->e_path);
+    } else {
+        hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
+                           n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la, w->c_ox, w->ids,
+                           w->keys);
+    }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return set_hip_error(e, "gmc_transport_step: gather");
     const int cu = device_cu_count();
@@ -881,19 +985,25 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.raw = nullptr;
         p.ids = w->ids;
         p.keys = w->keys;
-        p.face = w->e_face;
-        p.pos = w->e_pos;
-        p.dcos = w->e_dcos;
-        p.dsin = w->e_dsin;
-        p.path = w->e_path;
+        p.face = split ? w->s_face : w->e_face;
+        p.pos = split ? w->s_pos : w->e_pos;
+        p.dcos = split ? w->s_dcos : w->e_dcos;
+        p.dsin = split ? w->s_dsin : w->e_dsin;
+        p.path = split ? w->s_path : w->e_path;
         p.n = n_launch;
-        p.n_dev = n_dev;
+        p.n_dev = split ? w->s_count : n_dev;
         p.K = K;
         p.integrator = w->integrator;
         p.seed = 0;
         p.id_base = 0;
         const int64_t ntiles = (n_launch + kTileM - 1) / kTileM;
         e = launch_mlp_ode(m->precision, m->hidden, p, (int)std::min<int64_t>(ntiles, cu), s);
+        if (e == hipSuccess && split) {
+            hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, n_launch, w->s_count,
+                               w->s_idx, w->s_face, w->s_pos, w->s_dcos, w->s_dsin, w->s_path, w->e_face,
+                               w->e_pos, w->e_dcos, w->e_dsin, w->e_path);
+            e = hipGetLastError();
+        }
     } else {
         WalkParams p{};
         p.log_tau = w->c_ltau;

@@ -135,6 +135,37 @@ hipError_t launch_walk(const WalkParams &p, int grid, hipStream_t s)
     return hipGetLastError();
 }
 
+// First-flight split of n canonical transmissions (uncollided_exit): flag[i] = 1 and the exit
+// record written for an uncollided crossing, flag[i] = 0 and the record left untouched otherwise.
+__global__ __launch_bounds__(256) void split_kernel(WalkParams p, int32_t *flag)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= p.n) return;
+    const float s = p.sin_th[i];
+    const float la = p.log_aspect ? p.log_aspect[i] : 0.0f;
+    const float wa = la == 0.0f ? 1.0f : expf(la);
+    const float u = p.omega_x ? p.omega_x[i] : sqrtf(fmaxf(1.0f - s * s, 0.0f));
+    const uint64_t id = p.ids ? p.ids[i] : p.id_base + (uint64_t)i;
+    const uint64_t key = p.keys ? p.keys[i] : p.seed;
+    Exit e;
+    const bool unc = uncollided_exit(expf(p.log_tau[i]), p.c[i], p.y_in[i], u, s, wa, key, id, e);
+    flag[i] = unc ? 1 : 0;
+    if (unc) {
+        p.face[i] = e.face;
+        p.pos[i] = e.pos;
+        p.dcos[i] = e.u;
+        p.dsin[i] = e.v;
+        p.path[i] = e.path;
+    }
+}
+
+hipError_t launch_split(const WalkParams &p, int32_t *flag, hipStream_t s)
+{
+    const int64_t blocks = (p.n + 255) / 256;
+    hipLaunchKernelGGL(split_kernel, dim3((unsigned)blocks), dim3(256), 0, s, p, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_decode(const float *raw, int64_t n, int32_t *face, float *pos, float *dcos,
                          float *dsin, float *path, int32_t *flags, hipStream_t s)
 {

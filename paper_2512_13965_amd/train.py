@@ -6,7 +6,9 @@ of rectangular cells (the same plus ln A, A = width over entry-face length, ln A
 ln 4]), the boundary model in XY geometry (entry direction a projection of a direction on the
 sphere: its in-plane components omega_y, omega_x; exit directions inside the unit disk) and the
 internal model for particles born inside a cell (condition: ln tau, c, birth point, birth
-direction).
+direction).  A fifth, the collided boundary model (blob flag bit 1), is the boundary model fitted
+only on walks with at least one collision: the transport places the uncollided crossings exactly
+(first-flight split) and leaves the rest to it.
 
 Data come from this library's own analog walk (`mc_transmit` / `mc_transmit_internal`,
 continuous-absorption mode: the exit law of a walk whose flights are drawn from
@@ -25,6 +27,8 @@ Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_
            --out paper_2512_13965_amd/weights/gmc_h512_rect.bin
        python -m paper_2512_13965_amd.train --model xy --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_xy.bin
+       python -m paper_2512_13965_amd.train --model collided --hidden 512 \
+           --out paper_2512_13965_amd/weights/gmc_h512_collided.bin
 """
 from __future__ import annotations
 
@@ -55,6 +59,16 @@ def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
         dc = binding.DeviceCond.from_host(cond, device)
         ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
         feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th, dc.omega_x], dim=1)
+    elif kind == "collided":
+        # twice the walks, of which the first n with a collision are kept
+        cond = inputs.transmission_conditions(2 * n, seed, log_tau_range=LOG_TAU_TRAIN)
+        dc = binding.DeviceCond.from_host(cond, device)
+        nc = torch.empty(2 * n, dtype=torch.int32, device=device)
+        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919, ncoll=nc)
+        keep = torch.nonzero(nc > 0).squeeze(1)[:n]
+        ex = binding.DeviceExit(*(t[keep] for t in (ex.face, ex.pos, ex.dir_cos, ex.dir_sin, ex.path)))
+        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th], dim=1)[keep]
+        n = len(keep)
     else:
         la = LOG_ASPECT_TRAIN if kind == "rect" else None
         cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
@@ -123,6 +137,7 @@ def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=
     torch.manual_seed(seed)
     t0 = time.time()
     feats, tgt = make_dataset(n_data, seed, device, kind)
+    n_data = feats.shape[0]
     print(f"data: {n_data} {kind} exits in {time.time() - t0:.1f}s", flush=True)
     model = VelocityMLP(hidden, 5 + 1 + feats.shape[1]).to(device)
     opt = torch.optim.AdamW(model.parameters(), lr=lr, weight_decay=1e-4)
@@ -145,7 +160,8 @@ def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=
             print(f"step {it}/{steps} loss {run / (log_every / 50):.4f} ({time.time() - t0:.0f}s)", flush=True)
             run = 0.0
     scales = activation_scales(model, feats, tgt)
-    return model.to_weights(seed & 0xFFFFFFFF, scales, flags=1 if kind == "xy" else 0)
+    flags = {"xy": 1, "collided": 2}.get(kind, 0)
+    return model.to_weights(seed & 0xFFFFFFFF, scales, flags=flags)
 
 
 def main():
@@ -155,7 +171,7 @@ def main():
     ap.add_argument("--data", type=int, default=4_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal"), default="boundary")
+    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal", "collided"), default="boundary")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)

@@ -73,6 +73,13 @@ def test_model_create_rejects_bad_blobs(binding):
     # FP32 is built for H <= 256 only; H = 64 is built for no precision
     assert _create(binding, _blob(512), binding.FP32) == binding.GMC_EUNSUPPORTED
     assert _create(binding, _blob(64), binding.BF16) == binding.GMC_EUNSUPPORTED
+    # blob flags: bit 0 XY geometry (11 inputs), bit 1 fitted on collided exits (boundary models)
+    assert _create(binding, inputs.pack_blob(inputs.random_weights(256, 1, flags=4)),
+                   binding.FP32) == binding.GMC_EINVAL
+    assert _create(binding, inputs.pack_blob(inputs.random_weights(256, 1, flags=1)),
+                   binding.FP32) == binding.GMC_EINVAL
+    assert _create(binding, inputs.pack_blob(inputs.random_weights(256, 1, n_in=inputs.N_IN_INTERNAL,
+                                                                   flags=2)), binding.FP32) == binding.GMC_EINVAL
 
 
 def test_sampling_calls_reject_bad_arguments_without_a_device(binding):
@@ -85,4 +92,7 @@ def test_sampling_calls_reject_bad_arguments_without_a_device(binding):
     assert L.mc_transmit(cond, 0, 0, 0, 0, out, None, None) == binding.GMC_OK     # empty batch
     assert L.mc_transmit(cond, 10, 0, 0, 0, out, None, None) == binding.GMC_EINVAL
     assert L.gmc_decode(None, 10, out, None, None) == binding.GMC_EINVAL
+    assert L.gmc_uncollided_split(cond, 10, 0, 0, None, out, None) == binding.GMC_EINVAL
+    assert L.gmc_uncollided_split(cond, -1, 0, 0, None, out, None) == binding.GMC_EINVAL
+    assert L.gmc_uncollided_split(cond, 0, 0, 0, None, out, None) == binding.GMC_OK
     assert L.gmc_model_destroy(None) == binding.GMC_EINVAL
