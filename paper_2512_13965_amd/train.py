@@ -7,8 +7,8 @@ ln 4]), the boundary model in XY geometry (entry direction a projection of a dir
 sphere: its in-plane components omega_y, omega_x; exit directions inside the unit disk) and the
 internal model for particles born inside a cell (condition: ln tau, c, birth point, birth
 direction).  A fifth, the collided boundary model (blob flag bit 1), is the boundary model fitted
-only on walks with at least one collision: the transport places the uncollided crossings exactly
-(first-flight split) and leaves the rest to it.
+only on walks with at least one collision (and likewise the XY one, flags bits 0 and 1): the
+transport places the uncollided crossings exactly (first-flight split) and leaves the rest to it.
 
 Data come from this library's own analog walk (`mc_transmit` / `mc_transmit_internal`,
 continuous-absorption mode: the exit law of a walk whose flights are drawn from
@@ -29,6 +29,8 @@ Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_
            --out paper_2512_13965_amd/weights/gmc_h512_xy.bin
        python -m paper_2512_13965_amd.train --model collided --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_collided.bin
+       python -m paper_2512_13965_amd.train --model xy_collided --hidden 512 \
+           --out paper_2512_13965_amd/weights/gmc_h512_xy_collided.bin
 """
 from __future__ import annotations
 
@@ -46,38 +48,36 @@ LOG_ASPECT_TRAIN = (math.log(0.25), math.log(4.0))
 
 
 def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
-    """(conditions [n, 4] (boundary), [n, 5] (rect) or [n, 6] (internal), targets [n, 5]) on
-    `device`, from the GPU analog walk."""
+    """(conditions [n, 4] (boundary), [n, 5] (rect, xy) or [n, 6] (internal), targets [n, 5]) on
+    `device`, from the GPU analog walk.  For the collided models (kind "collided", boundary;
+    "xy_collided", XY geometry) twice the walks are run and the first n with a collision kept."""
     if kind == "internal":
         cond = inputs.internal_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
         dc = binding.DeviceCondInternal.from_host(cond, device)
         ex = binding.mc_transmit_internal(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
         feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.x - 1.0, 2.0 * dc.y - 1.0,
                              dc.cos_phi, dc.sin_phi], dim=1)
-    elif kind == "xy":
-        cond = inputs.xy_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
-        dc = binding.DeviceCond.from_host(cond, device)
-        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
-        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th, dc.omega_x], dim=1)
-    elif kind == "collided":
-        # twice the walks, of which the first n with a collision are kept
-        cond = inputs.transmission_conditions(2 * n, seed, log_tau_range=LOG_TAU_TRAIN)
-        dc = binding.DeviceCond.from_host(cond, device)
-        nc = torch.empty(2 * n, dtype=torch.int32, device=device)
-        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919, ncoll=nc)
-        keep = torch.nonzero(nc > 0).squeeze(1)[:n]
-        ex = binding.DeviceExit(*(t[keep] for t in (ex.face, ex.pos, ex.dir_cos, ex.dir_sin, ex.path)))
-        feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th], dim=1)[keep]
-        n = len(keep)
     else:
-        la = LOG_ASPECT_TRAIN if kind == "rect" else None
-        cond = inputs.transmission_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
+        collided = kind in ("collided", "xy_collided")
+        nw = 2 * n if collided else n
+        if kind in ("xy", "xy_collided"):
+            cond = inputs.xy_conditions(nw, seed, log_tau_range=LOG_TAU_TRAIN)
+        else:
+            la = LOG_ASPECT_TRAIN if kind == "rect" else None
+            cond = inputs.transmission_conditions(nw, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
         dc = binding.DeviceCond.from_host(cond, device)
-        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
+        nc = torch.empty(nw, dtype=torch.int32, device=device) if collided else None
+        ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919, ncoll=nc)
         cols = [dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th]
         if kind == "rect":
             cols.append(dc.log_aspect)
+        if kind in ("xy", "xy_collided"):
+            cols.append(dc.omega_x)
         feats = torch.stack(cols, dim=1)
+        if collided:
+            keep = torch.nonzero(nc > 0).squeeze(1)[:n]
+            ex = binding.DeviceExit(*(t[keep] for t in (ex.face, ex.pos, ex.dir_cos, ex.dir_sin, ex.path)))
+            feats = feats[keep]
     torch.cuda.synchronize()
     g = torch.Generator(device=device).manual_seed(seed + 1)
     u = torch.rand(n, device=device, generator=g) - 0.5
@@ -160,7 +160,7 @@ def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=
             print(f"step {it}/{steps} loss {run / (log_every / 50):.4f} ({time.time() - t0:.0f}s)", flush=True)
             run = 0.0
     scales = activation_scales(model, feats, tgt)
-    flags = {"xy": 1, "collided": 2}.get(kind, 0)
+    flags = {"xy": 1, "collided": 2, "xy_collided": 3}.get(kind, 0)
     return model.to_weights(seed & 0xFFFFFFFF, scales, flags=flags)
 
 
@@ -171,7 +171,7 @@ def main():
     ap.add_argument("--data", type=int, default=4_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal", "collided"), default="boundary")
+    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal", "collided", "xy_collided"), default="boundary")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)
