@@ -188,7 +188,7 @@ def bench_transport(binding, inputs, w512, w512_internal=None):
 
 
 def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512_rect=None, w512_xy=None,
-                      w512_collided=None, w512_xy_collided=None):
+                      w512_collided=None, w512_xy_collided=None, w512_rect_collided=None):
     """The paper's two benchmark problems at its mesh size and cross sections ("Benchmark
     Performance"; layouts defined by inputs.lattice_problem / inputs.hohlraum_problem): the
     7 x 7 cm lattice (112^2 cells, central volumetric source) and the 1.3 x 1.3 cm hohlraum
@@ -199,7 +199,8 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     different seeds (the statistical floor at this history count).  With the rectangular-cell
     model, also the lattice on 112 x 56 cells of 1/16 x 1/8 cm; with the XY-geometry model, the
     lattice in XY geometry (one world per geometry).  With the collided model, square-cell
-    problems (and with the XY collided model, the XY lattice) also run RK4 x 12 with the
+    problems (and with the rectangular-cell and XY collided models, the rectangular and XY
+    lattices) also run RK4 x 12 with the
     first-flight split (uncollided crossings placed exactly, the rest sampled by the model
     fitted on collided exits)."""
     import torch
@@ -211,6 +212,7 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     xym = None if w512_xy is None else binding.Model(inputs.pack_blob(w512_xy), "bf16")
     col = None if w512_collided is None else binding.Model(inputs.pack_blob(w512_collided), "bf16")
     colxy = None if w512_xy_collided is None else binding.Model(inputs.pack_blob(w512_xy_collided), "bf16")
+    colr = None if w512_rect_collided is None else binding.Model(inputs.pack_blob(w512_rect_collided), "bf16")
     world = binding.World(1 << 20, 2, 1 << 14)
     problems = [("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))]
     if rect is not None:
@@ -234,6 +236,8 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
                          src if prob.src_face < 0 else None))
         if colxy is not None and prob.xy:
             runs.append(("gmc_bf16_h512_rk4x12_split", binding.SAMPLER_GMC, colxy, 12, "rk4", None))
+        if colr is not None and prob.Ly > 0:
+            runs.append(("gmc_bf16_h512_rk4x12_split", binding.SAMPLER_GMC, colr, 12, "rk4", None))
         res, flux = {}, {}
         for name, smp, m, K, integ, sm in runs:
             kw = dict(integrator=integ, source_model=sm, source_K=K)
@@ -257,7 +261,7 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
         out[pname] = res
     world.close()
     model.close()
-    for mm in (src, rect, xym, col, colxy):
+    for mm in (src, rect, xym, col, colxy, colr):
         if mm is not None:
             mm.close()
     return out
@@ -465,6 +469,8 @@ def main():
     w5c = inputs.load_blob(cpath) if os.path.exists(cpath) else None
     cxpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512_xy_collided.bin")
     w5cx = inputs.load_blob(cxpath) if os.path.exists(cxpath) else None
+    crpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512_rect_collided.bin")
+    w5cr = inputs.load_blob(crpath) if os.path.exists(crpath) else None
     condB = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
     outB = binding.DeviceExit.empty(NB, dev)
     wide = []
@@ -507,7 +513,8 @@ def main():
     if not args.no_transport:
         res["transport"] = bench_transport(binding, inputs, w5t, w5i)
         res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i, w512_rect=w5r, w512_xy=w5x,
-                                               w512_collided=w5c, w512_xy_collided=w5cx)
+                                               w512_collided=w5c, w512_xy_collided=w5cx,
+                                               w512_rect_collided=w5cr)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests)
 
     if not args.no_cpu:

@@ -7,7 +7,7 @@ ln 4]), the boundary model in XY geometry (entry direction a projection of a dir
 sphere: its in-plane components omega_y, omega_x; exit directions inside the unit disk) and the
 internal model for particles born inside a cell (condition: ln tau, c, birth point, birth
 direction).  A fifth, the collided boundary model (blob flag bit 1), is the boundary model fitted
-only on walks with at least one collision (and likewise the XY one, flags bits 0 and 1): the
+only on walks with at least one collision (and likewise the rectangular-cell and XY ones): the
 transport places the uncollided crossings exactly (first-flight split) and leaves the rest to it.
 
 Data come from this library's own analog walk (`mc_transmit` / `mc_transmit_internal`,
@@ -29,6 +29,8 @@ Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_
            --out paper_2512_13965_amd/weights/gmc_h512_xy.bin
        python -m paper_2512_13965_amd.train --model collided --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_collided.bin
+       python -m paper_2512_13965_amd.train --model rect_collided --hidden 512 \
+           --out paper_2512_13965_amd/weights/gmc_h512_rect_collided.bin
        python -m paper_2512_13965_amd.train --model xy_collided --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_xy_collided.bin
 """
@@ -49,8 +51,9 @@ LOG_ASPECT_TRAIN = (math.log(0.25), math.log(4.0))
 
 def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
     """(conditions [n, 4] (boundary), [n, 5] (rect, xy) or [n, 6] (internal), targets [n, 5]) on
-    `device`, from the GPU analog walk.  For the collided models (kind "collided", boundary;
-    "xy_collided", XY geometry) twice the walks are run and the first n with a collision kept."""
+    `device`, from the GPU analog walk.  For the collided models (kinds "collided",
+    "rect_collided", "xy_collided") twice the walks are run and the first n with a collision
+    kept."""
     if kind == "internal":
         cond = inputs.internal_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
         dc = binding.DeviceCondInternal.from_host(cond, device)
@@ -58,18 +61,18 @@ def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
         feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.x - 1.0, 2.0 * dc.y - 1.0,
                              dc.cos_phi, dc.sin_phi], dim=1)
     else:
-        collided = kind in ("collided", "xy_collided")
+        collided = kind.endswith("collided")
         nw = 2 * n if collided else n
         if kind in ("xy", "xy_collided"):
             cond = inputs.xy_conditions(nw, seed, log_tau_range=LOG_TAU_TRAIN)
         else:
-            la = LOG_ASPECT_TRAIN if kind == "rect" else None
+            la = LOG_ASPECT_TRAIN if kind in ("rect", "rect_collided") else None
             cond = inputs.transmission_conditions(nw, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
         dc = binding.DeviceCond.from_host(cond, device)
         nc = torch.empty(nw, dtype=torch.int32, device=device) if collided else None
         ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919, ncoll=nc)
         cols = [dc.log_tau, dc.c, 2.0 * dc.y_in - 1.0, dc.sin_th]
-        if kind == "rect":
+        if kind in ("rect", "rect_collided"):
             cols.append(dc.log_aspect)
         if kind in ("xy", "xy_collided"):
             cols.append(dc.omega_x)
@@ -160,7 +163,7 @@ def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=
             print(f"step {it}/{steps} loss {run / (log_every / 50):.4f} ({time.time() - t0:.0f}s)", flush=True)
             run = 0.0
     scales = activation_scales(model, feats, tgt)
-    flags = {"xy": 1, "collided": 2, "xy_collided": 3}.get(kind, 0)
+    flags = {"xy": 1, "collided": 2, "rect_collided": 2, "xy_collided": 3}.get(kind, 0)
     return model.to_weights(seed & 0xFFFFFFFF, scales, flags=flags)
 
 
@@ -171,7 +174,8 @@ def main():
     ap.add_argument("--data", type=int, default=4_000_000)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--lr", type=float, default=1e-3)
-    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal", "collided", "xy_collided"), default="boundary")
+    ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal", "collided", "rect_collided",
+                                                "xy_collided"), default="boundary")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)

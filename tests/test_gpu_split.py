@@ -9,11 +9,13 @@ ray's exit, and only collided crossings go to a model fitted on collided exits.
   * a transport problem whose cells do not scatter (c = 0): every crossing is uncollided, so a
     step with a collided model (never evaluated) equals the analog-walk step up to rounding;
     square cells, rectangular cells and XY geometry;
-  * with the fitted collided models (weights/gmc_h512_collided.bin, and gmc_h512_xy_collided.bin
-    in XY geometry) the paper's lattice and hohlraum, and the lattice in XY geometry, lie at the
-    statistical floor of analog MC (parity unpinned: learned models).  Measured at 2e5
-    histories with RK4 x 12: lattice 0.0197 vs 0.0217 between analog runs, hohlraum 0.0242 vs
-    0.0257, XY lattice 0.0216 vs 0.0220 (the XY model without the split drifts to 0.109).
+  * with the fitted collided models (weights/gmc_h512_collided.bin; gmc_h512_xy_collided.bin in
+    XY geometry; gmc_h512_rect_collided.bin for rectangular cells) the paper's lattice and
+    hohlraum, the lattice in XY geometry and on 112 x 56 rectangular cells lie at the
+    statistical floor of analog MC (parity unpinned: learned models).  Measured with RK4 x 12 at
+    2e5 histories: lattice 0.0197 vs 0.0217 between analog runs, hohlraum 0.0242 vs 0.0257, XY
+    lattice 0.0216 vs 0.0220 (the XY model without the split drifts to 0.109); at 1e5:
+    rectangular lattice 0.0258 vs 0.0243.
 """
 import math
 import os
@@ -118,11 +120,13 @@ def test_transport_with_split_equals_the_walk_without_scattering(kind):
 def _floor_case(name):
     binding = require_gpu()
     from paper_2512_13965_amd import transport
-    cname = "gmc_h512_xy_collided.bin" if name == "lattice_xy" else "gmc_h512_collided.bin"
+    cname = {"lattice_xy": "gmc_h512_xy_collided.bin", "lattice_rect": "gmc_h512_rect_collided.bin"}.get(
+        name, "gmc_h512_collided.bin")
     cpath, ipath = os.path.join(WDIR, cname), os.path.join(WDIR, "gmc_h512_internal.bin")
     if not (os.path.exists(cpath) and os.path.exists(ipath)):
         pytest.skip("no fitted weights")
-    prob = inputs.hohlraum_problem(112) if name == "hohlraum" else inputs.lattice_problem(16)
+    prob = inputs.hohlraum_problem(112) if name == "hohlraum" else \
+        inputs.lattice_problem(16, 8 if name == "lattice_rect" else None)
     prob.xy = name == "lattice_xy"
     n = 100_000
     col = binding.Model(open(cpath, "rb").read(), "bf16")
@@ -131,14 +135,15 @@ def _floor_case(name):
     mc1 = transport.run_problem(w, prob, n, 1, binding.SAMPLER_MC)
     mc2 = transport.run_problem(w, prob, n, 2, binding.SAMPLER_MC)
     gm = transport.run_problem(w, prob, n, 3, binding.SAMPLER_GMC, col, 12, integrator="rk4",
-                               source_model=src if prob.src_face < 0 and not prob.xy else None, source_K=12)
+                               source_model=src if prob.src_face < 0 and name == "lattice" else None,
+                               source_K=12)
     w.close()
     col.close()
     src.close()
     return n, mc1, mc2, gm
 
 
-@pytest.mark.parametrize("name", ["lattice", "hohlraum", "lattice_xy"])
+@pytest.mark.parametrize("name", ["lattice", "hohlraum", "lattice_xy", "lattice_rect"])
 def test_split_transport_at_the_statistical_floor(name):
     n, mc1, mc2, gm = _floor_case(name)
     l1 = lambda a, b: np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum()
