@@ -318,7 +318,9 @@ def main():
                     help="only launch one kernel --steps times: fp32 | bf16 | fp8 (sampler, "
                          "H=256 / 512 / 512, Euler K=16), rk4 (BF16 H=512, RK4 x 12) or "
                          "walk:TAU (analog, 2^20 transmissions), transport (cfg3 checkerboard, "
-                         "2e5 analog histories per step)")
+                         "2e5 analog histories per step), lattice_split (112^2 lattice, 2e5 "
+                         "histories per step, first-flight split with the fitted collided model, "
+                         "BF16 RK4 x 12)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -343,6 +345,17 @@ def main():
             for _ in range(args.steps):
                 transport.run_problem(w, inputs.checkerboard_problem(32), 200_000, 1, binding.SAMPLER_MC)
             w.close()
+        elif kind == "lattice_split":
+            from paper_2512_13965_amd import transport
+            wdir = os.path.join(ROOT, "paper_2512_13965_amd", "weights")
+            m = binding.Model(open(os.path.join(wdir, "gmc_h512_collided.bin"), "rb").read(), "bf16")
+            src = binding.Model(open(os.path.join(wdir, "gmc_h512_internal.bin"), "rb").read(), "bf16")
+            w = binding.World(1 << 20, 1, 1 << 14)
+            for _ in range(args.steps):
+                transport.run_problem(w, inputs.lattice_problem(16), 200_000, 1, binding.SAMPLER_GMC, m, 12,
+                                      integrator="rk4", source_model=src, source_K=12)
+            w.close()
+            N = 200_000
         else:
             tau = float(args.profile.split(":")[1]) if ":" in args.profile else 100.0
             c = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(N, tau, 1.0, 9))

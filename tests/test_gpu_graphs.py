@@ -49,14 +49,16 @@ def _same(a, b, n):
         np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-12 * n)
 
 
-@pytest.mark.parametrize("sampler", ["mc", "gmc"])
+@pytest.mark.parametrize("sampler", ["mc", "gmc", "gmc_split"])
 def test_graph_steps_match_direct_launches(sampler):
     binding = require_gpu()
     prob = inputs.checkerboard_problem(16, src=2)
     n = 30_000
     model = None
-    if sampler == "gmc":
-        model = binding.Model(inputs.pack_blob(inputs.random_weights(256, 3)), "bf16")
+    if sampler != "mc":
+        # gmc_split: a model flagged as fitted on collided crossings (first-flight split step)
+        flags = 2 if sampler == "gmc_split" else 0
+        model = binding.Model(inputs.pack_blob(inputs.random_weights(256, 3, flags=flags)), "bf16")
     smp = binding.SAMPLER_MC if sampler == "mc" else binding.SAMPLER_GMC
     # chunks of 7,000 give particle counts in several buckets (1024 .. 16384)
     eager = _run(binding, prob, n, 5, smp, model, 16, False, 7_000)
