@@ -288,6 +288,17 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
  * an unknown sampler, or for GMC without a boundary model (n_in = 10) or with K outside 1..1024. */
 int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, void *stream,
                        int64_t *n_alive_out);
+/* Streaming of uncollided crossings in steps with the first-flight split (a model fitted on
+ * collided crossings): a particle whose crossing is uncollided is carried on inside the step,
+ * its attenuation, tallies and move done there (FP64, global atomics), through up to
+ * max_crossings cells; the step's sampler then sees it at its next collided crossing.  Every
+ * crossing is decided by the same random numbers (keyed by history and cell visit) whatever
+ * the value, so results are the same up to the order of FP64 additions; 1 = one crossing per
+ * particle per step.  Default 64.  GMC_EINVAL outside 1..1024. */
+int gmc_world_set_streaming(gmc_world *w, int max_crossings);
+/* Cell transmissions carried out by gmc_transport_step since the world was created: one per
+ * particle and step plus the crossings streamed inside steps (current after each step). */
+int gmc_world_transmissions(const gmc_world *w, int64_t *count);
 /* Source births of later gmc_world_inject calls: m = NULL (the default) walks each birth's first
  * leg with the analog walk; an internal model (n_in = 12) samples it with the generative sampler
  * instead (K steps of the world's integrator; paper "Transport Algorithm", first stage, and

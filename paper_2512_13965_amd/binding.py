@@ -351,6 +351,8 @@ def _transport_sigs(L):
     L.gmc_problem_tally.argtypes = [P, I32, P, P, P, P, P]
     L.gmc_world_set_integrator.argtypes = [P, I]
     L.gmc_world_set_graphs.argtypes = [P, I]
+    L.gmc_world_set_streaming.argtypes = [P, I]
+    L.gmc_world_transmissions.argtypes = [P, ctypes.POINTER(I64)]
     L.gmc_world_set_source_model.argtypes = [P, P, I]
     for name in ("gmc_world_set_integrator", "gmc_world_set_graphs", "gmc_world_set_source_model", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
                  "gmc_problem_remove", "gmc_world_inject", "gmc_transport_step",
@@ -409,6 +411,14 @@ class World:
     def set_source_model(self, model: Model | None, K: int = 16):
         """Births sampled by an internal model (None: analog first leg)."""
         _check(self._L.gmc_world_set_source_model(self._h, None if model is None else model.handle, int(K)))
+
+    def set_streaming(self, max_crossings: int):
+        _check(self._L.gmc_world_set_streaming(self._h, int(max_crossings)))
+
+    def transmissions(self) -> int:
+        v = ctypes.c_int64()
+        _check(self._L.gmc_world_transmissions(self._h, ctypes.byref(v)))
+        return v.value
 
     def set_graphs(self, enable: bool = True):
         """Replay captured HIP graphs of the transport step per particle-count bucket."""

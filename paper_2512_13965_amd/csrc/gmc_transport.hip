@@ -123,6 +123,21 @@ __device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemD
     return w - dw;
 }
 
+// visit_tally with the flux and deposit added straight to the global tallies (for a kernel
+// whose particles may visit more distinct cells than the LDS table holds).
+__device__ __forceinline__ double visit_tally_global(const CellsDev &cd, const ProblemDev &P, int cell,
+                                                     double w, float path_units, double unit)
+{
+    const double sig_a = (1.0 - cd.c[cell]) * cd.tau[cell] / P.L;
+    const double ls = (double)path_units * unit;
+    const double dw = w * (-expm1(-sig_a * ls));
+    const double V = P.L * P.Ly;
+    const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
+    atomicAdd(&cd.flux[cell], phi);
+    atomicAdd(&cd.absorbed[cell], dw);
+    return w - dw;
+}
+
 struct Next {
     int32_t cell, entry;
     float yin, gx, gy;
@@ -384,10 +399,22 @@ __global__ __launch_bounds__(256) void gather_kernel(BankDev b, int64_t n_arg,
     keys[i] = cd.prob[b.pid[i]].seed;
 }
 
-// Stage 1 with the first-flight split (models fitted on collided exits, blob flag bit 1):
-// canonical conditions as gather_kernel; a particle that crosses its cell without a collision
-// (uncollided_exit) gets its exit record written at its own index, the others are compacted
-// (one atomic per wave) into the sampler's staging with their bank index in sidx.
+// Exit-record face of a particle whose history ended inside the split gather: the apply stage
+// leaves it out.
+constexpr int32_t kFaceEnded = -1000;
+
+// Stage 1 with the first-flight split (models fitted on collided exits, blob flag bit 1).  Each
+// particle draws its crossing's split (uncollided_exit, keyed by history and cell visit); while
+// the crossings stay uncollided it is streamed through up to ff_max cells inside this kernel:
+// stages 3-4 of each such crossing (FP64 attenuation and tallies, here with global atomics, and
+// the move to the neighbour) exactly as the apply stage would do them with the same random
+// numbers, its bank slot then updated in place.  The crossing that ends the loop is
+//   * collided: canonical conditions compacted (one atomic per wave) into the sampler's staging
+//     with the bank index in sidx;
+//   * the ff_max-th uncollided one: its exit record written at the particle's own index, for
+//     the apply stage;
+//   * one that ended the history (leak, cutoff): face kFaceEnded.
+// ff_max = 1 is one crossing per particle per step.  `streamed` counts the crossings finished here.
 __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_arg,
                                                            const unsigned long long *n_dev, CellsDev cd,
                                                            float *ltau, float *cc, float *yin, float *sth,
@@ -395,7 +422,8 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
                                                            uint64_t *keys, int32_t *sidx,
                                                            unsigned long long *count, int32_t *e_face,
                                                            float *e_pos, float *e_dcos, float *e_dsin,
-                                                           float *e_path)
+                                                           float *e_path, int ff_max,
+                                                           unsigned long long *streamed)
 {
     const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,33 +431,77 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
     bool collided = false;
     float lt = 0.f, c = 0.f, y = 0.f, s = 0.f, la = 0.f, ox = 0.f;
     uint64_t id = 0, key = 0;
+    uint32_t nstream = 0;
+    bool e_face_ended = false;
     if (i < n) {
-        const int cell = b.cell[i];
-        const int e = b.entry[i];
-        const int k = (e + 1) & 3;
-        float U, V;
-        rot_quarter((4 - k) & 3, b.gx[i], b.gy[i], U, V);
+        int cell = b.cell[i];
+        int e = b.entry[i];
+        float gx = b.gx[i], gy = b.gy[i], yy = b.yin[i];
+        double w = b.w[i];
+        uint32_t ev = b.event[i];
+        const uint32_t hist = b.hist[i];
         const ProblemDev P = cd.prob[b.pid[i]];
-        lt = (e & 1) ? cd.ltau[cell] + P.lr : cd.ltau[cell];
-        la = (e & 1) ? -P.lr : P.lr;
-        c = cd.cf[cell];
-        y = b.yin[i];
-        s = fminf(fmaxf(V, -1.0f), 1.0f);
-        ox = U;
-        id = (uint64_t)b.hist[i] | ((uint64_t)b.event[i] << 32);
-        key = P.seed;
-        const float u = P.xy ? U : sqrtf(fmaxf(1.0f - s * s, 0.0f));
-        Exit ex;
-        if (uncollided_exit(expf(lt), c, y, u, s, la == 0.0f ? 1.0f : expf(la), key, id, ex)) {
-            e_face[i] = ex.face;
-            e_pos[i] = ex.pos;
-            e_dcos[i] = ex.u;
-            e_dsin[i] = ex.v;
-            e_path[i] = ex.path;
-        } else {
-            collided = true;
+        bool ended = false;
+        for (int it = 0;; ++it) {
+            const int k = (e + 1) & 3;
+            float U, V;
+            rot_quarter((4 - k) & 3, gx, gy, U, V);
+            lt = (e & 1) ? cd.ltau[cell] + P.lr : cd.ltau[cell];
+            la = (e & 1) ? -P.lr : P.lr;
+            c = cd.cf[cell];
+            y = yy;
+            s = fminf(fmaxf(V, -1.0f), 1.0f);
+            ox = U;
+            id = (uint64_t)hist | ((uint64_t)ev << 32);
+            key = P.seed;
+            const float u = P.xy ? U : sqrtf(fmaxf(1.0f - s * s, 0.0f));
+            Exit ex;
+            if (!uncollided_exit(expf(lt), c, y, u, s, la == 0.0f ? 1.0f : expf(la), key, id, ex)) {
+                collided = true;
+                break;
+            }
+            if (it + 1 >= ff_max) {
+                e_face[i] = ex.face;
+                e_pos[i] = ex.pos;
+                e_dcos[i] = ex.u;
+                e_dsin[i] = ex.v;
+                e_path[i] = ex.path;
+                break;
+            }
+            const double w_out = visit_tally_global(cd, P, cell, w, ex.path, (e & 1) ? P.Ly : P.L);
+            float ngx, ngy;
+            rot_quarter(k, ex.u, ex.v, ngx, ngy);
+            const Next nx = move_on(cd, P, cell, (ex.face + k) & 3, ex.pos, ngx, ngy, w_out);
+            ++nstream;
+            if (!nx.alive) {
+                e_face[i] = kFaceEnded;
+                ended = e_face_ended = true;
+                break;
+            }
+            cell = nx.cell;
+            e = nx.entry;
+            yy = nx.yin;
+            gx = nx.gx;
+            gy = nx.gy;
+            w = w_out;
+            ++ev;
+        }
+        if (nstream > 0 && !ended) {
+            b.cell[i] = cell;
+            b.entry[i] = e;
+            b.yin[i] = yy;
+            b.gx[i] = gx;
+            b.gy[i] = gy;
+            b.w[i] = w;
+            b.event[i] = ev;
         }
     }
+    // crossings beyond the one per particle that the step counts (a history that ended here
+    // finished its step's own crossing inside the loop)
+    uint32_t tot = nstream > 0 && e_face_ended ? nstream - 1 : nstream;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) tot += (uint32_t)__shfl_xor((int)tot, o);
+    if (lane == 0 && tot > 0) atomicAdd(streamed, (unsigned long long)tot);
     const uint64_t mask = __ballot(collided);
     if (!mask) return;
     const int leader = __ffsll((unsigned long long)mask) - 1;
@@ -487,7 +559,7 @@ __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
     double w_out = 0.0;
     int32_t pid = 0;
     uint32_t hist = 0, event = 0;
-    if (i < n) {
+    if (i < n && face_c[i] != kFaceEnded) {
         pid = in.pid[i];
         const ProblemDev P = cd.prob[pid];
         const int cell = in.cell[i];
@@ -545,6 +617,9 @@ struct gmc_world {
     int32_t *s_idx = nullptr, *s_face = nullptr;
     float *s_pos = nullptr, *s_dcos = nullptr, *s_dsin = nullptr, *s_path = nullptr;
     unsigned long long *s_count = nullptr;
+    unsigned long long *streamed = nullptr;      // crossings finished inside split gathers
+    int ff_max = 64;                             // cells a particle may stream through per step
+    int64_t stepped = 0;                         // particles stepped (one crossing each)
     uint64_t *ids = nullptr, *keys = nullptr;
     int32_t *e_face = nullptr;
     float *e_pos = nullptr, *e_dcos = nullptr, *e_dsin = nullptr, *e_path = nullptr;
@@ -558,7 +633,7 @@ struct gmc_world {
     unsigned long long *queue = nullptr;      // the analog walk's work counter (this world's own)
     // captured transport steps, one per (sampler, model, K, integrator, bank parity, bucket)
     struct StepGraph {
-        int sampler, K, integrator, cur;
+        int sampler, K, integrator, cur, ff;
         uint64_t model;        // serial of the model (0 for the analog walk)
         int64_t bucket;
         hipGraph_t graph;
@@ -622,6 +697,7 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->s_dsin, 4 * C);
     L.add((void **)&w->s_path, 4 * C);
     L.add((void **)&w->s_count, 8);
+    L.add((void **)&w->streamed, 8);
     L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);
     L.add((void **)&w->keys, 8 * C);
@@ -647,6 +723,8 @@ int sync_counters(gmc_world *w, int which, hipStream_t s)
 {
     const size_t bytes = 8 * (size_t)(1 + w->max_problems);
     hipError_t e = hipMemcpyAsync(w->host_counters, w->cnt(which), bytes, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(w->host_counters + 1 + w->max_problems, w->streamed, 8, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_hip_error(e, "transport: reading counters");
     w->n_alive = (int64_t)w->host_counters[0];
@@ -690,13 +768,15 @@ int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_ce
     e = hipMalloc(&w->mem, L.total);
     if (e != hipSuccess) { delete w; return set_error(GMC_ENOMEM, "gmc_world_create: device allocation failed"); }
     for (auto &pr : L.parts) *pr.first = (char *)w->mem + pr.second;
-    e = hipHostMalloc((void **)&w->host_counters, 8 * (size_t)(1 + max_problems), hipHostMallocDefault);
+    e = hipHostMalloc((void **)&w->host_counters, 8 * (size_t)(2 + max_problems), hipHostMallocDefault);
     if (e != hipSuccess) {
         (void)hipFree(w->mem);
         delete w;
         return set_error(GMC_ENOMEM, "gmc_world_create: pinned host allocation failed");
     }
+    std::memset(w->host_counters, 0, 8 * (size_t)(2 + max_problems));
     e = hipMemset(w->counters, 0, 8 * 2 * (size_t)(1 + max_problems));
+    if (e == hipSuccess) e = hipMemset(w->streamed, 0, 8);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         (void)hipHostFree(w->host_counters);
@@ -925,6 +1005,23 @@ int gmc_world_set_integrator(gmc_world *w, int integrator)
     return GMC_OK;
 }
 
+int gmc_world_set_streaming(gmc_world *w, int max_crossings)
+{
+    if (!w) return set_error(GMC_EINVAL, "gmc_world_set_streaming: null world");
+    if (max_crossings < 1 || max_crossings > 1024)
+        return set_error(GMC_EINVAL, "gmc_world_set_streaming: max_crossings must be in 1..1024");
+    std::lock_guard<std::mutex> lk(w->mu);
+    w->ff_max = max_crossings;
+    return GMC_OK;
+}
+
+int gmc_world_transmissions(const gmc_world *w, int64_t *count)
+{
+    if (!w || !count) return set_error(GMC_EINVAL, "gmc_world_transmissions: null argument");
+    *count = w->stepped + (int64_t)w->host_counters[1 + w->max_problems];
+    return GMC_OK;
+}
+
 int gmc_world_set_graphs(gmc_world *w, int enable)
 {
     if (!w) return set_error(GMC_EINVAL, "gmc_world_set_graphs: null world");
@@ -963,7 +1060,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         hipLaunchKernelGGL(gather_split_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur],
                            n_launch, n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la,
                            w->c_ox, w->ids, w->keys, w->s_idx, w->s_count, w->e_face, w->e_pos, w->e_dcos,
-                           w->e_dsin, w->e_path);
+                           w->e_dsin, w->e_path, w->ff_max, w->streamed);
     } else {
         hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, w->bank[cur], n_launch,
                            n_dev, w->cells(), w->c_ltau, w->c_c, w->c_yin, w->c_sth, w->c_la, w->c_ox, w->ids,
@@ -1053,9 +1150,10 @@ int step_graph(gmc_world *w, int sampler, const gmc_model *m, int K, int64_t buc
     const int integ = (sampler == GMC_SAMPLER_GMC) ? w->integrator : 0;
     const uint64_t mm = (sampler == GMC_SAMPLER_GMC) ? m->serial : 0;
     const int KK = (sampler == GMC_SAMPLER_GMC) ? K : 0;
+    const int ff = (sampler == GMC_SAMPLER_GMC && m->collided) ? w->ff_max : 0;
     for (auto &g : w->step_graphs)
         if (g.sampler == sampler && g.model == mm && g.K == KK && g.integrator == integ && g.cur == w->cur &&
-            g.bucket == bucket) {
+            g.ff == ff && g.bucket == bucket) {
             *exec = g.exec;
             return GMC_OK;
         }
@@ -1076,7 +1174,7 @@ int step_graph(gmc_world *w, int sampler, const gmc_model *m, int K, int64_t buc
         (void)hipGraphDestroy(graph);
         return set_hip_error(e, "gmc_transport_step: instantiate");
     }
-    w->step_graphs.push_back({sampler, KK, integ, w->cur, mm, bucket, graph, x});
+    w->step_graphs.push_back({sampler, KK, integ, w->cur, ff, mm, bucket, graph, x});
     *exec = x;
     return GMC_OK;
 }
@@ -1114,6 +1212,7 @@ int gmc_transport_step(gmc_world *w, int sampler, const gmc_model *m, int K, voi
         }
         const int nxt = 1 - w->cur;
         w->cur = nxt;
+        w->stepped += n;
         rc = sync_counters(w, nxt, s);
         if (rc != GMC_OK) return rc;
     }

@@ -95,4 +95,8 @@ def test_sampling_calls_reject_bad_arguments_without_a_device(binding):
     assert L.gmc_uncollided_split(cond, 10, 0, 0, None, out, None) == binding.GMC_EINVAL
     assert L.gmc_uncollided_split(cond, -1, 0, 0, None, out, None) == binding.GMC_EINVAL
     assert L.gmc_uncollided_split(cond, 0, 0, 0, None, out, None) == binding.GMC_OK
+    L.gmc_world_set_streaming.argtypes = [ctypes.c_void_p, ctypes.c_int]
+    L.gmc_world_transmissions.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    assert L.gmc_world_set_streaming(None, 4) == binding.GMC_EINVAL
+    assert L.gmc_world_transmissions(None, None) == binding.GMC_EINVAL
     assert L.gmc_model_destroy(None) == binding.GMC_EINVAL

@@ -9,6 +9,9 @@ ray's exit, and only collided crossings go to a model fitted on collided exits.
   * a transport problem whose cells do not scatter (c = 0): every crossing is uncollided, so a
     step with a collided model (never evaluated) equals the analog-walk step up to rounding;
     square cells, rectangular cells and XY geometry;
+  * streaming uncollided crossings inside a step (gmc_world_set_streaming) changes neither the
+    histories nor the transmission count: the same random numbers decide every crossing, so
+    tallies agree with one crossing per step up to the order of FP64 additions;
   * with the fitted collided models (weights/gmc_h512_collided.bin; gmc_h512_xy_collided.bin in
     XY geometry; gmc_h512_rect_collided.bin for rectangular cells) the paper's lattice and
     hohlraum, the lattice in XY geometry and on 112 x 56 rectangular cells lie at the
@@ -115,6 +118,30 @@ def test_transport_with_split_equals_the_walk_without_scattering(kind):
     assert mc["leak"].sum() > 0.01 * n
     assert abs(gm["leak"].sum() - mc["leak"].sum()) < 1e-3 * n
     assert gm["transmissions"] == mc["transmissions"] or abs(gm["transmissions"] / mc["transmissions"] - 1) < 1e-3
+
+
+@pytest.mark.parametrize("kind", ["square", "xy"])
+def test_streaming_gives_the_histories_of_one_crossing_per_step(kind):
+    binding = require_gpu()
+    from paper_2512_13965_amd import transport
+    n_in = inputs.N_IN if kind == "square" else inputs.N_IN_RECT
+    flags = 2 | (1 if kind == "xy" else 0)
+    m = binding.Model(inputs.pack_blob(inputs.random_weights(128, 5, n_in=n_in, flags=flags)), "fp32")
+    prob = inputs.lattice_problem(4)
+    prob.xy = kind == "xy"
+    n = 20_000
+    w = binding.World(1 << 15, 1, 1 << 12)
+    runs = {ff: transport.run_problem(w, prob, n, 9, binding.SAMPLER_GMC, m, 4, streaming=ff) for ff in (1, 3, 64)}
+    w.close()
+    m.close()
+    one = runs[1]
+    for ff in (3, 64):
+        r = runs[ff]
+        print(f"{kind} streaming {ff}: steps {r['steps']} vs {one['steps']}, transmissions {r['transmissions']}")
+        assert r["transmissions"] == one["transmissions"]
+        assert r["steps"] < one["steps"]
+        for k in ("flux", "absorbed", "leak", "cutoff"):
+            np.testing.assert_allclose(r[k], one[k], rtol=1e-11, atol=1e-11 * n)
 
 
 def _floor_case(name):
