@@ -267,19 +267,21 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     return out
 
 
-def bench_serving(binding, inputs, w512, n_req):
+def bench_serving(binding, inputs, w512, n_req, w512_collided=None):
     """Continuous batching of a Poisson stream of transport requests of the config-3 kind
     (grids 16^2..128^2, per-cell tau log-uniform in [0.1, 200], c ~ U[0, 1]); histories per
     request log-uniform in [1e4, 10^5.5] (scaled down from 1e4..1e7 so the stream completes in
-    tens of seconds); generative sampler BF16, H = 512, K = 16."""
+    tens of seconds); generative sampler BF16, H = 512, K = 16.  With the collided model, the
+    same stream (same arrivals) also with the first-flight split."""
     from paper_2512_13965_amd import serving
     model = binding.Model(inputs.pack_blob(w512), "bf16")
+    col = None if w512_collided is None else binding.Model(inputs.pack_blob(w512_collided), "bf16")
     world = binding.World(1 << 20, 16, 1 << 18)
     make = lambda i: inputs.random_problem(1000 + i, hist_log10_range=(4.0, 5.5))
 
-    def serve(reqs, graphs=True):
+    def serve(reqs, graphs=True, m=model):
         world.set_graphs(graphs)
-        return serving.Server(world, binding.SAMPLER_GMC, model, K=16, graphs=graphs,
+        return serving.Server(world, binding.SAMPLER_GMC, m, K=16, graphs=graphs,
                               cell_budget=(1 << 18) * serving.CELL_BYTES).run(reqs)
 
     # capacity: a burst of 48 requests all arriving at t = 0
@@ -290,10 +292,17 @@ def bench_serving(binding, inputs, w512, n_req):
     st = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make))
     # the same stream with direct kernel launches instead of the captured per-bucket step graphs
     direct = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make), graphs=False)
+    split = None
+    if col is not None:
+        sp = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make), m=col)
+        split = {"latency_s": sp.latency_percentiles((50, 90, 99)), "transmissions_per_s": sp.throughput,
+                 "wall_s": sp.wall, "steps": sp.steps,
+                 "model": "collided-only BF16 H=512 K=16, uncollided crossings streamed in steps"}
+        col.close()
     model.close()
     world.close()
     lat = st.latency_percentiles((50, 90, 99))
-    return {"requests": len(st.requests), "capacity_req_per_s": capacity_hz,
+    return {"first_flight_split": split,"requests": len(st.requests), "capacity_req_per_s": capacity_hz,
             "arrival_rate_hz": rate, "wall_s": st.wall, "steps": st.steps,
             "transmissions": st.transmissions, "transmissions_per_s": st.throughput,
             "latency_s": lat, "histories": int(sum(r.n_hist for r in st.requests)),
@@ -528,7 +537,7 @@ def main():
         res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i, w512_rect=w5r, w512_xy=w5x,
                                                w512_collided=w5c, w512_xy_collided=w5cx,
                                                w512_rect_collided=w5cr)
-        res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests)
+        res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, K)

@@ -133,6 +133,7 @@ class Server:
         heapq.heapify(pending)
         waiting: list[Request] = []          # arrived, not yet admitted (FIFO)
         stats = ServeStats()
+        x0 = self.world.transmissions()
         self._t0 = self.clock()
         while pending or waiting or self.active:
             now = self.clock() - self._t0
@@ -158,6 +159,9 @@ class Server:
                 stats.steps += 1
             self._retire(now, stats)
         stats.wall = self.clock() - self._t0
+        # cell transmissions, with the first-flight split also those streamed inside steps (the
+        # per-request counts are particle-steps)
+        stats.transmissions = self.world.transmissions() - x0
         return stats
 
 

@@ -21,6 +21,7 @@ class FakeWorld:
         self.injected = {}
         self.steps = 0
         self.max_alive = 0
+        self.xmit = 0
 
     def add_problem(self, problem, seed):
         free = [p for p in range(self.slots) if p not in self.used]
@@ -40,8 +41,12 @@ class FakeWorld:
         self.max_alive = max(self.max_alive, sum(self.alive_pp.values()))
         return sum(self.alive_pp.values())
 
+    def transmissions(self):
+        return self.xmit
+
     def step(self, sampler, model, K):
         self.steps += 1
+        self.xmit += sum(self.alive_pp.values())
         for p in self.alive_pp:
             self.alive_pp[p] //= 2
         return sum(self.alive_pp.values())
