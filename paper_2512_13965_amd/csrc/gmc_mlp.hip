@@ -260,13 +260,18 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
 {
 #if GMC_DRAIN_STAGED
     constexpr int DW = GMC_DRAIN_W;
+    // With per-layer scales (powers of two) the two scalings fold into the constants: acc * c1
+    // is -log2(e) * (acc * oscale) and (acc * c2) * sigmoid is (acc * oscale * sigmoid) * inv_next,
+    // each with its single rounding, since scaling by a power of two is exact.
+    const float c1 = SCALE ? -1.4426950408889634f * oscale : -1.4426950408889634f;
+    const float c2 = oscale * inv_next;
     sfor<16 / DW>([&](auto HH) {
         constexpr int h0 = decltype(HH)::value * DW;
         float a[DW], t[DW];
 #pragma unroll
         for (int i = 0; i < DW; ++i) {
-            a[i] = SCALE ? acc[h0 + i] * oscale : acc[h0 + i];
-            t[i] = -1.4426950408889634f * a[i];
+            a[i] = SCALE ? acc[h0 + i] * c2 : acc[h0 + i];
+            t[i] = c1 * acc[h0 + i];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -277,7 +282,7 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
         __builtin_amdgcn_sched_barrier(0);
         float y[DW];
 #pragma unroll
-        for (int i = 0; i < DW; ++i) y[i] = SCALE ? (a[i] * t[i]) * inv_next : a[i] * t[i];
+        for (int i = 0; i < DW; ++i) y[i] = a[i] * t[i];
         if constexpr (PO == kF32) {
 #pragma unroll
             for (int i = 0; i < DW; ++i) w[h0 + i] = __builtin_bit_cast(uint32_t, y[i]);
