@@ -469,6 +469,19 @@ def main():
     fnL()
     msL = float(np.median(time_launches(fnL, 3, stream)))
     res["analog_tau100_batch_2^23"] = {"ms": msL, "tps": NL / (msL * 1e-3)}
+    # thick cells: the analog walk's cost grows with tau (its longest walks grow faster), the
+    # sampler's does not; 2^23 walks per launch at tau = 100, 300, 1000 against the fitted
+    # samplers (BF16, H = 128 and 512) on 2^20 mixed-cell transmissions
+    thick = {"analog_batch": NL, "analog_tps": {}}
+    for tau in (100.0, 300.0, 1000.0):
+        if tau == 100.0:
+            thick["analog_tps"]["100"] = NL / (msL * 1e-3)
+            continue
+        cT = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(NL, tau, 1.0, 9), dev)
+        fnT = lambda: binding.mc_transmit(cT, binding.MODE_CONTINUOUS, 2, 0, out=oL)
+        fnT()
+        thick["analog_tps"][str(int(tau))] = NL / (float(np.median(time_launches(fnT, 3, stream))) * 1e-3)
+        del cT
     del cL, oL
     gmc_tps = N / (kms.mean() * 1e-3)
     for s in sweep:
@@ -526,6 +539,27 @@ def main():
                      "ms": t, "tps": NB / (t * 1e-3), "tflops": fl / 1e12, "frac_peak": fl / PEAK[prec]})
         m.close()
     res["h256_sampler"] = h256
+    # the fitted width-128 model (BF16): Euler K = 16 and RK4 x 12, 2^20 transmissions
+    h128 = {}
+    hpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h128.bin")
+    w1 = inputs.load_blob(hpath) if os.path.exists(hpath) else inputs.random_weights(128, 1)
+    m = binding.Model(inputs.pack_blob(w1), "bf16")
+    for name, integ, KK in (("euler16", "euler", 16), ("rk4x12", "rk4", 12)):
+        fn = lambda: binding.gmc_sample(m, condB, integ, KK, 2, 0, out=outB)
+        fn()
+        t = float(np.median(time_launches(fn, 3, stream)))
+        h128[name] = {"ms": t, "tps": NB / (t * 1e-3)}
+    m.close()
+    res["h128_bf16_sampler"] = h128
+    gmc_rates = {"fp32_h256_euler16": gmc_tps,
+                 "bf16_h512_euler16": next(x["tps"] for x in wide if x["precision"] == "bf16"
+                                           and x["integrator"] == "euler" and x["K"] == 16),
+                 "bf16_h512_rk4x12": next(x["tps"] for x in wide if x["precision"] == "bf16"
+                                          and x["integrator"] == "rk4"),
+                 "bf16_h128_euler16": h128["euler16"]["tps"], "bf16_h128_rk4x12": h128["rk4x12"]["tps"]}
+    thick["gmc_tps"] = gmc_rates
+    thick["gmc_over_analog"] = {t: {k: v / a for k, v in gmc_rates.items()} for t, a in thick["analog_tps"].items()}
+    res["thick_cells"] = thick
     for s in sweep:
         s["gmc_bf16_h512_k16_tps"] = next(x["tps"] for x in wide if x["precision"] == "bf16"
                                           and x["integrator"] == "euler" and x["K"] == 16)

@@ -21,6 +21,8 @@ Loss (eq. 9, sigma_min = 0): E || v(x_t, t | c) - (x1 - x0) ||^2, x_t = (1 - t) 
 x0 ~ N(0, I), t ~ U[0, 1].  The fit itself is offline PyTorch (autograd), not the hot path.
 
 Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_amd/weights/gmc_h512.bin
+       python -m paper_2512_13965_amd.train --hidden 128 --steps 150000 --data 8000000 \
+           --out paper_2512_13965_amd/weights/gmc_h128.bin
        python -m paper_2512_13965_amd.train --model internal --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_internal.bin
        python -m paper_2512_13965_amd.train --model rect --hidden 512 \
