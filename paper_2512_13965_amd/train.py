@@ -22,7 +22,7 @@ x0 ~ N(0, I), t ~ U[0, 1].  The fit itself is offline PyTorch (autograd), not th
 
 Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_amd/weights/gmc_h512.bin
        python -m paper_2512_13965_amd.train --hidden 128 --steps 150000 --data 8000000 \
-           --out paper_2512_13965_amd/weights/gmc_h128.bin
+           --tau-max 1000 --out paper_2512_13965_amd/weights/gmc_h128.bin
        python -m paper_2512_13965_amd.train --model internal --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_internal.bin
        python -m paper_2512_13965_amd.train --model rect --hidden 512 \
@@ -51,13 +51,13 @@ LOG_TAU_TRAIN = (math.log(0.05), math.log(300.0))
 LOG_ASPECT_TRAIN = (math.log(0.25), math.log(4.0))
 
 
-def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
+def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary", log_tau_range=LOG_TAU_TRAIN):
     """(conditions [n, 4] (boundary), [n, 5] (rect, xy) or [n, 6] (internal), targets [n, 5]) on
     `device`, from the GPU analog walk.  For the collided models (kinds "collided",
     "rect_collided", "xy_collided") twice the walks are run and the first n with a collision
     kept."""
     if kind == "internal":
-        cond = inputs.internal_conditions(n, seed, log_tau_range=LOG_TAU_TRAIN)
+        cond = inputs.internal_conditions(n, seed, log_tau_range=log_tau_range)
         dc = binding.DeviceCondInternal.from_host(cond, device)
         ex = binding.mc_transmit_internal(dc, binding.MODE_CONTINUOUS, seed=seed + 7919)
         feats = torch.stack([dc.log_tau, dc.c, 2.0 * dc.x - 1.0, 2.0 * dc.y - 1.0,
@@ -66,10 +66,10 @@ def make_dataset(n: int, seed: int, device="cuda", kind: str = "boundary"):
         collided = kind.endswith("collided")
         nw = 2 * n if collided else n
         if kind in ("xy", "xy_collided"):
-            cond = inputs.xy_conditions(nw, seed, log_tau_range=LOG_TAU_TRAIN)
+            cond = inputs.xy_conditions(nw, seed, log_tau_range=log_tau_range)
         else:
             la = LOG_ASPECT_TRAIN if kind in ("rect", "rect_collided") else None
-            cond = inputs.transmission_conditions(nw, seed, log_tau_range=LOG_TAU_TRAIN, log_aspect_range=la)
+            cond = inputs.transmission_conditions(nw, seed, log_tau_range=log_tau_range, log_aspect_range=la)
         dc = binding.DeviceCond.from_host(cond, device)
         nc = torch.empty(nw, dtype=torch.int32, device=device) if collided else None
         ex = binding.mc_transmit(dc, binding.MODE_CONTINUOUS, seed=seed + 7919, ncoll=nc)
@@ -138,10 +138,10 @@ def activation_scales(model: VelocityMLP, feats, tgt, n=65536, seed=0):
 
 
 def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=20251213,
-          log_every=1000, device="cuda", kind="boundary"):
+          log_every=1000, device="cuda", kind="boundary", log_tau_range=LOG_TAU_TRAIN):
     torch.manual_seed(seed)
     t0 = time.time()
-    feats, tgt = make_dataset(n_data, seed, device, kind)
+    feats, tgt = make_dataset(n_data, seed, device, kind, log_tau_range)
     n_data = feats.shape[0]
     print(f"data: {n_data} {kind} exits in {time.time() - t0:.1f}s", flush=True)
     model = VelocityMLP(hidden, 5 + 1 + feats.shape[1]).to(device)
@@ -178,9 +178,12 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--model", choices=("boundary", "rect", "xy", "internal", "collided", "rect_collided",
                                                 "xy_collided"), default="boundary")
+    ap.add_argument("--tau-max", type=float, default=math.exp(LOG_TAU_TRAIN[1]),
+                    help="largest optical thickness of the training cells (ln tau uniform)")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
-    w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model)
+    w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model,
+              log_tau_range=(LOG_TAU_TRAIN[0], math.log(a.tau_max)))
     inputs.save_blob(w, a.out)
     print("saved", a.out, "act scales", list(w.act_scale), "w scales", list(w.w_scale), flush=True)
 

@@ -1,12 +1,14 @@
 """Statistical acceptance of the fitted boundary model of width H = 128 (the network the
-sampler runs fastest, used to place GMC against the analog walk in optically thick cells).
+sampler runs fastest, used to place GMC against the analog walk in optically thick cells; fitted
+on cells up to tau = 1000).
 
 Parity unpinned (a learned model): the reference is the FP64 oracle's analog walk (mode C) at
 the same entry condition, with the paper's integrator (classic RK4, 12 steps).  Budgets are the
-measured distances plus sampling noise; measured: face TV <= 0.016, KS cos <= 0.009, KS ln l
-<= 0.011, KS position <= 0.06 up to tau = 100 and <= 0.17 at tau = 300 (the reflection-position
-law of very thick cells is the loosest fit, for the H = 512 model as well: 0.15); E[l] within
-2.6 % of pi / 4 at tau = 10, 100, 300.
+measured distances plus sampling noise; measured: face TV <= 0.012, KS cos <= 0.011, KS ln l
+<= 0.014; KS position <= 0.06 up to tau = 100, <= 0.15 at tau = 300 and <= 0.36 at tau = 1000
+(the exit position of a reflection from a very thick cell is sharply peaked at the entry point,
+which the flow smears: the loosest fit, also for the H = 512 model, 0.15 at tau = 300); E[l]
+within 5 % of pi / 4 at tau = 10, 100, 300, 1000.
 """
 import math
 import os
@@ -42,10 +44,11 @@ def trained():
 
 @pytest.mark.parametrize("tau,c,y,s,pos_budget", [(10.0, 1.0, 0.3, 0.5, 0.1), (100.0, 1.0, 0.5, -0.3, 0.1),
                                                   (30.0, 0.95, 0.9, -0.8, 0.1), (300.0, 1.0, 0.5, 0.2, 0.2),
-                                                  (300.0, 0.99, 0.2, -0.6, 0.22)])
+                                                  (300.0, 0.99, 0.2, -0.6, 0.2), (1000.0, 1.0, 0.5, 0.0, 0.32),
+                                                  (1000.0, 0.999, 0.8, 0.5, 0.42)])
 def test_h128_exit_law_matches_the_walk(orc, trained, tau, c, y, s, pos_budget):
     binding, m = trained
-    n_g, n_o = 100_000, 50_000
+    n_g, n_o = 100_000, (20_000 if tau > 500 else 50_000)
     g = binding.gmc_sample(m, binding.DeviceCond.from_host(_fixed(n_g, tau, c, y, s)), "rk4", 12,
                            5).to_host()
     o = orc.mc_transmit(_fixed(n_o, tau, c, y, s), 0, seed=17, nthreads=8)
@@ -64,9 +67,9 @@ def test_h128_exit_law_matches_the_walk(orc, trained, tau, c, y, s, pos_budget):
 def test_h128_mean_chord_invariance(trained):
     # P3: E[path] = pi / 4 at c = 1 for every tau
     binding, m = trained
-    for tau in (10.0, 100.0, 300.0):
+    for tau in (10.0, 100.0, 300.0, 1000.0):
         cond = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(200_000, tau, 1.0, seed=3))
         g = binding.gmc_sample(m, cond, "rk4", 12, 9).to_host()
         rel = abs(g["path"].mean() - math.pi / 4) / (math.pi / 4)
         print(f"H=128 rk4x12 tau={tau}: E[path] = {g['path'].mean():.4f}")
-        assert rel < 0.035
+        assert rel < 0.065
