@@ -267,6 +267,45 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     return out
 
 
+def bench_thick_transport(binding, inputs, w128, n=50_000):
+    """Transport through optically thick, highly scattering media: 16 x 16 checkerboards of
+    (tau, c) = (100, 0.99) / (300, 0.999) and (300, 0.999) / (1000, 0.99), a central 2 x 2
+    volumetric source, 50,000 histories.  Analog MC (two seeds: the statistical floor) against
+    the fitted H = 128 model (BF16, RK4 x 12 and Euler K = 16).  Every step waits for its
+    longest walk in the analog runs, while the sampler's cost does not depend on tau."""
+    import torch
+    from paper_2512_13965_amd import transport
+    m = binding.Model(inputs.pack_blob(w128), "bf16")
+    out = {"histories": n}
+    l1 = lambda a, b: float(np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum())
+    for name, tau, c in (("checker16_tau100_300", (100.0, 300.0), (0.99, 0.999)),
+                         ("checker16_tau300_1000", (300.0, 1000.0), (0.999, 0.99))):
+        prob = inputs.checkerboard_problem(16, tau=tau, c=c, src=2)
+        world = binding.World(1 << 18, 1, 1 << 12)
+        res, runs = {}, {}
+        for rn, smp, mm, integ, K, seed in (("analog", binding.SAMPLER_MC, None, "euler", 16, 1),
+                                            ("analog_seed2", binding.SAMPLER_MC, None, "euler", 16, 2),
+                                            ("gmc_bf16_h128_rk4x12", binding.SAMPLER_GMC, m, "rk4", 12, 3),
+                                            ("gmc_bf16_h128_k16", binding.SAMPLER_GMC, m, "euler", 16, 3)):
+            transport.run_problem(world, prob, 2_000, 7, smp, mm, K, integrator=integ)      # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = transport.run_problem(world, prob, n, seed, smp, mm, K, integrator=integ)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            runs[rn] = r
+            res[rn] = {"seconds": dt, "steps": r["steps"], "transmissions_per_history": r["transmissions"] / n,
+                       "transmissions_per_s": r["transmissions"] / dt}
+        world.close()
+        for rn in ("gmc_bf16_h128_rk4x12", "gmc_bf16_h128_k16"):
+            res[rn]["flux_rel_l1_vs_mc"] = l1(runs[rn], runs["analog"])
+            res[rn]["speedup_vs_analog"] = res["analog"]["seconds"] / res[rn]["seconds"]
+        res["mc_noise_rel_l1"] = l1(runs["analog_seed2"], runs["analog"])
+        out[name] = res
+    m.close()
+    return out
+
+
 def bench_serving(binding, inputs, w512, n_req, w512_collided=None):
     """Continuous batching of a Poisson stream of transport requests of the config-3 kind
     (grids 16^2..128^2, per-cell tau log-uniform in [0.1, 200], c ~ U[0, 1]); histories per
@@ -572,6 +611,7 @@ def main():
                                                w512_collided=w5c, w512_xy_collided=w5cx,
                                                w512_rect_collided=w5cr)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c)
+        res["thick_transport"] = bench_thick_transport(binding, inputs, w1)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, K)
