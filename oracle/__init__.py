@@ -315,8 +315,15 @@ def decode(raw, xy: bool = False) -> dict:
     face if the norm is below 1e-6), its normal component reflected if it points into the
     cell; path = exp(a3).  In XY geometry (xy=True) the direction is a projection: it is kept
     when its norm is at most 1 and scaled to norm 1 otherwise.  Also returns per-sample flags:
-    bit0 pos clamped, bit1 direction reflected, bit2 zero-norm direction."""
+    bit0 pos clamped, bit1 direction reflected, bit2 zero-norm direction.
+
+    Eq. 11 is defined on the range of the targets (|a| <= 16: a0, a1, a2 in [-1, 1], a4 in
+    [-2, 2], ln path above about -16); a state with a component beyond 32 in magnitude, or not
+    finite, is rejected: face -1, the other fields 0, flags = 8 (bit3)."""
     raw = np.asarray(raw, np.float64)
+    with np.errstate(invalid="ignore"):
+        rejected = ~(np.abs(raw).max(axis=1) <= 32.0) | ~np.isfinite(raw).all(axis=1)
+    raw = np.where(rejected[:, None], 0.0, raw)
     a0, a1, a2, a3, a4 = (raw[:, i] for i in range(5))
     face = (a4 >= -1.0).astype(np.int32) + (a4 >= 0.0) + (a4 >= 1.0)
     p = (a0 + 1.0) / 2.0
@@ -337,4 +344,8 @@ def decode(raw, xy: bool = False) -> dict:
     v = np.where(inward, v - 2.0 * dn * nout[:, 1], v)
     flags |= inward.astype(np.int32) << 1
     flags |= small.astype(np.int32) << 2
-    return dict(face=face, pos=pos, u=u, v=v, len=np.exp(a3), flags=flags)
+    length = np.exp(a3)
+    face = np.where(rejected, -1, face).astype(np.int32)
+    pos, u, v, length = (np.where(rejected, 0.0, a) for a in (pos, u, v, length))
+    flags = np.where(rejected, 8, flags).astype(np.int32)
+    return dict(face=face, pos=pos, u=u, v=v, len=length, flags=flags)

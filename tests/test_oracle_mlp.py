@@ -182,3 +182,23 @@ def test_decode_cases(orc):
     np.testing.assert_allclose(d["v"], [0.0, 0.0, 0.0, -0.8, -0.8, 1.0, 1.0, 1.0], atol=1e-15)
     np.testing.assert_allclose(d["len"], np.exp([0.0, 1.0, -2.0, 0.0, 0.0, 0, 0, 0]))
     np.testing.assert_array_equal(d["flags"], [0, 3, 4, 0, 2, 0, 0, 0])
+
+
+def test_decode_rejects_states_outside_the_fitted_range(orc):
+    # a component of magnitude 32 is still decoded; beyond it, or not finite, the sample is
+    # rejected (face -1, fields 0, flag bit 3) whatever the other components
+    raw = np.array([
+        [0.0, 1.0, 0.0, 32.0, -0.2],
+        [0.0, 1.0, 0.0, -32.0, -0.2],
+        [0.0, 1.0, 0.0, 32.000004, -0.2],
+        [-40.0, 1.0, 0.0, 0.0, -0.2],
+        [0.0, 1.0, np.nan, 0.0, -0.2],
+        [0.0, 1.0, 0.0, np.inf, -0.2],
+        [0.0, 1.0, 0.0, 0.0, -np.inf],
+    ])
+    d = orc.decode(raw)
+    np.testing.assert_array_equal(d["face"], [1, 1, -1, -1, -1, -1, -1])
+    np.testing.assert_array_equal(d["flags"], [0, 0, 8, 8, 8, 8, 8])
+    np.testing.assert_allclose(d["len"][:2], np.exp([32.0, -32.0]))
+    for k in ("pos", "u", "v", "len"):
+        np.testing.assert_array_equal(d[k][2:], 0.0)
