@@ -94,7 +94,8 @@ typedef struct {
 } gmc_cond_internal;
 
 /* Exit records of n transmissions, device SoA, [n] each (paper eq. 11):
- *   face     int32 exit face 0..3 (GMC_FACE_* for walks that did not exit)
+ *   face     int32 exit face 0..3 (GMC_FACE_* for walks that did not exit; -1 also for a
+ *            generative sample whose network state left the decodable range, see gmc_transmit)
  *   pos      float32 counter-clockwise position along the exit face, [0, 1]
  *   dir_cos, dir_sin   float32 exit direction (unit vector, pointing out of the face)
  *   path     float32 total track length in the cell, units of L */
@@ -132,7 +133,11 @@ int gmc_model_inputs(const gmc_model *m, int *n_in);
  * the exit record is decoded from x_K (eq. 11: a0 = 2*pos - 1, (a1, a2) = direction,
  * a3 = ln path, face = number of thresholds -1, 0, 1 reached by a4; position clamped to
  * [0, 1]; direction normalised and its normal component reflected if it points into the
- * cell; outward normal if its norm is below 1e-6).
+ * cell; outward normal if its norm is below 1e-6).  A state x_K with a component beyond 32 in
+ * magnitude, or not finite, lies outside the range the targets span (|a| <= 16) and is
+ * rejected: face -1, the other fields 0 (a diverging trajectory, a few in 10^7 samples of the
+ * fitted H = 128 models; the transport step drops such a particle's weight into the cutoff
+ * tally).
  *   K          1..1024
  *   seed, id_base   particle i draws its noise from Philox4x32-10 with key = seed and
  *              counter (id lo, id hi, j, 1), j = 0, 1, id = id_base + i; Box-Muller pairs
@@ -203,7 +208,7 @@ int mc_transmit_internal(gmc_cond_internal cond, int64_t n, int mode, uint64_t s
 
 /* Decodes raw network outputs (device float32 [5][n]) into exit records with the rule of
  * gmc_transmit.  flags_opt: NULL or device int32 [n]: bit0 position clamped, bit1 direction
- * reflected, bit2 zero-norm direction. */
+ * reflected, bit2 zero-norm direction, bit3 (alone) rejected state. */
 int gmc_decode(const float *raw, int64_t n, gmc_exit out, int32_t *flags_opt, void *stream);
 
 /* ---------------------------------------------------------------------------------------- */

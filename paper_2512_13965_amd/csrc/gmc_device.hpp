@@ -191,9 +191,25 @@ struct Exit {
 
 // In XY geometry the exit direction is a projection: (a1, a2) is kept inside the unit disk
 // (scaled to norm 1 only when it lies outside) instead of being normalised.
+// Largest |x_d| of a decodable network state: the targets lie within |a| <= 16 (ln path of the
+// shortest tracks); a state beyond 32, or not finite, left the fitted range (a rare diverging
+// trajectory from the noise's far tail) and is rejected.
+constexpr float kDecodeMax = 32.0f;
+
 __device__ __forceinline__ int decode_exit(float a0, float a1, float a2, float a3, float a4, Exit &e,
                                            bool xy = false)
 {
+    const float amax = fmaxf(fmaxf(fmaxf(fabsf(a0), fabsf(a1)), fmaxf(fabsf(a2), fabsf(a3))), fabsf(a4));
+    const bool finite = (a0 - a0 == 0.0f) && (a1 - a1 == 0.0f) && (a2 - a2 == 0.0f) && (a3 - a3 == 0.0f) &&
+                        (a4 - a4 == 0.0f);
+    if (!finite || !(amax <= kDecodeMax)) {
+        e.face = -1;
+        e.pos = 0.0f;
+        e.u = 0.0f;
+        e.v = 0.0f;
+        e.path = 0.0f;
+        return 8;
+    }
     int flags = 0;
     const int face = (a4 >= -1.0f) + (a4 >= 0.0f) + (a4 >= 1.0f);
     float p = (a0 + 1.0f) * 0.5f;

@@ -20,6 +20,14 @@ def sample_indices(n, k, seed=0):
     return idx
 
 
+def drop_rejected(g, max_frac=1e-4):
+    """Exit records without the samples the decoder rejected (face -1: a network state outside
+    the decodable range), after checking that they are rare."""
+    ok = np.asarray(g["face"]) >= 0
+    assert (~ok).mean() <= max_frac, f"{(~ok).sum()} rejected samples"
+    return {k: np.asarray(v)[ok] for k, v in g.items()}
+
+
 def face_threshold_margin(a4):
     """Distance of a4 from the nearest face-decoding threshold (-1, 0, 1)."""
     return np.min(np.abs(np.asarray(a4)[:, None] - np.array([-1.0, 0.0, 1.0])[None, :]), axis=1)

@@ -215,6 +215,10 @@ def test_decode_kernel_matches_oracle(orc):
     raw = (g.standard_normal((5, n)) * np.array([[0.8], [1.0], [1.0], [1.5], [1.6]])).astype(np.float32)
     raw[1:3, :50] = 0.0                          # zero-norm directions
     raw[4, 50:60] = np.array([-1, 0, 1, -1, 0, 1, -1, 0, 1, -1], np.float32)   # exact thresholds
+    # states at and beyond the decodable range (|a| <= 32), and not finite: rejected samples
+    raw[3, 60:68] = np.array([32.0, -32.0, 32.000004, -40.0, np.nan, np.inf, -np.inf, 1e30], np.float32)
+    raw[0, 68] = np.nan
+    raw[4, 69] = 33.0
     flags = torch.empty(n, dtype=torch.int32, device="cuda")
     out = binding.gmc_decode(torch.from_numpy(raw.reshape(-1)).cuda(), n, flags=flags).to_host()
     d = orc.decode(raw.T.astype(np.float64))

@@ -147,12 +147,13 @@ def test_streaming_gives_the_histories_of_one_crossing_per_step(kind):
 def _floor_case(name):
     binding = require_gpu()
     from paper_2512_13965_amd import transport
-    cname = {"lattice_xy": "gmc_h512_xy_collided.bin", "lattice_rect": "gmc_h512_rect_collided.bin"}.get(
+    cname = {"lattice_xy": "gmc_h512_xy_collided.bin", "lattice_rect": "gmc_h512_rect_collided.bin",
+             "lattice_h128": "gmc_h128_collided.bin", "hohlraum_h128": "gmc_h128_collided.bin"}.get(
         name, "gmc_h512_collided.bin")
     cpath, ipath = os.path.join(WDIR, cname), os.path.join(WDIR, "gmc_h512_internal.bin")
     if not (os.path.exists(cpath) and os.path.exists(ipath)):
         pytest.skip("no fitted weights")
-    prob = inputs.hohlraum_problem(112) if name == "hohlraum" else \
+    prob = inputs.hohlraum_problem(112) if name.startswith("hohlraum") else \
         inputs.lattice_problem(16, 8 if name == "lattice_rect" else None)
     prob.xy = name == "lattice_xy"
     n = 100_000
@@ -170,7 +171,8 @@ def _floor_case(name):
     return n, mc1, mc2, gm
 
 
-@pytest.mark.parametrize("name", ["lattice", "hohlraum", "lattice_xy", "lattice_rect"])
+@pytest.mark.parametrize("name", ["lattice", "hohlraum", "lattice_xy", "lattice_rect", "lattice_h128",
+                                  "hohlraum_h128"])
 def test_split_transport_at_the_statistical_floor(name):
     n, mc1, mc2, gm = _floor_case(name)
     l1 = lambda a, b: np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum()

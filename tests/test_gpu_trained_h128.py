@@ -18,7 +18,7 @@ import pytest
 from scipy import stats
 
 from paper_2512_13965_amd import inputs
-from tests.gpu_util import require_gpu
+from tests.gpu_util import drop_rejected, require_gpu
 
 pytestmark = pytest.mark.gpu
 
@@ -49,10 +49,10 @@ def trained():
 def test_h128_exit_law_matches_the_walk(orc, trained, tau, c, y, s, pos_budget):
     binding, m = trained
     n_g, n_o = 100_000, (20_000 if tau > 500 else 50_000)
-    g = binding.gmc_sample(m, binding.DeviceCond.from_host(_fixed(n_g, tau, c, y, s)), "rk4", 12,
-                           5).to_host()
+    g = drop_rejected(binding.gmc_sample(m, binding.DeviceCond.from_host(_fixed(n_g, tau, c, y, s)), "rk4",
+                                         12, 5).to_host())
     o = orc.mc_transmit(_fixed(n_o, tau, c, y, s), 0, seed=17, nthreads=8)
-    fg = np.bincount(g["face"], minlength=4) / n_g
+    fg = np.bincount(g["face"], minlength=4) / len(g["face"])
     fo = np.bincount(o["face"], minlength=4) / n_o
     tv_face = 0.5 * np.abs(fg - fo).sum()
     ks_cos = stats.ks_2samp(g["dir_cos"], o["u"]).statistic
@@ -69,7 +69,7 @@ def test_h128_mean_chord_invariance(trained):
     binding, m = trained
     for tau in (10.0, 100.0, 300.0, 1000.0):
         cond = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(200_000, tau, 1.0, seed=3))
-        g = binding.gmc_sample(m, cond, "rk4", 12, 9).to_host()
+        g = drop_rejected(binding.gmc_sample(m, cond, "rk4", 12, 9).to_host())
         rel = abs(g["path"].mean() - math.pi / 4) / (math.pi / 4)
         print(f"H=128 rk4x12 tau={tau}: E[path] = {g['path'].mean():.4f}")
         assert rel < 0.065
