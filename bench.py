@@ -517,7 +517,7 @@ def main():
     # sampler's does not; 2^23 walks per launch at tau = 100, 300, 1000 against the fitted
     # samplers (BF16, H = 128 and 512) on 2^20 mixed-cell transmissions
     thick = {"analog_batch": NL, "analog_tps": {}}
-    for tau in (100.0, 300.0, 1000.0):
+    for tau in (100.0, 150.0, 200.0, 300.0, 500.0, 700.0, 1000.0):
         if tau == 100.0:
             thick["analog_tps"]["100"] = NL / (msL * 1e-3)
             continue
@@ -605,6 +605,21 @@ def main():
                  "bf16_h128_euler16": h128["euler16"]["tps"], "bf16_h128_rk4x12": h128["rk4x12"]["tps"]}
     thick["gmc_tps"] = gmc_rates
     thick["gmc_over_analog"] = {t: {k: v / a for k, v in gmc_rates.items()} for t, a in thick["analog_tps"].items()}
+    # tau*: where each sampler's rate meets the analog walk's (log-log interpolation between the
+    # measured tau; None if it stays below over the whole range)
+    taus = sorted(float(t) for t in thick["analog_tps"])
+    star = {}
+    for k, g in gmc_rates.items():
+        star[k] = None
+        for t0, t1 in zip(taus, taus[1:]):
+            a0, a1 = thick["analog_tps"][str(int(t0))], thick["analog_tps"][str(int(t1))]
+            if g < a0 and g >= a1:
+                f = math.log(a0 / g) / math.log(a0 / a1)
+                star[k] = math.exp(math.log(t0) + f * math.log(t1 / t0))
+                break
+        if star[k] is None and g >= thick["analog_tps"][str(int(taus[0]))]:
+            star[k] = taus[0]
+    thick["tau_star"] = star
     res["thick_cells"] = thick
     for s in sweep:
         s["gmc_bf16_h512_k16_tps"] = next(x["tps"] for x in wide if x["precision"] == "bf16"
