@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
     float lt = 0.f, c = 0.f, y = 0.f, s = 0.f, la = 0.f, ox = 0.f;
     uint64_t id = 0, key = 0;
     uint32_t nstream = 0;
-    bool e_face_ended = false;
+    bool ended = false;
     if (i < n) {
         int cell = b.cell[i];
         int e = b.entry[i];
@@ -441,7 +441,6 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
         uint32_t ev = b.event[i];
         const uint32_t hist = b.hist[i];
         const ProblemDev P = cd.prob[b.pid[i]];
-        bool ended = false;
         for (int it = 0;; ++it) {
             const int k = (e + 1) & 3;
             float U, V;
@@ -475,7 +474,7 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
             ++nstream;
             if (!nx.alive) {
                 e_face[i] = kFaceEnded;
-                ended = e_face_ended = true;
+                ended = true;
                 break;
             }
             cell = nx.cell;
@@ -498,7 +497,7 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
     }
     // crossings beyond the one per particle that the step counts (a history that ended here
     // finished its step's own crossing inside the loop)
-    uint32_t tot = nstream > 0 && e_face_ended ? nstream - 1 : nstream;
+    uint32_t tot = ended ? nstream - 1 : nstream;
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) tot += (uint32_t)__shfl_xor((int)tot, o);
     if (lane == 0 && tot > 0) atomicAdd(streamed, (unsigned long long)tot);

@@ -120,15 +120,16 @@ def test_transport_with_split_equals_the_walk_without_scattering(kind):
     assert gm["transmissions"] == mc["transmissions"] or abs(gm["transmissions"] / mc["transmissions"] - 1) < 1e-3
 
 
-@pytest.mark.parametrize("kind", ["square", "xy"])
+@pytest.mark.parametrize("kind", ["square", "xy", "rect", "reflect"])
 def test_streaming_gives_the_histories_of_one_crossing_per_step(kind):
     binding = require_gpu()
     from paper_2512_13965_amd import transport
-    n_in = inputs.N_IN if kind == "square" else inputs.N_IN_RECT
+    n_in = inputs.N_IN if kind in ("square", "reflect") else inputs.N_IN_RECT
     flags = 2 | (1 if kind == "xy" else 0)
     m = binding.Model(inputs.pack_blob(inputs.random_weights(128, 5, n_in=n_in, flags=flags)), "fp32")
-    prob = inputs.lattice_problem(4)
+    prob = inputs.lattice_problem(4, 6 if kind == "rect" else None)
     prob.xy = kind == "xy"
+    prob.reflect = kind == "reflect"
     n = 20_000
     w = binding.World(1 << 15, 1, 1 << 12)
     runs = {ff: transport.run_problem(w, prob, n, 9, binding.SAMPLER_GMC, m, 4, streaming=ff) for ff in (1, 3, 64)}
