@@ -272,6 +272,35 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     return out
 
 
+def bench_convergence(binding, inputs, w128_collided, Ns=(100_000, 200_000, 400_000, 800_000, 1_600_000,
+                                                           3_200_000), runs=5):
+    """Statistical convergence ("Convergence and Performance", eq. 12): the cell-averaged standard
+    deviation of the scalar flux over `runs` independent runs at each history count N, for
+    analog MC and GMC (the fitted H = 128 collided model, BF16, RK4 x 12, first-flight split,
+    analog first legs for births), on the lattice and the hohlraum at 112^2.  The paper's N
+    range is 1e5 .. 1.28e7; this one stops at 3.2e6 to keep the run short.  Reports sigma(N),
+    the log-log slope and sigma_GMC / sigma_MC."""
+    from paper_2512_13965_amd import transport
+    m = binding.Model(inputs.pack_blob(w128_collided), "bf16")
+    out = {"N": list(Ns), "runs": runs}
+    for pname, prob in (("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))):
+        world = binding.World(1 << 20, 1, 1 << 14)
+        res = {}
+        for kind, smp, mm in (("analog", binding.SAMPLER_MC, None), ("gmc_bf16_h128_rk4x12_split", binding.SAMPLER_GMC, m)):
+            sig = []
+            for N in Ns:
+                maps = np.array([transport.run_problem(world, prob, N, 5000 + 101 * k, smp, mm, 12,
+                                                       integrator="rk4")["flux"] / N for k in range(runs)])
+                sig.append(float(np.mean(maps.std(0, ddof=1))))
+            res[kind] = {"sigma": sig, "slope": float(np.polyfit(np.log(Ns), np.log(sig), 1)[0])}
+        res["sigma_ratio_gmc_over_mc"] = [g / a for g, a in zip(res["gmc_bf16_h128_rk4x12_split"]["sigma"],
+                                                                 res["analog"]["sigma"])]
+        world.close()
+        out[pname] = res
+    m.close()
+    return out
+
+
 def bench_thick_transport(binding, inputs, w128, n=50_000):
     """Transport through optically thick, highly scattering media: 16 x 16 checkerboards of
     (tau, c) = (100, 0.99) / (300, 0.999) and (300, 0.999) / (1000, 0.99), a central 2 x 2
@@ -634,6 +663,8 @@ def main():
                                                w512_rect_collided=w5cr, w128_collided=w1c)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c)
         res["thick_transport"] = bench_thick_transport(binding, inputs, w1)
+        if w1c is not None:
+            res["convergence"] = bench_convergence(binding, inputs, w1c)
 
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(H, K)

@@ -132,6 +132,37 @@ def test_eq12_error_decays_as_inverse_sqrt_n():
     assert abs(slope + 0.5) < 0.1
 
 
+def test_eq12_generative_transport_converges_like_mc():
+    # eq. 12 with the generative sampler ("Convergence and Performance": the GMC and MC curves of
+    # sigma(N) coincide): the fitted H = 128 collided model with the first-flight split on the
+    # paper's lattice decays as N^-1/2 with the analog runs' spread
+    binding = require_gpu()
+    import os
+    from paper_2512_13965_amd import transport
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2512_13965_amd",
+                        "weights", "gmc_h128_collided.bin")
+    if not os.path.exists(path):
+        pytest.skip("no fitted weights")
+    m = binding.Model(open(path, "rb").read(), "bf16")
+    prob = inputs.lattice_problem(16)
+    w = binding.World(1 << 18, 1, 1 << 14)
+    Ns = [20_000, 80_000, 320_000]
+    sig = {}
+    for kind, smp, mm in (("mc", binding.SAMPLER_MC, None), ("gmc", binding.SAMPLER_GMC, m)):
+        s = []
+        for N in Ns:
+            runs = np.array([transport.run_problem(w, prob, N, 3000 + 13 * k, smp, mm, 12, integrator="rk4")["flux"] / N
+                             for k in range(5)])
+            s.append(np.mean(runs.std(0, ddof=1)))
+        sig[kind] = np.array(s)
+    w.close()
+    m.close()
+    slopes = {k: np.polyfit(np.log(Ns), np.log(v), 1)[0] for k, v in sig.items()}
+    print("eq12 lattice sigma", sig, "slopes", slopes)
+    assert abs(slopes["gmc"] + 0.5) < 0.1 and abs(slopes["mc"] + 0.5) < 0.1
+    assert np.all(np.abs(sig["gmc"] / sig["mc"] - 1) < 0.1)
+
+
 def test_world_errors():
     binding = require_gpu()
     w = binding.World(1000, 1, 100)
