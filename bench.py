@@ -189,7 +189,7 @@ def bench_transport(binding, inputs, w512, w512_internal=None):
 
 def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512_rect=None, w512_xy=None,
                       w512_collided=None, w512_xy_collided=None, w512_rect_collided=None,
-                      w128_collided=None):
+                      w128_collided=None, w128_internal=None):
     """The paper's two benchmark problems at its mesh size and cross sections ("Benchmark
     Performance"; layouts defined by inputs.lattice_problem / inputs.hohlraum_problem): the
     7 x 7 cm lattice (112^2 cells, central volumetric source) and the 1.3 x 1.3 cm hohlraum
@@ -215,6 +215,7 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
     colxy = None if w512_xy_collided is None else binding.Model(inputs.pack_blob(w512_xy_collided), "bf16")
     colr = None if w512_rect_collided is None else binding.Model(inputs.pack_blob(w512_rect_collided), "bf16")
     col128 = None if w128_collided is None else binding.Model(inputs.pack_blob(w128_collided), "bf16")
+    src128 = None if w128_internal is None else binding.Model(inputs.pack_blob(w128_internal), "bf16")
     world = binding.World(1 << 20, 2, 1 << 14)
     problems = [("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))]
     if rect is not None:
@@ -239,6 +240,9 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
         if col128 is not None and prob.Ly == 0 and not prob.xy:
             runs.append(("gmc_bf16_h128_rk4x12_split", binding.SAMPLER_GMC, col128, 12, "rk4", None))
             runs.append(("gmc_bf16_h128_k16_split", binding.SAMPLER_GMC, col128, 16, "euler", None))
+            if src128 is not None and prob.src_face < 0:
+                runs.append(("gmc_bf16_h128_rk4x12_split_internal_births", binding.SAMPLER_GMC, col128, 12, "rk4",
+                             src128))
         if colxy is not None and prob.xy:
             runs.append(("gmc_bf16_h512_rk4x12_split", binding.SAMPLER_GMC, colxy, 12, "rk4", None))
         if colr is not None and prob.Ly > 0:
@@ -266,7 +270,7 @@ def bench_paper_scale(binding, inputs, w512, w512_internal=None, n=200_000, w512
         out[pname] = res
     world.close()
     model.close()
-    for mm in (src, rect, xym, col, colxy, colr, col128):
+    for mm in (src, rect, xym, col, colxy, colr, col128, src128):
         if mm is not None:
             mm.close()
     return out
@@ -579,6 +583,8 @@ def main():
     w5cx = inputs.load_blob(cxpath) if os.path.exists(cxpath) else None
     c128path = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h128_collided.bin")
     w1c = inputs.load_blob(c128path) if os.path.exists(c128path) else None
+    i128path = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h128_internal.bin")
+    w1i = inputs.load_blob(i128path) if os.path.exists(i128path) else None
     crpath = os.path.join(ROOT, "paper_2512_13965_amd", "weights", "gmc_h512_rect_collided.bin")
     w5cr = inputs.load_blob(crpath) if os.path.exists(crpath) else None
     condB = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
@@ -660,7 +666,7 @@ def main():
         res["transport"] = bench_transport(binding, inputs, w5t, w5i)
         res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i, w512_rect=w5r, w512_xy=w5x,
                                                w512_collided=w5c, w512_xy_collided=w5cx,
-                                               w512_rect_collided=w5cr, w128_collided=w1c)
+                                               w512_rect_collided=w5cr, w128_collided=w1c, w128_internal=w1i)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c)
         res["thick_transport"] = bench_thick_transport(binding, inputs, w1)
         if w1c is not None:

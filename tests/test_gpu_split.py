@@ -149,9 +149,11 @@ def _floor_case(name):
     binding = require_gpu()
     from paper_2512_13965_amd import transport
     cname = {"lattice_xy": "gmc_h512_xy_collided.bin", "lattice_rect": "gmc_h512_rect_collided.bin",
-             "lattice_h128": "gmc_h128_collided.bin", "hohlraum_h128": "gmc_h128_collided.bin"}.get(
+             "lattice_h128": "gmc_h128_collided.bin", "hohlraum_h128": "gmc_h128_collided.bin",
+             "lattice_h128_internal": "gmc_h128_collided.bin"}.get(
         name, "gmc_h512_collided.bin")
-    cpath, ipath = os.path.join(WDIR, cname), os.path.join(WDIR, "gmc_h512_internal.bin")
+    iname = "gmc_h128_internal.bin" if name == "lattice_h128_internal" else "gmc_h512_internal.bin"
+    cpath, ipath = os.path.join(WDIR, cname), os.path.join(WDIR, iname)
     if not (os.path.exists(cpath) and os.path.exists(ipath)):
         pytest.skip("no fitted weights")
     prob = inputs.hohlraum_problem(112) if name.startswith("hohlraum") else \
@@ -164,7 +166,8 @@ def _floor_case(name):
     mc1 = transport.run_problem(w, prob, n, 1, binding.SAMPLER_MC)
     mc2 = transport.run_problem(w, prob, n, 2, binding.SAMPLER_MC)
     gm = transport.run_problem(w, prob, n, 3, binding.SAMPLER_GMC, col, 12, integrator="rk4",
-                               source_model=src if prob.src_face < 0 and name == "lattice" else None,
+                               source_model=src if prob.src_face < 0 and name in ("lattice", "lattice_h128_internal")
+                               else None,
                                source_K=12)
     w.close()
     col.close()
@@ -173,7 +176,7 @@ def _floor_case(name):
 
 
 @pytest.mark.parametrize("name", ["lattice", "hohlraum", "lattice_xy", "lattice_rect", "lattice_h128",
-                                  "hohlraum_h128"])
+                                  "hohlraum_h128", "lattice_h128_internal"])
 def test_split_transport_at_the_statistical_floor(name):
     n, mc1, mc2, gm = _floor_case(name)
     l1 = lambda a, b: np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum()
