@@ -403,7 +403,7 @@ def main():
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: fp32 | bf16 | fp8 (sampler, "
                          "H=256 / 512 / 512, Euler K=16), rk4 (BF16 H=512, RK4 x 12) or "
-                         "walk:TAU (analog, 2^20 transmissions), transport (cfg3 checkerboard, "
+                         "walk:TAU[:LOG2N] (analog, 2^20 or 2^LOG2N transmissions), transport (cfg3 checkerboard, "
                          "2e5 analog histories per step), lattice_split (112^2 lattice, 2e5 "
                          "histories per step, first-flight split with the fitted collided model, "
                          "BF16 RK4 x 12)")
@@ -443,7 +443,9 @@ def main():
             w.close()
             N = 200_000
         else:
-            tau = float(args.profile.split(":")[1]) if ":" in args.profile else 100.0
+            parts = args.profile.split(":")
+            tau = float(parts[1]) if len(parts) > 1 else 100.0
+            N = (1 << int(parts[2])) if len(parts) > 2 else N        # walk:TAU:LOG2N
             c = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(N, tau, 1.0, 9))
             o = binding.DeviceExit.empty(N)
             for _ in range(args.steps):
