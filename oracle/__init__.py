@@ -66,7 +66,8 @@ def lib():
         L.orc_transport.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int]
+                                    ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int,
+                                    ctypes.c_uint32]
         _lib = L
     return _lib
 
@@ -157,6 +158,8 @@ def mc_transmit_internal(cond, mode: int, seed: int, id_base: int = 0, nthreads:
 
 def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -> dict:
     """FP64 cell-to-cell transport (analog mode-C walk in every cell, track-length tally).
+    A history still alive on reaching cell visit number problem.max_visits (0: 2^24; visit 0 is
+    a volumetric birth's cell, 1 a surface birth's) ends there with its weight as cutoff.
     Returns sums over the histories: flux[n_cells], absorbed[n_cells], leak, cutoff, events."""
     tau = np.ascontiguousarray(problem.tau, np.float64)
     c = np.ascontiguousarray(problem.c, np.float64)
@@ -168,7 +171,7 @@ def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -
                         problem.src_y0, problem.src_nx, problem.src_ny, int(problem.reflect),
                         int(getattr(problem, "src_face", -1)), int(getattr(problem, "xy", False)),
                         problem.w_min, seed, h_begin, h_end,
-                        _p(flux), _p(absorbed), _p(sc), nthreads)
+                        _p(flux), _p(absorbed), _p(sc), nthreads, int(getattr(problem, "max_visits", 0)))
     return dict(flux=flux, absorbed=absorbed, leak=sc[0], cutoff=sc[1], events=sc[2])
 
 

@@ -318,6 +318,8 @@ typedef struct {
     double w_min;               /* weight cutoff */
     int32_t src_face;           /* -1 volumetric source; 0..3 isotropic incident flux on that side */
     int32_t xy;                 /* 0 flatland, 1 XY geometry (directions on the sphere) */
+    uint32_t max_visits;        /* a history still alive on reaching this cell visit number ends
+                                 * there, its weight tallied as cutoff */
 } orc_problem;
 
 typedef struct {
@@ -435,6 +437,7 @@ static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tal
             ci = ni; cj = nj;
             cell = cj * p->nx + ci;
             event += 1;
+            if (event >= p->max_visits) { t->cutoff += w; return; }
         }
         entering = 0;
         /* stage 1: rotate into the canonical left-entry frame */
@@ -483,11 +486,13 @@ static void *tr_worker(void *arg)
 void orc_transport(int32_t nx, int32_t ny, double L, double Ly, const double *tau, const double *c,
                    int32_t src_x0, int32_t src_y0, int32_t src_nx, int32_t src_ny, int32_t reflect,
                    int32_t src_face, int32_t xy, double w_min, uint64_t seed, uint32_t h_begin,
-                   uint32_t h_end, double *flux, double *absorbed, double *out_scalars, int nthreads)
+                   uint32_t h_end, double *flux, double *absorbed, double *out_scalars, int nthreads,
+                   uint32_t max_visits)
 {
     if (!(Ly > 0.0)) Ly = L;                          /* square cells */
+    if (max_visits == 0) max_visits = 1u << 24;
     orc_problem p = {nx, ny, L, Ly, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face,
-                     xy ? 1 : 0};
+                     xy ? 1 : 0, max_visits};
     int ncell = nx * ny;
     if (nthreads < 1) nthreads = 1;
     if (nthreads > 256) nthreads = 256;

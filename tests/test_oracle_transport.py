@@ -149,3 +149,21 @@ def test_cell_to_cell_transport_matches_global_walk(orc, Ly, xy):
     se = np.sqrt(ref.var(0, ddof=1) / runs + got.var(0, ddof=1) / runs)
     z = np.abs(ref.mean(0) - got.mean(0)) / np.maximum(se, 1e-12)
     assert z.max() < 5.0, z
+
+
+def test_visit_cap_ends_histories_that_would_never_end(orc):
+    # a reflecting box without absorption keeps every history forever; with max_visits = M a
+    # volumetric birth is transmitted in visits 0 .. M-1 and then cut off: cutoff = n exactly,
+    # nothing absorbed or leaked, M transmissions per history
+    n, M = 2_000, 50
+    prob = inputs.homogeneous_problem(4, 1.0, 1.0, reflect=True)
+    prob.max_visits = M
+    o = orc.transport(prob, seed=3, h_begin=0, h_end=n, nthreads=4)
+    assert o["cutoff"] == pytest.approx(n, rel=1e-12)
+    assert o["leak"] == 0.0 and np.all(o["absorbed"] == 0.0)
+    assert o["events"] == M * n
+    # a larger cap gives each history more visits: the flux grows in proportion
+    prob.max_visits = 2 * M
+    o2 = orc.transport(prob, seed=3, h_begin=0, h_end=n, nthreads=4)
+    assert o2["events"] == 2 * M * n
+    assert 1.8 < o2["flux"].sum() / o["flux"].sum() < 2.2
