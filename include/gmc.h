@@ -233,7 +233,10 @@ typedef struct gmc_world gmc_world;
  * of a world share one geometry (GMC_EINVAL otherwise); the generative sampler then needs a
  * model of that geometry.  Boundaries are vacuum
  * (reflect = 0) or specular (reflect = 1).  A history ends when it leaves the domain or when its
- * weight drops below w_min after a cell visit (the weight is then tallied as cutoff).
+ * weight drops below w_min after a cell visit (the weight is then tallied as cutoff), and at the
+ * latest before its cell visit number max_visits (0: 2^24; otherwise at least 2), its weight
+ * then tallied as cutoff too: a bound for histories that would never end (a reflecting box
+ * without absorption).
  * Sources (one unit-weight particle per history):
  *   src_face = -1: isotropic volumetric source, uniform over the cells
  *     [src_x0, src_x0 + src_nx) x [src_y0, src_y0 + src_ny) (a birth picks the cell with the
@@ -259,6 +262,7 @@ typedef struct {
     int32_t src_face;
     double Ly;
     int32_t xy;
+    int64_t max_visits;
 } gmc_problem_desc;
 
 /* Device bytes gmc_world_create would allocate for these capacities (admission control). */

@@ -335,7 +335,8 @@ class _ProblemDesc(ctypes.Structure):
                 ("src_x0", ctypes.c_int32), ("src_y0", ctypes.c_int32),
                 ("src_nx", ctypes.c_int32), ("src_ny", ctypes.c_int32),
                 ("reflect", ctypes.c_int32), ("w_min", ctypes.c_double), ("seed", ctypes.c_uint64),
-                ("src_face", ctypes.c_int32), ("Ly", ctypes.c_double), ("xy", ctypes.c_int32)]
+                ("src_face", ctypes.c_int32), ("Ly", ctypes.c_double), ("xy", ctypes.c_int32),
+                ("max_visits", ctypes.c_int64)]
 
 
 def _transport_sigs(L):
@@ -387,7 +388,8 @@ class World:
         d = _ProblemDesc(problem.nx, problem.ny, problem.L, tau.ctypes.data, c.ctypes.data,
                          problem.src_x0, problem.src_y0, problem.src_nx, problem.src_ny,
                          int(problem.reflect), problem.w_min, seed, int(getattr(problem, "src_face", -1)),
-                         float(getattr(problem, "Ly", 0.0)), int(bool(getattr(problem, "xy", False))))
+                         float(getattr(problem, "Ly", 0.0)), int(bool(getattr(problem, "xy", False))),
+                         int(getattr(problem, "max_visits", 0)))
         pid = ctypes.c_int32()
         _check(self._L.gmc_problem_add(self._h, ctypes.byref(d), ctypes.byref(pid), _stream(stream)))
         self._shapes[pid.value] = problem.n_cells

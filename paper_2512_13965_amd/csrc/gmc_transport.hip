@@ -42,6 +42,7 @@ struct ProblemDev {
     uint64_t seed;
     int32_t src_face;              // -1 volumetric, else the domain side of a surface source
     int32_t xy;                    // XY geometry: directions on the sphere, projected
+    uint32_t max_visits;           // a history is cut off before its cell visit of this number
 };
 
 struct BankDev {
@@ -470,7 +471,11 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
             const double w_out = visit_tally_global(cd, P, cell, w, ex.path, (e & 1) ? P.Ly : P.L);
             float ngx, ngy;
             rot_quarter(k, ex.u, ex.v, ngx, ngy);
-            const Next nx = move_on(cd, P, cell, (ex.face + k) & 3, ex.pos, ngx, ngy, w_out);
+            Next nx = move_on(cd, P, cell, (ex.face + k) & 3, ex.pos, ngx, ngy, w_out);
+            if (nx.alive && ev + 1 >= P.max_visits) {
+                atomicAdd(&cd.cutoff[cell], w_out);
+                nx.alive = false;
+            }
             ++nstream;
             if (!nx.alive) {
                 e_face[i] = kFaceEnded;
@@ -570,6 +575,10 @@ __global__ __launch_bounds__(256) void apply_kernel(BankDev in, int64_t n_arg,
         float gx, gy;
         rot_quarter(k, dcos[i], dsin[i], gx, gy);
         nx = move_on(cd, P, cell, fc >= 0 ? (fc + k) & 3 : fc, pos[i], gx, gy, w_out);
+        if (nx.alive && event >= P.max_visits) {
+            atomicAdd(&cd.cutoff[cell], w_out);
+            nx.alive = false;
+        }
         alive = nx.alive;
     }
     append(alive, nx, pid, w_out, hist, event, out, counter, pcount);
@@ -824,6 +833,8 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     const double Ly = d->Ly > 0.0 ? d->Ly : d->L;
     if (d->xy != 0 && d->xy != 1)
         return set_error(GMC_EINVAL, "gmc_problem_add: xy must be 0 (flatland) or 1 (XY geometry)");
+    if (d->max_visits != 0 && (d->max_visits < 2 || d->max_visits > ((int64_t)1 << 31)))
+        return set_error(GMC_EINVAL, "gmc_problem_add: max_visits must be 0 (2^24) or in 2..2^31");
     if (d->src_face < -1 || d->src_face > 3)
         return set_error(GMC_EINVAL, "gmc_problem_add: src_face must be -1 (volumetric) or a side 0..3");
     if (d->src_face >= 0) {
@@ -864,8 +875,10 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
         lt[i] = d->tau[i] > 0.0 ? (float)std::log(d->tau[i]) : -1.0e4f;
         cf[i] = (float)d->c[i];
     }
+    const uint32_t max_visits = d->max_visits == 0 ? (1u << 24) : (uint32_t)d->max_visits;
     ProblemDev P{d->nx, d->ny, d->L, Ly, (float)std::log(Ly / d->L), cell0, d->src_x0, d->src_y0,
-                 d->src_nx, d->src_ny, d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face, d->xy ? 1 : 0};
+                 d->src_nx, d->src_ny, d->reflect ? 1 : 0, d->w_min, d->seed, d->src_face, d->xy ? 1 : 0,
+                 max_visits};
     hipStream_t s = (hipStream_t)stream;
     hipError_t e = hipMemcpyAsync(w->tau + cell0, d->tau, 8 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(w->c + cell0, d->c, 8 * n, hipMemcpyHostToDevice, s);

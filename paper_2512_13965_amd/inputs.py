@@ -323,6 +323,7 @@ class Problem:
     src_face: int = -1
     Ly: float = 0.0
     xy: bool = False          # XY geometry: directions on the sphere (eq. 1), invariant along z
+    max_visits: int = 0       # a history is cut off before this cell visit number (0: 2^24)
 
     @property
     def n_cells(self) -> int:

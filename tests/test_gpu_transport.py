@@ -182,3 +182,38 @@ def test_world_errors():
         n = w.step(binding.SAMPLER_MC)
     w.remove(pid)
     w.close()
+
+
+def test_visit_cap_matches_oracle_and_ends_every_history(orc):
+    # a reflecting box without absorption: every history runs into the visit cap (visits
+    # 0 .. M-1, the birth leg in inject and M - 1 transmissions in steps) and is cut off
+    binding = require_gpu()
+    from paper_2512_13965_amd import transport
+    n, M = 20_000, 50
+    prob = inputs.homogeneous_problem(4, 1.0, 1.0, reflect=True)
+    prob.max_visits = M
+    w = binding.World(1 << 15, 1, 1 << 8)
+    g = transport.run_problem(w, prob, n, 3, binding.SAMPLER_MC)
+    o = orc.transport(prob, seed=3, h_begin=0, h_end=n, nthreads=8)
+    rel = np.abs(g["flux"] - o["flux"]).sum() / np.abs(o["flux"]).sum()
+    print(f"visit cap: flux L1 rel diff {rel:.2e}, steps {g['steps']}")
+    assert rel < 5e-5
+    assert g["cutoff"].sum() == pytest.approx(n, rel=1e-12) and g["leak"].sum() == 0.0
+    assert g["transmissions"] == (M - 1) * n
+    # the same cap inside the split's streamed crossings: a thin non-scattering medium, so every
+    # crossing is uncollided and the split step equals the walk step
+    prob2 = inputs.homogeneous_problem(4, 1e-3, 0.0, reflect=True)
+    prob2.max_visits = M
+    m = binding.Model(inputs.pack_blob(inputs.random_weights(128, 5, flags=2)), "fp32")
+    g1 = transport.run_problem(w, prob2, n, 4, binding.SAMPLER_MC)
+    g2 = transport.run_problem(w, prob2, n, 4, binding.SAMPLER_GMC, m, 4)
+    w.close()
+    m.close()
+    for r in (g1, g2):
+        # the thin absorber takes a few per cent; the cap takes the rest, nothing leaks
+        assert r["cutoff"].sum() + r["absorbed"].sum() == pytest.approx(n, rel=1e-9)
+        assert r["leak"].sum() == 0.0 and r["cutoff"].sum() > 0.9 * n
+        assert r["transmissions"] == (M - 1) * n
+    assert g2["cutoff"].sum() == pytest.approx(g1["cutoff"].sum(), rel=1e-6)
+    assert np.abs(g2["flux"] - g1["flux"]).sum() / np.abs(g1["flux"]).sum() < 1e-6
+    assert g2["steps"] < g1["steps"]
