@@ -305,15 +305,18 @@ def bench_convergence(binding, inputs, w128_collided, Ns=(100_000, 200_000, 400_
     return out
 
 
-def bench_thick_transport(binding, inputs, w128, n=50_000):
+def bench_thick_transport(binding, inputs, w128, n=50_000, w128_internal=None):
     """Transport through optically thick, highly scattering media: 16 x 16 checkerboards of
     (tau, c) = (100, 0.99) / (300, 0.999) and (300, 0.999) / (1000, 0.99), a central 2 x 2
     volumetric source, 50,000 histories.  Analog MC (two seeds: the statistical floor) against
-    the fitted H = 128 model (BF16, RK4 x 12 and Euler K = 16).  Every step waits for its
-    longest walk in the analog runs, while the sampler's cost does not depend on tau."""
+    the fitted H = 128 model (BF16, RK4 x 12 and Euler K = 16; births by the analog first leg,
+    and with the internal model also by the H = 128 internal model).  Every step waits for its
+    longest walk in the analog runs (the analog births too), while the sampler's cost does not
+    depend on tau."""
     import torch
     from paper_2512_13965_amd import transport
     m = binding.Model(inputs.pack_blob(w128), "bf16")
+    src = None if w128_internal is None else binding.Model(inputs.pack_blob(w128_internal), "bf16")
     out = {"histories": n}
     l1 = lambda a, b: float(np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum())
     for name, tau, c in (("checker16_tau100_300", (100.0, 300.0), (0.99, 0.999)),
@@ -321,26 +324,32 @@ def bench_thick_transport(binding, inputs, w128, n=50_000):
         prob = inputs.checkerboard_problem(16, tau=tau, c=c, src=2)
         world = binding.World(1 << 18, 1, 1 << 12)
         res, runs = {}, {}
-        for rn, smp, mm, integ, K, seed in (("analog", binding.SAMPLER_MC, None, "euler", 16, 1),
-                                            ("analog_seed2", binding.SAMPLER_MC, None, "euler", 16, 2),
-                                            ("gmc_bf16_h128_rk4x12", binding.SAMPLER_GMC, m, "rk4", 12, 3),
-                                            ("gmc_bf16_h128_k16", binding.SAMPLER_GMC, m, "euler", 16, 3)):
-            transport.run_problem(world, prob, 2_000, 7, smp, mm, K, integrator=integ)      # warm-up
+        cases = [("analog", binding.SAMPLER_MC, None, "euler", 16, 1, None),
+                 ("analog_seed2", binding.SAMPLER_MC, None, "euler", 16, 2, None),
+                 ("gmc_bf16_h128_rk4x12", binding.SAMPLER_GMC, m, "rk4", 12, 3, None),
+                 ("gmc_bf16_h128_k16", binding.SAMPLER_GMC, m, "euler", 16, 3, None)]
+        if src is not None:
+            cases.append(("gmc_bf16_h128_rk4x12_internal_births", binding.SAMPLER_GMC, m, "rk4", 12, 3, src))
+        for rn, smp, mm, integ, K, seed, sm in cases:
+            kw = dict(integrator=integ, source_model=sm, source_K=K)
+            transport.run_problem(world, prob, 2_000, 7, smp, mm, K, **kw)      # warm-up
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = transport.run_problem(world, prob, n, seed, smp, mm, K, integrator=integ)
+            r = transport.run_problem(world, prob, n, seed, smp, mm, K, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             runs[rn] = r
             res[rn] = {"seconds": dt, "steps": r["steps"], "transmissions_per_history": r["transmissions"] / n,
                        "transmissions_per_s": r["transmissions"] / dt}
         world.close()
-        for rn in ("gmc_bf16_h128_rk4x12", "gmc_bf16_h128_k16"):
+        for rn in [c[0] for c in cases if c[0].startswith("gmc")]:
             res[rn]["flux_rel_l1_vs_mc"] = l1(runs[rn], runs["analog"])
             res[rn]["speedup_vs_analog"] = res["analog"]["seconds"] / res[rn]["seconds"]
         res["mc_noise_rel_l1"] = l1(runs["analog_seed2"], runs["analog"])
         out[name] = res
     m.close()
+    if src is not None:
+        src.close()
     return out
 
 
@@ -406,7 +415,9 @@ def main():
                          "walk:TAU[:LOG2N] (analog, 2^20 or 2^LOG2N transmissions), transport (cfg3 checkerboard, "
                          "2e5 analog histories per step), lattice_split (112^2 lattice, 2e5 "
                          "histories per step, first-flight split with the fitted collided model, "
-                         "BF16 RK4 x 12)")
+                         "BF16 RK4 x 12), thick (16^2 checkerboard tau = 300/1000, c = 0.999/0.99, "
+                         "2e4 histories per step: one analog run, one GMC run with the fitted H = 128 "
+                         "model, BF16 RK4 x 12)")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -431,6 +442,17 @@ def main():
             for _ in range(args.steps):
                 transport.run_problem(w, inputs.checkerboard_problem(32), 200_000, 1, binding.SAMPLER_MC)
             w.close()
+        elif kind == "thick":
+            from paper_2512_13965_amd import transport
+            wdir = os.path.join(ROOT, "paper_2512_13965_amd", "weights")
+            m = binding.Model(open(os.path.join(wdir, "gmc_h128.bin"), "rb").read(), "bf16")
+            w = binding.World(1 << 18, 1, 1 << 12)
+            prob = inputs.checkerboard_problem(16, tau=(300.0, 1000.0), c=(0.999, 0.99), src=2)
+            for _ in range(args.steps):
+                transport.run_problem(w, prob, 20_000, 1, binding.SAMPLER_MC)
+                transport.run_problem(w, prob, 20_000, 3, binding.SAMPLER_GMC, m, 12, integrator="rk4")
+            w.close()
+            N = 20_000
         elif kind == "lattice_split":
             from paper_2512_13965_amd import transport
             wdir = os.path.join(ROOT, "paper_2512_13965_amd", "weights")
@@ -670,7 +692,7 @@ def main():
                                                w512_collided=w5c, w512_xy_collided=w5cx,
                                                w512_rect_collided=w5cr, w128_collided=w1c, w128_internal=w1i)
         res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c)
-        res["thick_transport"] = bench_thick_transport(binding, inputs, w1)
+        res["thick_transport"] = bench_thick_transport(binding, inputs, w1, w128_internal=w1i)
         if w1c is not None:
             res["convergence"] = bench_convergence(binding, inputs, w1c)
 

@@ -23,8 +23,8 @@ x0 ~ N(0, I), t ~ U[0, 1].  The fit itself is offline PyTorch (autograd), not th
 Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_amd/weights/gmc_h512.bin
        python -m paper_2512_13965_amd.train --hidden 128 --steps 150000 --data 8000000 \
            --tau-max 1000 --out paper_2512_13965_amd/weights/gmc_h128.bin
-       (width 128 likewise: --model collided -> gmc_h128_collided.bin, --model internal ->
-        gmc_h128_internal.bin, both with --steps 150000 --data 8000000)
+       (width 128 likewise, --steps 150000 --data 8000000: --model collided ->
+        gmc_h128_collided.bin; --model internal --tau-max 1000 -> gmc_h128_internal.bin)
        python -m paper_2512_13965_amd.train --model internal --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_internal.bin
        python -m paper_2512_13965_amd.train --model rect --hidden 512 \
