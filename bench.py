@@ -353,15 +353,17 @@ def bench_thick_transport(binding, inputs, w128, n=50_000, w128_internal=None):
     return out
 
 
-def bench_serving(binding, inputs, w512, n_req, w512_collided=None):
+def bench_serving(binding, inputs, w512, n_req, w512_collided=None, w128_collided=None):
     """Continuous batching of a Poisson stream of transport requests of the config-3 kind
     (grids 16^2..128^2, per-cell tau log-uniform in [0.1, 200], c ~ U[0, 1]); histories per
     request log-uniform in [1e4, 10^5.5] (scaled down from 1e4..1e7 so the stream completes in
     tens of seconds); generative sampler BF16, H = 512, K = 16.  With the collided model, the
-    same stream (same arrivals) also with the first-flight split."""
+    same stream (same arrivals) also with the first-flight split (H = 512, and the H = 128
+    collided model)."""
     from paper_2512_13965_amd import serving
     model = binding.Model(inputs.pack_blob(w512), "bf16")
     col = None if w512_collided is None else binding.Model(inputs.pack_blob(w512_collided), "bf16")
+    col128 = None if w128_collided is None else binding.Model(inputs.pack_blob(w128_collided), "bf16")
     world = binding.World(1 << 20, 16, 1 << 18)
     make = lambda i: inputs.random_problem(1000 + i, hist_log10_range=(4.0, 5.5))
 
@@ -385,10 +387,17 @@ def bench_serving(binding, inputs, w512, n_req, w512_collided=None):
                  "wall_s": sp.wall, "steps": sp.steps,
                  "model": "collided-only BF16 H=512 K=16, uncollided crossings streamed in steps"}
         col.close()
+    split128 = None
+    if col128 is not None:
+        sp = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make), m=col128)
+        split128 = {"latency_s": sp.latency_percentiles((50, 90, 99)), "transmissions_per_s": sp.throughput,
+                    "wall_s": sp.wall, "steps": sp.steps,
+                    "model": "collided-only BF16 H=128 K=16, uncollided crossings streamed in steps"}
+        col128.close()
     model.close()
     world.close()
     lat = st.latency_percentiles((50, 90, 99))
-    return {"first_flight_split": split,"requests": len(st.requests), "capacity_req_per_s": capacity_hz,
+    return {"first_flight_split": split, "first_flight_split_h128": split128,"requests": len(st.requests), "capacity_req_per_s": capacity_hz,
             "arrival_rate_hz": rate, "wall_s": st.wall, "steps": st.steps,
             "transmissions": st.transmissions, "transmissions_per_s": st.throughput,
             "latency_s": lat, "histories": int(sum(r.n_hist for r in st.requests)),
@@ -691,7 +700,7 @@ def main():
         res["paper_scale"] = bench_paper_scale(binding, inputs, w5t, w5i, w512_rect=w5r, w512_xy=w5x,
                                                w512_collided=w5c, w512_xy_collided=w5cx,
                                                w512_rect_collided=w5cr, w128_collided=w1c, w128_internal=w1i)
-        res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c)
+        res["serving"] = bench_serving(binding, inputs, w5t, args.serve_requests, w5c, w1c)
         res["thick_transport"] = bench_thick_transport(binding, inputs, w1, w128_internal=w1i)
         if w1c is not None:
             res["convergence"] = bench_convergence(binding, inputs, w1c)
