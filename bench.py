@@ -317,7 +317,11 @@ def bench_thick_transport(binding, inputs, w128, n=50_000, w128_internal=None):
     from paper_2512_13965_amd import transport
     m = binding.Model(inputs.pack_blob(w128), "bf16")
     src = None if w128_internal is None else binding.Model(inputs.pack_blob(w128_internal), "bf16")
-    out = {"histories": n}
+    out = {"histories": n,
+           "note": "the analog runs keep the transport algorithm's stage structure (one whole cell "
+                   "transmission per particle per step, births' first legs walked to the end), so a "
+                   "step lasts as long as its longest walk; thick_cells holds the kernel-level ratios "
+                   "free of that effect"}
     l1 = lambda a, b: float(np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum())
     for name, tau, c in (("checker16_tau100_300", (100.0, 300.0), (0.99, 0.999)),
                          ("checker16_tau300_1000", (300.0, 1000.0), (0.999, 0.99))):
