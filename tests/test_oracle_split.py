@@ -55,3 +55,19 @@ def test_uncollided_exits_are_ray_exits_and_xy_keeps_the_direction(orc):
     np.testing.assert_array_equal(sp["face"], np.where(tx <= ty, 1, np.where(v > 0, 2, 0)))
     np.testing.assert_array_equal(sp["u"], u)
     np.testing.assert_array_equal(sp["v"], v)
+
+
+@pytest.mark.parametrize("tau,c", [(0.3, 1.0), (2.0, 0.5), (5.0, 0.2)])
+def test_normal_incidence_uncollided_fraction_is_exp_minus_c_tau(orc, tau, c):
+    # entering along the normal, every ray crosses the unit cell in d_b = 1: the uncollided
+    # fraction is exp(-c tau) (flights of rate c tau, eq. 4) and every uncollided exit is the
+    # opposite face at the entry height
+    n = 200_000
+    cond = inputs.fixed_cell_conditions(n, tau, c, seed=14)
+    cond.sin_th[:] = 0.0
+    sp = orc.uncollided_split(cond, seed=7)
+    p = math.exp(-c * tau)
+    assert abs(sp["flag"].mean() - p) < 4.5 * math.sqrt(p * (1 - p) / n)
+    np.testing.assert_array_equal(sp["face"], 1)
+    np.testing.assert_allclose(sp["pos"], cond.y_in.astype(np.float64), atol=1e-7)
+    np.testing.assert_allclose(sp["len"], 1.0, rtol=1e-12)
