@@ -241,24 +241,40 @@ def condition_features(cond) -> np.ndarray:
     return np.stack(cols, axis=1)
 
 
+def layer_affine(weights, l: int, h, precision=PREC_FP64):
+    """Affine part W_l h + b_l of layer l (0-based) of the velocity network for a batch
+    h [n, in] -> [n, out], with the operand rounding of `precision` (paper "Conditional Flow
+    Matching", eq. 8, evaluated in reduced precision; the reading of the quantised network):
+      * PREC_FP64: no rounding.
+      * PREC_BF16: the layer input h and the weights W_l are rounded to bfloat16 (to nearest,
+        ties to even); the products are summed exactly (FP64 here, FP32 on the matrix core);
+        the bias b_l is added unrounded (its float32 value).
+      * PREC_FP8: the hidden H x H layers (0 < l < last) take e4m3 operands: h divided by the
+        layer's activation scale sa and W_l by its weight scale sw (both powers of two), each
+        rounded to e4m3 (to nearest, ties to even, saturating at +-448); the exact sum of the
+        products is multiplied by sa * sw and the unrounded bias added.  The first and the last
+        layer are BF16 as above."""
+    W = weights.W[l].astype(np.float64)
+    b = weights.b[l].astype(np.float64)
+    last = len(weights.W) - 1
+    if precision == PREC_BF16 or (precision == PREC_FP8 and not 0 < l < last):
+        return round_bf16(h) @ round_bf16(W).T + b
+    if precision == PREC_FP8:
+        sa = float(weights.act_scale[l])
+        sw = float(weights.w_scale[l])
+        return (round_e4m3(h / sa) @ round_e4m3(W / sw).T) * (sa * sw) + b
+    return h @ W.T + b
+
+
 def velocity(weights, x, t, condf, precision=PREC_FP64):
     """v_theta(x, t | c) for a batch: x [n,5], t scalar, condf [n,4] -> [n,5].
-    Layers: Linear(10,H) SiLU, 3 x (Linear(H,H) SiLU), Linear(H,5)."""
+    Layers: Linear(10,H) SiLU, 3 x (Linear(H,H) SiLU), Linear(H,5); the input of the first
+    layer is [x, t, condition]."""
     n = x.shape[0]
     h = np.concatenate([x, np.full((n, 1), float(t)), condf], axis=1)
     L = len(weights.W)
     for l in range(L):
-        W = weights.W[l].astype(np.float64)
-        b = weights.b[l].astype(np.float64)
-        hidden_hh = 0 < l < L - 1
-        if precision == PREC_BF16 or (precision == PREC_FP8 and not hidden_hh):
-            h = round_bf16(h) @ round_bf16(W).T + b
-        elif precision == PREC_FP8:
-            sa = float(weights.act_scale[l])
-            sw = float(weights.w_scale[l])
-            h = (round_e4m3(h / sa) @ round_e4m3(W / sw).T) * (sa * sw) + b
-        else:
-            h = h @ W.T + b
+        h = layer_affine(weights, l, h, precision)
         if l < L - 1:
             h = silu(h)
     return h
