@@ -334,6 +334,20 @@ int gmc_problem_alive(const gmc_world *w, int32_t pid, int64_t *n_alive);
  * Synchronises `stream`. */
 int gmc_problem_tally(gmc_world *w, int32_t pid, double *flux, double *absorbed, double *leak,
                       double *cutoff, void *stream);
+/* Copies problem pid's FP64 path tallies (paper "Transport Algorithm", third stage: the physical
+ * track length of every cell visit, the quantity the flux estimator of eqs. 5-7 integrates),
+ * summed over its histories so far, to host arrays of nx * ny doubles (any pointer may be NULL):
+ *   wpath       sum over the visits of the cell of w_in * l_phys (entry weight times the visit's
+ *               physical track length)
+ *   path        sum of l_phys
+ *   visits      number of visits (births' first legs, transmissions and crossings streamed by the
+ *               first-flight split alike; exact up to 2^53)
+ *   rejected_w  weight of the particles whose generative sample the decoder rejected in the cell
+ *               (a part of the cutoff tally; see gmc_transmit)
+ *   rejected_n  number of such rejections
+ * Synchronises `stream`.  GMC_EINVAL for an unknown problem. */
+int gmc_problem_path_tally(gmc_world *w, int32_t pid, double *wpath, double *path, double *visits,
+                           double *rejected_w, double *rejected_n, void *stream);
 
 /* Device diagnostic, not part of the paper's method: measures the sustained matrix-core
  * throughput (TFLOP/s, dense) of the MFMA instruction the sampler uses for `precision`

@@ -67,7 +67,7 @@ def lib():
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                     ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P, P, ctypes.c_int,
-                                    ctypes.c_uint32]
+                                    ctypes.c_uint32, P]
         _lib = L
     return _lib
 
@@ -160,19 +160,23 @@ def transport(problem, seed: int, h_begin: int, h_end: int, nthreads: int = 1) -
     """FP64 cell-to-cell transport (analog mode-C walk in every cell, track-length tally).
     A history still alive on reaching cell visit number problem.max_visits (0: 2^24; visit 0 is
     a volumetric birth's cell, 1 a surface birth's) ends there with its weight as cutoff.
-    Returns sums over the histories: flux[n_cells], absorbed[n_cells], leak, cutoff, events."""
+    Returns sums over the histories: flux[n_cells], absorbed[n_cells], leak, cutoff, events, and
+    the path tallies wpath (w_in * l), path (l) and visits [n_cells] (track length of every cell
+    visit, "Transport Algorithm" third stage)."""
     tau = np.ascontiguousarray(problem.tau, np.float64)
     c = np.ascontiguousarray(problem.c, np.float64)
     flux = np.zeros(problem.n_cells)
     absorbed = np.zeros(problem.n_cells)
     sc = np.zeros(3)
+    pt = np.zeros((3, problem.n_cells))
     lib().orc_transport(problem.nx, problem.ny, problem.L, float(getattr(problem, "Ly", 0.0)),
                         _p(tau), _p(c), problem.src_x0,
                         problem.src_y0, problem.src_nx, problem.src_ny, int(problem.reflect),
                         int(getattr(problem, "src_face", -1)), int(getattr(problem, "xy", False)),
                         problem.w_min, seed, h_begin, h_end,
-                        _p(flux), _p(absorbed), _p(sc), nthreads, int(getattr(problem, "max_visits", 0)))
-    return dict(flux=flux, absorbed=absorbed, leak=sc[0], cutoff=sc[1], events=sc[2])
+                        _p(flux), _p(absorbed), _p(sc), nthreads, int(getattr(problem, "max_visits", 0)), _p(pt))
+    return dict(flux=flux, absorbed=absorbed, leak=sc[0], cutoff=sc[1], events=sc[2], wpath=pt[0], path=pt[1],
+                visits=pt[2])
 
 
 # ----------------------------------------------------------------------------------------
@@ -368,3 +372,271 @@ def decode(raw, xy: bool = False) -> dict:
     pos, u, v, length = (np.where(rejected, 0.0, a) for a in (pos, u, v, length))
     flags = np.where(rejected, 8, flags).astype(np.int32)
     return dict(face=face, pos=pos, u=u, v=v, len=length, flags=flags)
+
+
+# ----------------------------------------------------------------------------------------
+# transport composition with a pluggable second stage (paper "Transport Algorithm", stages
+# 1-4): the analog walk or the generative sampler (network of eq. 8 + decoding of eq. 11)
+# ----------------------------------------------------------------------------------------
+
+def _setup_composition(L):
+    P = ctypes.c_void_p
+    if getattr(L, "_composition_ready", False):
+        return
+    L.orc_noise_ids.argtypes = [ctypes.c_uint64, P, ctypes.c_int64, P]
+    L.orc_walk_ids.argtypes = [P, P, P, P, P, P, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, P,
+                               P, P, P, P, P]
+    L.orc_split_ids.argtypes = [P, P, P, P, P, P, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, P,
+                                P, P, P, P, P, P, P]
+    L.orc_birth_states.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double, P, P,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                   ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, P, P, P, P, P]
+    L._composition_ready = True
+
+
+def noise_ids(seed: int, ids) -> np.ndarray:
+    """z ~ N(0, I_5) of the random streams ids (Philox + Box-Muller, as `noise`), [5][n]."""
+    L = lib()
+    _setup_composition(L)
+    ids = np.ascontiguousarray(ids, np.uint64)
+    z = np.zeros((5, ids.size))
+    L.orc_noise_ids(seed, _p(ids), ids.size, _p(z))
+    return z
+
+
+def _canon_arrays(cond):
+    f = lambda a: np.ascontiguousarray(a, np.float64)
+    return [f(cond["tau"]), f(cond["c"]), f(cond["y_in"]), f(cond["u"]), f(cond["sin_th"]), f(cond["aspect"])]
+
+
+def walk_ids(cond, seed: int, ids, xy: bool) -> dict:
+    """Mode-C analog walks of canonical transmissions with FP64 conditions (dict with tau, c,
+    y_in, u, sin_th, aspect) and random streams ids."""
+    L = lib()
+    _setup_composition(L)
+    ids = np.ascontiguousarray(ids, np.uint64)
+    n = ids.size
+    arrs = _canon_arrays(cond)
+    out = dict(face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n), v=np.zeros(n), len=np.zeros(n))
+    L.orc_walk_ids(*(_p(a) for a in arrs), int(xy), n, seed, _p(ids), _p(out["face"]), _p(out["pos"]),
+                   _p(out["u"]), _p(out["v"]), _p(out["len"]))
+    return out
+
+
+def split_ids(cond, seed: int, ids, xy: bool) -> dict:
+    """First-flight split (uncollided_split) of canonical transmissions with FP64 conditions and
+    random streams ids; also `margin` = |xi - exp(-c tau d_b)| of each decision."""
+    L = lib()
+    _setup_composition(L)
+    ids = np.ascontiguousarray(ids, np.uint64)
+    n = ids.size
+    arrs = _canon_arrays(cond)
+    out = dict(flag=np.zeros(n, np.int32), face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n),
+               v=np.zeros(n), len=np.zeros(n), margin=np.zeros(n))
+    L.orc_split_ids(*(_p(a) for a in arrs), int(xy), n, seed, _p(ids), _p(out["flag"]), _p(out["face"]),
+                    _p(out["pos"]), _p(out["u"]), _p(out["v"]), _p(out["len"]), _p(out["margin"]))
+    return out
+
+
+def stage2_analog(cond, seed, ids, xy):
+    """Stage 2 by the analog walk (orc_transport's own second stage)."""
+    e = walk_ids(cond, seed, ids, xy)
+    e["margin"] = np.full(len(e["face"]), np.inf)
+    return e
+
+
+def stage2_generative(weights, K: int, integrator: str = "euler", precision=PREC_FP64):
+    """Stage 2 by the generative sampler: noise z of the transmission's random stream (Philox
+    counter (id lo, id hi, j, 1)), the ODE of eq. 8 integrated over K steps (explicit Euler or
+    classic RK4) through the velocity network `weights`, and the decoder of eq. 11.  A model
+    fitted on collided crossings (flags bit 1) first takes the first-flight split: uncollided
+    crossings exit at the end of their entry ray, only the others are sampled.  The network's
+    condition is (ln tau, c, 2 y_in - 1, sin theta) in the canonical frame, plus ln A for an
+    11-input model of rectangular cells or omega_x for an XY-geometry model.  Returns the exits
+    and `margin`: the smallest distance of a decision from its threshold (a4 from the face
+    thresholds -1, 0, 1, the largest |a| from the rejection bound 32, the split's xi from its
+    probability), which bounds where a computation in another precision could decide
+    differently."""
+    from types import SimpleNamespace
+    collided = bool(int(getattr(weights, "flags", 0)) & 2)
+    xy_model = bool(int(getattr(weights, "flags", 0)) & 1)
+    n_in = int(getattr(weights, "n_in", 10))
+
+    def f(cond, seed, ids, xy):
+        n = len(ids)
+        out = dict(face=np.zeros(n, np.int32), pos=np.zeros(n), u=np.zeros(n), v=np.zeros(n),
+                   len=np.zeros(n), margin=np.full(n, np.inf))
+        todo = np.arange(n)
+        if collided:
+            sp = split_ids(cond, seed, ids, xy)
+            unc = sp["flag"] == 1
+            for k in ("face", "pos", "u", "v", "len", "margin"):
+                out[k][unc] = sp[k][unc]
+            out["margin"][~unc] = sp["margin"][~unc]
+            todo = np.nonzero(~unc)[0]
+        if todo.size == 0:
+            return out
+        c_ = SimpleNamespace(log_tau=np.log(cond["tau"][todo]), c=cond["c"][todo], y_in=cond["y_in"][todo],
+                             sin_th=cond["sin_th"][todo], log_aspect=None, omega_x=None)
+        if xy_model:
+            c_.omega_x = cond["u"][todo]
+        elif n_in == 11:
+            c_.log_aspect = np.log(cond["aspect"][todo])
+        z = noise_ids(seed, np.asarray(ids, np.uint64)[todo])
+        raw = (sample_raw_rk4 if integrator == "rk4" else sample_raw)(weights, c_, K, z, precision)
+        d = decode(raw, xy=xy)
+        for k in ("face", "pos", "u", "v", "len"):
+            out[k][todo] = d[k]
+        with np.errstate(invalid="ignore"):
+            m_face = np.min(np.abs(raw[:, 4:5] - np.array([[-1.0, 0.0, 1.0]])), axis=1)
+            m_rej = np.abs(np.abs(raw).max(axis=1) - 32.0)
+        out["margin"][todo] = np.minimum(out["margin"][todo], np.minimum(m_face, m_rej))
+        return out
+    return f
+
+
+def _rot(k, a, b):
+    """Rotation of the vector (a, b) by k quarter turns counter-clockwise (k per element)."""
+    k = np.asarray(k) & 3
+    ra = np.select([k == 0, k == 1, k == 2], [a, -b, -a], b)
+    rb = np.select([k == 0, k == 1, k == 2], [b, a, -b], -a)
+    return ra, rb
+
+
+def transport_composed(problem, seed: int, hist, stage2, w_margin: float = 1e-5) -> dict:
+    """Cell-to-cell transport of the histories `hist` (ids below 2^32), every cell transmission
+    sampled by `stage2(cond, seed, ids, xy)`, in the order of the paper's transport algorithm,
+    all particles of a step at once:
+      births: source sampling and, for a volumetric source, the first leg in the birth cell by
+        the analog walk (tallied; orc_birth_states);
+      stage 4 after every visit: a rejected sample (face -1) or a weight below w_min ends the
+        history (weight to the cutoff tally); otherwise the move to the neighbour through the
+        exit face (entry height = exit position), or leakage / specular reflection at the
+        domain boundary; a history reaching cell visit max_visits ends there (cutoff);
+      stage 1: the entry face e turned to the canonical left face by (e + 1) mod 4 quarter turns,
+        the entry face taken as the unit of length (tau * h_e / L, aspect w_e / h_e);
+      stage 2: stage2 with random stream id h + 2^32 * (cell visit);
+      stage 3: FP64 attenuation w_out = w e^{-sigma_a l} (eq. 5), deposit (eq. 6), track-length
+        flux (eq. 7; w l / V when sigma_a = 0) and the path tallies, l = the physical length.
+    Returns per-cell sums over the histories (flux, absorbed, leak, cutoff, wpath, path, visits,
+    rejected_w, rejected_n), the number of transmissions (`events`, birth legs included) and
+    `at_risk`: the histories with a decision within its margin (stage 2's margin below 1e-4, or
+    a weight within w_margin relative of w_min)."""
+    L_ = lib()
+    _setup_composition(L_)
+    P = problem
+    nc = P.n_cells
+    Lx = P.L
+    Ly = P.Ly if getattr(P, "Ly", 0.0) > 0 else P.L
+    xy = bool(getattr(P, "xy", False))
+    max_visits = int(getattr(P, "max_visits", 0)) or (1 << 24)
+    tau = np.ascontiguousarray(P.tau, np.float64)
+    cc = np.ascontiguousarray(P.c, np.float64)
+    T = {k: np.zeros(nc) for k in ("flux", "absorbed", "leak", "cutoff", "wpath", "path", "visits",
+                                   "rejected_w", "rejected_n")}
+    hist = np.unique(np.asarray(hist, np.int64))
+    # births, per contiguous run of history ids
+    runs = np.split(hist, np.nonzero(np.diff(hist) != 1)[0] + 1) if hist.size else []
+    states, sc = [], np.zeros(3)
+    for r in runs:
+        st = np.zeros((9, r.size))
+        pt = np.zeros((3, nc))
+        L_.orc_birth_states(P.nx, P.ny, Lx, float(getattr(P, "Ly", 0.0)), _p(tau), _p(cc), P.src_x0, P.src_y0,
+                            P.src_nx, P.src_ny, int(P.reflect), int(getattr(P, "src_face", -1)), int(xy),
+                            P.w_min, seed, int(r[0]), int(r[-1]) + 1, _p(st), _p(T["flux"]), _p(T["absorbed"]),
+                            _p(pt), _p(sc))
+        T["wpath"] += pt[0]
+        T["path"] += pt[1]
+        T["visits"] += pt[2]
+        states.append(st)
+    st = np.concatenate(states, axis=1) if states else np.zeros((9, 0))
+    events = sc[2]
+    at_entry = st[0] == 1.0
+    cell = st[1].astype(np.int64)
+    face = st[2].astype(np.int64)          # exit face after a visit / entry face at an entry
+    pos = st[3].copy()                      # exit position / canonical entry height
+    gx, gy, w = st[4].copy(), st[5].copy(), st[6].copy()
+    ev = st[7].astype(np.int64)
+    h = hist.copy()
+    at_risk = set()
+    V = Lx * Ly
+    while h.size:
+        # ---- stage 4 for the particles that have just finished a visit
+        done = ~at_entry
+        entry = face.copy()
+        y_in = pos.copy()
+        alive = np.ones(h.size, bool)
+        if done.any():
+            i = np.nonzero(done)[0]
+            near = np.abs(w[i] - P.w_min) <= w_margin * P.w_min
+            at_risk.update(h[i[near]].tolist())
+            rej = face[i] < 0
+            low = (~rej) & (w[i] < P.w_min)
+            np.add.at(T["cutoff"], cell[i[rej | low]], w[i[rej | low]])
+            np.add.at(T["rejected_w"], cell[i[rej]], w[i[rej]])
+            np.add.at(T["rejected_n"], cell[i[rej]], 1.0)
+            alive[i[rej | low]] = False
+            mv = i[~(rej | low)]
+            f = face[mv]
+            ci, cj = cell[mv] % P.nx, cell[mv] // P.nx
+            ni = ci + np.where(f == 1, 1, np.where(f == 3, -1, 0))
+            nj = cj + np.where(f == 2, 1, np.where(f == 0, -1, 0))
+            out = (ni < 0) | (nj < 0) | (ni >= P.nx) | (nj >= P.ny)
+            if not P.reflect:
+                np.add.at(T["leak"], cell[mv[out]], w[mv[out]])
+                alive[mv[out]] = False
+            else:
+                r_ = mv[out]
+                entry[r_] = face[r_]
+                y_in[r_] = 1.0 - pos[r_]
+                horiz = (face[r_] == 0) | (face[r_] == 2)
+                gy[r_] = np.where(horiz, -gy[r_], gy[r_])
+                gx[r_] = np.where(horiz, gx[r_], -gx[r_])
+            inn = mv[~out]
+            cell[inn] = nj[~out] * P.nx + ni[~out]
+            entry[inn] = (face[inn] + 2) & 3
+            y_in[inn] = pos[inn]
+            moved = mv[alive[mv]]
+            ev[moved] += 1
+            cap = moved[ev[moved] >= max_visits]
+            np.add.at(T["cutoff"], cell[cap], w[cap])
+            alive[cap] = False
+        keep = np.nonzero(alive)[0]
+        h, cell, entry, y_in, gx, gy, w, ev = (a[keep] for a in (h, cell, entry, y_in, gx, gy, w, ev))
+        if not h.size:
+            break
+        # ---- stage 1: canonical frame of the entry face
+        k = (entry + 1) & 3
+        U, Vc = _rot((4 - k) & 3, gx, gy)
+        odd = (entry & 1) == 1
+        h_e = np.where(odd, Ly, Lx)
+        w_e = np.where(odd, Lx, Ly)
+        s = Vc if xy else np.clip(Vc, -1.0, 1.0)
+        u0 = U if xy else np.sqrt(1.0 - s * s)
+        cond = dict(tau=tau[cell] * h_e / Lx, c=cc[cell], y_in=y_in, u=u0, sin_th=s, aspect=w_e / h_e)
+        ids = h.astype(np.uint64) | (ev.astype(np.uint64) << np.uint64(32))
+        # ---- stage 2
+        e = stage2(cond, seed, ids, xy)
+        events += h.size
+        at_risk.update(h[e["margin"] < 1e-4].tolist())
+        # ---- stage 3 (FP64)
+        sig_a = (1.0 - cc[cell]) * tau[cell] / Lx
+        ls = e["len"] * h_e
+        dw = w * (-np.expm1(-sig_a * ls))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            phi = np.where(sig_a > 0.0, dw / (V * sig_a), w * ls / V)
+        np.add.at(T["flux"], cell, phi)
+        np.add.at(T["absorbed"], cell, dw)
+        np.add.at(T["wpath"], cell, w * ls)
+        np.add.at(T["path"], cell, ls)
+        np.add.at(T["visits"], cell, 1.0)
+        w = w - dw
+        # back to the global frame
+        face = np.where(e["face"] >= 0, (e["face"] + k) & 3, e["face"])
+        pos = e["pos"]
+        gx, gy = _rot(k, e["u"], e["v"])
+        at_entry = np.zeros(h.size, bool)
+    T["events"] = events
+    T["at_risk"] = sorted(at_risk)
+    return T

@@ -293,6 +293,50 @@ void orc_mc_transmit_internal(const float *log_tau, const float *c, const float 
               len, ncoll, nthreads);
 }
 
+/* Canonical transmissions with FP64 conditions and explicit random stream ids (the transport
+ * composition of the oracle): particle i enters the left face of the cell [0, a[i]] x [0, 1] at
+ * height y[i] with direction (u[i], s[i]) (flatland: u = sqrt(1 - s^2); XY geometry: the
+ * in-plane projection), optical height tau[i], scattering ratio c[i], stream ids[i].
+ *   orc_noise_ids:  z ~ N(0, I_5) of stream ids[i] (orc_noise), [5][n]
+ *   orc_walk_ids:   the mode-C analog walk (orc_walk)
+ *   orc_split_ids:  the first-flight split of orc_uncollided_split (flag, and the entry ray's
+ *                   exit for every particle) */
+void orc_noise_ids(uint64_t seed, const uint64_t *ids, int64_t n, double *z /* [5][n] */)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double v[5];
+        orc_noise(seed, ids[i], v);
+        for (int d = 0; d < 5; ++d) z[d * n + i] = v[d];
+    }
+}
+
+void orc_walk_ids(const double *tau, const double *c, const double *y, const double *u, const double *s,
+                  const double *a, int xy, int64_t n, uint64_t seed, const uint64_t *ids, int32_t *face,
+                  double *pos, double *eu, double *ev, double *len)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_exit e;
+        orc_walk(tau[i], c[i], 0, xy, a[i], 0.0, y[i], u[i], s[i], seed, ids[i], &e);
+        face[i] = e.face; pos[i] = e.pos; eu[i] = e.u; ev[i] = e.v; len[i] = e.len;
+    }
+}
+
+void orc_split_ids(const double *tau, const double *c, const double *y, const double *u, const double *s,
+                   const double *a, int xy, int64_t n, uint64_t seed, const uint64_t *ids, int32_t *flag,
+                   int32_t *face, double *pos, double *eu, double *ev, double *len, double *margin)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_exit e;
+        orc_walk(0.0, 0.0, 0, xy, a[i], 0.0, y[i], u[i], s[i], seed, ids[i], &e);
+        double pu = exp(-c[i] * tau[i] * e.len);
+        uint32_t r[4];
+        draw4(seed, ids[i], 0u, ORC_TAG_SPLIT, r);
+        flag[i] = orc_u01(r[0]) <= pu;
+        if (margin) margin[i] = fabs(orc_u01(r[0]) - pu);
+        face[i] = e.face; pos[i] = e.pos; eu[i] = e.u; ev[i] = e.v; len[i] = e.len;
+    }
+}
+
 /* ------------------------------------------------------------------------------------ */
 /* Cell-to-cell transport with the track-length estimator (eqs. 5-7, section "Transport   */
 /* Algorithm"), analog mode-C walk inside every cell.                                      */
@@ -325,11 +369,15 @@ typedef struct {
 typedef struct {
     double *flux;               /* [n_cells] sum of track-length estimates (eq. 7), per history */
     double *absorbed;           /* [n_cells] deposited weight (eq. 6) */
+    double *wpath;              /* [n_cells] sum of entry weight times physical track length */
+    double *path;               /* [n_cells] sum of physical track lengths */
+    double *visits;             /* [n_cells] number of cell visits */
     double leak, cutoff;        /* weight leaving the domain / killed by the cutoff */
     double events;              /* number of cell transmissions sampled (incl. birth legs) */
 } orc_tally;
 
-/* Stage 3 of the transport loop for one cell visit: attenuate and tally. Returns w_out.
+/* Stage 3 of the transport loop for one cell visit: attenuate and tally (flux, deposit, and the
+ * visit's track length: w_in * l, l and one visit). Returns w_out.
  * len_units is the track length in units of `unit` (the length of the face the walk's frame
  * took as its height). */
 static double visit_tally(const orc_problem *p, int cell, double w_in, double len_units,
@@ -343,6 +391,9 @@ static double visit_tally(const orc_problem *p, int cell, double w_in, double le
                                : w_in * ls / V;      /* sigma_a -> 0 limit of eq. 7 */
     t->flux[cell] += phi;
     t->absorbed[cell] += dw;
+    t->wpath[cell] += w_in * ls;
+    t->path[cell] += ls;
+    t->visits[cell] += 1.0;
     return w_in - dw;
 }
 
@@ -359,64 +410,97 @@ static void inward_direction(int f, double cth, double sth, double *gx, double *
     }
 }
 
-static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tally *t)
+/* The state of a history between cell visits. */
+typedef struct {
+    int ci, cj;                 /* current cell */
+    int face;                   /* after a visit: the global exit face */
+    int entry;                  /* at an entry: the global entry face */
+    double pos;                 /* after a visit: counter-clockwise exit position */
+    double y_in;                /* at an entry: canonical entry height */
+    double gx, gy;              /* global direction */
+    double w;                   /* weight */
+    uint32_t event;             /* cell visit index */
+} orc_state;
+
+/* Birth of history h.  Volumetric source: a uniformly picked cell of the source block, a
+ * uniform point and an isotropic direction, and the first leg in that cell by the analog walk
+ * (cell visit 0), tallied; the state is the leg's exit.  Surface source: the entry into a
+ * uniformly picked strip cell (cell visit 1), nothing tallied.  Returns 1 when the history is at
+ * the entry of its cell (surface source), 0 when it has just finished a visit. */
+static int birth(const orc_problem *p, uint64_t seed, uint32_t h, orc_tally *t, orc_state *st)
 {
     /* birth: uniform cell of the source block (or strip) */
     uint32_t r[4];
     draw4(seed, (uint64_t)h, 0u, ORC_TAG_SOURCE, r);
     uint32_t nsrc = (uint32_t)(p->src_nx * p->src_ny);
     uint32_t pick = (uint32_t)(((uint64_t)r[0] * nsrc) >> 32);
-    int ci = p->src_x0 + (int)(pick % (uint32_t)p->src_nx);
-    int cj = p->src_y0 + (int)(pick / (uint32_t)p->src_nx);
-    int cell = cj * p->nx + ci;
-    double gx, gy, w = 1.0, pos = 0.0, y_in = 0.0;
-    uint32_t event = 0;
-    int face = 0, entry = 0;
-    orc_exit e;
+    st->ci = p->src_x0 + (int)(pick % (uint32_t)p->src_nx);
+    st->cj = p->src_y0 + (int)(pick / (uint32_t)p->src_nx);
+    int cell = st->cj * p->nx + st->ci;
+    st->w = 1.0;
+    st->pos = 0.0;
+    st->y_in = 0.0;
+    st->event = 0;
+    st->face = 0;
+    st->entry = 0;
 
     if (p->src_face >= 0) {
         /* surface source: enter through side src_face at a uniform canonical height with the
          * cosine law for the angle to the inward normal (sin theta uniform on (-1, 1)); the
          * first transmission is this cell's, cell visit 1 */
-        entry = p->src_face;
-        y_in = u01_open(r[1]);
+        st->entry = p->src_face;
+        st->y_in = u01_open(r[1]);
         if (p->xy) {
             /* isotropic incident flux in three dimensions: the cosine of the angle to the
              * inward normal is sqrt(xi) (pdf 2 cos over the hemisphere), the azimuth about the
              * normal psi = 2 pi xi'; the in-plane components are (sqrt(xi), sqrt(1 - xi) cos psi) */
             double xi = u01_open(r[2]);
             double psi = 2.0 * ORC_PI * orc_u01(r[3]);
-            inward_direction(entry, sqrt(xi), sqrt(1.0 - xi) * cos(psi), &gx, &gy);
+            inward_direction(st->entry, sqrt(xi), sqrt(1.0 - xi) * cos(psi), &st->gx, &st->gy);
         } else {
             double s = 2.0 * u01_open(r[2]) - 1.0;
-            inward_direction(entry, sqrt(1.0 - s * s), s, &gx, &gy);
+            inward_direction(st->entry, sqrt(1.0 - s * s), s, &st->gx, &st->gy);
         }
-        event = 1;
-    } else {
-        /* volumetric source: uniform point, isotropic direction; first leg by the analog walk
-         * from the interior birth point in the cell's own frame [0, L / Ly] x [0, 1] (lengths
-         * in units of the height Ly), cell visit 0 */
-        double ry = p->Ly / p->L;                        /* 1 for square cells */
-        double a = p->L / p->Ly;
-        double x = a * u01_open(r[1]), y = u01_open(r[2]);
-        double phi = 2.0 * ORC_PI * orc_u01(r[3]);
-        double st = 1.0;
-        if (p->xy) {             /* isotropic on the sphere: mu from a second draw */
-            uint32_t r2[4];
-            draw4(seed, (uint64_t)h, 1u, ORC_TAG_SOURCE, r2);
-            double mu = 2.0 * orc_u01(r2[0]) - 1.0;
-            st = sqrt(1.0 - mu * mu);
-        }
-        orc_walk(p->tau[cell] * ry, p->c[cell], 0, p->xy, a, x, y, st * cos(phi), st * sin(phi), seed,
-                 (uint64_t)h | ((uint64_t)event << 32), &e);
-        t->events += 1.0;
-        face = e.face;
-        pos = e.pos;
-        gx = e.u; gy = e.v;
-        w = visit_tally(p, cell, w, e.len, p->Ly, t);
+        st->event = 1;
+        return 1;
     }
+    /* volumetric source: uniform point, isotropic direction; first leg by the analog walk
+     * from the interior birth point in the cell's own frame [0, L / Ly] x [0, 1] (lengths
+     * in units of the height Ly), cell visit 0 */
+    double ry = p->Ly / p->L;                        /* 1 for square cells */
+    double a = p->L / p->Ly;
+    double x = a * u01_open(r[1]), y = u01_open(r[2]);
+    double phi = 2.0 * ORC_PI * orc_u01(r[3]);
+    double sth = 1.0;
+    if (p->xy) {             /* isotropic on the sphere: mu from a second draw */
+        uint32_t r2[4];
+        draw4(seed, (uint64_t)h, 1u, ORC_TAG_SOURCE, r2);
+        double mu = 2.0 * orc_u01(r2[0]) - 1.0;
+        sth = sqrt(1.0 - mu * mu);
+    }
+    orc_exit e;
+    orc_walk(p->tau[cell] * ry, p->c[cell], 0, p->xy, a, x, y, sth * cos(phi), sth * sin(phi), seed,
+             (uint64_t)h | ((uint64_t)st->event << 32), &e);
+    t->events += 1.0;
+    st->face = e.face;
+    st->pos = e.pos;
+    st->gx = e.u; st->gy = e.v;
+    st->w = visit_tally(p, cell, st->w, e.len, p->Ly, t);
+    return 0;
+}
 
-    int entering = (p->src_face >= 0);      /* already at the entry of its first cell */
+static void one_history(const orc_problem *p, uint64_t seed, uint32_t h, orc_tally *t)
+{
+    orc_state st;
+    const int at_entry = birth(p, seed, h, t, &st);
+    int ci = st.ci, cj = st.cj;
+    int cell = cj * p->nx + ci;
+    double gx = st.gx, gy = st.gy, w = st.w, pos = st.pos, y_in = st.y_in;
+    uint32_t event = st.event;
+    int face = st.face, entry = st.entry;
+    orc_exit e;
+
+    int entering = at_entry;                /* already at the entry of its first cell */
     for (;;) {
         if (!entering) {
             if (w < p->w_min) { t->cutoff += w; return; }
@@ -482,12 +566,13 @@ static void *tr_worker(void *arg)
 }
 
 /* Runs histories [h_begin, h_end).  Tallies are sums over histories (the caller divides by the
- * number of source particles).  out_scalars = {leak, cutoff, events}. */
+ * number of source particles).  out_scalars = {leak, cutoff, events}; path_out (NULL or
+ * [3][n_cells]) = the path tallies: sum of w_in * l, sum of l, visits. */
 void orc_transport(int32_t nx, int32_t ny, double L, double Ly, const double *tau, const double *c,
                    int32_t src_x0, int32_t src_y0, int32_t src_nx, int32_t src_ny, int32_t reflect,
                    int32_t src_face, int32_t xy, double w_min, uint64_t seed, uint32_t h_begin,
                    uint32_t h_end, double *flux, double *absorbed, double *out_scalars, int nthreads,
-                   uint32_t max_visits)
+                   uint32_t max_visits, double *path_out)
 {
     if (!(Ly > 0.0)) Ly = L;                          /* square cells */
     if (max_visits == 0) max_visits = 1u << 24;
@@ -506,6 +591,9 @@ void orc_transport(int32_t nx, int32_t ny, double L, double Ly, const double *ta
         jobs[t].h1 = h_begin + (uint32_t)(nh * (uint64_t)(t + 1) / (uint64_t)nthreads);
         jobs[t].t.flux = (double *)calloc((size_t)ncell, sizeof(double));
         jobs[t].t.absorbed = (double *)calloc((size_t)ncell, sizeof(double));
+        jobs[t].t.wpath = (double *)calloc((size_t)ncell, sizeof(double));
+        jobs[t].t.path = (double *)calloc((size_t)ncell, sizeof(double));
+        jobs[t].t.visits = (double *)calloc((size_t)ncell, sizeof(double));
         jobs[t].t.leak = jobs[t].t.cutoff = jobs[t].t.events = 0.0;
     }
     for (int t = 1; t < nthreads; ++t) pthread_create(&th[t], NULL, tr_worker, &jobs[t]);
@@ -513,16 +601,53 @@ void orc_transport(int32_t nx, int32_t ny, double L, double Ly, const double *ta
     for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
     memset(flux, 0, sizeof(double) * (size_t)ncell);
     memset(absorbed, 0, sizeof(double) * (size_t)ncell);
+    if (path_out) memset(path_out, 0, 3 * sizeof(double) * (size_t)ncell);
     out_scalars[0] = out_scalars[1] = out_scalars[2] = 0.0;
     for (int t = 0; t < nthreads; ++t) {
         for (int i = 0; i < ncell; ++i) {
             flux[i] += jobs[t].t.flux[i];
             absorbed[i] += jobs[t].t.absorbed[i];
+            if (path_out) {
+                path_out[i] += jobs[t].t.wpath[i];
+                path_out[ncell + i] += jobs[t].t.path[i];
+                path_out[2 * ncell + i] += jobs[t].t.visits[i];
+            }
         }
         out_scalars[0] += jobs[t].t.leak;
         out_scalars[1] += jobs[t].t.cutoff;
         out_scalars[2] += jobs[t].t.events;
         free(jobs[t].t.flux);
         free(jobs[t].t.absorbed);
+        free(jobs[t].t.wpath);
+        free(jobs[t].t.path);
+        free(jobs[t].t.visits);
     }
+}
+
+/* Births of histories [h_begin, h_end) (the source stage of orc_transport) for the oracle's
+ * transport composition: state[9][n] per history = {at entry (1: surface source, the entry of
+ * its cell; 0: volumetric, the exit of its first leg), cell index, face (exit face, or the
+ * entry face at an entry), pos (exit position, or the canonical entry height), gx, gy, w,
+ * event, 0}; the birth legs' tallies are added to flux, absorbed, path_out ([3][n_cells]) and
+ * scalars[2] (events). */
+void orc_birth_states(int32_t nx, int32_t ny, double L, double Ly, const double *tau, const double *c,
+                      int32_t src_x0, int32_t src_y0, int32_t src_nx, int32_t src_ny, int32_t reflect,
+                      int32_t src_face, int32_t xy, double w_min, uint64_t seed, uint32_t h_begin,
+                      uint32_t h_end, double *state, double *flux, double *absorbed, double *path_out,
+                      double *scalars)
+{
+    if (!(Ly > 0.0)) Ly = L;
+    orc_problem p = {nx, ny, L, Ly, tau, c, src_x0, src_y0, src_nx, src_ny, reflect, w_min, src_face,
+                     xy ? 1 : 0, 1u << 24};
+    int ncell = nx * ny;
+    orc_tally t = {flux, absorbed, path_out, path_out + ncell, path_out + 2 * ncell, 0.0, 0.0, 0.0};
+    int64_t n = (int64_t)(h_end - h_begin);
+    for (int64_t i = 0; i < n; ++i) {
+        orc_state st;
+        int at_entry = birth(&p, seed, h_begin + (uint32_t)i, &t, &st);
+        double v[9] = {(double)at_entry, (double)(st.cj * nx + st.ci), (double)(at_entry ? st.entry : st.face),
+                       at_entry ? st.y_in : st.pos, st.gx, st.gy, st.w, (double)st.event, 0.0};
+        for (int k = 0; k < 9; ++k) state[k * n + i] = v[k];
+    }
+    scalars[2] += t.events;
 }

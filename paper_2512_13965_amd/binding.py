@@ -350,6 +350,7 @@ def _transport_sigs(L):
     L.gmc_transport_step.argtypes = [P, I, P, I, P, ctypes.POINTER(I64)]
     L.gmc_problem_alive.argtypes = [P, I32, ctypes.POINTER(I64)]
     L.gmc_problem_tally.argtypes = [P, I32, P, P, P, P, P]
+    L.gmc_problem_path_tally.argtypes = [P, I32, P, P, P, P, P, P]
     L.gmc_world_set_integrator.argtypes = [P, I]
     L.gmc_world_set_graphs.argtypes = [P, I]
     L.gmc_world_set_streaming.argtypes = [P, I]
@@ -357,7 +358,7 @@ def _transport_sigs(L):
     L.gmc_world_set_source_model.argtypes = [P, P, I]
     for name in ("gmc_world_set_integrator", "gmc_world_set_graphs", "gmc_world_set_source_model", "gmc_world_footprint", "gmc_world_create", "gmc_world_destroy", "gmc_problem_add",
                  "gmc_problem_remove", "gmc_world_inject", "gmc_transport_step",
-                 "gmc_problem_alive", "gmc_problem_tally"):
+                 "gmc_problem_alive", "gmc_problem_tally", "gmc_problem_path_tally"):
         getattr(L, name).restype = ctypes.c_int
 
 
@@ -438,12 +439,19 @@ class World:
         return n.value
 
     def tally(self, pid: int, stream=None) -> dict:
+        """Per-cell FP64 tallies summed over the histories so far: flux, absorbed, leak, cutoff
+        (gmc_problem_tally) and the path tallies wpath, path, visits, rejected_w, rejected_n
+        (gmc_problem_path_tally)."""
         import numpy as np
         m = self._shapes[pid]
-        out = {k: np.zeros(m) for k in ("flux", "absorbed", "leak", "cutoff")}
+        out = {k: np.zeros(m) for k in ("flux", "absorbed", "leak", "cutoff", "wpath", "path", "visits",
+                                        "rejected_w", "rejected_n")}
         _check(self._L.gmc_problem_tally(self._h, pid, out["flux"].ctypes.data,
                                          out["absorbed"].ctypes.data, out["leak"].ctypes.data,
                                          out["cutoff"].ctypes.data, _stream(stream)))
+        _check(self._L.gmc_problem_path_tally(self._h, pid, out["wpath"].ctypes.data, out["path"].ctypes.data,
+                                              out["visits"].ctypes.data, out["rejected_w"].ctypes.data,
+                                              out["rejected_n"].ctypes.data, _stream(stream)))
         return out
 
     def close(self):

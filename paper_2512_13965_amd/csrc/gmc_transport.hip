@@ -56,6 +56,9 @@ struct CellsDev {
     const double *tau, *c;         // per global cell (FP64: tallies)
     const float *ltau, *cf;        // per global cell (FP32: sampler conditions)
     double *flux, *absorbed, *leak, *cutoff;
+    // path tallies per cell: sum of w_in * l_phys, sum of l_phys, number of visits; weight and
+    // number of generative samples rejected by the decoder (a part of the cutoff)
+    double *wpath, *path, *visits, *rej_w, *rej_n;
     const ProblemDev *prob;
 };
 
@@ -65,15 +68,16 @@ __device__ __forceinline__ int lane_rank(uint64_t mask)
                                           __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Per-workgroup tally staging: the flux and deposit of a workgroup's particles are summed per
-// cell in an LDS hash table and flushed with one pair of FP64 global atomics per distinct cell.
+// Per-workgroup tally staging: the flux, deposit and path tallies of a workgroup's particles are
+// summed per cell in an LDS hash table and flushed with one FP64 global atomic per tally and
+// distinct cell.
 // Particles near a source crowd into few cells, whose same-address global atomics would
 // otherwise serialise in L2.  A block holds at most 256 particles, so at most 256 of the 512
 // slots fill and linear probing always ends.
 constexpr int kTallySlots = 512;
 struct TallyLds {
     int32_t key[kTallySlots];
-    double flux[kTallySlots], dep[kTallySlots];
+    double flux[kTallySlots], dep[kTallySlots], wpath[kTallySlots], path[kTallySlots], visits[kTallySlots];
 };
 
 __device__ __forceinline__ void tally_init(TallyLds &tl)
@@ -82,10 +86,13 @@ __device__ __forceinline__ void tally_init(TallyLds &tl)
         tl.key[s] = -1;
         tl.flux[s] = 0.0;
         tl.dep[s] = 0.0;
+        tl.wpath[s] = 0.0;
+        tl.path[s] = 0.0;
+        tl.visits[s] = 0.0;
     }
 }
 
-__device__ __forceinline__ void tally_add(TallyLds &tl, int cell, double phi, double dw)
+__device__ __forceinline__ void tally_add(TallyLds &tl, int cell, double phi, double dw, double wl, double l)
 {
     uint32_t s = ((uint32_t)cell * 2654435761u) >> 23;     // 9-bit multiplicative hash
     for (;;) {
@@ -95,6 +102,9 @@ __device__ __forceinline__ void tally_add(TallyLds &tl, int cell, double phi, do
     }
     atomicAdd(&tl.flux[s], phi);
     atomicAdd(&tl.dep[s], dw);
+    atomicAdd(&tl.wpath[s], wl);
+    atomicAdd(&tl.path[s], l);
+    atomicAdd(&tl.visits[s], 1.0);
 }
 
 __device__ __forceinline__ void tally_flush(TallyLds &tl, const CellsDev &cd)
@@ -104,6 +114,9 @@ __device__ __forceinline__ void tally_flush(TallyLds &tl, const CellsDev &cd)
         if (cell >= 0) {
             atomicAdd(&cd.flux[cell], tl.flux[s]);
             atomicAdd(&cd.absorbed[cell], tl.dep[s]);
+            atomicAdd(&cd.wpath[cell], tl.wpath[s]);
+            atomicAdd(&cd.path[cell], tl.path[s]);
+            atomicAdd(&cd.visits[cell], tl.visits[s]);
         }
     }
 }
@@ -111,7 +124,7 @@ __device__ __forceinline__ void tally_flush(TallyLds &tl, const CellsDev &cd)
 // Stage 3 for one cell visit: w_out = w e^{-sigma_a l} (eq. 5), deposit dw (eq. 6) and flux
 // dw / (V sigma_a) (eq. 7; w l / V when sigma_a = 0), all in FP64 with the physical path
 // (path_units in units of `unit`, the length of the face the walk's frame took as its height),
-// staged in the workgroup's table.
+// plus the path tallies w l, l and one visit, staged in the workgroup's table.
 __device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemDev &P, int cell,
                                               double w, float path_units, double unit, TallyLds &tl)
 {
@@ -120,7 +133,7 @@ __device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemD
     const double dw = w * (-expm1(-sig_a * ls));
     const double V = P.L * P.Ly;
     const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
-    tally_add(tl, cell, phi, dw);
+    tally_add(tl, cell, phi, dw, w * ls, ls);
     return w - dw;
 }
 
@@ -136,6 +149,9 @@ __device__ __forceinline__ double visit_tally_global(const CellsDev &cd, const P
     const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
     atomicAdd(&cd.flux[cell], phi);
     atomicAdd(&cd.absorbed[cell], dw);
+    atomicAdd(&cd.wpath[cell], w * ls);
+    atomicAdd(&cd.path[cell], ls);
+    atomicAdd(&cd.visits[cell], 1.0);
     return w - dw;
 }
 
@@ -153,8 +169,12 @@ __device__ __forceinline__ Next move_on(const CellsDev &cd, const ProblemDev &P,
                                         float pos, float gx, float gy, double w_out)
 {
     Next nx{cell, 0, 0.0f, gx, gy, false};
-    if (face < 0 || face > 3) {              // capped walk: drop its weight with the cutoff
-        atomicAdd(&cd.cutoff[cell], w_out);
+    if (face < 0 || face > 3) {              // capped walk or rejected sample: drop its weight
+        atomicAdd(&cd.cutoff[cell], w_out);  // with the cutoff
+        if (face == -1) {
+            atomicAdd(&cd.rej_w[cell], w_out);
+            atomicAdd(&cd.rej_n[cell], 1.0);
+        }
         return nx;
     }
     if (w_out < P.w_min) {
@@ -641,7 +661,7 @@ struct gmc_world {
     unsigned long long *queue = nullptr;      // the analog walk's work counter (this world's own)
     // captured transport steps, one per (sampler, model, K, integrator, bank parity, bucket)
     struct StepGraph {
-        int sampler, K, integrator, cur, ff;
+        int sampler, K, integrator, cur, ff, xy;
         uint64_t model;        // serial of the model (0 for the analog walk)
         int64_t bucket;
         hipGraph_t graph;
@@ -662,7 +682,11 @@ struct gmc_world {
     std::mutex mu;
 
     unsigned long long *cnt(int which) { return counters + (size_t)which * (1 + max_problems); }
-    CellsDev cells() const { return CellsDev{tau, c, ltau, cf, flux, absorbed, leak, cutoff, prob}; }
+    double *wpath = nullptr, *path = nullptr, *visits = nullptr, *rej_w = nullptr, *rej_n = nullptr;
+    CellsDev cells() const
+    {
+        return CellsDev{tau, c, ltau, cf, flux, absorbed, leak, cutoff, wpath, path, visits, rej_w, rej_n, prob};
+    }
 };
 
 namespace {
@@ -722,6 +746,11 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->absorbed, 8 * N);
     L.add((void **)&w->leak, 8 * N);
     L.add((void **)&w->cutoff, 8 * N);
+    L.add((void **)&w->wpath, 8 * N);
+    L.add((void **)&w->path, 8 * N);
+    L.add((void **)&w->visits, 8 * N);
+    L.add((void **)&w->rej_w, 8 * N);
+    L.add((void **)&w->rej_n, 8 * N);
     L.add((void **)&w->prob, sizeof(ProblemDev) * P);
     L.add((void **)&w->counters, 8 * 2 * (1 + P));
     L.add((void **)&w->queue, 8);
@@ -885,7 +914,7 @@ int gmc_problem_add(gmc_world *w, const gmc_problem_desc *d, int32_t *pid_out, v
     if (e == hipSuccess) e = hipMemcpyAsync(w->ltau + cell0, lt.data(), 4 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(w->cf + cell0, cf.data(), 4 * n, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(w->prob + pid, &P, sizeof P, hipMemcpyHostToDevice, s);
-    double *tallies[4] = {w->flux, w->absorbed, w->leak, w->cutoff};
+    double *tallies[9] = {w->flux, w->absorbed, w->leak, w->cutoff, w->wpath, w->path, w->visits, w->rej_w, w->rej_n};
     for (double *t : tallies) {
         if (e != hipSuccess) break;
         hipLaunchKernelGGL(zero_f64_kernel, dim3(blocks_for(n)), dim3(256), 0, s, t + cell0, n);
@@ -1163,9 +1192,12 @@ int step_graph(gmc_world *w, int sampler, const gmc_model *m, int K, int64_t buc
     const uint64_t mm = (sampler == GMC_SAMPLER_GMC) ? m->serial : 0;
     const int KK = (sampler == GMC_SAMPLER_GMC) ? K : 0;
     const int ff = (sampler == GMC_SAMPLER_GMC && m->collided) ? w->ff_max : 0;
+    // the captured launches bake in the world's geometry (the analog walk reads omega_x only in
+    // XY geometry), so the key holds it too
+    const int xy = world_xy(w) ? 1 : 0;
     for (auto &g : w->step_graphs)
         if (g.sampler == sampler && g.model == mm && g.K == KK && g.integrator == integ && g.cur == w->cur &&
-            g.ff == ff && g.bucket == bucket) {
+            g.ff == ff && g.xy == xy && g.bucket == bucket) {
             *exec = g.exec;
             return GMC_OK;
         }
@@ -1186,7 +1218,7 @@ int step_graph(gmc_world *w, int sampler, const gmc_model *m, int K, int64_t buc
         (void)hipGraphDestroy(graph);
         return set_hip_error(e, "gmc_transport_step: instantiate");
     }
-    w->step_graphs.push_back({sampler, KK, integ, w->cur, ff, mm, bucket, graph, x});
+    w->step_graphs.push_back({sampler, KK, integ, w->cur, ff, xy, mm, bucket, graph, x});
     *exec = x;
     return GMC_OK;
 }
@@ -1255,6 +1287,24 @@ int gmc_problem_tally(gmc_world *w, int32_t pid, double *flux, double *absorbed,
         if (dst[t]) e = hipMemcpyAsync(dst[t], src[t] + P.cell0, 8 * n, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return set_hip_error(e, "gmc_problem_tally: copy");
+    return GMC_OK;
+}
+
+int gmc_problem_path_tally(gmc_world *w, int32_t pid, double *wpath, double *path, double *visits,
+                           double *rejected_w, double *rejected_n, void *stream)
+{
+    if (!w || pid < 0 || pid >= w->max_problems || !w->in_use[pid])
+        return set_error(GMC_EINVAL, "gmc_problem_path_tally: no such problem");
+    const ProblemDev &P = w->prob_host[pid];
+    const int64_t n = (int64_t)P.nx * P.ny;
+    hipStream_t s = (hipStream_t)stream;
+    double *dst[5] = {wpath, path, visits, rejected_w, rejected_n};
+    const double *src[5] = {w->wpath, w->path, w->visits, w->rej_w, w->rej_n};
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < 5 && e == hipSuccess; ++t)
+        if (dst[t]) e = hipMemcpyAsync(dst[t], src[t] + P.cell0, 8 * n, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return set_hip_error(e, "gmc_problem_path_tally: copy");
     return GMC_OK;
 }
 

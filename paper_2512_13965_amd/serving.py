@@ -21,7 +21,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-CELL_BYTES = 8 + 8 + 4 + 4 + 4 * 8     # tau, c (FP64), ln tau, c (FP32), 4 FP64 tallies
+CELL_BYTES = 8 + 8 + 4 + 4 + 9 * 8     # tau, c (FP64), ln tau, c (FP32), 9 FP64 tallies
 
 
 @dataclass

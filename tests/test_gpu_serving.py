@@ -40,3 +40,64 @@ def test_request_alone_and_in_mix(sampler):
     p = mix.latency_percentiles()
     assert p["p99"] >= p["p50"] > 0
     assert mix.transmissions > 0 and mix.steps > 0
+
+
+def test_served_requests_match_the_oracle(orc):
+    # every request of a Poisson stream served with the analog sampler against the oracle's
+    # transport of the same problem and seed (the same random numbers per history and cell
+    # visit): per cell |d| <= 1e-4 |phi| + 1e-9 N, leak and absorption within 1e-3 per history
+    binding = require_gpu()
+    from paper_2512_13965_amd import serving
+    from tests.test_gpu_transport import check_within_noise, oracle_batches, per_cell_ok
+    world = binding.World(1 << 17, 8, 1 << 16)
+    reqs = serving.poisson_requests(
+        8, rate_hz=300.0, seed=9,
+        make_problem=lambda i: inputs.random_problem(300 + i, side_range=(16, 40), hist_log10_range=(3.5, 4.3)))
+    st = serving.Server(world, binding.SAMPLER_MC, None).run(reqs)
+    world.close()
+    assert len(st.requests) == len(reqs)
+    for r in st.requests:
+        o, se = oracle_batches(orc, r.problem, r.seed, r.n_hist)
+        n = r.n_hist
+        for k in ("flux", "absorbed"):
+            ok, worst = per_cell_ok(r.tallies[k], o[k], n)
+            print(f"request {r.rid} ({r.problem.nx}^2, {n} histories): {k} worst ratio {worst:.2e}")
+            assert ok, (r.rid, k, worst)
+        check_within_noise(r.tallies, o, se, n, f"request {r.rid}")
+        assert abs(r.tallies["leak"].sum() - o["leak"]) <= 1e-3 * n
+        assert abs(r.tallies["absorbed"].sum() - o["absorbed"].sum()) <= 1e-3 * n
+
+
+def test_served_generative_requests_match_the_oracle_composition(orc):
+    # requests served with the generative sampler (FP32, H = 128, random-init, Euler K = 4)
+    # against the oracle's transport composition with the same network; each request's seed is
+    # the first for which the oracle lists no history at risk of an FP32 / FP64 decision flip
+    binding = require_gpu()
+    from paper_2512_13965_amd import serving
+    from tests.test_gpu_transport import per_cell_ok
+    w = inputs.random_weights(128, 61)
+    stage2 = orc.stage2_generative(w, 4)
+    reqs, refs = [], []
+    for i in range(4):
+        prob, _ = inputs.random_problem(500 + i, side_range=(8, 12))
+        n = 400 + 100 * i
+        for seed in range(1000 * (i + 1), 1000 * (i + 1) + 50):
+            ref = orc.transport_composed(prob, seed, np.arange(n), stage2)
+            if not ref["at_risk"]:
+                break
+        else:
+            pytest.fail("no seed without histories at risk")
+        reqs.append(serving.Request(i, prob, n, seed=seed, arrival=0.002 * i))
+        refs.append(ref)
+    m = binding.Model(inputs.pack_blob(w), "fp32")
+    world = binding.World(1 << 14, 4, 1 << 12)
+    st = serving.Server(world, binding.SAMPLER_GMC, m, K=4).run(reqs)
+    world.close()
+    m.close()
+    assert len(st.requests) == len(reqs)
+    for r in st.requests:
+        ref = refs[r.rid]
+        for k in ("flux", "absorbed", "leak", "cutoff", "wpath", "path", "visits"):
+            ok, worst = per_cell_ok(r.tallies[k], ref[k], r.n_hist)
+            print(f"generative request {r.rid}: {k} worst ratio {worst:.2e}")
+            assert ok, (r.rid, k, worst)

@@ -18,6 +18,44 @@ from tests.gpu_util import require_gpu
 pytestmark = pytest.mark.gpu
 
 
+def per_cell_ok(g, o, n, rel=1e-4, abs_per_hist=1e-9):
+    """Per-cell bound |g - o| <= rel * |o| + abs_per_hist * n; returns (ok, worst ratio)."""
+    g, o = np.asarray(g, np.float64), np.asarray(o, np.float64)
+    ratio = np.abs(g - o) / (rel * np.abs(o) + abs_per_hist * n)
+    return bool(np.all(ratio <= 1.0)), float(ratio.max())
+
+
+TALLIES = ("flux", "absorbed", "wpath", "path", "visits")
+
+
+def oracle_batches(orc, prob, seed, n, batches=16):
+    """The oracle's transport of histories [0, n) run in `batches` contiguous batches: their
+    sums (the one-run result: histories are independent of the chunking) and the standard error
+    of each per-cell sum, sqrt(batches) times the spread of the batch sums."""
+    parts = [orc.transport(prob, seed=seed, h_begin=n * b // batches, h_end=n * (b + 1) // batches, nthreads=8)
+             for b in range(batches)]
+    ref = {k: np.sum([p[k] for p in parts], axis=0) for k in TALLIES}
+    ref["leak"] = sum(p["leak"] for p in parts)
+    se = {k: np.std([p[k] for p in parts], axis=0, ddof=1) * math.sqrt(batches) for k in TALLIES}
+    return ref, se
+
+
+def check_within_noise(g, ref, se, n, label):
+    """Analog transport, GPU against the oracle on the same random numbers, per cell: the
+    difference must stay below 1e-4 |ref| + 1e-9 n plus half the cell's own statistical
+    standard error (measured: at most a tenth of it).  A history takes the same cells on both sides unless an FP32 near-tie sends the GPU
+    walk the other way (a few in 10^7 flights, see test_gpu_walk.py); such a history moves the
+    tallies of the cells it touches by less than their noise, while a wrong tally in a low-flux
+    cell (hidden in a map-wide L1 norm) would not be."""
+    for k in TALLIES:
+        d = np.abs(np.asarray(g[k], np.float64) - ref[k])
+        ratio = d / (1e-4 * np.abs(ref[k]) + 1e-9 * n + 0.5 * se[k])
+        strict = d / (1e-4 * np.abs(ref[k]) + 1e-9 * n)
+        print(f"{label}: {k} worst ratio to the bound {ratio.max():.2e} (to 1e-4 |ref| + 1e-9 n alone: "
+              f"{strict.max():.2e}, cells over it {int((strict > 1).sum())})")
+        assert ratio.max() <= 1.0, (k, ratio.max())
+
+
 def _gpu(binding, prob, n, seed, sampler, model=None, K=16, capacity=1 << 18):
     from paper_2512_13965_amd import transport
     w = binding.World(capacity, 2, max(prob.n_cells, 1 << 12))
@@ -35,13 +73,17 @@ def test_mc_transport_matches_oracle(orc, name, prob):
     binding = require_gpu()
     n = 20_000
     g = _gpu(binding, prob, n, seed=11, sampler=binding.SAMPLER_MC)
-    o = orc.transport(prob, seed=11, h_begin=0, h_end=n, nthreads=8)
+    o, se = oracle_batches(orc, prob, 11, n)
     rel = np.abs(g["flux"] - o["flux"]).sum() / np.abs(o["flux"]).sum()
     print(f"{name}: flux L1 rel diff {rel:.2e}; leak {g['leak'].sum():.6f} vs {o['leak']:.6f}; "
           f"absorbed {g['absorbed'].sum():.6f} vs {o['absorbed'].sum():.6f}")
     assert rel < 5e-5          # measured <= 3e-6
     assert abs(g["leak"].sum() - o["leak"]) <= 1e-3 * n
     assert abs(g["absorbed"].sum() - o["absorbed"].sum()) <= 1e-3 * n
+    # per cell: a low-flux cell must not hide inside the map's total
+    check_within_noise(g, o, se, n, name)
+    # every visit is a birth leg or a transmission of a step
+    assert g["visits"].sum() == n + g["transmissions"]
 
 
 @pytest.mark.parametrize("sampler", ["mc", "gmc"])
@@ -110,11 +152,12 @@ def test_cfg3_checkerboard_gpu_vs_oracle(orc):
     prob = inputs.checkerboard_problem(32)
     n = 100_000
     g = _gpu(binding, prob, n, 1, binding.SAMPLER_MC, capacity=1 << 20)
-    o = orc.transport(prob, seed=1, h_begin=0, h_end=n, nthreads=8)
+    o, se = oracle_batches(orc, prob, 1, n)
     rel = np.abs(g["flux"] - o["flux"]).sum() / np.abs(o["flux"]).sum()
     print(f"cfg3: flux L1 rel diff {rel:.2e}, transmissions {g['transmissions']}, steps {g['steps']}")
     assert rel < 5e-5          # measured <= 3e-6
     assert abs(g["absorbed"].sum() + g["leak"].sum() + g["cutoff"].sum() - n) < 1e-9 * n
+    check_within_noise(g, o, se, n, "cfg3")
 
 
 def test_eq12_error_decays_as_inverse_sqrt_n():
@@ -217,3 +260,31 @@ def test_visit_cap_matches_oracle_and_ends_every_history(orc):
     assert g2["cutoff"].sum() == pytest.approx(g1["cutoff"].sum(), rel=1e-6)
     assert np.abs(g2["flux"] - g1["flux"]).sum() / np.abs(g1["flux"]).sum() < 1e-6
     assert g2["steps"] < g1["steps"]
+
+
+def test_p3_mean_track_per_cell_visit_on_gpu(orc):
+    # P3 per cell type on the GPU path tallies: reflecting 4 x 4 checkerboard of pure scatterers
+    # (tau = 0.5 / 20), histories cut at visit M; the difference between two caps holds the
+    # visits M1 .. M2 - 1, whose mean track is pi L / 4 in every cell type (mean-chord
+    # invariance); and the GPU's differences equal the oracle's per cell
+    binding = require_gpu()
+    from paper_2512_13965_amd import transport
+    t = np.where((np.arange(4)[:, None] + np.arange(4)[None, :]) % 2 == 0, 0.5, 20.0).reshape(-1)
+    L, n = 0.5, 50_000
+    prob = inputs.Problem(4, 4, L, t, np.ones(16), 0, 0, 4, 4, reflect=True)
+    w = binding.World(1 << 17, 1, 1 << 8)
+    g, o = {}, {}
+    for M in (16, 64):
+        prob.max_visits = M
+        g[M] = transport.run_problem(w, prob, n, 8, binding.SAMPLER_MC)
+        o[M] = oracle_batches(orc, prob, 8, n)
+    w.close()
+    dl, dv = g[64]["path"] - g[16]["path"], g[64]["visits"] - g[16]["visits"]
+    assert dv.sum() == 48 * n
+    for sel in (t == 0.5, t == 20.0):
+        mean = dl[sel].sum() / dv[sel].sum()
+        tol = 4 * L * math.sqrt(4.0 / dv[sel].sum())
+        print(f"P3 cell type tau={t[sel][0]:g}: mean track per visit {mean:.5f} vs pi L / 4 = {math.pi * L / 4:.5f}")
+        assert abs(mean - math.pi * L / 4) < tol
+    for M in (16, 64):
+        check_within_noise(g[M], o[M][0], o[M][1], n, f"cap {M}")

@@ -78,10 +78,13 @@ def test_eq12_statistical_error_decays_as_inverse_sqrt_n(orc):
     assert abs(slope + 0.5) < 0.1
 
 
-def _global_walk_flux(prob, n, seed):
+def _global_walk_flux(prob, n, seed, paths=None):
     """Brute-force reference: one continuous random walk per history in global coordinates
     over the whole grid (no per-cell canonical frames), flights from the local sigma_s,
-    continuous absorption per segment, track-length tally per segment.  Pure Python."""
+    continuous absorption per segment, track-length tally per segment.  Pure Python.  With
+    `paths` (a dict), also the per-cell path tallies of every cell visit (from entering a cell
+    to leaving it): paths["wpath"] += w at entry * track length in the cell, paths["path"] +=
+    track length, paths["visits"] += 1."""
     g = np.random.default_rng(seed)
     L = prob.L
     Ly = prob.Ly if prob.Ly > 0 else L
@@ -92,6 +95,9 @@ def _global_walk_flux(prob, n, seed):
         st = math.sqrt(1.0 - (2.0 * g.random() - 1.0) ** 2) if prob.xy else 1.0
         return st * math.cos(ph), st * math.sin(ph)
     flux = np.zeros(prob.n_cells)
+    if paths is not None:
+        for k in ("wpath", "path", "visits"):
+            paths[k] = np.zeros(prob.n_cells)
     for _ in range(n):
         k = g.integers(prob.src_nx * prob.src_ny)
         ci = prob.src_x0 + k % prob.src_nx
@@ -101,6 +107,7 @@ def _global_walk_flux(prob, n, seed):
         u, v = direction()
         w = 1.0
         d_s = None
+        w_in, l_in = 1.0, 0.0
         while True:
             cell = cj * prob.nx + ci
             sig_t = prob.tau[cell] / L
@@ -117,11 +124,17 @@ def _global_walk_flux(prob, n, seed):
             w -= dw
             x += seg * u
             y += seg * v
+            l_in += seg
             if d_s < db:
                 u, v = direction()
                 d_s = None
                 continue
             d_s = None         # exponential flights are memoryless: redraw in the next cell
+            if paths is not None:
+                paths["wpath"][cell] += w_in * l_in
+                paths["path"][cell] += l_in
+                paths["visits"][cell] += 1.0
+            w_in, l_in = w, 0.0
             if tx <= ty:
                 ci += 1 if u > 0 else -1
             else:
@@ -143,12 +156,20 @@ def test_cell_to_cell_transport_matches_global_walk(orc, Ly, xy):
     c = np.array([0.9, 0.5, 0.99, 0.7, 0.8, 0.95, 0.3, 1.0, 0.6])
     prob = inputs.Problem(3, 3, 0.7, t, c, 1, 1, 1, 1, Ly=Ly, xy=xy)
     n, runs = 3000, 5
-    ref = np.array([_global_walk_flux(prob, n, seed=s) / n for s in range(runs)])
-    got = np.array([orc.transport(prob, seed=40 + s, h_begin=0, h_end=n, nthreads=NT)["flux"] / n
-                    for s in range(runs)])
+    refp = [dict() for _ in range(runs)]
+    ref = np.array([_global_walk_flux(prob, n, seed=s, paths=refp[s]) / n for s in range(runs)])
+    orcs = [orc.transport(prob, seed=40 + s, h_begin=0, h_end=n, nthreads=NT) for s in range(runs)]
+    got = np.array([o["flux"] / n for o in orcs])
     se = np.sqrt(ref.var(0, ddof=1) / runs + got.var(0, ddof=1) / runs)
     z = np.abs(ref.mean(0) - got.mean(0)) / np.maximum(se, 1e-12)
     assert z.max() < 5.0, z
+    # the path tallies of every cell visit (the third stage's physical track length)
+    for k in ("wpath", "path", "visits"):
+        a = np.array([r[k] / n for r in refp])
+        b = np.array([o[k] / n for o in orcs])
+        se = np.sqrt(a.var(0, ddof=1) / runs + b.var(0, ddof=1) / runs)
+        z = np.abs(a.mean(0) - b.mean(0)) / np.maximum(se, 1e-12)
+        assert z.max() < 5.0, (k, z)
 
 
 def test_visit_cap_ends_histories_that_would_never_end(orc):
@@ -167,3 +188,48 @@ def test_visit_cap_ends_histories_that_would_never_end(orc):
     o2 = orc.transport(prob, seed=3, h_begin=0, h_end=n, nthreads=4)
     assert o2["events"] == 2 * M * n
     assert 1.8 < o2["flux"].sum() / o["flux"].sum() < 2.2
+
+
+def test_path_tally_invariants(orc):
+    # with sigma_a = 0 the flux estimator of a visit is w_in * l / V, so flux * V equals the
+    # weighted path tally; elsewhere dw / sigma_a <= w_in * l; weights never exceed 1, so the
+    # unweighted path tally bounds the weighted one; every sampled transmission is one visit
+    prob = inputs.checkerboard_problem(8, tau=(0.5, 3.0), c=(1.0, 0.7), src=2)
+    n = 3000
+    r = orc.transport(prob, seed=6, h_begin=0, h_end=n, nthreads=NT)
+    V = prob.L ** 2
+    pure = prob.c == 1.0
+    np.testing.assert_allclose(r["flux"][pure] * V, r["wpath"][pure], rtol=1e-12)
+    assert np.all(r["flux"][~pure] * V <= r["wpath"][~pure] * (1 + 1e-12))
+    assert np.all(r["wpath"] <= r["path"] * (1 + 1e-12))
+    assert r["visits"].sum() == r["events"]
+    assert np.all(r["visits"] == np.round(r["visits"]))
+
+
+def test_p3_mean_track_per_cell_visit(orc):
+    # P3 (mean-chord invariance, per cell type): in a reflecting box of pure scatterers (any
+    # per-cell thickness) a uniform isotropic field stays uniform and isotropic, so a cell is
+    # entered uniformly along its faces with the cosine law and the mean track per entry is
+    # pi A / P = pi L / 4, whatever the cell's thickness.  Histories are cut at visit M; two caps
+    # M1 < M2 run the same random numbers for the first M1 visits, so the difference of the path
+    # tallies holds exactly the visits M1 .. M2 - 1 (entries long after the birth leg).
+    t = np.where((np.arange(4)[:, None] + np.arange(4)[None, :]) % 2 == 0, 0.5, 20.0).reshape(-1)
+    L = 0.5
+    prob = inputs.Problem(4, 4, L, t, np.ones(16), 0, 0, 4, 4, reflect=True)
+    n = 6000
+    out = {}
+    for M in (16, 64):
+        prob.max_visits = M
+        out[M] = orc.transport(prob, seed=8, h_begin=0, h_end=n, nthreads=NT)
+    dl = out[64]["path"] - out[16]["path"]
+    dv = out[64]["visits"] - out[16]["visits"]
+    assert dv.sum() == n * 48
+    thin = t == 0.5
+    for sel in (thin, ~thin):
+        mean = dl[sel].sum() / dv[sel].sum()
+        # per-visit tracks have a standard deviation below L; 4 sigma with room for the
+        # correlation along a history
+        tol = 4 * L * math.sqrt(4.0 / dv[sel].sum())
+        assert abs(mean - math.pi * L / 4) < tol, (mean, math.pi * L / 4, tol)
+    # the weighted tally equals the unweighted one (w = 1 throughout without absorption)
+    np.testing.assert_allclose(out[64]["wpath"], out[64]["path"], rtol=1e-12)
