@@ -106,6 +106,14 @@ typedef struct {
 
 typedef struct gmc_model gmc_model;
 
+/* Per-device set-up of the current device: queries its compute units and allocates the ring of
+ * 4096 work counters (32 KiB) that mc_transmit and mc_transmit_internal launches take in turn
+ * (kept until the process ends).  Needed once per device before those calls, which allocate
+ * nothing themselves (GMC_EINVAL if the device was not set up); gmc_model_create and
+ * gmc_world_create do it for their device.  Idempotent and thread-safe.  Errors: GMC_EDEVICE,
+ * GMC_ENOMEM, GMC_EUNSUPPORTED (device index beyond 63). */
+int gmc_device_init(void);
+
 /* Parses a weights blob and uploads it to the current device in the layout the kernels read.
  * Blob (little-endian): "GMCW0001", u32 version=1, n_in=10, hidden H, n_out=5, n_layers=5,
  * flags, seed, reserved; f32 act_scale[5], w_scale[5]; then per layer l = 1..5 the float32
@@ -198,6 +206,8 @@ int gmc_uncollided_split(gmc_cond cond, int64_t n, uint64_t seed, uint64_t id_ba
  *   2 -> absorption test.
  *   ncoll_opt  NULL, or device uint32 [n] receiving the number of collisions in the cell.
  * Errors: GMC_EINVAL, GMC_EDEVICE. */
+/* The walk's lanes take particles from a work counter of the ring gmc_device_init allocates
+ * (GMC_EINVAL if the current device was not set up); the call allocates nothing. */
 int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
                 gmc_exit out, uint32_t *ncoll_opt, void *stream);
 /* The analog walk of mc_transmit started inside the cell at (x, y) with direction
@@ -348,13 +358,6 @@ int gmc_problem_tally(gmc_world *w, int32_t pid, double *flux, double *absorbed,
  * Synchronises `stream`.  GMC_EINVAL for an unknown problem. */
 int gmc_problem_path_tally(gmc_world *w, int32_t pid, double *wpath, double *path, double *visits,
                            double *rejected_w, double *rejected_n, void *stream);
-
-/* Device diagnostic, not part of the paper's method: measures the sustained matrix-core
- * throughput (TFLOP/s, dense) of the MFMA instruction the sampler uses for `precision`
- * (FP32 32x32x2, BF16 32x32x16, FP8 e4m3 32x32x64) with waves_per_simd (1..4) independent
- * waves per SIMD on the current device.  Allocates and frees a small scratch buffer and
- * synchronises the device.  Used to read roofline fractions against what the chip sustains. */
-int gmc_probe_mfma_peak(int precision, int waves_per_simd, double *tflops);
 
 /* Thread-local description of the last error on this thread ("" if none). */
 const char *gmc_last_error(void);

@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgmc.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["gmc_mlp.hip", "gmc_walk.hip", "gmc_transport.hip", "gmc_probe.hip", "gmc_api.cpp"]
+SOURCES = ["gmc_mlp.hip", "gmc_walk.hip", "gmc_transport.hip", "gmc_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",
@@ -31,6 +31,46 @@ def _compile(src: str) -> str:
     if errs.strip():
         print(errs, file=sys.stderr)
     return out
+
+
+# Host-code sanitizer build (CPU checks only): AddressSanitizer and UndefinedBehaviorSanitizer
+# on the host side of every source, device code unchanged.  Loaded by the CPU tests with the
+# compiler's ASan runtime preloaded; never shipped as the product library.
+ASAN_LIB = os.path.join(BUILD, "libgmc_asan.so")
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"]
+
+
+def asan_runtime() -> str:
+    """Path of the compiler's shared AddressSanitizer runtime (to preload)."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "lib", "llvm", "bin", "clang")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang"
+    return subprocess.check_output([clang, "--print-file-name=libclang_rt.asan-x86_64.so"], text=True).strip()
+
+
+def _compile_asan(src: str) -> str:
+    out = os.path.join(BUILD, "asan_" + os.path.basename(src) + ".o")
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g"] + ASAN_HOST
+    r = subprocess.run([HIPCC, *flags, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc (sanitizer build) failed for {src}:\n{r.stdout}{r.stderr}")
+    return out
+
+
+def build_asan() -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(_compile_asan, srcs))
+    tmp = ASAN_LIB + ".tmp"
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *ASAN_HOST[:4],
+                        "-Xarch_host", "-shared-libsan", "-o", tmp, *objs], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("sanitizer link failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
 
 
 def build(verbose: bool = False) -> str:

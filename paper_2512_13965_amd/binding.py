@@ -68,12 +68,24 @@ def lib() -> ctypes.CDLL:
         L.gmc_sample_internal.argtypes = [P, _CondInternal, I64, I, I, U64, U64, P, P, _Exit, P]
         L.mc_transmit_internal.argtypes = [_CondInternal, I64, I, U64, U64, _Exit, P, P]
         L.gmc_uncollided_split.argtypes = [_Cond, I64, U64, U64, P, _Exit, P]
+        L.gmc_device_init.argtypes = []
         for name in ("gmc_model_create", "gmc_model_destroy", "gmc_model_info", "gmc_transmit",
                      "mc_transmit", "gmc_decode", "gmc_sample", "gmc_model_inputs",
-                     "gmc_sample_internal", "mc_transmit_internal", "gmc_uncollided_split"):
+                     "gmc_sample_internal", "mc_transmit_internal", "gmc_uncollided_split", "gmc_device_init"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
+
+
+_ready_devices = set()
+
+
+def device_init():
+    """gmc_device_init on the current device (once per device): the analog walk's counters."""
+    dev = torch.cuda.current_device()
+    if dev not in _ready_devices:
+        _check(lib().gmc_device_init())
+        _ready_devices.add(dev)
 
 
 def _check(rc: int):
@@ -281,6 +293,7 @@ def mc_transmit_internal(cond: DeviceCondInternal, mode: int, seed: int, id_base
         out = DeviceExit.empty(n, cond.log_tau.device)
     if ncoll is not None:
         _need(ncoll, torch.int32, n, "ncoll")
+    device_init()
     _check(lib().mc_transmit_internal(cond.c_struct(), n, int(mode), seed, id_base, out.c_struct(n),
                                       _ptr(ncoll), _stream(stream)))
     return out
@@ -294,6 +307,7 @@ def mc_transmit(cond: DeviceCond, mode: int, seed: int, id_base: int = 0,
         out = DeviceExit.empty(n, cond.log_tau.device)
     if ncoll is not None:
         _need(ncoll, torch.int32, n, "ncoll")
+    device_init()
     _check(lib().mc_transmit(cond.c_struct(), n, int(mode), seed, id_base, out.c_struct(n),
                              _ptr(ncoll), _stream(stream)))
     return out
@@ -464,15 +478,3 @@ class World:
             self.close()
         except Exception:
             pass
-
-
-def probe_mfma_peak(precision, waves_per_simd: int = 2) -> float:
-    """Sustained dense MFMA TFLOP/s of the sampler's instruction for `precision` (diagnostic)."""
-    if isinstance(precision, str):
-        precision = PRECISIONS[precision]
-    L = lib()
-    L.gmc_probe_mfma_peak.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
-    L.gmc_probe_mfma_peak.restype = ctypes.c_int
-    t = ctypes.c_double()
-    _check(L.gmc_probe_mfma_peak(int(precision), waves_per_simd, ctypes.byref(t)))
-    return t.value

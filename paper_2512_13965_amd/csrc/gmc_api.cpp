@@ -88,6 +88,7 @@ unsigned long long *g_queue[64] = {nullptr};
 unsigned g_queue_next[64] = {0};
 constexpr int kQueueRing = 4096;
 
+
 }  // namespace
 
 namespace gmc {
@@ -105,18 +106,15 @@ int device_cu_count()
     return g_cu[dev];
 }
 
-// A ring of per-call work counters on the current device (allocated once, kept until the
-// process ends).  Each launch takes the next slot and zeroes it on its own stream first.
+// A ring of per-call work counters on the current device (allocated by gmc_device_init, kept
+// until the process ends).  Each launch takes the next slot and zeroes it on its own stream
+// first.
 unsigned long long *device_queue_counter()
 {
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
     std::lock_guard<std::mutex> lk(g_dev_mu);
-    if (!g_queue[dev]) {
-        void *p = nullptr;
-        if (hipMalloc(&p, sizeof(unsigned long long) * kQueueRing) != hipSuccess) return nullptr;
-        g_queue[dev] = (unsigned long long *)p;
-    }
+    if (!g_queue[dev]) return nullptr;
     unsigned slot = g_queue_next[dev]++ % kQueueRing;
     return g_queue[dev] + slot;
 }
@@ -131,6 +129,23 @@ int set_hip_error(hipError_t e, const char *what) { return hip_fail(e, what); }
 extern "C" {
 
 const char *gmc_last_error(void) { return g_err.c_str(); }
+
+int gmc_device_init(void)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "gmc_device_init: hipGetDevice");
+    if (dev < 0 || dev >= 64) return fail(GMC_EUNSUPPORTED, "gmc_device_init: device index beyond 63");
+    if (gmc::device_cu_count() <= 0) return fail(GMC_EDEVICE, "gmc_device_init: cannot query the device");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_queue[dev]) {
+        void *p = nullptr;
+        e = hipMalloc(&p, sizeof(unsigned long long) * kQueueRing);
+        if (e != hipSuccess) return fail(GMC_ENOMEM, "gmc_device_init: cannot allocate the walk's work counters");
+        g_queue[dev] = (unsigned long long *)p;
+    }
+    return GMC_OK;
+}
 
 int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_model **out)
 {
@@ -174,6 +189,9 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         for (int i = 0; i < dims[l][0] * (dims[l][1] + 1); ++i)
             if (!std::isfinite(W[l][i])) return fail(GMC_EINVAL, "gmc_model_create: non-finite weight");
     }
+
+    const int irc = gmc_device_init();     // the blob is valid: set up the device
+    if (irc != GMC_OK) return irc;
 
     // arrange every layer into fragment order, then one device allocation for all of it
     std::vector<std::vector<uint8_t>> frag(5);
@@ -353,7 +371,7 @@ int launch_walk_api(gmc::WalkParams p, int64_t n, int mode, uint64_t seed, uint6
     p.seed = seed;
     p.id_base = id_base;
     p.queue = gmc::device_queue_counter();
-    if (!p.queue) return fail(GMC_ENOMEM, w + ": cannot allocate the work counter");
+    if (!p.queue) return fail(GMC_EINVAL, w + ": gmc_device_init has not been called on this device");
     const int cu = gmc::device_cu_count();
     if (cu <= 0) return fail(GMC_EDEVICE, w + ": cannot query the device");
     const int grid = gmc::walk_grid(n, cu);

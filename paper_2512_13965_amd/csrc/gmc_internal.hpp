@@ -116,6 +116,8 @@ hipError_t launch_decode(const float *raw, int64_t n, int32_t *face, float *pos,
                          float *dsin, float *path, int32_t *flags, hipStream_t s);
 
 int device_cu_count();
+// The next work counter of the analog walk's ring on the current device (allocated by
+// gmc_device_init), or nullptr if the device has not been set up.
 unsigned long long *device_queue_counter();
 
 // Record a thread-local error message (returned by gmc_last_error) and return `code`.

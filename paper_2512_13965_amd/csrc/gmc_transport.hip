@@ -794,6 +794,8 @@ int gmc_world_create(int64_t bank_capacity, int32_t max_problems, int64_t max_ce
     if (bank_capacity <= 0 || bank_capacity > ((int64_t)1 << 31) || max_problems <= 0 ||
         max_problems > 65536 || max_cells <= 0 || max_cells > ((int64_t)1 << 31))
         return set_error(GMC_EINVAL, "gmc_world_create: capacity out of range");
+    const int irc = gmc_device_init();
+    if (irc != GMC_OK) return irc;
     gmc_world *w = new gmc_world();
     w->cap = bank_capacity;
     w->max_problems = max_problems;

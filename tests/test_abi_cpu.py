@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import numpy as np
 import pytest
@@ -46,57 +47,19 @@ def test_every_declared_symbol_is_exported(binding):
     assert not missing, missing
 
 
-def _blob(H=256):
-    return bytearray(inputs.pack_blob(inputs.random_weights(H, 1)))
+def test_host_checks(binding):
+    from tests import abi_host_checks
+    abi_host_checks.run(binding.lib())
 
 
-def _create(binding, blob, prec):
-    h = ctypes.c_void_p()
-    buf = ctypes.create_string_buffer(bytes(blob), len(blob))
-    return binding.lib().gmc_model_create(buf, len(blob), prec, ctypes.byref(h))
-
-
-def test_model_create_rejects_bad_blobs(binding):
-    L = binding.lib()
-    b = _blob()
-    bad = bytearray(b); bad[0:8] = b"XXXXXXXX"
-    assert _create(binding, bad, binding.FP32) == binding.GMC_EINVAL
-    assert b"magic" in L.gmc_last_error()
-    assert _create(binding, b[:-4], binding.FP32) == binding.GMC_EINVAL
-    assert _create(binding, b, 7) == binding.GMC_EINVAL
-    w = inputs.random_weights(256, 1)
-    w.act_scale[2] = 0.3
-    assert _create(binding, inputs.pack_blob(w), binding.FP8_E4M3) == binding.GMC_EINVAL
-    w = inputs.random_weights(256, 1)
-    w.W[1][3, 4] = np.nan
-    assert _create(binding, inputs.pack_blob(w), binding.FP32) == binding.GMC_EINVAL
-    # FP32 is built for H <= 256 only; H = 64 is built for no precision
-    assert _create(binding, _blob(512), binding.FP32) == binding.GMC_EUNSUPPORTED
-    assert _create(binding, _blob(64), binding.BF16) == binding.GMC_EUNSUPPORTED
-    # blob flags: bit 0 XY geometry (11 inputs), bit 1 fitted on collided exits (boundary models)
-    assert _create(binding, inputs.pack_blob(inputs.random_weights(256, 1, flags=4)),
-                   binding.FP32) == binding.GMC_EINVAL
-    assert _create(binding, inputs.pack_blob(inputs.random_weights(256, 1, flags=1)),
-                   binding.FP32) == binding.GMC_EINVAL
-    assert _create(binding, inputs.pack_blob(inputs.random_weights(256, 1, n_in=inputs.N_IN_INTERNAL,
-                                                                   flags=2)), binding.FP32) == binding.GMC_EINVAL
-
-
-def test_sampling_calls_reject_bad_arguments_without_a_device(binding):
-    L = binding.lib()
-    cond = binding._Cond(None, None, None, None)
-    out = binding._Exit(None, None, None, None, None)
-    assert L.gmc_transmit(None, cond, 10, 16, 0, 0, None, None, out, None) == binding.GMC_EINVAL
-    assert L.mc_transmit(cond, 10, 5, 0, 0, out, None, None) == binding.GMC_EINVAL
-    assert L.mc_transmit(cond, -1, 0, 0, 0, out, None, None) == binding.GMC_EINVAL
-    assert L.mc_transmit(cond, 0, 0, 0, 0, out, None, None) == binding.GMC_OK     # empty batch
-    assert L.mc_transmit(cond, 10, 0, 0, 0, out, None, None) == binding.GMC_EINVAL
-    assert L.gmc_decode(None, 10, out, None, None) == binding.GMC_EINVAL
-    assert L.gmc_uncollided_split(cond, 10, 0, 0, None, out, None) == binding.GMC_EINVAL
-    assert L.gmc_uncollided_split(cond, -1, 0, 0, None, out, None) == binding.GMC_EINVAL
-    assert L.gmc_uncollided_split(cond, 0, 0, 0, None, out, None) == binding.GMC_OK
-    L.gmc_world_set_streaming.argtypes = [ctypes.c_void_p, ctypes.c_int]
-    L.gmc_world_transmissions.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
-    assert L.gmc_world_set_streaming(None, 4) == binding.GMC_EINVAL
-    assert L.gmc_world_transmissions(None, None) == binding.GMC_EINVAL
-    assert L.gmc_model_destroy(None) == binding.GMC_EINVAL
+def test_host_checks_under_address_and_undefined_behaviour_sanitizers():
+    # the host code (blob parsing, argument checks) built with -fsanitize=address,undefined on the
+    # host side only, exercised in a child process with the sanitizer runtime preloaded
+    from paper_2512_13965_amd import _build
+    lib = _build.ASAN_LIB if os.path.exists(_build.ASAN_LIB) else _build.build_asan()
+    env = dict(os.environ, LD_PRELOAD=_build.asan_runtime(), ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1", PYTHONPATH=ROOT)
+    r = subprocess.run([sys.executable, "-m", "tests.abi_host_checks", lib], cwd=ROOT, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "host checks passed" in r.stdout, r.stdout + r.stderr
+    assert "runtime error" not in r.stderr and "AddressSanitizer" not in r.stderr, r.stderr
