@@ -210,6 +210,17 @@ int gmc_uncollided_split(gmc_cond cond, int64_t n, uint64_t seed, uint64_t id_ba
  * (GMC_EINVAL if the current device was not set up); the call allocates nothing. */
 int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
                 gmc_exit out, uint32_t *ncoll_opt, void *stream);
+/* mc_transmit for callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the same walk, arguments, random
+ * streams and outputs, bit for bit, but its work counter is one of 64 counters of a fixed
+ * 512-byte device array that the library holds on each GPU until the process ends (its address
+ * looked up by gmc_device_init, which must have run on the current device: GMC_EINVAL
+ * otherwise).  The call allocates nothing, calls no allocating routine and records no memset:
+ * it zeroes its counter with a kernel on `stream`.  Calls take the 64 counters in turn; calls
+ * that overlap on one GPU (other streams, or more than 64 in flight) may share a counter and
+ * then race.  Errors as mc_transmit, plus GMC_EINVAL for n beyond 2^62 (the counter's range). */
+int mc_transmit_noalloc(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,
+                        gmc_exit out, uint32_t *ncoll_opt, void *stream);
 /* The analog walk of mc_transmit started inside the cell at (x, y) with direction
  * (cos_phi, sin_phi) (the walk the internal model replaces); same modes, random streams,
  * outputs and errors.  The first flight starts at the birth point. */

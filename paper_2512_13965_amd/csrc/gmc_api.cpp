@@ -87,6 +87,11 @@ int g_cu[64] = {0};
 unsigned long long *g_queue[64] = {nullptr};
 unsigned g_queue_next[64] = {0};
 constexpr int kQueueRing = 4096;
+unsigned long long *g_noalloc[64] = {nullptr};   // address of the allocation-free walk's counters
+unsigned g_noalloc_next[64] = {0};
+// Largest n of mc_transmit_noalloc: its work counter (64 bits) runs up to n plus one chunk
+// per wave.
+constexpr int64_t kNoAllocMaxN = (int64_t)1 << 62;
 
 
 }  // namespace
@@ -119,6 +124,18 @@ unsigned long long *device_queue_counter()
     return g_queue[dev] + slot;
 }
 
+// The next counter of the allocation-free walk on the current device, or nullptr if the device
+// has not been set up.
+unsigned long long *noalloc_counter()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return nullptr;
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_noalloc[dev]) return nullptr;
+    unsigned slot = g_noalloc_next[dev]++ % gmc::kNoAllocCounters;
+    return g_noalloc[dev] + slot;
+}
+
 }  // namespace gmc
 
 namespace gmc {
@@ -143,6 +160,12 @@ int gmc_device_init(void)
         e = hipMalloc(&p, sizeof(unsigned long long) * kQueueRing);
         if (e != hipSuccess) return fail(GMC_ENOMEM, "gmc_device_init: cannot allocate the walk's work counters");
         g_queue[dev] = (unsigned long long *)p;
+    }
+    if (!g_noalloc[dev]) {     // once per device, with that device current
+        unsigned long long *base = nullptr;
+        e = gmc::lookup_noalloc_counters(&base);
+        if (e != hipSuccess) return hip_fail(e, "gmc_device_init: looking up the allocation-free walk's counters");
+        g_noalloc[dev] = base;
     }
     return GMC_OK;
 }
@@ -352,7 +375,7 @@ int launch_sampler(const gmc_model *m, gmc::MlpParams p, int64_t n, int integrat
 }
 
 int launch_walk_api(gmc::WalkParams p, int64_t n, int mode, uint64_t seed, uint64_t id_base, gmc_exit out,
-                    uint32_t *ncoll_opt, void *stream, const char *who)
+                    uint32_t *ncoll_opt, void *stream, const char *who, bool noalloc = false)
 {
     const std::string w(who);
     if (mode != GMC_MODE_CONTINUOUS && mode != GMC_MODE_ANALOG)
@@ -370,7 +393,7 @@ int launch_walk_api(gmc::WalkParams p, int64_t n, int mode, uint64_t seed, uint6
     p.mode = mode;
     p.seed = seed;
     p.id_base = id_base;
-    p.queue = gmc::device_queue_counter();
+    p.queue = noalloc ? gmc::noalloc_counter() : gmc::device_queue_counter();
     if (!p.queue) return fail(GMC_EINVAL, w + ": gmc_device_init has not been called on this device");
     const int cu = gmc::device_cu_count();
     if (cu <= 0) return fail(GMC_EDEVICE, w + ": cannot query the device");
@@ -442,6 +465,23 @@ int mc_transmit(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_b
     p.log_aspect = cond.log_aspect;
     p.omega_x = cond.omega_x;
     return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit");
+}
+
+int mc_transmit_noalloc(gmc_cond cond, int64_t n, int mode, uint64_t seed, uint64_t id_base, gmc_exit out,
+                        uint32_t *ncoll_opt, void *stream)
+{
+    if (n < 0) return fail(GMC_EINVAL, "mc_transmit_noalloc: negative n");
+    if (n > kNoAllocMaxN)
+        return fail(GMC_EINVAL, "mc_transmit_noalloc: n beyond 2^62, the range of its work counter");
+    if (n > 0 && !cond_ok(cond)) return fail(GMC_EINVAL, "mc_transmit_noalloc: null condition array");
+    gmc::WalkParams p{};
+    p.log_tau = cond.log_tau;
+    p.c = cond.c;
+    p.y_in = cond.y_in;
+    p.sin_th = cond.sin_th;
+    p.log_aspect = cond.log_aspect;
+    p.omega_x = cond.omega_x;
+    return launch_walk_api(p, n, mode, seed, id_base, out, ncoll_opt, stream, "mc_transmit_noalloc", true);
 }
 
 int mc_transmit_internal(gmc_cond_internal cond, int64_t n, int mode, uint64_t seed, uint64_t id_base,

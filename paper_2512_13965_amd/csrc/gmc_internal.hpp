@@ -119,6 +119,11 @@ int device_cu_count();
 // The next work counter of the analog walk's ring on the current device (allocated by
 // gmc_device_init), or nullptr if the device has not been set up.
 unsigned long long *device_queue_counter();
+// Work counters of the allocation-free walk (mc_transmit_noalloc): a file-scope device array of
+// kNoAllocCounters counters in gmc_walk.hip.  lookup_noalloc_counters gives its address on the
+// current device (a host-side lookup, no allocation).
+constexpr int kNoAllocCounters = 64;
+hipError_t lookup_noalloc_counters(unsigned long long **base);
 
 // Record a thread-local error message (returned by gmc_last_error) and return `code`.
 int set_error(int code, const char *msg);

@@ -11,6 +11,22 @@
 #include "gmc_internal.hpp"
 
 namespace gmc {
+
+// Work counters of the allocation-free walk: every GPU the library runs on holds this array
+// until the process ends; each mc_transmit_noalloc call on a device takes the next of its
+// kNoAllocCounters counters in turn and zeroes it with a kernel before the walk.
+static __device__ __align__(256) unsigned long long scratch[kNoAllocCounters];
+
+// Device address of `scratch` on the current device (each device has its own copy).  Host code
+// passes this address to kernels, never the array's name.
+hipError_t lookup_noalloc_counters(unsigned long long **base)
+{
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+    *base = e == hipSuccess ? (unsigned long long *)ptr : nullptr;
+    return e;
+}
+
 namespace {
 
 __device__ __forceinline__ int lane_rank(uint64_t mask)
