@@ -39,6 +39,14 @@
 #ifndef GMC_PFA
 #define GMC_PFA 2
 #endif
+// Drains of the two-group schedule: 1 = software-pipelined epilogue (drain_pipe), 0 = one
+// accumulator tile at a time (epi_tile).  GMC_PIPE_D: iterations between a value's stages.
+#ifndef GMC_DRAIN_PIPE
+#define GMC_DRAIN_PIPE 1
+#endif
+#ifndef GMC_PIPE_D
+#define GMC_PIPE_D 1
+#endif
 // 8: BF16 / FP8 models of width >= 256 use the two-group schedule (eight waves); 4: they use
 // the single-group cross-layer pipeline (four waves).  Both give bit-identical results.
 #ifndef GMC_WIDE_WAVES
@@ -218,10 +226,11 @@ __device__ __forceinline__ uint32_t pack_bf16(float a, float b)
 
 __device__ __forceinline__ uint32_t pack_fp8x4(float a, float b, float c, float d)
 {
-    a = fminf(fmaxf(a, -448.0f), 448.0f);
-    b = fminf(fmaxf(b, -448.0f), 448.0f);
-    c = fminf(fmaxf(c, -448.0f), 448.0f);
-    d = fminf(fmaxf(d, -448.0f), 448.0f);
+    // saturate to the largest finite e4m3 value (one median-of-three each)
+    a = __builtin_amdgcn_fmed3f(a, -448.0f, 448.0f);
+    b = __builtin_amdgcn_fmed3f(b, -448.0f, 448.0f);
+    c = __builtin_amdgcn_fmed3f(c, -448.0f, 448.0f);
+    d = __builtin_amdgcn_fmed3f(d, -448.0f, 448.0f);
     int w = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
     w = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, w, true);
     return (uint32_t)w;
@@ -299,6 +308,49 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
 #pragma unroll
     for (int g = 0; g < 4; ++g) epi_unit<PO, SCALE>(acc, g, oscale, inv_next, &w[g * WPU]);
 #endif
+}
+
+// The SiLU epilogue of the NT accumulator tiles a(t) (16 values each, value i = 16 t + i % 16),
+// software-pipelined: iteration j issues the first multiply of value j, the exponential of value
+// j - D, the add of value j - 2D, the reciprocal of value j - 3D and the final multiply of value
+// j - 4D -- independent instructions -- and packs groups of values as they complete;
+// store(t, words) receives each tile's packed words (the layout of epi_tile) once its last value
+// is done.  The arithmetic is epi_tile's: acc * c1 is -log2(e) times the scaled pre-activation,
+// and with per-layer scales the output factor c2 = oscale * inv_next (a power of two) moves into
+// the reciprocal's argument, acc * rcp((1 + e) / c2) being exactly (acc * c2) * rcp(1 + e).
+template <int PO, bool SCALE, int NT, typename Val, typename Store>
+__device__ __forceinline__ void drain_pipe(Val &&val, float oscale, float inv_next, Store &&store)
+{
+    constexpr int NV = NT * 16;
+    constexpr int D = GMC_PIPE_D;
+    const float c1 = SCALE ? -1.4426950408889634f * oscale : -1.4426950408889634f;
+    const float k = SCALE ? 1.0f / (oscale * inv_next) : 1.0f;
+    float t[NV], y[NV];
+    uint32_t wd[NT][4 * words_per_unit(PO)];
+    sfor<NV + 4 * D>([&](auto J) {
+        constexpr int j = decltype(J)::value;
+        if constexpr (j < NV) t[j] = c1 * val(std::integral_constant<int, j>{});
+        if constexpr (j - D >= 0 && j - D < NV) t[j - D] = __builtin_amdgcn_exp2f(t[j - D]);
+        if constexpr (j - 2 * D >= 0 && j - 2 * D < NV) {
+            if constexpr (SCALE) t[j - 2 * D] = __builtin_fmaf(t[j - 2 * D], k, k);
+            else t[j - 2 * D] = 1.0f + t[j - 2 * D];
+        }
+        if constexpr (j - 3 * D >= 0 && j - 3 * D < NV) t[j - 3 * D] = __builtin_amdgcn_rcpf(t[j - 3 * D]);
+        if constexpr (j - 4 * D >= 0 && j - 4 * D < NV) {
+            constexpr int i = j - 4 * D;
+            y[i] = val(std::integral_constant<int, i>{}) * t[i];
+            constexpr int tt = i / 16, v = i % 16;
+            if constexpr (PO == kF32) {
+                wd[tt][v] = __builtin_bit_cast(uint32_t, y[i]);
+            } else if constexpr (PO == kBF16) {
+                if constexpr (v % 2 == 1) wd[tt][v / 2] = pack_bf16(y[i - 1], y[i]);
+            } else {
+                if constexpr (v % 4 == 3) wd[tt][v / 4] = pack_fp8x4(y[i - 3], y[i - 2], y[i - 1], y[i]);
+            }
+            if constexpr (v == 15) store(std::integral_constant<int, tt>{}, wd[tt]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
 }
 
 // Store the packed epilogue of accumulator tile (row tile T, column tile c) into the LDS
@@ -669,6 +721,19 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     constexpr int PO = decltype(POC)::value;
                     using A = std::remove_reference_t<decltype(a)>;
                     constexpr int RX = std::extent_v<A, 0>, CX = std::extent_v<A, 1>;
+#if GMC_DRAIN_PIPE
+                    drain_pipe<PO, C::SCALE, RX * CX>(
+                        [&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            return a[(i / 16) / CX][(i / 16) % CX][i % 16];
+                        },
+                        osc, inv,
+                        [&](auto TT, const uint32_t *wd) {
+                            constexpr int tt = decltype(TT)::value;
+                            store_tile<PO>(wd, (T0 + tt / CX) ^ xt, c0 + tt % CX, act, C::ACT_STRIDE, lane);
+                        });
+                    return;
+#endif
                     sfor<RX * CX>([&](auto TC) {
                         constexpr int r = decltype(TC)::value / CX, c = decltype(TC)::value % CX;
                         uint32_t wd[4 * words_per_unit(PO)];
@@ -679,6 +744,19 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 auto drain = [&](auto POC, float osc, float inv, int xt = 0) {
                     constexpr int PO = decltype(POC)::value;
                     constexpr int WPU = words_per_unit(PO);
+#if GMC_DRAIN_PIPE
+                    drain_pipe<PO, C::SCALE, RG * 4>(
+                        [&](auto I) {
+                            constexpr int i = decltype(I)::value;
+                            return acc[(i / 16) / 4][(i / 16) % 4][i % 16];
+                        },
+                        osc, inv,
+                        [&](auto TT, const uint32_t *wd) {
+                            constexpr int tt = decltype(TT)::value;
+                            store_tile<PO>(wd, (TB + tt / 4) ^ xt, tt % 4, act, C::ACT_STRIDE, lane);
+                        });
+                    return;
+#endif
                     sfor<RG * 4>([&](auto TC) {
                         constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
                         uint32_t wd[4 * WPU];
