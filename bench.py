@@ -128,7 +128,7 @@ def cpu_baseline(w, K, budget_s=20.0):
     import oracle
     from threadpoolctl import threadpool_info
     from paper_2512_13965_amd import inputs
-    probe = 128
+    probe = 2048
     cond = inputs.transmission_conditions(probe, 3)
     t0 = time.perf_counter()
     oracle.sample_raw(w, cond, K, oracle.noise(2, 0, probe))
@@ -286,6 +286,16 @@ def bench_serving(binding, inputs, w512, n_req, hist_log10=(4.0, 7.0), load=0.7)
 # longer studies (--study)
 # ------------------------------------------------------------------------------------------
 
+def sampler_health(r: dict, n: int) -> dict:
+    """Rejected generative samples in one transport run (decoded exits outside the cell, turned
+    into cutoff weight): their share of the transmissions, the weight they removed per history,
+    and the whole cutoff weight per history."""
+    tx = max(int(r["transmissions"]), 1)
+    return {"rejected_fraction": float(r["rejected_n"].sum() / tx),
+            "rejected_weight_per_history": float(r["rejected_w"].sum() / n),
+            "cutoff_per_history": float(r["cutoff"].sum() / n)}
+
+
 def study_convergence(binding, inputs, w512, Ns=None, runs=5):
     """Statistical convergence (paper "Convergence and Performance", eq. 12) on the 32 x 32
     checkerboard ((tau, c) = (0.5, 0.5) / (50, 0.99), central 4 x 4 source, vacuum): the
@@ -300,15 +310,17 @@ def study_convergence(binding, inputs, w512, Ns=None, runs=5):
     out = {"problem": "32x32 checkerboard (0.5,0.5)/(50,0.99), central 4x4 source, vacuum", "N": Ns,
            "runs": runs}
     for kind, smp, mm in (("analog", binding.SAMPLER_MC, None), ("gmc_bf16_h512_k16", binding.SAMPLER_GMC, m)):
-        sig, secs = [], []
+        sig, secs, health = [], [], []
         for N in Ns:
             t0 = time.perf_counter()
-            maps = np.array([transport.run_problem(world, prob, N, 5000 + 101 * k, smp, mm, 16)["flux"] / N
-                             for k in range(runs)])
+            rs = [transport.run_problem(world, prob, N, 5000 + 101 * k, smp, mm, 16) for k in range(runs)]
             secs.append(time.perf_counter() - t0)
+            maps = np.array([r["flux"] / N for r in rs])
             sig.append(float(np.mean(maps.std(0, ddof=1))))
+            health.append(sampler_health({k: sum(r[k] for r in rs) for k in ("transmissions", "rejected_n",
+                                                                            "rejected_w", "cutoff")}, N * runs))
             log(f"convergence {kind} N={N}: sigma {sig[-1]:.3e} ({secs[-1]:.1f} s)")
-        out[kind] = {"sigma": sig, "seconds": secs,
+        out[kind] = {"sigma": sig, "seconds": secs, "health": health,
                      "slope": float(np.polyfit(np.log(Ns), np.log(sig), 1)[0])}
     out["sigma_ratio_gmc_over_mc"] = [g / a for g, a in zip(out["gmc_bf16_h512_k16"]["sigma"], out["analog"]["sigma"])]
     world.close()
@@ -338,8 +350,7 @@ def study_transport(binding, inputs, w512, n=1_000_000):
         flux[name] = r["flux"] / n
         out[name] = {"seconds": dt, "histories_per_s": n / dt, "transmissions": int(r["transmissions"]),
                      "transmissions_per_s": r["transmissions"] / dt, "steps": r["steps"],
-                     "leak_per_history": float(r["leak"].sum() / n),
-                     "cutoff_per_history": float(r["cutoff"].sum() / n)}
+                     "leak_per_history": float(r["leak"].sum() / n), **sampler_health(r, n)}
         log(f"transport {name}: {dt:.2f} s")
     for name in flux:
         if name != "analog":
@@ -376,7 +387,7 @@ def study_paper_scale(binding, inputs, w512, n=200_000):
             dt = time.perf_counter() - t0
             flux[name] = r["flux"] / n
             res[name] = {"seconds": dt, "transmissions_per_s": r["transmissions"] / dt,
-                         "leak_per_history": float(r["leak"].sum() / n)}
+                         "leak_per_history": float(r["leak"].sum() / n), **sampler_health(r, n)}
             log(f"{pname} {name}: {dt:.2f} s")
         l1 = lambda a: float(np.abs(a - flux["analog"]).sum() / np.abs(flux["analog"]).sum())
         for name in flux:
@@ -413,7 +424,7 @@ def study_thick(binding, inputs, n=50_000):
             t0 = time.perf_counter()
             runs[rn] = transport.run_problem(world, prob, n, seed, smp, mm, K, integrator=integ)
             torch.cuda.synchronize()
-            res[rn] = {"seconds": time.perf_counter() - t0}
+            res[rn] = {"seconds": time.perf_counter() - t0, **sampler_health(runs[rn], n)}
             log(f"{name} {rn}: {res[rn]['seconds']:.2f} s")
         world.close()
         l1 = lambda a, b: float(np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum())
