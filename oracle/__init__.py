@@ -9,8 +9,8 @@ Contents
   * `gmc_oracle.c` (built to `liboracle.so`): Philox4x32-10, Box-Muller noise, the analog
     walk through one cell in FP64 (modes C and A), and FP64 cell-to-cell transport.
   * this module: ctypes bindings for the above, and the FP64 velocity-MLP sampler (explicit
-    Euler and classic RK4) with optional BF16 / FP8-e4m3 quantisation emulation, plus the exit
-    decoder.
+    Euler and classic RK4) with optional BF16 / FP8-e4m3 quantisation emulation, the residual
+    network with adaptive modulation (FP64 or BF16 operands), plus the exit decoder.
 
 Paper references are to arXiv 2512.13965 (sections and equation numbers in order of
 appearance).
@@ -270,10 +270,55 @@ def layer_affine(weights, l: int, h, precision=PREC_FP64):
     return h @ W.T + b
 
 
+def time_features(t) -> np.ndarray:
+    """Time input of the residual network (its learned time embedding starts from these):
+    sin and cos of pi 2^j t for j = 0, 1, 2, 3, as [sin pi t, cos pi t, sin 2 pi t, ...].  The
+    lowest frequency makes t = 0 and t = 1 distinct."""
+    out = []
+    for j in range(4):
+        a = math.pi * (2.0 ** j) * float(t)
+        out += [math.sin(a), math.cos(a)]
+    return np.array(out)
+
+
+def film_velocity(weights, x, t, condf, precision=PREC_FP64):
+    """v_theta(x, t | c) of the residual network with adaptive modulation (paper "Network
+    Architecture and Inputs": learned embeddings of t and c, residual blocks modulated by the
+    physical context; the layer details are this library's reading).  With phi = time_features(t)
+    and u = [x, phi, c]:
+        h_0 = W_in u + b_in
+        e   = SiLU(W_e [phi, c] + b_e)                       (the embedding, width E)
+        for each block j:  h_j = h_{j-1} + SiLU((1 + G_j e + g_j) * (A_j h_{j-1} + a_j)
+                                                  + (S_j e + s_j))
+        v   = W_o h_B + b_o
+    PREC_BF16: every layer's input and weights rounded to bfloat16 (layer_affine's reading),
+    and the residual stream h_j stored in bfloat16 (rounded after each block's sum)."""
+    if precision not in (PREC_FP64, PREC_BF16):
+        raise ValueError("the residual network is evaluated in FP64 or with BF16 operands")
+    rd = round_bf16 if precision == PREC_BF16 else (lambda a: np.asarray(a, np.float64))
+    W = [w.astype(np.float64) for w in weights.W]
+    b = [v.astype(np.float64) for v in weights.b]
+    lin = lambda l, a: rd(a) @ rd(W[l]).T + b[l]
+    n = x.shape[0]
+    phi = np.broadcast_to(time_features(t), (n, 8))
+    h = rd(lin(0, np.concatenate([x, phi, condf], axis=1)))
+    e = silu(lin(1, np.concatenate([phi, condf], axis=1)))
+    nb = (len(W) - 3) // 3
+    for j in range(nb):
+        a = lin(2 + 3 * j, h)
+        scale = 1.0 + lin(3 + 3 * j, e)
+        shift = lin(4 + 3 * j, e)
+        h = rd(h + silu(scale * a + shift))
+    return lin(2 + 3 * nb, h)
+
+
 def velocity(weights, x, t, condf, precision=PREC_FP64):
     """v_theta(x, t | c) for a batch: x [n,5], t scalar, condf [n,4] -> [n,5].
     Layers: Linear(10,H) SiLU, 3 x (Linear(H,H) SiLU), Linear(H,5); the input of the first
-    layer is [x, t, condition]."""
+    layer is [x, t, condition].  Weights of the residual network (those with an embedding
+    width `emb`) go to film_velocity."""
+    if getattr(weights, "emb", None) is not None:
+        return film_velocity(weights, x, t, condf, precision)
     n = x.shape[0]
     h = np.concatenate([x, np.full((n, 1), float(t)), condf], axis=1)
     L = len(weights.W)

@@ -25,6 +25,9 @@ Workload recipes (sizes and laws follow the paper's workloads):
   (n_in = 10 for the boundary model, 12 for the internal model),
   every weight and bias U(-1/sqrt(fan_in), +1/sqrt(fan_in)) (the usual
   default initialisation of a linear layer), float32.
+* weights of the residual network with adaptive modulation (blob flag bit 2): the same
+  initialisation law for every layer (input layer, embedding, the three blocks' main,
+  scale and shift maps, output layer).
 * noise z ~ N(0, I_5) when a caller wants to hand the sampler its noise
   explicitly (paper, "Conditional Flow Matching", eq. 8).
 """
@@ -41,6 +44,13 @@ N_IN_RECT = 11       # boundary model of rectangular cells: x (5), t (1), condit
 N_IN_INTERNAL = 12   # internal (volumetric-source) model: x (5), t (1), condition (6)
 N_OUT = 5   # exit state: position, cos, sin, log path, face
 N_LAYERS = 5
+
+# Residual network with adaptive modulation (blob flag bit 2): embedding width, residual
+# blocks and number of time features of its input.
+FILM_FLAG = 4
+FILM_EMB = 32
+FILM_BLOCKS = 3
+N_TIME_FEATURES = 8
 
 BLOB_MAGIC = b"GMCW0001"
 BLOB_VERSION = 1
@@ -225,6 +235,51 @@ class Weights:
         return int(sum(w.size + bb.size for w, bb in zip(self.W, self.b)))
 
 
+def film_layer_dims(hidden: int, emb: int = FILM_EMB, n_in: int = N_IN, blocks: int = FILM_BLOCKS):
+    """[out, in] of every layer of the residual network in blob order: the input layer over
+    [x (5), time features (8), condition (n_in - 6)], the embedding over [time features,
+    condition], then per block the main H x H map and the E -> H scale and shift maps, and the
+    output layer."""
+    n_c = n_in - 6
+    dims = [(hidden, 5 + N_TIME_FEATURES + n_c), (emb, N_TIME_FEATURES + n_c)]
+    for _ in range(blocks):
+        dims += [(hidden, hidden), (hidden, emb), (hidden, emb)]
+    return dims + [(N_OUT, hidden)]
+
+
+@dataclass
+class FilmWeights:
+    """Float32 layers W[l] [out, in] and biases b[l] [out] of the residual network with
+    adaptive modulation, in the order of film_layer_dims."""
+    hidden: int
+    emb: int
+    W: list
+    b: list
+    seed: int = 0
+    n_in: int = N_IN
+    flags: int = FILM_FLAG    # bit 2 set; bits 0 and 1 as for Weights
+
+    @property
+    def blocks(self) -> int:
+        return (len(self.W) - 3) // 3
+
+    def n_params(self) -> int:
+        return int(sum(w.size + bb.size for w, bb in zip(self.W, self.b)))
+
+
+def random_film_weights(hidden: int, seed: int, emb: int = FILM_EMB, blocks: int = FILM_BLOCKS,
+                        n_in: int = N_IN, flags: int = 0) -> FilmWeights:
+    """Seeded random-init residual network, U(-1/sqrt(fan_in), 1/sqrt(fan_in)) for every
+    weight and bias."""
+    g = rng(seed)
+    W, b = [], []
+    for (o, i) in film_layer_dims(hidden, emb, n_in, blocks):
+        bound = 1.0 / math.sqrt(i)
+        W.append(g.uniform(-bound, bound, size=(o, i)).astype(np.float32))
+        b.append(g.uniform(-bound, bound, size=(o,)).astype(np.float32))
+    return FilmWeights(hidden, emb, W, b, seed, n_in, int(flags) | FILM_FLAG)
+
+
 def pow2_ceil_scale(amax: float, fmax: float = 448.0) -> float:
     """Smallest power of two s with amax / s <= fmax (1.0 for amax == 0)."""
     if amax <= 0.0:
@@ -253,11 +308,18 @@ def random_weights(hidden: int, seed: int, act_scale: float = 2.0 ** -5, n_in: i
     return Weights(hidden, W, b, a_scale, w_scale, seed, n_in, flags)
 
 
-def pack_blob(w: Weights) -> bytes:
-    """Serialise to the versioned little-endian blob read by gmc_model_create()."""
-    hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, w.n_in, w.hidden, N_OUT, N_LAYERS, int(w.flags),
-                    int(w.seed) & 0xFFFFFFFF, 0,
-                    *[float(x) for x in w.act_scale], *[float(x) for x in w.w_scale])
+def pack_blob(w) -> bytes:
+    """Serialise to the versioned little-endian blob read by gmc_model_create().  A residual
+    network (FilmWeights) sets flag bit 2 and stores its block count in the n_layers field and
+    its embedding width in the reserved field; its scale fields are 1."""
+    if isinstance(w, FilmWeights):
+        hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, w.n_in, w.hidden, N_OUT, w.blocks,
+                        int(w.flags) | FILM_FLAG, int(w.seed) & 0xFFFFFFFF, w.emb,
+                        *([1.0] * 5), *([1.0] * 5))
+    else:
+        hdr = _HDR.pack(BLOB_MAGIC, BLOB_VERSION, w.n_in, w.hidden, N_OUT, N_LAYERS, int(w.flags),
+                        int(w.seed) & 0xFFFFFFFF, 0,
+                        *[float(x) for x in w.act_scale], *[float(x) for x in w.w_scale])
     parts = [hdr]
     for W, b in zip(w.W, w.b):
         parts.append(np.ascontiguousarray(W, np.float32).tobytes())
@@ -265,23 +327,27 @@ def pack_blob(w: Weights) -> bytes:
     return b"".join(parts)
 
 
-def unpack_blob(blob: bytes) -> Weights:
+def unpack_blob(blob: bytes):
     fields = _HDR.unpack_from(blob, 0)
-    magic, version, n_in, hidden, n_out, n_layers, flags, seed, _res = fields[:9]
+    magic, version, n_in, hidden, n_out, n_layers, flags, seed, res = fields[:9]
+    film = bool(flags & FILM_FLAG)
     if magic != BLOB_MAGIC or version != BLOB_VERSION or n_in not in (N_IN, N_IN_RECT, N_IN_INTERNAL) \
-            or n_out != N_OUT or n_layers != N_LAYERS:
+            or n_out != N_OUT or (n_layers != N_LAYERS and not film):
         raise ValueError("not a GMC weights blob of a supported version")
     act = np.array(fields[9:14], np.float32)
     wsc = np.array(fields[14:19], np.float32)
     off = _HDR.size
     W, b = [], []
-    for (o, i) in layer_dims(hidden, n_in):
+    dims = film_layer_dims(hidden, res, n_in, n_layers) if film else layer_dims(hidden, n_in)
+    for (o, i) in dims:
         W.append(np.frombuffer(blob, np.float32, o * i, off).reshape(o, i).copy())
         off += 4 * o * i
         b.append(np.frombuffer(blob, np.float32, o, off).copy())
         off += 4 * o
     if off != len(blob):
         raise ValueError("weights blob has trailing or missing bytes")
+    if film:
+        return FilmWeights(hidden, res, W, b, seed, n_in, flags)
     return Weights(hidden, W, b, act, wsc, seed, n_in, flags)
 
 

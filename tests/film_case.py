@@ -1,0 +1,63 @@
+"""Hand-built residual networks with adaptive modulation (width H = 128, embedding 32, three
+blocks: the shape the GPU kernel runs) whose sampler outputs are worked out by hand.  Used by
+the oracle's pins and, bit for bit, by the GPU tests.
+
+Network input u = [x0..x4, phi0..phi7, c0..], phi = (sin pi t, cos pi t, sin 2 pi t, cos 2 pi t,
+sin 4 pi t, cos 4 pi t, sin 8 pi t, cos 8 pi t); layers in the order of
+inputs.film_layer_dims: input, embedding, (main, scale, shift) x 3, output."""
+import numpy as np
+
+from paper_2512_13965_amd import inputs
+
+H, E, B = 128, inputs.FILM_EMB, inputs.FILM_BLOCKS
+
+
+def zeros(n_in: int = inputs.N_IN) -> inputs.FilmWeights:
+    dims = inputs.film_layer_dims(H, E, n_in, B)
+    return inputs.FilmWeights(H, E, [np.zeros(d, np.float32) for d in dims],
+                              [np.zeros(d[0], np.float32) for d in dims], 0, n_in)
+
+
+def constant(bias_out) -> inputs.FilmWeights:
+    """Every weight zero, output bias b: v = b everywhere, so x_K = z + b for every K and
+    integrator."""
+    w = zeros()
+    w.b[-1][:] = np.asarray(bias_out, np.float32)
+    return w
+
+
+def time_probe() -> inputs.FilmWeights:
+    """v = (sin pi t, cos pi t, cos 8 pi t, 0, 0): the input layer copies time features 0, 1
+    and 7 into h0[0..2], the blocks add nothing (zero main maps and shifts: SiLU(0) = 0), the
+    output layer copies h[0..2]."""
+    w = zeros()
+    w.W[0][0, 5] = 1.0
+    w.W[0][1, 6] = 1.0
+    w.W[0][2, 12] = 1.0
+    for d in range(3):
+        w.W[-1][d, d] = 1.0
+    return w
+
+
+def residual_tie() -> inputs.FilmWeights:
+    """One Euler step (K = 1, t = 0) from noise with z0 = 1.25:
+      h0[0] = x0 = 1.25;
+      embedding e0 = SiLU(64) = 64 (bias only);
+      block 0, row 0: main 31 (bias), scale 1 + e0/64 = 2, shift e0/32 = 2, so the branch is
+      SiLU(2 * 31 + 2) = SiLU(64) = 64 and h1[0] = 1.25 + 64 = 65.25;
+      blocks 1 and 2 add SiLU(0) = 0; v0 = h3[0].
+    With a bfloat16 residual stream 65.25 lies halfway between 65 and 65.5 and rounds to the
+    even 65.  So x_1[0] = 1.25 + 65.25 = 66.5 exactly, or 66.25 in BF16; every other component
+    is z unchanged (zero velocity)."""
+    w = zeros()
+    w.W[0][0, 0] = 1.0
+    w.b[1][0] = 64.0
+    w.b[2][0] = 31.0
+    w.W[3][0, 0] = 1.0 / 64.0
+    w.W[4][0, 0] = 1.0 / 32.0
+    w.W[-1][0, 0] = 1.0
+    return w
+
+
+RESIDUAL_TIE_Z0 = 1.25
+RESIDUAL_TIE_X1 = {"fp32": 66.5, "bf16": 66.25}
