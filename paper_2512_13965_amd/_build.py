@@ -11,7 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libgmc.so")
 BUILD = os.path.join(PKG, "_build")
 
-SOURCES = ["gmc_mlp.hip", "gmc_walk.hip", "gmc_transport.hip", "gmc_api.cpp"]
+SOURCES = ["gmc_mlp.hip", "gmc_film.hip", "gmc_walk.hip", "gmc_transport.hip", "gmc_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-version=5",

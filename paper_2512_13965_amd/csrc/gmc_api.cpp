@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <atomic>
 #include <cmath>
 #include <cstdio>
@@ -182,19 +183,42 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     std::memcpy(&hd, host_blob, sizeof hd);
     if (std::memcmp(hd.magic, "GMCW0001", 8) != 0 || hd.version != 1)
         return fail(GMC_EINVAL, "gmc_model_create: bad magic or version");
-    if (hd.n_in < 10 || hd.n_in > 12 || hd.n_out != 5 || hd.n_layers != 5)
-        return fail(GMC_EINVAL, "gmc_model_create: network must be 10, 11 or 12 -> H x4 -> 5");
-    if (hd.flags & ~3u) return fail(GMC_EINVAL, "gmc_model_create: unknown flags");
+    const bool film = (hd.flags & 4u) != 0;
+    if (hd.n_in < 10 || hd.n_in > 12 || hd.n_out != 5)
+        return fail(GMC_EINVAL, "gmc_model_create: network must have 10, 11 or 12 inputs and 5 outputs");
+    if (!film && hd.n_layers != 5)
+        return fail(GMC_EINVAL, "gmc_model_create: the plain network is 10, 11 or 12 -> H x4 -> 5");
+    if (film && (hd.n_layers != (uint32_t)kFilmBlocks || hd.reserved != (uint32_t)kFilmEmb))
+        return fail(GMC_EINVAL, "gmc_model_create: the residual network has " + std::to_string(kFilmBlocks) +
+                                    " blocks and embedding width " + std::to_string(kFilmEmb));
+    if (hd.flags & ~7u) return fail(GMC_EINVAL, "gmc_model_create: unknown flags");
     if ((hd.flags & 2u) && hd.n_in == 12)
         return fail(GMC_EINVAL, "gmc_model_create: only boundary models can be fitted on collided exits");
     if ((hd.flags & 1u) && hd.n_in != 11)
         return fail(GMC_EINVAL, "gmc_model_create: an XY-geometry model has 11 inputs");
     const int H = (int)hd.hidden;
-    if (!mlp_supported(precision, H))
-        return fail(GMC_EUNSUPPORTED, "gmc_model_create: hidden width " + std::to_string(H) +
+    if (film ? !film_supported(precision, H) : !mlp_supported(precision, H))
+        return fail(GMC_EUNSUPPORTED, std::string("gmc_model_create: ") + (film ? "residual network" : "network") +
+                                          " of hidden width " + std::to_string(H) +
                                           " not built for this precision");
-    const int NI = (int)hd.n_in;
-    const int dims[5][2] = {{H, NI}, {H, H}, {H, H}, {H, H}, {5, H}};
+    const int NI = (int)hd.n_in, NC = NI - 6;
+    // [out, in] of every layer in blob order: the plain MLP's five layers, or the residual
+    // network's input layer [x, time features, condition], embedding [time features,
+    // condition], (main, scale, shift) per block and output layer
+    std::vector<std::array<int, 2>> dims;
+    if (film) {
+        dims.push_back({H, 13 + NC});
+        dims.push_back({kFilmEmb, 8 + NC});
+        for (int j = 0; j < kFilmBlocks; ++j) {
+            dims.push_back({H, H});
+            dims.push_back({H, kFilmEmb});
+            dims.push_back({H, kFilmEmb});
+        }
+        dims.push_back({5, H});
+    } else {
+        dims = {{H, NI}, {H, H}, {H, H}, {H, H}, {5, H}};
+    }
+    const int NL = (int)dims.size();
     size_t need = sizeof(BlobHeader);
     for (auto &d : dims) need += sizeof(float) * (size_t)(d[0] * d[1] + d[0]);
     if (nbytes != need) return fail(GMC_EINVAL, "gmc_model_create: blob size does not match header");
@@ -203,8 +227,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
             return fail(GMC_EINVAL, "gmc_model_create: scales must be positive powers of two");
 
     const float *src = (const float *)((const char *)host_blob + sizeof(BlobHeader));
-    std::vector<const float *> W(5), B(5);
-    for (int l = 0; l < 5; ++l) {
+    std::vector<const float *> W(NL), B(NL);
+    for (int l = 0; l < NL; ++l) {
         W[l] = src;
         src += dims[l][0] * dims[l][1];
         B[l] = src;
@@ -217,8 +241,8 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     if (irc != GMC_OK) return irc;
 
     // arrange every layer into fragment order, then one device allocation for all of it
-    std::vector<std::vector<uint8_t>> frag(5);
-    std::vector<std::vector<float>> bias(5);
+    std::vector<std::vector<uint8_t>> frag(NL);
+    std::vector<std::vector<float>> bias(NL);
     gmc_model *m = new gmc_model();
     static std::atomic<uint64_t> next_serial{1};
     m->serial = next_serial++;
@@ -226,19 +250,35 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     m->n_in = NI;
     m->xy = (hd.flags & 1u) != 0;
     m->collided = (hd.flags & 2u) != 0;
+    m->film = film;
+    m->tmpl.net = film ? 1 : 0;
     m->tmpl.xy = m->xy ? 1 : 0;
-    m->tmpl.n_cond = NI - 6;
+    m->tmpl.n_cond = NC;
     m->hidden = H;
-    for (int l = 0; l < 5; ++l) {
-        const int P = layer_prec(precision, l);
+    for (int l = 0; l < NL; ++l) {
+        const int P = film ? precision : layer_prec(precision, l);
         const int KBW = kb_width(P), FB = frag_bytes(P), EB = elem_bytes(P);
         const int out_dim = dims[l][0], in_dim = dims[l][1];
-        const int kpad = (l == 0) ? 16 : H;
+        // padded input width and the blob column of physical input column k (-1: zero).  The
+        // first layers read rows the threads wrote in natural order: the plain input
+        // [x, t, condition]; the residual network's [x (0..4), time features (5..12),
+        // condition (13..)], of which its embedding reads columns 5 on.  Every other layer
+        // reads a tile its producer's accumulators stored (phys_to_feature).
+        const bool first = (l == 0) || (film && l == 1);
+        const bool from_emb = film && l >= 2 && l < NL - 1 && (l - 2) % 3 != 0;
+        const int kpad = first ? (film ? kFilmIn : 16) : (from_emb ? kFilmEmb : H);
+        auto column = [&](int k) {
+            if (!first) return phys_to_feature(P, k);
+            if (film && l == 1) return k >= 5 ? k - 5 : -1;
+            return k;
+        };
         const int nkb = kpad / KBW, nt = (out_dim + 31) / 32;
         const bool f8 = (P == kFP8);
         const float sw = f8 ? hd.w_scale[l] : 1.0f, sa = f8 ? hd.act_scale[l] : 1.0f;
-        m->tmpl.oscale[l] = sw * sa;
-        m->tmpl.inv_in_scale[l] = 1.0f / sa;
+        if (l < 5) {
+            m->tmpl.oscale[l] = sw * sa;
+            m->tmpl.inv_in_scale[l] = 1.0f / sa;
+        }
         frag[l].assign((size_t)nt * nkb * 64 * FB, 0);
         for (int T = 0; T < nt; ++T)
             for (int kb = 0; kb < nkb; ++kb)
@@ -247,7 +287,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
                     uint8_t *dst = frag[l].data() + ((size_t)(T * nkb + kb) * 64 + lane) * FB;
                     for (int e = 0; e < KBW / 2; ++e) {
                         const int k = kb * KBW + h * (KBW / 2) + e;
-                        const int f = (l == 0) ? (k < in_dim ? k : -1) : phys_to_feature(P, k);
+                        const int f = column(k);
                         const float w = (row < out_dim && f >= 0 && f < in_dim)
                                             ? W[l][(size_t)row * in_dim + f] : 0.0f;
                         if (P == kF32) {
@@ -260,12 +300,15 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
                         }
                     }
                 }
+        // the residual network's scale maps carry the "1 +" of the modulation in their bias
+        const float one = (film && l >= 2 && l < NL - 1 && (l - 2) % 3 == 1) ? 1.0f : 0.0f;
         bias[l].assign((size_t)nt * 32, 0.0f);
-        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] / (sw * sa);
+        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] / (sw * sa) + one;
     }
+    static_assert(3 + 3 * kFilmBlocks == kMaxLayers, "the residual network fills every layer slot");
     size_t total = 0;
-    std::vector<size_t> off_f(5), off_b(5);
-    for (int l = 0; l < 5; ++l) {
+    std::vector<size_t> off_f(NL), off_b(NL);
+    for (int l = 0; l < NL; ++l) {
         off_f[l] = total;
         total += (frag[l].size() + 255) & ~(size_t)255;
         off_b[l] = total;
@@ -276,7 +319,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     e = hipMalloc(&m->dev_mem, total);
     if (e != hipSuccess) { delete m; return fail(GMC_ENOMEM, "gmc_model_create: hipMalloc failed"); }
     std::vector<uint8_t> staging(total, 0);
-    for (int l = 0; l < 5; ++l) {
+    for (int l = 0; l < NL; ++l) {
         std::memcpy(staging.data() + off_f[l], frag[l].data(), frag[l].size());
         std::memcpy(staging.data() + off_b[l], bias[l].data(), bias[l].size() * sizeof(float));
         m->tmpl.wA[l] = (const char *)m->dev_mem + off_f[l];

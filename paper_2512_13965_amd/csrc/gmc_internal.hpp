@@ -54,10 +54,19 @@ __host__ __device__ inline int phys_to_feature(int p_in, int p)
     return 32 * T + 8 * (i / 4) + 4 * h + (i % 4);
 }
 
+// The residual velocity network with adaptive modulation: embedding width, residual blocks,
+// features of its input row ([x (5), time features (8), condition (<= 6)], zero-padded) and
+// layers (input, embedding, main / scale / shift per block, output).
+constexpr int kFilmEmb = 32;
+constexpr int kFilmBlocks = 3;
+constexpr int kFilmIn = 32;
+constexpr int kMaxLayers = 3 + 3 * kFilmBlocks;
+
 struct MlpParams {
-    const void *wA[5];        // arranged operand fragments per layer
-    const float *bias[5];     // per layer, rows padded to a multiple of 32, pre-divided by oscale
-    uint32_t wA_bytes[5], bias_bytes[5];   // sizes of the above (bounds of the buffer loads)
+    int net;                  // 0: plain MLP (5 layers), 1: residual network (kMaxLayers layers)
+    const void *wA[kMaxLayers];     // arranged operand fragments per layer
+    const float *bias[kMaxLayers];  // per layer, rows padded to a multiple of 32, pre-divided by oscale
+    uint32_t wA_bytes[kMaxLayers], bias_bytes[kMaxLayers];   // sizes (bounds of the buffer loads)
     float oscale[5];          // accumulator multiplier per layer (FP8 hidden layers: sw * sa)
     float inv_in_scale[5];    // 1 / activation scale of the input of layer l (FP8 hidden layers)
     const float *log_tau, *c, *y_in, *sin_th;
@@ -79,8 +88,11 @@ struct MlpParams {
     uint64_t seed, id_base;
 };
 
+// One fused sampler launch for the network p.net (plain MLP or residual network).
 hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s);
 bool mlp_supported(int prec, int hidden);
+hipError_t launch_film_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s);
+bool film_supported(int prec, int hidden);
 
 struct WalkParams {
     const float *log_tau, *c, *y_in, *sin_th;
@@ -138,6 +150,7 @@ struct gmc_model {
     int n_in = 10;           // 10: boundary model, 11: rectangular-cell or XY boundary model, 12: internal
     bool xy = false;         // XY geometry (blob flags bit 0): condition carries omega_x
     bool collided = false;   // fitted on collided exits (blob flags bit 1): transport splits first flights
+    bool film = false;       // residual network with adaptive modulation (blob flags bit 2)
     int device = 0;
     void *dev_mem = nullptr;
     gmc::MlpParams tmpl{};   // weight / bias pointers and scales

@@ -37,6 +37,10 @@ Usage: python -m paper_2512_13965_amd.train --hidden 512 --out paper_2512_13965_
            --out paper_2512_13965_amd/weights/gmc_h512_rect_collided.bin
        python -m paper_2512_13965_amd.train --model xy_collided --hidden 512 \
            --out paper_2512_13965_amd/weights/gmc_h512_xy_collided.bin
+       python -m paper_2512_13965_amd.train --net film --hidden 512 --steps 150000 --data 8000000 \
+           --batch 16384 --out paper_2512_13965_amd/weights/gmc_film_h512.bin
+The residual network with adaptive modulation (--net film; section "Network Architecture and
+Inputs") is fitted with the same loss and data.
 """
 from __future__ import annotations
 
@@ -119,6 +123,43 @@ class VelocityMLP(torch.nn.Module):
                               n_in=W[0].shape[1], flags=flags)
 
 
+class VelocityFiLM(torch.nn.Module):
+    """The residual network with adaptive modulation of the sampler kernel for such models
+    (blob flag bit 2): u = [x, phi(t), c], phi = sin and cos of pi 2^j t (j = 0..3);
+    h = W_in u + b_in; e = SiLU(W_e [phi, c] + b_e); per block
+    h <- h + SiLU((1 + G e + g) * (A h + a) + (S e + s)); v = W_o h + b_o.  The scale and shift
+    maps start at zero, so training starts from unmodulated residual blocks."""
+
+    def __init__(self, hidden: int, n_in: int = inputs.N_IN, emb: int = inputs.FILM_EMB,
+                 blocks: int = inputs.FILM_BLOCKS):
+        super().__init__()
+        dims = inputs.film_layer_dims(hidden, emb, n_in, blocks)
+        self.layers = torch.nn.ModuleList([torch.nn.Linear(i, o) for (o, i) in dims])
+        self.blocks = blocks
+        with torch.no_grad():
+            for j in range(blocks):
+                for l in (3 + 3 * j, 4 + 3 * j):
+                    self.layers[l].weight.zero_()
+                    self.layers[l].bias.zero_()
+
+    def forward(self, x, t, c):
+        silu = torch.nn.functional.silu
+        ang = math.pi * t[:, None] * torch.tensor([1.0, 2.0, 4.0, 8.0], device=t.device)
+        phi = torch.stack([torch.sin(ang), torch.cos(ang)], dim=2).reshape(-1, 8)
+        L = self.layers
+        h = L[0](torch.cat([x, phi, c], dim=1))
+        e = silu(L[1](torch.cat([phi, c], dim=1)))
+        for j in range(self.blocks):
+            h = h + silu((1.0 + L[3 + 3 * j](e)) * L[2 + 3 * j](h) + L[4 + 3 * j](e))
+        return L[-1](h)
+
+    def to_weights(self, seed: int, flags: int = 0) -> inputs.FilmWeights:
+        W = [l.weight.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
+        b = [l.bias.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
+        n_in = W[0].shape[1] - 8
+        return inputs.FilmWeights(W[0].shape[0], W[1].shape[0], W, b, seed, n_in, flags | inputs.FILM_FLAG)
+
+
 @torch.no_grad()
 def activation_scales(model: VelocityMLP, feats, tgt, n=65536, seed=0):
     """Static per-layer FP8 activation scales: the power of two bringing the largest input of
@@ -140,13 +181,14 @@ def activation_scales(model: VelocityMLP, feats, tgt, n=65536, seed=0):
 
 
 def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=20251213,
-          log_every=1000, device="cuda", kind="boundary", log_tau_range=LOG_TAU_TRAIN):
+          log_every=1000, device="cuda", kind="boundary", log_tau_range=LOG_TAU_TRAIN, net="mlp"):
     torch.manual_seed(seed)
     t0 = time.time()
     feats, tgt = make_dataset(n_data, seed, device, kind, log_tau_range)
     n_data = feats.shape[0]
     print(f"data: {n_data} {kind} exits in {time.time() - t0:.1f}s", flush=True)
-    model = VelocityMLP(hidden, 5 + 1 + feats.shape[1]).to(device)
+    n_in = 5 + 1 + feats.shape[1]
+    model = (VelocityFiLM(hidden, n_in) if net == "film" else VelocityMLP(hidden, n_in)).to(device)
     opt = torch.optim.AdamW(model.parameters(), lr=lr, weight_decay=1e-4)
     sched = torch.optim.lr_scheduler.OneCycleLR(opt, max_lr=lr, total_steps=steps, pct_start=0.05)
     g = torch.Generator(device=device).manual_seed(seed + 2)
@@ -166,8 +208,10 @@ def train(hidden=512, n_data=4_000_000, steps=40_000, batch=8192, lr=1e-3, seed=
         if it % log_every == 0:
             print(f"step {it}/{steps} loss {run / (log_every / 50):.4f} ({time.time() - t0:.0f}s)", flush=True)
             run = 0.0
-    scales = activation_scales(model, feats, tgt)
     flags = {"xy": 1, "collided": 2, "rect_collided": 2, "xy_collided": 3}.get(kind, 0)
+    if net == "film":
+        return model.to_weights(seed & 0xFFFFFFFF, flags=flags)
+    scales = activation_scales(model, feats, tgt)
     return model.to_weights(seed & 0xFFFFFFFF, scales, flags=flags)
 
 
@@ -182,12 +226,17 @@ def main():
                                                 "xy_collided"), default="boundary")
     ap.add_argument("--tau-max", type=float, default=math.exp(LOG_TAU_TRAIN[1]),
                     help="largest optical thickness of the training cells (ln tau uniform)")
+    ap.add_argument("--net", choices=("mlp", "film"), default="mlp",
+                    help="plain MLP, or the residual network with adaptive modulation")
     ap.add_argument("--out", required=True)
     a = ap.parse_args()
     w = train(a.hidden, a.data, a.steps, a.batch, a.lr, kind=a.model,
-              log_tau_range=(LOG_TAU_TRAIN[0], math.log(a.tau_max)))
+              log_tau_range=(LOG_TAU_TRAIN[0], math.log(a.tau_max)), net=a.net)
     inputs.save_blob(w, a.out)
-    print("saved", a.out, "act scales", list(w.act_scale), "w scales", list(w.w_scale), flush=True)
+    if a.net == "film":
+        print("saved", a.out, "residual network", w.hidden, "x", w.blocks, "blocks", flush=True)
+    else:
+        print("saved", a.out, "act scales", list(w.act_scale), "w scales", list(w.w_scale), flush=True)
 
 
 if __name__ == "__main__":

@@ -57,8 +57,20 @@ def run(L):
     # FP32 is built for H <= 256 only; H = 64 is built for no precision
     assert _create(L, inputs.pack_blob(inputs.random_weights(512, 1)), FP32) == EUNSUPPORTED
     assert _create(L, inputs.pack_blob(inputs.random_weights(64, 1)), BF16) == EUNSUPPORTED
-    # blob flags: bit 0 XY geometry (11 inputs), bit 1 fitted on collided exits (boundary models)
+    # blob flags: bit 0 XY geometry (11 inputs), bit 1 fitted on collided exits (boundary models),
+    # bit 2 the residual network (a plain five-layer blob with it set does not parse)
     assert _create(L, inputs.pack_blob(inputs.random_weights(256, 1, flags=4)), FP32) == EINVAL
+    assert _create(L, inputs.pack_blob(inputs.random_weights(256, 1, flags=8)), FP32) == EINVAL
+    # the residual network: FP32 at H = 128 and BF16 only; 3 blocks of embedding width 32
+    fw = inputs.random_film_weights(128, 1)
+    fb = inputs.pack_blob(fw)
+    assert _create(L, fb, FP8) == EUNSUPPORTED
+    assert _create(L, inputs.pack_blob(inputs.random_film_weights(256, 1)), FP32) == EUNSUPPORTED
+    assert _create(L, fb[:-4], BF16) == EINVAL
+    assert _create(L, inputs.pack_blob(inputs.random_film_weights(128, 1, emb=64)), BF16) == EINVAL
+    assert _create(L, inputs.pack_blob(inputs.random_film_weights(128, 1, blocks=2)), BF16) == EINVAL
+    fw.W[4][2, 3] = np.inf
+    assert _create(L, inputs.pack_blob(fw), BF16) == EINVAL
     assert _create(L, inputs.pack_blob(inputs.random_weights(256, 1, flags=1)), FP32) == EINVAL
     assert _create(L, inputs.pack_blob(inputs.random_weights(256, 1, n_in=inputs.N_IN_INTERNAL, flags=2)),
                    FP32) == EINVAL

@@ -1,0 +1,171 @@
+"""GPU parity of the residual velocity network with adaptive modulation (paper "Network
+Architecture and Inputs"; the sampler of eq. 8, Euler or RK4; decoding of eq. 11) against the
+oracle on the same seeded weights and noise, through the C ABI (gmc_sample,
+gmc_sample_internal).
+
+Tolerances, per sample, infinity norm of x_K - x_K^oracle (the plain network's bounds and
+reasons, tests/test_gpu_sampler.py):
+  * FP32 against exact FP64: 1e-5.
+  * BF16 against the oracle that rounds the same operands and the residual stream at the same
+    points.  A sample agrees to FP32 accuracy unless one of its stored BF16 values (input row,
+    embedding, residual stream) lies so close to a rounding midpoint that FP32 accumulation on
+    the matrix core and FP64 in the oracle round it to neighbouring values (a "flip", about
+    one value in 10^4-10^5).  A flip changes that value by one BF16 step, the size of the
+    rounding error itself, so its effect on x_K is bounded by the order of the sample's
+    distance to exact FP64 arithmetic, which this network amplifies 30x more than the plain
+    MLP (median 1.3e-3 to 1.6e-3 against 4e-5).  The share of samples with a visible flip grows
+    with the number of rounded values (measured beyond 1e-5: 2 % at H = 128, 3 % at 256,
+    11-18 % at 512).  Bounds, with d the median distance to exact FP64: median 1e-6 (most
+    samples see no flip), p95 0.1 d, every sample 0.5 d (measured at H = 512: p95 0.03-0.05 d,
+    max 0.16-0.44 d).  A dropped rounding step or a wrong scale moves every sample by about d.
+  * Hand-built networks (tests/film_case.py): the values worked out by hand, bit for bit where
+    every operation is exact (the residual-stream tie), else within 1e-6 (the time features
+    come from the device's sinpi / cospi in FP32).
+"""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_13965_amd import inputs
+from tests import film_case
+from tests.gpu_util import require_gpu, sample_indices
+from tests.test_gpu_sampler import _check_decoded
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(binding, w, prec, cond_h, integ, K, seed=2, id_base=0, noise=None):
+    m = binding.Model(inputs.pack_blob(w), prec)
+    internal = hasattr(cond_h, "x")
+    dc = (binding.DeviceCondInternal if internal else binding.DeviceCond).from_host(cond_h)
+    n = len(cond_h)
+    raw = torch.empty(5 * n, dtype=torch.float32, device="cuda")
+    nz = None if noise is None else torch.from_numpy(np.ascontiguousarray(noise, np.float32).reshape(-1)).cuda()
+    fn = binding.gmc_sample_internal if internal else binding.gmc_sample
+    out = fn(m, dc, integ, K, seed, id_base, noise=nz, raw=raw)
+    torch.cuda.synchronize()
+    m.close()
+    return raw.view(5, n).cpu().numpy().astype(np.float64), out.to_host()
+
+
+def _oracle(orc, w, cond_h, idx, integ, K, prec, z_full=None, seed=2, id_base=0):
+    sub = cond_h.subset(idx)
+    if z_full is None:
+        z = np.stack([orc.noise(seed, id_base + int(i), 1)[:, 0] for i in idx], axis=1)
+    else:
+        z = z_full[:, idx].astype(np.float64)
+    f = orc.sample_raw_rk4 if integ == "rk4" else orc.sample_raw
+    return f(w, sub, K, z, prec)
+
+
+@pytest.mark.parametrize("prec,key", [("fp32", "fp32"), ("bf16", "bf16")])
+def test_residual_stream_tie_bit_exact(orc, prec, key):
+    binding = require_gpu()
+    n = 300
+    z = inputs.noise(n, 3)
+    z[0] = film_case.RESIDUAL_TIE_Z0
+    raw, _ = _run(binding, film_case.residual_tie(), prec, inputs.transmission_conditions(n, 4), "euler", 1,
+                  noise=z)
+    np.testing.assert_array_equal(raw[0], film_case.RESIDUAL_TIE_X1[key])
+    np.testing.assert_array_equal(raw[1:], z[1:].astype(np.float32).astype(np.float64))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("integ,K", [("euler", 5), ("rk4", 3)])
+def test_hand_networks(orc, prec, integ, K):
+    binding = require_gpu()
+    n = 257
+    cond = inputs.transmission_conditions(n, 5)
+    z = inputs.noise(n, 6)
+    b = np.array([0.5, -1.25, 2.0, 0.75, -0.5])
+    raw, _ = _run(binding, film_case.constant(b), prec, cond, integ, K, noise=z)
+    np.testing.assert_allclose(raw.T, z.T.astype(np.float64) + b, rtol=0, atol=2e-6)
+    w = film_case.time_probe()
+    raw, _ = _run(binding, w, prec, cond, integ, K, noise=z)
+    ref = _oracle(orc, w, cond, np.arange(n), integ, K, orc.PREC_BF16 if prec == "bf16" else orc.PREC_FP64, z)
+    np.testing.assert_allclose(raw.T, ref, rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("n_in", [10, 11, 12])
+@pytest.mark.parametrize("integ,K", [("euler", 8), ("rk4", 3)])
+def test_fp32_parity(orc, n_in, integ, K):
+    binding = require_gpu()
+    n = 2_085                                    # 17 tiles, ragged tail
+    if n_in == 12:
+        cond = inputs.internal_conditions(n, 7)
+    else:
+        cond = inputs.transmission_conditions(n, 7, log_aspect_range=(-1.4, 1.4) if n_in == 11 else None)
+    w = inputs.random_film_weights(128, 21 + n_in, n_in=n_in)
+    raw, out = _run(binding, w, "fp32", cond, integ, K, seed=9, id_base=33)
+    idx = sample_indices(n, 500, seed=1)
+    ref = _oracle(orc, w, cond, idx, integ, K, orc.PREC_FP64, seed=9, id_base=33)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    print(f"film fp32 n_in={n_in} {integ} K={K}: max {err.max():.2e} p99 {np.quantile(err, 0.99):.2e}")
+    assert err.max() < 1e-5
+    _check_decoded(orc, raw[:, idx], ref, out, idx)
+
+
+@pytest.mark.parametrize("n", [1, 127, 129])
+def test_fp32_small_batches(orc, n):
+    binding = require_gpu()
+    cond = inputs.transmission_conditions(n, 8)
+    w = inputs.random_film_weights(128, 30)
+    raw, _ = _run(binding, w, "fp32", cond, "euler", 4)
+    ref = _oracle(orc, w, cond, np.arange(n), "euler", 4, orc.PREC_FP64)
+    assert np.abs(raw.T - ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("H,integ,K", [(512, "euler", 8), (512, "rk4", 2), (256, "euler", 8), (128, "rk4", 3)])
+def test_bf16_parity_vs_emulating_oracle(orc, H, integ, K):
+    binding = require_gpu()
+    n = 6_077
+    cond = inputs.transmission_conditions(n, 9)
+    w = inputs.random_film_weights(H, 40 + H)
+    z = inputs.noise(n, 10)
+    raw, out = _run(binding, w, "bf16", cond, integ, K, noise=z)
+    idx = sample_indices(n, 400, seed=2)
+    ref = _oracle(orc, w, cond, idx, integ, K, orc.PREC_BF16, z)
+    exact = _oracle(orc, w, cond, idx, integ, K, orc.PREC_FP64, z)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    err_exact = np.abs(raw[:, idx].T - exact).max(axis=1)
+    check_bf16(err, err_exact, f"film bf16 H={H} {integ} K={K}")
+    _check_decoded(orc, raw[:, idx], ref, out, idx, pos_tol=1e-3)
+
+
+def check_bf16(err, err_exact, label):
+    q = np.quantile(err, [0.5, 0.9, 0.95, 0.99])
+    far = float(np.mean(err > 1e-5))
+    d = float(np.median(err_exact))
+    print(f"{label}: vs emulation p50 {q[0]:.2e} p90 {q[1]:.2e} p95 {q[2]:.2e} p99 {q[3]:.2e} "
+          f"max {err.max():.2e}, beyond 1e-5 {far:.2%}; vs fp64 p50 {d:.2e} max {err_exact.max():.2e}")
+    assert q[0] < 1e-6
+    assert q[2] < 0.1 * d
+    assert err.max() < 0.5 * d
+
+
+def test_bf16_h512_full_batch_sampled(orc):
+    # 2^20 transmissions, Euler K = 16, Philox noise, per sample against the emulating oracle
+    binding = require_gpu()
+    n = 1 << 20
+    cond = inputs.transmission_conditions(n, 3)
+    w = inputs.random_film_weights(512, 1)
+    raw, out = _run(binding, w, "bf16", cond, "euler", 16)
+    idx = sample_indices(n, 100, seed=3)
+    ref = _oracle(orc, w, cond, idx, "euler", 16, orc.PREC_BF16)
+    exact = _oracle(orc, w, cond, idx, "euler", 16, orc.PREC_FP64)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    check_bf16(err, np.abs(raw[:, idx].T - exact).max(axis=1), "film bf16 2^20")
+    assert np.all((out["face"] >= 0) & (out["face"] <= 3))
+
+
+def test_model_checks():
+    binding = require_gpu()
+    w = inputs.random_film_weights(128, 2)
+    with pytest.raises(RuntimeError):
+        binding.Model(inputs.pack_blob(w), "fp8")          # no FP8 residual network
+    with pytest.raises(RuntimeError):
+        binding.Model(inputs.pack_blob(inputs.random_film_weights(256, 2)), "fp32")   # FP32 is H = 128
+    blob = bytearray(inputs.pack_blob(w))
+    blob[36:40] = (7).to_bytes(4, "little")              # reserved field: embedding width
+    with pytest.raises(RuntimeError):
+        binding.Model(bytes(blob), "bf16")
