@@ -20,7 +20,8 @@ The same run also measures, with HIP events on the launch stream:
 
 The last stdout line is one compact JSON record; the full results go to --detail (a JSON file).
 `--study NAME` runs one of the longer studies instead (eq. 12 convergence on the 32 x 32
-checkerboard, whole transport runs, the 112^2 benchmark layouts, thick media).
+checkerboard, whole transport runs, the 112^2 benchmark layouts, thick media, the residual
+network with adaptive modulation against the plain MLP).
 """
 from __future__ import annotations
 
@@ -207,7 +208,8 @@ def tau_star(rate: float, analog_tps: dict):
 
 
 def bench_samplers(binding, inputs, dev, stream, w512, reps=3):
-    """The width-512 sampler in BF16 and FP8 (Euler K = 8, 16, 32; RK4 x 12), the fitted
+    """The width-512 sampler in BF16 and FP8 (Euler K = 8, 16, 32; RK4 x 12), the width-512
+    residual network with adaptive modulation (BF16; Euler K = 16, RK4 x 12), the fitted
     width-128 model, and the FP32 H = 256 sampler on 65,536 transmissions (random-init)."""
     NB = 1 << 20
     cond = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
@@ -224,6 +226,18 @@ def bench_samplers(binding, inputs, dev, stream, w512, reps=3):
             rows.append({"precision": prec, "hidden": 512, "integrator": integ, "K": KK, "batch": NB,
                          "ms": t, "tps": NB / (t * 1e-3), "frac_peak": fl / PEAK[prec]})
         m.close()
+    wf = fitted("gmc_film_h512.bin")
+    wf = inputs.random_film_weights(512, 1) if wf is None else wf
+    m = binding.Model(inputs.pack_blob(wf), "bf16")
+    for integ, KK in (("euler", 16), ("rk4", 12)):
+        fn = lambda: binding.gmc_sample(m, cond, integ, KK, 2, 0, out=out_b)
+        fn()
+        t = float(np.median(time_launches(fn, reps, stream)))
+        fl = film_flops_per_sample(512, KK * (4 if integ == "rk4" else 1)) * NB / (t * 1e-3)
+        rows.append({"precision": "bf16", "hidden": 512, "net": "residual, adaptive modulation",
+                     "integrator": integ, "K": KK, "batch": NB, "ms": t, "tps": NB / (t * 1e-3),
+                     "frac_peak": fl / PEAK["bf16"]})
+    m.close()
     w128 = fitted("gmc_h128.bin")
     if w128 is not None:
         m = binding.Model(inputs.pack_blob(w128), "bf16")
@@ -436,6 +450,92 @@ def study_thick(binding, inputs, n=50_000):
     return out
 
 
+def film_flops_per_sample(H: int, evals: int, n_c: int = 4, E: int = 32, B: int = 3) -> float:
+    """Algorithmic FLOP of `evals` evaluations of the residual network: input layer over
+    13 + n_c features, embedding over 8 + n_c, per block the H x H map and the two E -> H
+    modulation maps, output layer H -> 5 (multiply-adds counted as 2)."""
+    return evals * 2.0 * (H * (13 + n_c) + E * (8 + n_c) + B * (H * H + 2 * H * E) + 5 * H)
+
+
+def study_film(binding, inputs, w512, n=100_000):
+    """The paper's network (residual blocks with adaptive modulation, learned time and
+    condition embeddings; "Network Architecture and Inputs") against the plain MLP, both BF16,
+    width 512, fitted on the same data: exit-law distances to the analog walk at fixed entry
+    conditions (face TV, KS of position, exit cosine and ln path), the mean path at c = 1
+    against pi / 4 (P3), whole transport on the 32 x 32 checkerboard (flux L1 to analog MC
+    beside the analog-vs-analog floor) and the cost of a 2^20 launch, for Euler K = 16 and
+    RK4 x 12."""
+    import torch
+    from scipy import stats
+    from paper_2512_13965_amd import transport
+    wf = fitted("gmc_film_h512.bin")
+    if wf is None:
+        return {"skipped": "no fitted residual network"}
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream()
+    models = {"mlp": binding.Model(inputs.pack_blob(w512), "bf16"),
+              "film": binding.Model(inputs.pack_blob(wf), "bf16")}
+    integs = (("euler", 16), ("rk4", 12))
+    fix = lambda m, tau, c, y, s_: inputs.Conditions(*[np.full(m, np.float32(v)) for v in
+                                                       (math.log(tau), c, y, s_)])
+    out = {"exit_law": [], "mean_path": [], "cost": [], "transport": {}}
+    for tau, c, y, s_ in ((1.0, 1.0, 0.5, 0.2), (10.0, 1.0, 0.3, 0.5), (100.0, 1.0, 0.5, -0.3),
+                          (30.0, 0.95, 0.9, -0.8)):
+        ref = binding.mc_transmit(binding.DeviceCond.from_host(fix(n, tau, c, y, s_), dev), binding.MODE_CONTINUOUS,
+                                  17, 0).to_host()
+        for name, m in models.items():
+            for integ, K in integs:
+                g = binding.gmc_sample(m, binding.DeviceCond.from_host(fix(n, tau, c, y, s_), dev), integ, K,
+                                       5).to_host()
+                fg = np.bincount(g["face"][g["face"] >= 0], minlength=4) / n
+                fo = np.bincount(ref["face"], minlength=4) / n
+                out["exit_law"].append({
+                    "net": name, "integrator": integ, "K": K, "tau": tau, "c": c, "y_in": y, "sin_th": s_,
+                    "face_tv": float(0.5 * np.abs(fg - fo).sum()),
+                    "ks_pos": float(stats.ks_2samp(g["pos"] + g["face"], ref["pos"] + ref["face"]).statistic),
+                    "ks_cos": float(stats.ks_2samp(g["dir_cos"], ref["dir_cos"]).statistic),
+                    "ks_ln_path": float(stats.ks_2samp(np.log(g["path"]), np.log(ref["path"])).statistic)})
+    for tau in (1.0, 10.0, 100.0):
+        cond = binding.DeviceCond.from_host(inputs.fixed_cell_conditions(200_000, tau, 1.0, 3), dev)
+        for name, m in models.items():
+            for integ, K in integs:
+                g = binding.gmc_sample(m, cond, integ, K, 9).to_host()
+                out["mean_path"].append({"net": name, "integrator": integ, "K": K, "tau": tau,
+                                         "mean_path": float(g["path"].mean()), "pi_over_4": math.pi / 4})
+    NB = 1 << 20
+    cond = binding.DeviceCond.from_host(inputs.transmission_conditions(NB, 3), dev)
+    ob = binding.DeviceExit.empty(NB, dev)
+    for name, m in models.items():
+        for integ, K in integs:
+            fn = lambda: binding.gmc_sample(m, cond, integ, K, 2, 0, out=ob)
+            fn()
+            t = float(np.median(time_launches(fn, 5, stream)))
+            ev = K * (4 if integ == "rk4" else 1)
+            fl = (film_flops_per_sample(512, ev) if name == "film" else flops_per_sample(512, ev)) * NB
+            out["cost"].append({"net": name, "integrator": integ, "K": K, "batch": NB, "ms": t,
+                                "tps": NB / (t * 1e-3), "flop_per_launch": fl,
+                                "frac_peak": fl / (t * 1e-3) / PEAK["bf16"]})
+    prob = inputs.checkerboard_problem(32)
+    world = binding.World(1 << 20, 1, 1 << 12)
+    nh = 200_000
+    flux = {"analog": transport.run_problem(world, prob, nh, 1, binding.SAMPLER_MC)["flux"] / nh,
+            "analog_seed2": transport.run_problem(world, prob, nh, 2, binding.SAMPLER_MC)["flux"] / nh}
+    for name, m in models.items():
+        for integ, K in integs:
+            r = transport.run_problem(world, prob, nh, 3, binding.SAMPLER_GMC, m, K, integrator=integ)
+            flux[f"{name}_{integ}{K}"] = r["flux"] / nh
+            out["transport"][f"{name}_{integ}{K}"] = sampler_health(r, nh)
+    world.close()
+    l1 = lambda a: float(np.abs(a - flux["analog"]).sum() / np.abs(flux["analog"]).sum())
+    for k, v in flux.items():
+        if k != "analog":
+            out["transport"].setdefault(k, {})["flux_rel_l1_vs_analog"] = l1(v)
+    out["transport"]["workload"] = f"32x32 checkerboard (0.5,0.5)/(50,0.99), central 4x4 source, {nh} histories"
+    for m in models.values():
+        m.close()
+    return out
+
+
 # ------------------------------------------------------------------------------------------
 
 def profile_launches(args):
@@ -484,7 +584,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving stream")
     ap.add_argument("--detail", default=None, help="file for the full results (JSON)")
-    ap.add_argument("--study", default=None, choices=["convergence", "transport", "paper_scale", "thick"],
+    ap.add_argument("--study", default=None, choices=["convergence", "transport", "paper_scale", "thick", "film"],
                     help="run one longer study instead of the benchmark")
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: bf16 | fp8 | rk4 (H = 512, 2^20, "
@@ -521,7 +621,8 @@ def main():
         fn = {"convergence": lambda: study_convergence(binding, inputs, w512),
               "transport": lambda: study_transport(binding, inputs, w512),
               "paper_scale": lambda: study_paper_scale(binding, inputs, w512),
-              "thick": lambda: study_thick(binding, inputs)}[args.study]
+              "thick": lambda: study_thick(binding, inputs),
+              "film": lambda: study_film(binding, inputs, w512)}[args.study]
         res = {"study": args.study, "result": fn()}
         os.makedirs(os.path.dirname(detail_path), exist_ok=True)
         with open(detail_path, "w") as f:

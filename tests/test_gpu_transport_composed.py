@@ -87,3 +87,37 @@ def test_gmc_transport_matches_oracle_composition(orc, name, prob, n_in, flags, 
     assert g["rejected_n"].sum() == ref["rejected_n"].sum()
     bal = g["leak"].sum() + g["absorbed"].sum() + g["cutoff"].sum()
     assert abs(bal - ns) < 1e-9 * ns
+
+
+FILM_CASES = [
+    ("film_square_euler", inputs.Problem(8, 8, 0.5, _T, _C, 3, 3, 2, 2), 10, 0, "euler", 8),
+    ("film_rect_rk4", inputs.Problem(8, 8, 0.5, _T, _C, 3, 3, 2, 2, Ly=0.7), 11, 0, "rk4", 2),
+    ("film_split_square_euler", inputs.Problem(8, 8, 0.5, _T, _C, 3, 3, 2, 2), 10, 2, "euler", 8),
+]
+
+
+@pytest.mark.parametrize("name,prob,n_in,flags,integ,K", FILM_CASES, ids=[c[0] for c in FILM_CASES])
+def test_gmc_transport_with_the_residual_network(orc, name, prob, n_in, flags, integ, K):
+    # the same composition with the residual velocity network with adaptive modulation as the
+    # stage-2 sampler (FP32, H = 128, random-init)
+    binding = require_gpu()
+    n, seed = 1200, 37
+    w = inputs.random_film_weights(128, 60 + n_in + flags, n_in=n_in, flags=flags)
+    stage2 = orc.stage2_generative(w, K, integ)
+    full = orc.transport_composed(prob, seed, np.arange(n), stage2)
+    risk = np.array(full["at_risk"], np.int64)
+    safe = np.setdiff1d(np.arange(n), risk)
+    ref = orc.transport_composed(prob, seed, safe, stage2) if risk.size else full
+    print(f"{name}: {full['events']:.0f} transmissions, {risk.size} histories at risk ({risk.size / n:.2%})")
+    assert risk.size / n < 0.05
+    m = binding.Model(inputs.pack_blob(w), "fp32")
+    world = binding.World(1 << 12, 1, 1 << 8)
+    world.set_streaming(64 if flags & 2 else 1)
+    g = gpu_histories(binding, world, prob, seed, safe, m, K, integ)
+    world.close()
+    m.close()
+    for k in ("flux", "absorbed", "leak", "cutoff", "wpath", "path", "visits"):
+        ok, worst = per_cell_ok(g[k], ref[k], safe.size)
+        print(f"{name}: {k} per-cell worst ratio to the bound {worst:.2e}")
+        assert ok, (k, worst)
+    assert g["rejected_n"].sum() == ref["rejected_n"].sum()
