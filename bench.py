@@ -553,6 +553,15 @@ def profile_launches(args):
         o = binding.DeviceExit.empty(N)
         for s in range(args.steps):
             binding.gmc_sample(m, c, integ, K, 2, s * N, out=o)
+    elif kind in ("film", "film_rk4"):
+        integ, K = ("rk4", 12) if kind == "film_rk4" else ("euler", HEAD_K)
+        w = fitted("gmc_film_h512.bin") or inputs.random_film_weights(HEAD_H, 1)
+        m = binding.Model(inputs.pack_blob(w), "bf16")
+        N = HEAD_N
+        c = binding.DeviceCond.from_host(inputs.transmission_conditions(N, 3))
+        o = binding.DeviceExit.empty(N)
+        for s in range(args.steps):
+            binding.gmc_sample(m, c, integ, K, 2, s * N, out=o)
     elif kind == "walk":
         parts = args.profile.split(":")
         tau = float(parts[1]) if len(parts) > 1 else 100.0
@@ -587,7 +596,7 @@ def main():
     ap.add_argument("--study", default=None, choices=["convergence", "transport", "paper_scale", "thick", "film"],
                     help="run one longer study instead of the benchmark")
     ap.add_argument("--profile", default=None,
-                    help="only launch one kernel --steps times: bf16 | fp8 | rk4 (H = 512, 2^20, "
+                    help="only launch one kernel --steps times: bf16 | fp8 | rk4 | film | film_rk4 (H = 512, 2^20, "
                          "fitted weights) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")

@@ -156,7 +156,7 @@ class VelocityFiLM(torch.nn.Module):
     def to_weights(self, seed: int, flags: int = 0) -> inputs.FilmWeights:
         W = [l.weight.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
         b = [l.bias.detach().float().cpu().numpy().astype(np.float32) for l in self.layers]
-        n_in = W[0].shape[1] - 8
+        n_in = W[0].shape[1] - 7          # input layer over [x (5), time features (8), condition]
         return inputs.FilmWeights(W[0].shape[0], W[1].shape[0], W, b, seed, n_in, flags | inputs.FILM_FLAG)
 
 
