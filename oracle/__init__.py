@@ -220,6 +220,13 @@ def round_e4m3(a) -> np.ndarray:
 PREC_FP64 = "fp64"    # exact arithmetic of the network, no rounding
 PREC_BF16 = "bf16"    # inputs of every layer and all weights rounded to bfloat16
 PREC_FP8 = "fp8"      # hidden H x H layers in e4m3 with per-layer scales, first/last in bf16
+# BF16 operands with the hidden activations carried scaled by -log2(e) (fold_exp2): the order
+# in which the library's BF16 sampler evaluates the network
+PREC_BF16_EXP2 = "bf16-exp2"
+
+# -log2(e) and -ln 2 as float32 values
+NEG_LOG2E_F32 = np.float32(-1.0 / math.log(2.0))
+NEG_LN2_F32 = np.float32(-math.log(2.0))
 
 
 def silu(a):
@@ -312,20 +319,51 @@ def film_velocity(weights, x, t, condf, precision=PREC_FP64):
     return lin(2 + 3 * nb, h)
 
 
+def fold_exp2(weights):
+    """The same network with every hidden activation carried scaled by -log2(e): the first
+    layer's weights and every hidden bias multiplied by -log2(e), the output layer's weights by
+    -ln 2, each product rounded to float32.  A layer then computes a' = -log2(e) a, and its
+    scaled activation -log2(e) SiLU(a) is a' / (1 + 2^a'); the next layer's inputs carry the
+    factor, which the following layer's unscaled weights and scaled bias keep, and the output
+    layer's -ln 2 = 1 / -log2(e) removes.  In exact arithmetic this is the network unchanged
+    (up to the float32 rounding of the products); with BF16 operands the rounded values are
+    the scaled ones."""
+    from types import SimpleNamespace
+    last = len(weights.W) - 1
+    W = [np.asarray(w, np.float32) for w in weights.W]
+    b = [np.asarray(v, np.float32) for v in weights.b]
+    W[0] = W[0] * NEG_LOG2E_F32
+    W[last] = W[last] * NEG_LN2_F32
+    b = [v * NEG_LOG2E_F32 if l < last else v for l, v in enumerate(b)]
+    return SimpleNamespace(hidden=weights.hidden, W=W, b=b, act_scale=weights.act_scale,
+                           w_scale=weights.w_scale, seed=weights.seed, n_in=weights.n_in,
+                           flags=weights.flags, exp2_folded=True)
+
+
+def silu_exp2(a):
+    """-log2(e) SiLU(x) from a = -log2(e) x: a / (1 + 2^a)."""
+    with np.errstate(over="ignore"):
+        return a / (1.0 + np.exp2(a))
+
+
 def velocity(weights, x, t, condf, precision=PREC_FP64):
     """v_theta(x, t | c) for a batch: x [n,5], t scalar, condf [n,4] -> [n,5].
     Layers: Linear(10,H) SiLU, 3 x (Linear(H,H) SiLU), Linear(H,5); the input of the first
     layer is [x, t, condition].  Weights of the residual network (those with an embedding
-    width `emb`) go to film_velocity."""
+    width `emb`) go to film_velocity.  PREC_BF16_EXP2: the network of fold_exp2 with BF16
+    operands."""
     if getattr(weights, "emb", None) is not None:
         return film_velocity(weights, x, t, condf, precision)
+    if precision == PREC_BF16_EXP2:
+        weights, precision = fold_exp2(weights), PREC_BF16
+    act = silu_exp2 if getattr(weights, "exp2_folded", False) else silu
     n = x.shape[0]
     h = np.concatenate([x, np.full((n, 1), float(t)), condf], axis=1)
     L = len(weights.W)
     for l in range(L):
         h = layer_affine(weights, l, h, precision)
         if l < L - 1:
-            h = silu(h)
+            h = act(h)
     return h
 
 

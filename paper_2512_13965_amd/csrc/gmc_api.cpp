@@ -255,6 +255,14 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     m->tmpl.xy = m->xy ? 1 : 0;
     m->tmpl.n_cond = NC;
     m->hidden = H;
+    // BF16 plain networks carry their hidden activations scaled by -log2(e) (the sampler's
+    // SiLU then takes its exponential without a multiply): the first layer's weights and every
+    // hidden bias times -log2(e), the output layer's weights times -ln 2, each product rounded
+    // to float32 before the BF16 rounding of the weights.
+    const bool fold = !film && precision == GMC_BF16;
+    constexpr float kNegLog2e = -1.4426950408889634f, kNegLn2 = -0.6931471805599453f;
+    auto weight_factor = [&](int l) { return !fold ? 1.0f : (l == 0 ? kNegLog2e : (l == NL - 1 ? kNegLn2 : 1.0f)); };
+    auto bias_factor = [&](int l) { return (fold && l < NL - 1) ? kNegLog2e : 1.0f; };
     for (int l = 0; l < NL; ++l) {
         const int P = film ? precision : layer_prec(precision, l);
         const int KBW = kb_width(P), FB = frag_bytes(P), EB = elem_bytes(P);
@@ -289,7 +297,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
                         const int k = kb * KBW + h * (KBW / 2) + e;
                         const int f = column(k);
                         const float w = (row < out_dim && f >= 0 && f < in_dim)
-                                            ? W[l][(size_t)row * in_dim + f] : 0.0f;
+                                            ? W[l][(size_t)row * in_dim + f] * weight_factor(l) : 0.0f;
                         if (P == kF32) {
                             std::memcpy(dst + e * EB, &w, 4);
                         } else if (P == kBF16) {
@@ -303,7 +311,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         // the residual network's scale maps carry the "1 +" of the modulation in their bias
         const float one = (film && l >= 2 && l < NL - 1 && (l - 2) % 3 == 1) ? 1.0f : 0.0f;
         bias[l].assign((size_t)nt * 32, 0.0f);
-        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] / (sw * sa) + one;
+        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] * bias_factor(l) / (sw * sa) + one;
     }
     static_assert(3 + 3 * kFilmBlocks == kMaxLayers, "the residual network fills every layer slot");
     size_t total = 0;

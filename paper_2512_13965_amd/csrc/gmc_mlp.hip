@@ -57,8 +57,35 @@
 namespace gmc {
 namespace {
 
+// BF16 models carry every hidden activation scaled by -log2(e): the host scales the first
+// layer's weights and every hidden bias by -log2(e) and the output layer's weights by -ln 2 (the
+// same network in exact arithmetic), so an accumulator holds a' = -log2(e) a, and the scaled
+// activation -log2(e) SiLU(a) is a' / (1 + 2^a'): the exponential takes the accumulator as it
+// is.  FP32 models keep plain activations; FP8 models (SCALE) fold their power-of-two scales.
+template <int PO, bool SCALE>
+constexpr bool exp2_folded()
+{
+    return PO == kBF16 && !SCALE;
+}
+
+// -log2(e) SiLU(a) from a' = -log2(e) a.
+__device__ __forceinline__ float silu_exp2(float a)
+{
+    return a * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(a));
+}
+
+// Multiplier of the accumulator that gives the exponential's argument: -log2(e) times the
+// scaled pre-activation, or 1 where the activations carry that factor already.
+template <int PO, bool SCALE>
+__device__ __forceinline__ float exp2_factor(float oscale)
+{
+    if constexpr (SCALE) return -1.4426950408889634f * oscale;
+    else if constexpr (exp2_folded<PO, SCALE>()) return 1.0f;
+    else return -1.4426950408889634f;
+}
+
 // One epilogue unit: SiLU(acc * oscale) * inv_next for accumulator values 4g .. 4g+3, packed in
-// the consumer's operand type.
+// the consumer's operand type (BF16 models: the scaled activation, see exp2_folded).
 template <int PO, bool SCALE>
 __device__ __forceinline__ void epi_unit(const f32x16 &acc, int g, float oscale, float inv_next,
                                          uint32_t *w)
@@ -67,7 +94,9 @@ __device__ __forceinline__ void epi_unit(const f32x16 &acc, int g, float oscale,
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const float a = SCALE ? acc[4 * g + j] * oscale : acc[4 * g + j];
-        y[j] = SCALE ? silu(a) * inv_next : silu(a);
+        if constexpr (SCALE) y[j] = silu(a) * inv_next;
+        else if constexpr (exp2_folded<PO, SCALE>()) y[j] = silu_exp2(a);
+        else y[j] = silu(a);
     }
     if constexpr (PO == kF32) {
 #pragma unroll
@@ -90,7 +119,7 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
     // With per-layer scales (powers of two) the two scalings fold into the constants: acc * c1
     // is -log2(e) * (acc * oscale) and (acc * c2) * sigmoid is (acc * oscale * sigmoid) * inv_next,
     // each with its single rounding, since scaling by a power of two is exact.
-    const float c1 = SCALE ? -1.4426950408889634f * oscale : -1.4426950408889634f;
+    const float c1 = exp2_factor<PO, SCALE>(oscale);
     const float c2 = oscale * inv_next;
     sfor<16 / DW>([&](auto HH) {
         constexpr int h0 = decltype(HH)::value * DW;
@@ -133,7 +162,8 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
 // j - D, the add of value j - 2D, the reciprocal of value j - 3D and the final multiply of value
 // j - 4D -- independent instructions -- and packs groups of values as they complete;
 // store(t, words) receives each tile's packed words (the layout of epi_tile) once its last value
-// is done.  The arithmetic is epi_tile's: acc * c1 is -log2(e) times the scaled pre-activation,
+// is done.  The arithmetic is epi_tile's: acc * c1 is -log2(e) times the scaled pre-activation
+// (c1 = 1 in BF16 models, whose accumulators carry the factor: the multiply drops out),
 // and with per-layer scales the output factor c2 = oscale * inv_next (a power of two) moves into
 // the reciprocal's argument, acc * rcp((1 + e) / c2) being exactly (acc * c2) * rcp(1 + e).
 template <int PO, bool SCALE, int NT, typename Val, typename Store>
@@ -141,7 +171,7 @@ __device__ __forceinline__ void drain_pipe(Val &&val, float oscale, float inv_ne
 {
     constexpr int NV = NT * 16;
     constexpr int D = GMC_PIPE_D;
-    const float c1 = SCALE ? -1.4426950408889634f * oscale : -1.4426950408889634f;
+    const float c1 = exp2_factor<PO, SCALE>(oscale);
     const float k = SCALE ? 1.0f / (oscale * inv_next) : 1.0f;
     float t[NV], y[NV];
     uint32_t wd[NT][4 * words_per_unit(PO)];

@@ -98,7 +98,7 @@ def test_xy_sampler_matches_oracle(orc, prec, H, K):
     from tests.gpu_util import sample_indices
     idx = sample_indices(n, 200, seed=5)
     z = np.stack([orc.noise(2, int(i), 1)[:, 0] for i in idx], axis=1)
-    ref = orc.sample_raw(w, cond.subset(idx), K, z, orc.PREC_FP64 if prec == "fp32" else orc.PREC_BF16)
+    ref = orc.sample_raw(w, cond.subset(idx), K, z, orc.PREC_FP64 if prec == "fp32" else orc.PREC_BF16_EXP2)
     err = np.abs(raw[:, idx].T - ref).max(axis=1)
     print(f"XY {prec}: p99 {np.quantile(err, .99):.2e} max {err.max():.2e}")
     tol = (1e-5, 1e-5) if prec == "fp32" else (1e-5, 5e-5)
