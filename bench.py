@@ -45,7 +45,7 @@ TAUS = [1.0, 2.0, 5.0, 10.0, 20.0, 50.0, 100.0]
 THICK_TAUS = [150.0, 200.0, 300.0, 500.0, 700.0, 1000.0]
 PEAK = {"f32": 157.3e12, "bf16": 2.5e15, "fp8": 5.0e15}
 HEAD_H, HEAD_K, HEAD_N = 512, 16, 1 << 20
-KERNEL_SOURCES = ["gmc_mlp.hip", "gmc_device.hpp", "gmc_internal.hpp"]
+KERNEL_SOURCES = ["gmc_mlp.hip", "gmc_mma.hpp", "gmc_device.hpp", "gmc_internal.hpp"]
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "mlp_ode_bf16_h512_k16_b1048576.md")
 
 

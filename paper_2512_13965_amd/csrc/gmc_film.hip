@@ -10,18 +10,22 @@
 //   h  <- h + SiLU((1 + G_j e + g_j) * (A_j h + a_j) + (S_j e + s_j)),  j = 1..3
 //   v   = W_o h + b_o
 //
-// One persistent workgroup per CU (four waves, one per SIMD) carries a tile of 128 samples
-// through all evaluations:
-//   * LDS holds the input row tile (32 features), the embedding tile (32 features) and the
-//     residual stream h (128 x H), all in the operand precision, and the ODE state;
-//   * the input layer and the embedding are MFMA contractions over the input row tile;
-//   * a block: the main H x H contraction for all of the wave's row tiles (accumulators in
-//     registers); a barrier (every wave has read h); then per accumulator tile the two
-//     32 -> H modulation contractions over the embedding tile, issued one tile ahead so they
-//     run on the matrix core while the previous tile's modulated SiLU runs on the vector
-//     units, the residual add of h read from the position the result overwrites, and the
-//     store; a barrier;
-//   * the output layer: wave w takes sample column tile w and applies the ODE update.
+// One persistent workgroup per CU carries a tile of 128 samples through all evaluations; LDS
+// holds the input row tile (32 features), the embedding tile (32 features) and the residual
+// stream h (128 x H), all in the operand precision, and the ODE state.  The input layer and the
+// embedding are MFMA contractions over the input row tile.
+//   * BF16, H >= 256: two groups of four waves (two waves per SIMD).  Group 0 owns the first
+//     half of a block's output rows, group 1 the second; per block, three barrier-separated
+//     phases pair one group's matrix k-loop with the other group's epilogue on the same SIMDs
+//     (the plain sampler's schedule).  A group's epilogue (two 32 -> H modulation
+//     contractions over the embedding tile, the modulated SiLU, the residual add, the store)
+//     writes rows of h that only it reads at that time, and reads the residual from the rows
+//     it overwrites, which still hold the block's input.
+//   * FP32 and H = 128: four waves, one per SIMD: a block's main H x H contraction for all of
+//     the wave's row tiles, a barrier, then per accumulator tile the modulation contractions,
+//     issued one tile ahead so they overlap the previous tile's vector work, the modulated
+//     SiLU, the residual add and the store; a barrier.
+//   * The output layer: four waves, one sample column tile each, and the ODE update.
 // The weights of every layer are arranged on the host in MFMA fragment order; the columns of
 // the layers that read an accumulator-written tile are permuted to the order the producing
 // accumulators stored (phys_to_feature), the "1 +" of the scale is folded into its bias.
@@ -36,9 +40,14 @@ struct FilmCfg {
     static constexpr int ACT_STRIDE = H * EB + 16;          // +16 B: conflict-free row reads
     static constexpr int IN_STRIDE = kFilmIn * EB + 16;
     static constexpr int EMB_STRIDE = kFilmEmb * EB + 16;
-    static constexpr int W = 4;                              // waves
+    // Two-group schedule (BF16, H >= 256): eight waves, two per SIMD; group 0 owns the first
+    // half of every block's output rows, group 1 the second half, and while one group runs its
+    // matrix k-loop the other runs its epilogue on the same SIMDs.
+    static constexpr bool GROUPS = (MP == kBF16 && H >= 256);
+    static constexpr int W = GROUPS ? 8 : 4;                 // waves
+    static constexpr int THREADS = 64 * W;
     static constexpr int NT = H / 32;                        // row tiles of a hidden layer
-    static constexpr int RTW = NT / W;                       // row tiles per wave
+    static constexpr int RTW = GROUPS ? NT / 8 : NT / W;     // row tiles per wave
     static constexpr int NKB_IN = kFilmIn / kb_width(MP);
     static constexpr int NKB_E = kFilmEmb / kb_width(MP);
     static constexpr int NKBH = H / kb_width(MP);
@@ -93,11 +102,12 @@ __device__ __forceinline__ void pack_tile(const float *y, uint32_t *w)
 }
 
 template <int MP, int H, int RK>
-__global__ __launch_bounds__(256, 1) void film_ode_kernel(MlpParams p)
+__global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(MlpParams p)
 {
     using C = FilmCfg<MP, H>;
     static_assert(C::LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(C::RTW >= 1 && C::NT % C::W == 0, "row tiles must split evenly over the waves");
+    static_assert(!C::GROUPS || C::NKBH % 2 == 0, "two-group schedule: each group's rows fill whole k-blocks");
     __shared__ __attribute__((aligned(16))) char smem[C::LDS_BYTES];
     char *act = smem;
     char *in0 = smem + C::LDS_ACT;
@@ -186,88 +196,221 @@ __global__ __launch_bounds__(256, 1) void film_ode_kernel(MlpParams p)
             }
             __syncthreads();
 
-            // embedding (wave w: sample column tile w) and input layer (the wave's row tiles):
-            // both read only the input row tile
-            {
-                f32x16 ea[1][1];
-                init_bias<1, 1>(ea, make_rsrc(p.bias[1], p.bias_bytes[1]), 0, lane);
-                mma_pass<MP, 1, 1, C::NKB_IN>(ea, make_rsrc(p.wA[1], p.wA_bytes[1]), 0, in0, C::IN_STRIDE,
-                                              wave, lane, nohook);
-                float y[16];
-#pragma unroll
-                for (int i = 0; i < 16; ++i) y[i] = silu(ea[0][0][i]);
-                uint32_t w[C::WPT];
-                pack_tile<MP>(y, w);
-                store_tile<MP>(w, 0, wave, emb, C::EMB_STRIDE, lane);
-            }
-            {
-                f32x16 acc[C::RTW][4];
-                init_bias<C::RTW, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), T0, lane);
-                mma_pass<MP, C::RTW, 4, C::NKB_IN>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), T0, in0,
-                                                   C::IN_STRIDE, 0, lane, nohook);
-                sfor<C::RTW * 4>([&](auto TC) {
+            if constexpr (C::GROUPS) {
+                // Two-group schedule.  Per block, three barrier-separated phases (as in the plain
+                // sampler): P1 group 0 multiplies over the first half of the k-blocks (its own
+                // rows of h) while group 1 runs the epilogue of its rows of the previous block;
+                // P2 group 0 over the second half, group 1 over the first; P3 group 0 runs its
+                // epilogue while group 1 multiplies over the second half.  A group's epilogue
+                // writes rows of h only it reads meanwhile, and reads the residual from the rows
+                // it overwrites, which still hold the block's input.
+                constexpr int RG = C::RTW;
+                constexpr int GH = C::NKBH / 2;
+                const int grp = wave >> 2, wg = wave & 3;
+                const int TB = grp * (C::NT / 2) + wg * RG;      // first row tile of this wave
+                f32x16 acc[RG][4];
+                // input layer: every wave its own rows (no activation); group 1 also the
+                // embedding (wave wg: sample column tile wg)
+                init_bias<RG, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), TB, lane);
+                mma_seq<MP, RG, 4, C::NKB_IN, C::NKB_IN, MapAll>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), TB, in0,
+                                                                 C::IN_STRIDE, 0, lane, nohook);
+                sfor<RG * 4>([&](auto TC) {
                     constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
                     float y[16];
 #pragma unroll
                     for (int i = 0; i < 16; ++i) y[i] = acc[r][c][i];
                     uint32_t w[C::WPT];
                     pack_tile<MP>(y, w);
-                    store_tile<MP>(w, T0 + r, c, act, C::ACT_STRIDE, lane);
+                    store_tile<MP>(w, TB + r, c, act, C::ACT_STRIDE, lane);
                 });
-            }
-            __syncthreads();
-
-            // residual blocks
-#pragma unroll 1
-            for (int j = 0; j < kFilmBlocks; ++j) {
-                const int lA = 2 + 3 * j, lG = lA + 1, lS = lA + 2;
-                const Rsrc wG = make_rsrc(p.wA[lG], p.wA_bytes[lG]), bG = make_rsrc(p.bias[lG], p.bias_bytes[lG]);
-                const Rsrc wS = make_rsrc(p.wA[lS], p.wA_bytes[lS]), bS = make_rsrc(p.bias[lS], p.bias_bytes[lS]);
-                f32x16 acc[C::RTW][4];
-                init_bias<C::RTW, 4>(acc, make_rsrc(p.bias[lA], p.bias_bytes[lA]), T0, lane);
-                mma_pass<MP, C::RTW, 4, C::NKBH>(acc, make_rsrc(p.wA[lA], p.wA_bytes[lA]), T0, act,
-                                                 C::ACT_STRIDE, 0, lane, nohook);
-                __syncthreads();   // every wave has read h: the block's outputs may overwrite it
-                // modulation of tile q (row tile T0 + q / 4, column tile q % 4) into slot q % 2
-                f32x16 sc[2][1][1], sh[2][1][1];
-                auto modulation = [&](auto Q) {
-                    constexpr int q = decltype(Q)::value, r = q / 4, c = q % 4;
-                    init_bias<1, 1>(sc[q % 2], bG, T0 + r, lane);
-                    mma_pass<MP, 1, 1, C::NKB_E>(sc[q % 2], wG, T0 + r, emb, C::EMB_STRIDE, c, lane, nohook);
-                    init_bias<1, 1>(sh[q % 2], bS, T0 + r, lane);
-                    mma_pass<MP, 1, 1, C::NKB_E>(sh[q % 2], wS, T0 + r, emb, C::EMB_STRIDE, c, lane, nohook);
-                };
-                modulation(std::integral_constant<int, 0>{});
-                sfor<C::RTW * 4>([&](auto Q) {
-                    constexpr int q = decltype(Q)::value, r = q / 4, c = q % 4;
-                    if constexpr (q + 1 < C::RTW * 4) modulation(std::integral_constant<int, q + 1>{});
-                    float hp[16], y[16];
-                    load_tile<MP>(hp, T0 + r, c, act, C::ACT_STRIDE, lane);
+                if (grp == 1) {
+                    f32x16 ea[1][1];
+                    init_bias<1, 1>(ea, make_rsrc(p.bias[1], p.bias_bytes[1]), 0, lane);
+                    mma_seq<MP, 1, 1, C::NKB_IN, C::NKB_IN, MapAll>(ea, make_rsrc(p.wA[1], p.wA_bytes[1]), 0, in0,
+                                                                    C::IN_STRIDE, wg, lane, nohook);
+                    float y[16];
 #pragma unroll
-                    for (int i = 0; i < 16; ++i)
-                        y[i] = hp[i] + silu(__builtin_fmaf(sc[q % 2][0][0][i], acc[r][c][i], sh[q % 2][0][0][i]));
+                    for (int i = 0; i < 16; ++i) y[i] = silu(ea[0][0][i]);
                     uint32_t w[C::WPT];
                     pack_tile<MP>(y, w);
-                    store_tile<MP>(w, T0 + r, c, act, C::ACT_STRIDE, lane);
-                });
+                    store_tile<MP>(w, 0, wg, emb, C::EMB_STRIDE, lane);
+                }
+                __syncthreads();
+                // the epilogue of block j for this wave's tiles: the two modulation contractions
+                // over the embedding tile, the modulated SiLU, the residual add, the store
+                // Per row tile the scale and shift maps' weight fragments and biases are loaded
+                // once and serve the four sample column tiles.
+                auto epilogue = [&](int j) {
+                    using M = Mma<MP>;
+                    constexpr int KBB = kb_width(MP) * elem_bytes(MP);
+                    const int lG = 3 + 3 * j, lS = lG + 1;
+                    const Rsrc wG = make_rsrc(p.wA[lG], p.wA_bytes[lG]), bG = make_rsrc(p.bias[lG], p.bias_bytes[lG]);
+                    const Rsrc wS = make_rsrc(p.wA[lS], p.wA_bytes[lS]), bS = make_rsrc(p.bias[lS], p.bias_bytes[lS]);
+                    const int h = lane >> 5, n = lane & 31;
+                    sfor<RG>([&](auto R) {
+                        constexpr int r = decltype(R)::value;
+                        const int t = __builtin_amdgcn_readfirstlane(TB + r);
+                        typename M::Frag ga[C::NKB_E], sa[C::NKB_E];
+#pragma unroll
+                        for (int kb = 0; kb < C::NKB_E; ++kb) {
+                            ga[kb] = M::load_g(wG, lane * frag_bytes(MP), (t * C::NKB_E + kb) * 64 * frag_bytes(MP));
+                            sa[kb] = M::load_g(wS, lane * frag_bytes(MP), (t * C::NKB_E + kb) * 64 * frag_bytes(MP));
+                        }
+                        f32x16 bgv[1][1], bsv[1][1];
+                        init_bias<1, 1>(bgv, bG, TB + r, lane);
+                        init_bias<1, 1>(bsv, bS, TB + r, lane);
+                        sfor<4>([&](auto CC) {
+                            constexpr int c = decltype(CC)::value;
+                            f32x16 sc = bgv[0][0], sh = bsv[0][0];
+                            const char *sb = emb + (c * 32 + n) * C::EMB_STRIDE + h * (KBB / 2);
+#pragma unroll
+                            for (int kb = 0; kb < C::NKB_E; ++kb) {
+                                const typename M::Frag b = M::load_s(sb + kb * KBB);
+                                M::run(sc, ga[kb], b);
+                                M::run(sh, sa[kb], b);
+                            }
+                            float hp[16], y[16];
+                            load_tile<MP>(hp, TB + r, c, act, C::ACT_STRIDE, lane);
+#pragma unroll
+                            for (int i = 0; i < 16; ++i)
+                                y[i] = hp[i] + silu(__builtin_fmaf(sc[i], acc[r][c][i], sh[i]));
+                            uint32_t w[C::WPT];
+                            pack_tile<MP>(y, w);
+                            store_tile<MP>(w, TB + r, c, act, C::ACT_STRIDE, lane);
+                        });
+                    });
+                };
+#pragma unroll 1
+                for (int j = 0; j < kFilmBlocks; ++j) {
+                    const int lA = 2 + 3 * j;
+                    const Rsrc wA = make_rsrc(p.wA[lA], p.wA_bytes[lA]), bA = make_rsrc(p.bias[lA], p.bias_bytes[lA]);
+                    if (grp == 0) {
+                        init_bias<RG, 4>(acc, bA, TB, lane);
+                        mma_seq<MP, RG, 4, C::NKBH, GH, MapHalf0<GH>>(acc, wA, TB, act, C::ACT_STRIDE, 0, lane, nohook);
+                    } else if (j > 0) {
+                        epilogue(j - 1);
+                    }
+                    __syncthreads();
+                    if (grp == 0) {
+                        mma_seq<MP, RG, 4, C::NKBH, GH, MapHalf1<GH>>(acc, wA, TB, act, C::ACT_STRIDE, 0, lane, nohook);
+                    } else {
+                        init_bias<RG, 4>(acc, bA, TB, lane);
+                        mma_seq<MP, RG, 4, C::NKBH, GH, MapHalf0<GH>>(acc, wA, TB, act, C::ACT_STRIDE, 0, lane, nohook);
+                    }
+                    __syncthreads();
+                    if (grp == 0) {
+                        epilogue(j);
+                    } else {
+                        mma_seq<MP, RG, 4, C::NKBH, GH, MapHalf1<GH>>(acc, wA, TB, act, C::ACT_STRIDE, 0, lane, nohook);
+                    }
+                    __syncthreads();
+                }
+                // output layer (5 x H, rows padded to one tile): group 0 wave wg, sample column
+                // tile wg, over the first half while group 1 writes its rows of the last block
+                f32x16 out[1][1];
+                const Rsrc wO = make_rsrc(p.wA[kMaxLayers - 1], p.wA_bytes[kMaxLayers - 1]);
+                if (grp == 0) {
+                    init_bias<1, 1>(out, make_rsrc(p.bias[kMaxLayers - 1], p.bias_bytes[kMaxLayers - 1]), 0, lane);
+                    mma_seq<MP, 1, 1, C::NKBH, GH, MapHalf0<GH>>(out, wO, 0, act, C::ACT_STRIDE, wg, lane, nohook);
+                } else {
+                    epilogue(kFilmBlocks - 1);
+                }
+                __syncthreads();
+                if (grp == 0) {
+                    mma_seq<MP, 1, 1, C::NKBH, GH, MapHalf1<GH>>(out, wO, 0, act, C::ACT_STRIDE, wg, lane, nohook);
+                    const int sn = wg * 32 + (lane & 31);
+                    if (lane < 32) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
+                    } else {
+                        emit(4, sn, out[0][0][0]);
+                    }
+                }
+                __syncthreads();
+            } else {
+                // embedding (wave w: sample column tile w) and input layer (the wave's row tiles):
+                // both read only the input row tile
+                {
+                    f32x16 ea[1][1];
+                    init_bias<1, 1>(ea, make_rsrc(p.bias[1], p.bias_bytes[1]), 0, lane);
+                    mma_pass<MP, 1, 1, C::NKB_IN>(ea, make_rsrc(p.wA[1], p.wA_bytes[1]), 0, in0, C::IN_STRIDE,
+                                                  wave, lane, nohook);
+                    float y[16];
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) y[i] = silu(ea[0][0][i]);
+                    uint32_t w[C::WPT];
+                    pack_tile<MP>(y, w);
+                    store_tile<MP>(w, 0, wave, emb, C::EMB_STRIDE, lane);
+                }
+                {
+                    f32x16 acc[C::RTW][4];
+                    init_bias<C::RTW, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), T0, lane);
+                    mma_pass<MP, C::RTW, 4, C::NKB_IN>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), T0, in0,
+                                                       C::IN_STRIDE, 0, lane, nohook);
+                    sfor<C::RTW * 4>([&](auto TC) {
+                        constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
+                        float y[16];
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) y[i] = acc[r][c][i];
+                        uint32_t w[C::WPT];
+                        pack_tile<MP>(y, w);
+                        store_tile<MP>(w, T0 + r, c, act, C::ACT_STRIDE, lane);
+                    });
+                }
+                __syncthreads();
+
+                // residual blocks
+#pragma unroll 1
+                for (int j = 0; j < kFilmBlocks; ++j) {
+                    const int lA = 2 + 3 * j, lG = lA + 1, lS = lA + 2;
+                    const Rsrc wG = make_rsrc(p.wA[lG], p.wA_bytes[lG]), bG = make_rsrc(p.bias[lG], p.bias_bytes[lG]);
+                    const Rsrc wS = make_rsrc(p.wA[lS], p.wA_bytes[lS]), bS = make_rsrc(p.bias[lS], p.bias_bytes[lS]);
+                    f32x16 acc[C::RTW][4];
+                    init_bias<C::RTW, 4>(acc, make_rsrc(p.bias[lA], p.bias_bytes[lA]), T0, lane);
+                    mma_pass<MP, C::RTW, 4, C::NKBH>(acc, make_rsrc(p.wA[lA], p.wA_bytes[lA]), T0, act,
+                                                     C::ACT_STRIDE, 0, lane, nohook);
+                    __syncthreads();   // every wave has read h: the block's outputs may overwrite it
+                    // modulation of tile q (row tile T0 + q / 4, column tile q % 4) into slot q % 2
+                    f32x16 sc[2][1][1], sh[2][1][1];
+                    auto modulation = [&](auto Q) {
+                        constexpr int q = decltype(Q)::value, r = q / 4, c = q % 4;
+                        init_bias<1, 1>(sc[q % 2], bG, T0 + r, lane);
+                        mma_pass<MP, 1, 1, C::NKB_E>(sc[q % 2], wG, T0 + r, emb, C::EMB_STRIDE, c, lane, nohook);
+                        init_bias<1, 1>(sh[q % 2], bS, T0 + r, lane);
+                        mma_pass<MP, 1, 1, C::NKB_E>(sh[q % 2], wS, T0 + r, emb, C::EMB_STRIDE, c, lane, nohook);
+                    };
+                    modulation(std::integral_constant<int, 0>{});
+                    sfor<C::RTW * 4>([&](auto Q) {
+                        constexpr int q = decltype(Q)::value, r = q / 4, c = q % 4;
+                        if constexpr (q + 1 < C::RTW * 4) modulation(std::integral_constant<int, q + 1>{});
+                        float hp[16], y[16];
+                        load_tile<MP>(hp, T0 + r, c, act, C::ACT_STRIDE, lane);
+#pragma unroll
+                        for (int i = 0; i < 16; ++i)
+                            y[i] = hp[i] + silu(__builtin_fmaf(sc[q % 2][0][0][i], acc[r][c][i], sh[q % 2][0][0][i]));
+                        uint32_t w[C::WPT];
+                        pack_tile<MP>(y, w);
+                        store_tile<MP>(w, T0 + r, c, act, C::ACT_STRIDE, lane);
+                    });
+                    __syncthreads();
+                }
+
+                // output layer (5 x H, rows padded to one tile): wave w, sample column tile w
+                {
+                    f32x16 out[1][1];
+                    init_bias<1, 1>(out, make_rsrc(p.bias[kMaxLayers - 1], p.bias_bytes[kMaxLayers - 1]), 0, lane);
+                    mma_pass<MP, 1, 1, C::NKBH>(out, make_rsrc(p.wA[kMaxLayers - 1], p.wA_bytes[kMaxLayers - 1]), 0,
+                                                act, C::ACT_STRIDE, wave, lane, nohook);
+                    const int sn = wave * 32 + (lane & 31);
+                    if (lane < 32) {
+#pragma unroll
+                        for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
+                    } else {
+                        emit(4, sn, out[0][0][0]);
+                    }
+                }
                 __syncthreads();
             }
-
-            // output layer (5 x H, rows padded to one tile): wave w, sample column tile w
-            {
-                f32x16 out[1][1];
-                init_bias<1, 1>(out, make_rsrc(p.bias[kMaxLayers - 1], p.bias_bytes[kMaxLayers - 1]), 0, lane);
-                mma_pass<MP, 1, 1, C::NKBH>(out, make_rsrc(p.wA[kMaxLayers - 1], p.wA_bytes[kMaxLayers - 1]), 0,
-                                            act, C::ACT_STRIDE, wave, lane, nohook);
-                const int sn = wave * 32 + (lane & 31);
-                if (lane < 32) {
-#pragma unroll
-                    for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
-                } else {
-                    emit(4, sn, out[0][0][0]);
-                }
-            }
-            __syncthreads();
         }
 
         if (tid < kTileM) {
@@ -288,8 +431,9 @@ __global__ __launch_bounds__(256, 1) void film_ode_kernel(MlpParams p)
 template <int MP, int H>
 hipError_t launch_film(const MlpParams &p, int grid, hipStream_t s)
 {
-    if (p.integrator == 1) hipLaunchKernelGGL((film_ode_kernel<MP, H, 1>), dim3(grid), dim3(256), 0, s, p);
-    else hipLaunchKernelGGL((film_ode_kernel<MP, H, 0>), dim3(grid), dim3(256), 0, s, p);
+    constexpr int threads = FilmCfg<MP, H>::THREADS;
+    if (p.integrator == 1) hipLaunchKernelGGL((film_ode_kernel<MP, H, 1>), dim3(grid), dim3(threads), 0, s, p);
+    else hipLaunchKernelGGL((film_ode_kernel<MP, H, 0>), dim3(grid), dim3(threads), 0, s, p);
     return hipGetLastError();
 }
 

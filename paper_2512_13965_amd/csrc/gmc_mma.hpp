@@ -11,6 +11,11 @@
 #include "gmc_device.hpp"
 #include "gmc_internal.hpp"
 
+// Weight fragments the half-range k-loop (mma_seq) loads ahead of the k-block it multiplies.
+#ifndef GMC_PFA
+#define GMC_PFA 2
+#endif
+
 namespace gmc {
 namespace {
 
@@ -219,6 +224,73 @@ __device__ __forceinline__ void store_tile(const uint32_t *w, int T, int c, char
     } else {
         *(u32x4 *)(row + (T / 2) * 64 + 32 * h + 16 * (T % 2)) = u32x4{w[0], w[1], w[2], w[3]};
     }
+}
+
+// k-block visiting orders.  The activation tile's k-blocks split into two halves: those holding
+// the outputs of the producing layer's first row pass ("half 0") and those of its second
+// ("half 1"); G consecutive k-blocks belong to one pass of one wave.
+struct MapAll {
+    static constexpr int kb(int j) { return j; }
+};
+template <int G>
+struct MapHalf0 {
+    static constexpr int kb(int j) { return (j / G) * 2 * G + j % G; }
+};
+template <int G>
+struct MapHalf1 {
+    static constexpr int kb(int j) { return (j / G) * 2 * G + G + j % G; }
+};
+
+// acc[r][c] += W[T0 + r] x act[column tile col0 + c] over the NJ k-blocks Map::kb(0..NJ-1) of
+// a layer with NKB k-blocks (same fragment layout and prefetch scheme as mma_pass).
+template <int P, int RP, int CT, int NKB, int NJ, typename Map, int VPM = 0, int SWAPB = 0, typename Hook>
+__device__ __forceinline__ void mma_seq(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, const char *act,
+                                        int stride, int col0, int lane, Hook &&hook)
+{
+    constexpr int MFMA_PER_RUN = (P == kF32) ? 4 : 1;
+    using M = Mma<P>;
+    using Frag = typename M::Frag;
+    constexpr int FB = frag_bytes(P);
+    constexpr int KBB = kb_width(P) * elem_bytes(P);
+    const int h = lane >> 5, n = lane & 31;
+    const int t0 = __builtin_amdgcn_readfirstlane(T0);
+    const int voff = lane * FB;
+    const char *sb = act + (col0 * 32 + n) * stride + h * (KBB / 2);
+    // k-blocks the weight loads run ahead (an FP8 k-block is four times the matrix work of a
+    // BF16 one, and its fragments twice the registers)
+    constexpr int PA = (P == kFP8) ? 1 : GMC_PFA;
+    Frag a[PA + 1][RP], b[2][CT];
+    auto loadA = [&](int slot, int kb) {
+#pragma unroll
+        for (int r = 0; r < RP; ++r) a[slot][r] = M::load_g(wA, voff, ((t0 + r) * NKB + kb) * 64 * FB);
+    };
+    auto loadB = [&](int slot, int kb) {
+#pragma unroll
+        for (int c = 0; c < CT; ++c) b[slot][c] = M::load_s(sb + c * 32 * stride + (kb ^ SWAPB) * KBB);
+    };
+    sfor<PA>([&](auto I) {
+        if constexpr (decltype(I)::value < NJ) loadA(decltype(I)::value, Map::kb(decltype(I)::value));
+    });
+    loadB(0, Map::kb(0));
+    sfor<NJ>([&](auto JJ) {
+        constexpr int j = decltype(JJ)::value;
+        if constexpr (j + PA < NJ) loadA((j + PA) % (PA + 1), Map::kb(j + PA));
+        if constexpr (j + 1 < NJ) loadB((j + 1) % 2, Map::kb(j + 1));
+#pragma unroll
+        for (int r = 0; r < RP; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[j % (PA + 1)][r], b[j % 2][c]);
+        hook(JJ);
+        if constexpr (VPM > 0) {
+            // interleave the hook's epilogue arithmetic between the MFMAs: one MFMA, then up
+            // to VPM vector instructions, so transcendental latencies hide behind matrix work
+            sfor<RP * CT * MFMA_PER_RUN>([&](auto) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x002, VPM, 0);
+            });
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    });
 }
 
 // Noise z and condition features cf of sample i of a launch (paper "Transport Algorithm",
