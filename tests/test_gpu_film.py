@@ -105,6 +105,30 @@ def test_fp32_parity(orc, n_in, integ, K):
     _check_decoded(orc, raw[:, idx], ref, out, idx)
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_xy_geometry_model(orc, prec):
+    # XY-geometry condition (fifth feature omega_x, blob flag bit 0) and exit directions decoded
+    # into the unit disk
+    binding = require_gpu()
+    n = 1_537
+    cond = inputs.xy_conditions(n, 12)
+    w = inputs.random_film_weights(128 if prec == "fp32" else 256, 70, n_in=11, flags=1)
+    raw, out = _run(binding, w, prec, cond, "rk4", 2, seed=3)
+    idx = sample_indices(n, 300, seed=4)
+    ref = _oracle(orc, w, cond, idx, "rk4", 2, orc.PREC_FP64 if prec == "fp32" else orc.PREC_BF16, seed=3)
+    err = np.abs(raw[:, idx].T - ref).max(axis=1)
+    print(f"film xy {prec}: max {err.max():.2e} p50 {np.median(err):.2e}")
+    if prec == "fp32":
+        assert err.max() < 1e-5
+    else:
+        assert np.median(err) < 1e-6
+    assert np.all(out["dir_cos"] ** 2 + out["dir_sin"] ** 2 <= 1.0 + 1e-5)
+    d = orc.decode(ref, xy=True)
+    from tests.gpu_util import face_threshold_margin
+    ok = face_threshold_margin(ref[:, 4]) > 1e-3
+    np.testing.assert_array_equal(out["face"][idx][ok], d["face"][ok])
+
+
 @pytest.mark.parametrize("n", [1, 127, 129])
 def test_fp32_small_batches(orc, n):
     binding = require_gpu()

@@ -49,13 +49,16 @@ def _same(a, b, n):
         np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-12 * n)
 
 
-@pytest.mark.parametrize("sampler", ["mc", "gmc", "gmc_split"])
+@pytest.mark.parametrize("sampler", ["mc", "gmc", "gmc_split", "gmc_film"])
 def test_graph_steps_match_direct_launches(sampler):
     binding = require_gpu()
     prob = inputs.checkerboard_problem(16, src=2)
     n = 30_000
     model = None
-    if sampler != "mc":
+    if sampler == "gmc_film":
+        # the residual network with adaptive modulation (its own kernel, eight waves)
+        model = binding.Model(inputs.pack_blob(inputs.random_film_weights(256, 3)), "bf16")
+    elif sampler != "mc":
         # gmc_split: a model flagged as fitted on collided crossings (first-flight split step)
         flags = 2 if sampler == "gmc_split" else 0
         model = binding.Model(inputs.pack_blob(inputs.random_weights(256, 3, flags=flags)), "bf16")
