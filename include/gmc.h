@@ -123,7 +123,21 @@ int gmc_device_init(void);
  * Supported: H in {128, 256} for GMC_FP32, H in {128, 256, 512} for GMC_BF16 / GMC_FP8_E4M3.
  * flags: bit 0 XY geometry (n_in = 11, condition ln tau, c, 2 y_in - 1, omega_y, omega_x);
  * bit 1 a boundary model fitted on collided crossings only (the transport step then places
- * uncollided crossings itself, see gmc_uncollided_split); other bits GMC_EINVAL.
+ * uncollided crossings itself, see gmc_uncollided_split); bit 2 the residual network with
+ * adaptive modulation (below); other bits GMC_EINVAL.
+ * GMC_BF16 models of the plain network are evaluated with their hidden activations scaled by
+ * -log2(e): the first layer's weights and the hidden biases are multiplied by -log2(e) and the
+ * output layer's weights by -ln 2 (float32 products) before the BF16 rounding (the same network
+ * in exact arithmetic).
+ * Residual network (flag bit 2; paper "Network Architecture and Inputs": learned embeddings of
+ * t and c, residual blocks with adaptive modulation): n_layers = 3 (blocks), reserved = 32
+ * (embedding width E), scales 1; layers in blob order: input W_in[H][13 + n_c] over
+ * [x0..x4, sin pi t, cos pi t, sin 2 pi t, ..., cos 8 pi t, condition (n_c = n_in - 6)];
+ * embedding W_e[32][8 + n_c] over [time features, condition] with SiLU; per block the main map
+ * A[H][H], the scale map G[H][32] and the shift map S[H][32] (h += SiLU((1 + G e + g) *
+ * (A h + a) + S e + s)); output W_o[5][H].  Supported: H = 128 for GMC_FP32, H in
+ * {128, 256, 512} for GMC_BF16 (BF16: the residual stream is stored in BF16); FP8
+ * GMC_EUNSUPPORTED.
  * The scales must be positive powers of two.  The blob is host memory owned by the caller.
  * On success *out owns device memory until gmc_model_destroy(). */
 int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_model **out);
