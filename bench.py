@@ -287,9 +287,11 @@ def bench_serving(binding, inputs, w512, n_req, hist_log10=(4.0, 7.0), load=0.7)
     world.close()
     hist = np.array([r.n_hist for r in st.requests])
     lat = st.latency_percentiles((50, 90, 99))
+    tot = {k: sum(float(r.tallies[k].sum()) for r in st.requests) for k in ("rejected_n", "rejected_w", "cutoff")}
     return {"requests": len(st.requests), "capacity_req_per_s": capacity_hz, "arrival_rate_hz": rate,
             "wall_s": st.wall, "steps": st.steps, "transmissions": st.transmissions,
             "transmissions_per_s": st.throughput, "latency_s": lat,
+            **sampler_health({"transmissions": st.transmissions, **tot}, int(hist.sum())),
             "histories": {"total": int(hist.sum()), "min": int(hist.min()), "max": int(hist.max())},
             "workload": f"Poisson stream at {load:.0%} of the measured capacity; grids 16^2-128^2, "
                         f"tau log-U[0.1,200], c U[0,1], 10^{hist_log10[0]:g}-10^{hist_log10[1]:g} "
@@ -721,7 +723,8 @@ def main():
         head["serving"] = {"p50_s": sv["latency_s"]["p50"], "p99_s": sv["latency_s"]["p99"],
                            "requests": sv["requests"], "transmissions_per_s": sv["transmissions_per_s"],
                            "histories_per_request": "1e4-1e7 log-uniform",
-                           "load": "70% of measured capacity"}
+                           "load": "70% of measured capacity",
+                           "rejected_fraction": sv["rejected_fraction"]}
         log(f"serving p50 {sv['latency_s']['p50']:.3f} s p99 {sv['latency_s']['p99']:.3f} s")
 
     if not args.no_cpu:
