@@ -307,9 +307,9 @@ def sampler_health(r: dict, n: int) -> dict:
     into cutoff weight): their share of the transmissions, the weight they removed per history,
     and the whole cutoff weight per history."""
     tx = max(int(r["transmissions"]), 1)
-    return {"rejected_fraction": float(r["rejected_n"].sum() / tx),
-            "rejected_weight_per_history": float(r["rejected_w"].sum() / n),
-            "cutoff_per_history": float(r["cutoff"].sum() / n)}
+    return {"rejected_fraction": float(np.sum(r["rejected_n"]) / tx),
+            "rejected_weight_per_history": float(np.sum(r["rejected_w"]) / n),
+            "cutoff_per_history": float(np.sum(r["cutoff"]) / n)}
 
 
 def study_convergence(binding, inputs, w512, Ns=None, runs=5):
