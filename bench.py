@@ -572,6 +572,27 @@ def profile_launches(args):
         o = binding.DeviceExit.empty(N)
         for _ in range(args.steps):
             binding.mc_transmit(c, binding.MODE_CONTINUOUS, 2, 0, out=o)
+    elif kind == "lattice_split":
+        # the paper's lattice (112^2 cells) with the full method at width 512: births from the
+        # internal model, collided crossings from the collided boundary model (RK4 x 12), the
+        # uncollided ones streamed through up to 64 cells inside a step
+        from paper_2512_13965_amd import transport
+        col = binding.Model(inputs.pack_blob(fitted("gmc_h512_collided.bin")), "bf16")
+        src = binding.Model(inputs.pack_blob(fitted("gmc_h512_internal.bin")), "bf16")
+        w = binding.World(1 << 20, 2, 1 << 14)
+        N = 200_000
+        walls = []
+        for _ in range(args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = transport.run_problem(w, inputs.lattice_problem(16), N, 1, binding.SAMPLER_GMC, col, 12,
+                                      integrator="rk4", source_model=src, source_K=12, streaming=64)
+            torch.cuda.synchronize()
+            walls.append(time.perf_counter() - t0)
+        w.close()
+        col.close()
+        src.close()
+        print(json.dumps({"lattice_split_s": walls, "steps": r["steps"], "transmissions": int(r["transmissions"])}))
     elif kind == "transport":
         from paper_2512_13965_amd import transport
         w = binding.World(1 << 20, 1, 1 << 12)
@@ -599,7 +620,7 @@ def main():
                     help="run one longer study instead of the benchmark")
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: bf16 | fp8 | rk4 | film | film_rk4 (H = 512, 2^20, "
-                         "fitted weights) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport")
+                         "fitted weights) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport | lattice_split")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()

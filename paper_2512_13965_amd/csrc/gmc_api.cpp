@@ -418,9 +418,7 @@ int launch_sampler(const gmc_model *m, gmc::MlpParams p, int64_t n, int integrat
     p.id_base = id_base;
     const int cu = gmc::device_cu_count();
     if (cu <= 0) return fail(GMC_EDEVICE, w + ": cannot query the device");
-    const int64_t ntiles = (n + gmc::kTileM - 1) / gmc::kTileM;
-    const int grid = (int)std::min<int64_t>(ntiles, cu);
-    hipError_t e = gmc::launch_mlp_ode(m->precision, m->hidden, p, grid, (hipStream_t)stream);
+    hipError_t e = gmc::launch_mlp_ode(m->precision, m->hidden, p, cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, (w + ": launch").c_str());
     return GMC_OK;
 }

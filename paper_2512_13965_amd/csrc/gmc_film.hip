@@ -29,6 +29,8 @@
 // The weights of every layer are arranged on the host in MFMA fragment order; the columns of
 // the layers that read an accumulator-written tile are permuted to the order the producing
 // accumulators stored (phys_to_feature), the "1 +" of the scale is folded into its bias.
+#include <algorithm>
+
 #include "gmc_mma.hpp"
 
 namespace gmc {
@@ -429,9 +431,10 @@ __global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(
 }
 
 template <int MP, int H>
-hipError_t launch_film(const MlpParams &p, int grid, hipStream_t s)
+hipError_t launch_film(const MlpParams &p, int cu, hipStream_t s)
 {
     constexpr int threads = FilmCfg<MP, H>::THREADS;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>((p.n + kTileM - 1) / kTileM, cu));
     if (p.integrator == 1) hipLaunchKernelGGL((film_ode_kernel<MP, H, 1>), dim3(grid), dim3(threads), 0, s, p);
     else hipLaunchKernelGGL((film_ode_kernel<MP, H, 0>), dim3(grid), dim3(threads), 0, s, p);
     return hipGetLastError();
@@ -446,13 +449,13 @@ bool film_supported(int prec, int hidden)
     return false;
 }
 
-hipError_t launch_film_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s)
+hipError_t launch_film_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s)
 {
     switch (prec * 1000 + hidden) {
-    case kF32 * 1000 + 128: return launch_film<kF32, 128>(p, grid, s);
-    case kBF16 * 1000 + 128: return launch_film<kBF16, 128>(p, grid, s);
-    case kBF16 * 1000 + 256: return launch_film<kBF16, 256>(p, grid, s);
-    case kBF16 * 1000 + 512: return launch_film<kBF16, 512>(p, grid, s);
+    case kF32 * 1000 + 128: return launch_film<kF32, 128>(p, cu, s);
+    case kBF16 * 1000 + 128: return launch_film<kBF16, 128>(p, cu, s);
+    case kBF16 * 1000 + 256: return launch_film<kBF16, 256>(p, cu, s);
+    case kBF16 * 1000 + 512: return launch_film<kBF16, 512>(p, cu, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -8,8 +8,10 @@ namespace gmc {
 
 enum Prec { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
-// Samples per workgroup tile of the fused MLP/ODE kernel and waves per workgroup.
+// Samples per workgroup tile of the fused MLP/ODE kernel (and the small tile of launches with
+// at most kSmallTileM samples per compute unit) and waves per workgroup.
 constexpr int kTileM = 128;
+constexpr int kSmallTileM = 32;
 constexpr int kWaves = 4;
 
 // Operand geometry of one "k-block" for each operand precision: features consumed per
@@ -88,10 +90,12 @@ struct MlpParams {
     uint64_t seed, id_base;
 };
 
-// One fused sampler launch for the network p.net (plain MLP or residual network).
-hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s);
+// One fused sampler launch over p.n samples (the launch's bound: p.n_dev, when set, holds the
+// count) for the network p.net (plain MLP or residual network) on a device of cu compute units:
+// the launcher picks the tile size and a grid of at most cu persistent workgroups.
+hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s);
 bool mlp_supported(int prec, int hidden);
-hipError_t launch_film_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s);
+hipError_t launch_film_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s);
 bool film_supported(int prec, int hidden);
 
 struct WalkParams {

@@ -13,6 +13,7 @@
 //     type) writes each accumulator tile back into the LDS activation tile in the column order
 //     the next layer's operand reads expect, so the next layer's B-operand reads are contiguous
 //     16-byte LDS reads; the host permutes the next layer's weight columns to match.
+#include <algorithm>
 #include <type_traits>
 #include <utility>
 
@@ -281,7 +282,7 @@ __device__ __forceinline__ void store_pass(const uint32_t *pk, int Tb, char *act
     });
 }
 
-template <int MP, int H>
+template <int MP, int H, int TM = kTileM>
 struct Cfg {
     static constexpr int P1 = layer_prec(MP, 0);            // layer 1 operand precision
     static constexpr int PH = layer_prec(MP, 1);            // hidden layers' operand precision
@@ -312,18 +313,21 @@ struct Cfg {
     static constexpr int GH = (PIPE || GROUPS) ? NKBH / 2 : 1;
     static constexpr int G5 = (PIPE || GROUPS) ? NKB5 / 2 : 1;
     static constexpr int WPK = words_per_unit(PH) > words_per_unit(P5) ? words_per_unit(PH) : words_per_unit(P5);
-    static constexpr int LDS_ACT = kTileM * ACT_STRIDE;
-    static constexpr int LDS_IN = kTileM * IN_STRIDE;
-    static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 6 + 5 + 5) * kTileM * 4;
+    static constexpr int CT = TM / 32;                      // sample column tiles of a tile
+    static constexpr int LDS_ACT = TM * ACT_STRIDE;
+    static constexpr int LDS_IN = TM * IN_STRIDE;
+    static constexpr int LDS_BYTES = LDS_ACT + LDS_IN + (5 + 6 + 5 + 5) * TM * 4;
 };
 
-template <int MP, int H, int RK>
-__global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpParams p)
+template <int MP, int H, int RK, int TM>
+__global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(MlpParams p)
 {
-    using C = Cfg<MP, H>;
+    using C = Cfg<MP, H, TM>;
+    static_assert(TM == kTileM || (C::GROUPS && TM == kSmallTileM),
+                  "small tiles run the two-group schedule only");
     static_assert(C::LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(C::RTW >= 1 && C::NT % C::W == 0, "row tiles must split evenly over the waves");
-    static_assert(C::GROUPS || C::PIPE || C::W == kTileM / 32,
+    static_assert(C::GROUPS || C::PIPE || C::W == TM / 32,
                   "the layer-by-layer path maps one wave per column tile in layer 5");
     static_assert(!C::GROUPS || (C::RPG >= 1 && C::NKBH % 2 == 0 && C::NKB5 % 2 == 0),
                   "two-group schedule: each group's rows fill whole k-blocks of the consumer");
@@ -331,16 +335,16 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
     char *act = smem;
     char *in0 = smem + C::LDS_ACT;
     float *xs = (float *)(smem + C::LDS_ACT + C::LDS_IN);   // [5][128] ODE state
-    float *cf = xs + 5 * kTileM;                              // [6][128] condition features
-    float *ksum = cf + 6 * kTileM;                            // [5][128] RK4 stage sum
-    float *vout = ksum + 5 * kTileM;                          // [5][128] last network output
+    float *cf = xs + 5 * TM;                              // [6][128] condition features
+    float *ksum = cf + 6 * TM;                            // [5][128] RK4 stage sum
+    float *vout = ksum + 5 * TM;                          // [5][128] last network output
 
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
     // samples to process: the launch's own count, or one the device holds (a captured graph
     // sized for a bucket of counts); noise and raw keep the row stride p.n
     const int64_t n_items = p.n_dev ? (int64_t)*p.n_dev : p.n;
-    const int64_t ntiles = (n_items + kTileM - 1) / kTileM;
+    const int64_t ntiles = (n_items + TM - 1) / TM;
     const float dt = 1.0f / (float)p.K;
     constexpr bool rk4 = (RK == 1);
     const int nevals = rk4 ? 4 * p.K : p.K;
@@ -349,7 +353,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
     // stage input (stages at t, t + dt/2, t + dt/2, t + dt take x, x + dt/2 k1, x + dt/2 k2,
     // x + dt k3) and after the fourth stage x += dt/6 (k1 + 2 k2 + 2 k3 + k4).
     auto emit = [&](int d, int sn, float v) {
-        const int o = d * kTileM + sn;
+        const int o = d * TM + sn;
         if constexpr (rk4) vout[o] = v;
         else xs[o] += v * dt;
     };
@@ -357,7 +361,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
         const int stage = e & 3;
 #pragma unroll
         for (int d = 0; d < 5; ++d) {
-            const int o = d * kTileM + tid;
+            const int o = d * TM + tid;
             const float v = vout[o];
             if (stage < 3) {
                 ksum[o] = stage == 0 ? v : ksum[o] + 2.0f * v;
@@ -371,8 +375,8 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
     const int TX = wave * C::RP, TY = C::NT / 2 + wave * C::RP;   // pass row tiles (pipelined path)
 
     for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t base = tile * kTileM;
-        if (tid < kTileM) {
+        const int64_t base = tile * TM;
+        if (tid < TM) {
             const int64_t i = base + tid;
             float z[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
             float lt = 0.f, cc = 0.f, yy = 0.5f, ss = 0.f, xx = 0.5f, co = 1.f, la = 0.f;
@@ -395,22 +399,22 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 }
             }
 #pragma unroll
-            for (int d = 0; d < 5; ++d) xs[d * kTileM + tid] = z[d];
+            for (int d = 0; d < 5; ++d) xs[d * TM + tid] = z[d];
             // boundary model: (ln tau, c, 2 y_in - 1, sin th), rectangular cells add ln A, an
             // XY-geometry model the entry direction's in-plane x component omega_x;
             // internal model: (ln tau, c, 2 x - 1, 2 y - 1, cos phi, sin phi)
-            cf[0 * kTileM + tid] = lt;
-            cf[1 * kTileM + tid] = cc;
+            cf[0 * TM + tid] = lt;
+            cf[1 * TM + tid] = cc;
             if (p.n_cond == 6) {
-                cf[2 * kTileM + tid] = 2.0f * xx - 1.0f;
-                cf[3 * kTileM + tid] = 2.0f * yy - 1.0f;
-                cf[4 * kTileM + tid] = co;
-                cf[5 * kTileM + tid] = ss;
+                cf[2 * TM + tid] = 2.0f * xx - 1.0f;
+                cf[3 * TM + tid] = 2.0f * yy - 1.0f;
+                cf[4 * TM + tid] = co;
+                cf[5 * TM + tid] = ss;
             } else {
-                cf[2 * kTileM + tid] = 2.0f * yy - 1.0f;
-                cf[3 * kTileM + tid] = ss;
-                cf[4 * kTileM + tid] = la;
-                cf[5 * kTileM + tid] = 0.0f;
+                cf[2 * TM + tid] = 2.0f * yy - 1.0f;
+                cf[3 * TM + tid] = ss;
+                cf[4 * TM + tid] = la;
+                cf[5 * TM + tid] = 0.0f;
             }
         }
         __syncthreads();
@@ -423,17 +427,17 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             const int k = rk4 ? (e >> 2) : e;
             const float t = ((float)k + (stage == 0 ? 0.0f : (stage == 3 ? 1.0f : 0.5f))) * dt;
             // layer-1 input row of sample tid: [x0..x4, t, ln tau, c, 2y-1, sin th, 0 x 6]
-            if ((!fold || e == 0) && tid < kTileM) {
+            if ((!fold || e == 0) && tid < TM) {
                 float v[16];
                 if (!rk4 || e == 0) {
 #pragma unroll
-                    for (int d = 0; d < 5; ++d) v[d] = xs[d * kTileM + tid];
+                    for (int d = 0; d < 5; ++d) v[d] = xs[d * TM + tid];
                 } else {
                     advance(e - 1, v);
                 }
                 v[5] = t;
 #pragma unroll
-                for (int d = 0; d < 6; ++d) v[6 + d] = cf[d * kTileM + tid];   // zero past n_cond
+                for (int d = 0; d < 6; ++d) v[6 + d] = cf[d * TM + tid];   // zero past n_cond
 #pragma unroll
                 for (int d = 12; d < 16; ++d) v[d] = 0.0f;
                 char *row = in0 + tid * C::IN_STRIDE;
@@ -469,7 +473,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 constexpr int SW5 = (C::PH != C::P5) ? C::NKB5 / 2 : 0;
                 const int grp = wave >> 2, wg = wave & 3;
                 const int TB = grp * (C::NT / 2) + wg * RG;       // first row tile of this wave
-                f32x16 acc[RG][4];
+                f32x16 acc[RG][C::CT];
                 // SiLU epilogue of accumulator tiles a[r][c] (row tile T0 + r, column tile c0 + c)
                 // into the activation tile, row tile index xor xt
                 auto drain_tiles = [&](auto POC, auto &a, int T0, int c0, float osc, float inv, int xt) {
@@ -500,20 +504,20 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     constexpr int PO = decltype(POC)::value;
                     constexpr int WPU = words_per_unit(PO);
 #if GMC_DRAIN_PIPE
-                    drain_pipe<PO, C::SCALE, RG * 4>(
+                    drain_pipe<PO, C::SCALE, RG * C::CT>(
                         [&](auto I) {
                             constexpr int i = decltype(I)::value;
-                            return acc[(i / 16) / 4][(i / 16) % 4][i % 16];
+                            return acc[(i / 16) / C::CT][(i / 16) % C::CT][i % 16];
                         },
                         osc, inv,
                         [&](auto TT, const uint32_t *wd) {
                             constexpr int tt = decltype(TT)::value;
-                            store_tile<PO>(wd, (TB + tt / 4) ^ xt, tt % 4, act, C::ACT_STRIDE, lane);
+                            store_tile<PO>(wd, (TB + tt / C::CT) ^ xt, tt % C::CT, act, C::ACT_STRIDE, lane);
                         });
                     return;
 #endif
-                    sfor<RG * 4>([&](auto TC) {
-                        constexpr int r = decltype(TC)::value / 4, c = decltype(TC)::value % 4;
+                    sfor<RG * C::CT>([&](auto TC) {
+                        constexpr int r = decltype(TC)::value / C::CT, c = decltype(TC)::value % C::CT;
                         uint32_t wd[4 * WPU];
                         epi_tile<PO, C::SCALE>(acc[r][c], osc, inv, wd);
                         store_tile<PO>(wd, (TB + r) ^ xt, c, act, C::ACT_STRIDE, lane);
@@ -524,9 +528,9 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 // the most vector work) split group 0's rows between the two waves of each SIMD
                 // instead: group 1 recomputes the second half of them (a single k-block of
                 // MFMAs) and runs that half's epilogue.
-                if constexpr (MP != kFP8) {
-                    init_bias<RG, 4>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), TB, lane);
-                    mma_seq<C::P1, RG, 4, C::NKB1, C::NKB1, MapAll>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), TB,
+                if constexpr (MP != kFP8 || C::CT < 4) {
+                    init_bias<RG, C::CT>(acc, make_rsrc(p.bias[0], p.bias_bytes[0]), TB, lane);
+                    mma_seq<C::P1, RG, C::CT, C::NKB1, C::NKB1, MapAll>(acc, make_rsrc(p.wA[0], p.wA_bytes[0]), TB,
                                                                     in0, C::IN_STRIDE, 0, lane, [](auto) {});
                     if (grp == 0) drain(std::integral_constant<int, C::PH>{}, p.oscale[0], p.inv_in_scale[1]);
                 } else {
@@ -537,8 +541,8 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                     f32x16 part[RS][CS];
                     const int TS0 = wg * RG + (grp == 0 ? 0 : R_OFF), CS0 = (grp == 0) ? 0 : C_OFF;
                     if (grp != 0) {
-                        init_bias<RG, 4>(acc, b0, TB, lane);
-                        mma_seq<C::P1, RG, 4, C::NKB1, C::NKB1, MapAll>(acc, w0, TB, in0, C::IN_STRIDE, 0, lane,
+                        init_bias<RG, C::CT>(acc, b0, TB, lane);
+                        mma_seq<C::P1, RG, C::CT, C::NKB1, C::NKB1, MapAll>(acc, w0, TB, in0, C::IN_STRIDE, 0, lane,
                                                                         [](auto) {});
                     }
                     init_bias<RS, CS>(part, b0, TS0, lane);
@@ -551,19 +555,19 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 auto hidden = [&](int l, auto OUTP) {
                     const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
                     if (grp == 0) {
-                        init_bias<RG, 4>(acc, bl, TB, lane);
-                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
+                        init_bias<RG, C::CT>(acc, bl, TB, lane);
+                        mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
                             acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
                     } else {
                         drain(std::integral_constant<int, C::PH>{}, p.oscale[l - 1], p.inv_in_scale[l]);
                     }
                     __syncthreads();
                     if (grp == 0) {
-                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
+                        mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
                             acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
                     } else {
-                        init_bias<RG, 4>(acc, bl, TB, lane);
-                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
+                        init_bias<RG, C::CT>(acc, bl, TB, lane);
+                        mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
                             acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
                     }
                     __syncthreads();
@@ -571,7 +575,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                         drain(OUTP, p.oscale[l], (l < 3) ? p.inv_in_scale[l + 1] : 1.0f,
                               decltype(OUTP)::value != C::PH ? XT : 0);
                     } else {
-                        mma_seq<C::PH, RG, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
+                        mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
                             acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
                     }
                     __syncthreads();
@@ -582,17 +586,18 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 if constexpr (NSAME == 2) hidden(3, std::integral_constant<int, C::P5>{});
                 f32x16 out[1][1];
                 const Rsrc w4 = make_rsrc(p.wA[4], p.wA_bytes[4]);
-                // layer 5 (5 x H): group 0 wave w owns sample column tile w; group 1 writes
-                // its layer-4 rows meanwhile
-                if (grp == 0) {
+                // layer 5 (5 x H): group 0 wave w owns sample column tile w (small tiles: the
+                // waves w < CT); group 1 writes its layer-4 rows meanwhile
+                const bool l5 = (grp == 0) && (C::CT == 4 || wg < C::CT);
+                if (l5) {
                     init_bias<1, 1>(out, make_rsrc(p.bias[4], p.bias_bytes[4]), 0, lane);
                     mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf0<C::G5>, 0, SW5>(
                         out, w4, 0, act, C::ACT_STRIDE, wg, lane, [](auto) {});
-                } else {
+                } else if (grp != 0) {
                     drain(std::integral_constant<int, C::P5>{}, p.oscale[3], 1.0f, XT);
                 }
                 __syncthreads();
-                if (grp == 0) {
+                if (l5) {
                     mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>, 0, SW5>(
                         out, w4, 0, act, C::ACT_STRIDE, wg, lane, [](auto) {});
                     const int sn = wg * 32 + (lane & 31);
@@ -603,13 +608,13 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                             float x[4];
 #pragma unroll
                             for (int d = 0; d < 4; ++d) {
-                                x[d] = xs[d * kTileM + sn] + out[0][0][d] * dt;
-                                xs[d * kTileM + sn] = x[d];
+                                x[d] = xs[d * TM + sn] + out[0][0][d] * dt;
+                                xs[d * TM + sn] = x[d];
                             }
                             *(u32x2 *)row = u32x2{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3])};
                         } else {
-                            const float x4 = xs[4 * kTileM + sn] + out[0][0][0] * dt;
-                            xs[4 * kTileM + sn] = x4;
+                            const float x4 = xs[4 * TM + sn] + out[0][0][0] * dt;
+                            xs[4 * TM + sn] = x4;
                             *(uint32_t *)(row + 8) = pack_bf16(x4, (float)(e + 1) * dt);
                         }
                     } else if (lane < 32) {
@@ -670,7 +675,7 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
                 // layer 5 (5 x H, rows padded to one tile) over the first-pass k-blocks while
                 // layer 4's second pass drains; wave w < 4 owns sample column tile w, further
                 // waves only drain
-                constexpr int CT5 = kTileM / 32;
+                constexpr int CT5 = TM / 32;
                 f32x16 out[1][1];
                 const Rsrc w4 = make_rsrc(p.wA[4], p.wA_bytes[4]);
                 auto drain4 = [&](auto J) {
@@ -740,14 +745,14 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
             __syncthreads();
         }
 
-        if (tid < kTileM) {
+        if (tid < TM) {
             const int64_t i = base + tid;
             float xk[5];
             if constexpr (rk4) {
                 advance(nevals - 1, xk);
             } else {
 #pragma unroll
-                for (int d = 0; d < 5; ++d) xk[d] = xs[d * kTileM + tid];
+                for (int d = 0; d < 5; ++d) xk[d] = xs[d * TM + tid];
             }
             if (i < n_items) {
                 const float a0 = xk[0], a1 = xk[1], a2 = xk[2], a3 = xk[3], a4 = xk[4];
@@ -771,13 +776,28 @@ __global__ __launch_bounds__((Cfg<MP, H>::THREADS), 1) void mlp_ode_kernel(MlpPa
     }
 }
 
-template <int MP, int H>
-hipError_t launch_one(const MlpParams &p, int grid, hipStream_t s)
+template <int MP, int H, int TM>
+hipError_t launch_tiles(const MlpParams &p, int cu, hipStream_t s)
 {
-    constexpr int threads = Cfg<MP, H>::THREADS;
-    if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1>), dim3(grid), dim3(threads), 0, s, p);
-    else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0>), dim3(grid), dim3(threads), 0, s, p);
+    constexpr int threads = Cfg<MP, H, TM>::THREADS;
+    const int64_t ntiles = (p.n + TM - 1) / TM;
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cu));
+    if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1, TM>), dim3(grid), dim3(threads), 0, s, p);
+    else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0, TM>), dim3(grid), dim3(threads), 0, s, p);
     return hipGetLastError();
+}
+
+// Launches with at most kSmallTileM samples per compute unit (the tail steps of a transport
+// run, small requests) take 32-sample tiles when the model runs the two-group schedule: a
+// tile's latency is then set by streaming the weights from L2 rather than by four column
+// tiles of matrix work.
+template <int MP, int H>
+hipError_t launch_one(const MlpParams &p, int cu, hipStream_t s)
+{
+    if constexpr (Cfg<MP, H>::GROUPS) {
+        if (p.n <= (int64_t)kSmallTileM * cu) return launch_tiles<MP, H, kSmallTileM>(p, cu, s);
+    }
+    return launch_tiles<MP, H, kTileM>(p, cu, s);
 }
 
 }  // namespace
@@ -789,18 +809,18 @@ bool mlp_supported(int prec, int hidden)
     return false;
 }
 
-hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int grid, hipStream_t s)
+hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s)
 {
-    if (p.net == 1) return launch_film_ode(prec, hidden, p, grid, s);
+    if (p.net == 1) return launch_film_ode(prec, hidden, p, cu, s);
     switch (prec * 1000 + hidden) {
-    case kF32 * 1000 + 128: return launch_one<kF32, 128>(p, grid, s);
-    case kF32 * 1000 + 256: return launch_one<kF32, 256>(p, grid, s);
-    case kBF16 * 1000 + 128: return launch_one<kBF16, 128>(p, grid, s);
-    case kBF16 * 1000 + 256: return launch_one<kBF16, 256>(p, grid, s);
-    case kBF16 * 1000 + 512: return launch_one<kBF16, 512>(p, grid, s);
-    case kFP8 * 1000 + 128: return launch_one<kFP8, 128>(p, grid, s);
-    case kFP8 * 1000 + 256: return launch_one<kFP8, 256>(p, grid, s);
-    case kFP8 * 1000 + 512: return launch_one<kFP8, 512>(p, grid, s);
+    case kF32 * 1000 + 128: return launch_one<kF32, 128>(p, cu, s);
+    case kF32 * 1000 + 256: return launch_one<kF32, 256>(p, cu, s);
+    case kBF16 * 1000 + 128: return launch_one<kBF16, 128>(p, cu, s);
+    case kBF16 * 1000 + 256: return launch_one<kBF16, 256>(p, cu, s);
+    case kBF16 * 1000 + 512: return launch_one<kBF16, 512>(p, cu, s);
+    case kFP8 * 1000 + 128: return launch_one<kFP8, 128>(p, cu, s);
+    case kFP8 * 1000 + 256: return launch_one<kFP8, 256>(p, cu, s);
+    case kFP8 * 1000 + 512: return launch_one<kFP8, 512>(p, cu, s);
     default: return hipErrorInvalidValue;
     }
 }

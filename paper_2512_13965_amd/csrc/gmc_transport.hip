@@ -1011,8 +1011,7 @@ int gmc_world_inject(gmc_world *w, int32_t pid, uint64_t h_begin, int64_t count,
             p.id_base = 0;
             const int cu = device_cu_count();
             if (cu <= 0) return set_error(GMC_EDEVICE, "gmc_world_inject: cannot query the device");
-            hipError_t e = launch_mlp_ode(m->precision, m->hidden, p,
-                                          (int)std::min<int64_t>((count + kTileM - 1) / kTileM, cu), s);
+            hipError_t e = launch_mlp_ode(m->precision, m->hidden, p, cu, s);
             if (e != hipSuccess) return set_hip_error(e, "gmc_world_inject: internal sampler");
             hipLaunchKernelGGL(source_apply_kernel, dim3(blocks_for(count)), dim3(256), 0, s, w->cells(), pid,
                                (uint32_t)h_begin, count, w->e_face, w->e_pos, w->e_dcos, w->e_dsin,
@@ -1136,8 +1135,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.integrator = w->integrator;
         p.seed = 0;
         p.id_base = 0;
-        const int64_t ntiles = (n_launch + kTileM - 1) / kTileM;
-        e = launch_mlp_ode(m->precision, m->hidden, p, (int)std::min<int64_t>(ntiles, cu), s);
+        e = launch_mlp_ode(m->precision, m->hidden, p, cu, s);
         if (e == hipSuccess && split) {
             hipLaunchKernelGGL(scatter_kernel, dim3(blocks_for(n_launch)), dim3(256), 0, s, n_launch, w->s_count,
                                w->s_idx, w->s_face, w->s_pos, w->s_dcos, w->s_dsin, w->s_path, w->e_face,

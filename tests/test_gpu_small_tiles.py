@@ -1,0 +1,61 @@
+"""Sampler launches with at most 32 samples per compute unit run 32-sample tiles (the tail steps
+of a transport run, small requests).  Every accumulator sums its k-blocks in the same order as
+with 128-sample tiles, so a sample's result does not depend on the tile size: the samples of a
+small launch must equal, bit for bit, the same samples inside a large launch (same conditions,
+same random-number ids), and match the rounding-emulating oracle like any launch."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2512_13965_amd import inputs
+from tests.gpu_util import require_gpu
+from tests.test_gpu_sampler import _oracle_raw
+
+pytestmark = pytest.mark.gpu
+
+
+def _raw(binding, m, cond_h, integ, K, n=None):
+    dc = binding.DeviceCond.from_host(cond_h)
+    n = len(cond_h) if n is None else n
+    raw = torch.empty(5 * n, dtype=torch.float32, device="cuda")
+    binding.gmc_sample(m, dc, integ, K, 7, 0, raw=raw, n=n)
+    torch.cuda.synchronize()
+    return raw.view(5, n).cpu().numpy()
+
+
+def _small_limit():
+    return 32 * torch.cuda.get_device_properties(0).multi_processor_count
+
+
+@pytest.mark.parametrize("prec,H,integ,K", [("bf16", 512, "euler", 16), ("bf16", 256, "rk4", 3),
+                                            ("fp8", 512, "euler", 8), ("fp8", 256, "rk4", 2)])
+def test_small_launch_equals_the_same_samples_in_a_large_launch(prec, H, integ, K):
+    binding = require_gpu()
+    small = _small_limit()
+    big = 8 * small                                   # 128-sample tiles
+    cond = inputs.transmission_conditions(big, 21)
+    m = binding.Model(inputs.pack_blob(inputs.random_weights(H, 22)), prec)
+    ref = _raw(binding, m, cond, integ, K)
+    for n in (1, 31, 32, 33, 1000, small):
+        got = _raw(binding, m, cond.subset(slice(0, n)), integ, K)
+        np.testing.assert_array_equal(got, ref[:, :n], err_msg=f"n = {n}")
+    m.close()
+
+
+@pytest.mark.parametrize("prec,H", [("bf16", 512), ("fp8", 512), ("bf16", 256)])
+def test_small_launch_matches_the_emulating_oracle(orc, prec, H):
+    binding = require_gpu()
+    n = 77
+    cond = inputs.transmission_conditions(n, 23)
+    w = inputs.random_weights(H, 24)
+    m = binding.Model(inputs.pack_blob(w), prec)
+    raw = _raw(binding, m, cond, "euler", 8).astype(np.float64)
+    m.close()
+    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8
+    ref = _oracle_raw(orc, w, cond, np.arange(n), 8, oprec, seed=7)
+    err = np.abs(raw.T - ref).max(axis=1)
+    print(f"{prec} H={H} small launch: p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
+    if prec == "bf16":
+        assert np.quantile(err, 0.99) < 1e-5 and err.max() < 5e-5
+    else:
+        assert np.quantile(err, 0.99) < 1e-4 and err.max() < 3e-4
