@@ -88,6 +88,15 @@ struct MlpParams {
     const float *omega_x;     // XY boundary model: in-plane x component of the entry direction
     int xy;                   // XY geometry: exit directions decoded into the unit disk
     uint64_t seed, id_base;
+    // Device-side tile choice, for launches whose count n_dev is known only on the device and
+    // whose bound n exceeds what 32-sample tiles serve: the launcher runs the 32-sample kernel
+    // first; its first lane writes to n_dev_large the count left to the 128-sample kernel (0
+    // when the count is at most small_max, else the whole count) and it exits when that count
+    // is not 0; the 128-sample kernel then takes n_dev_large as its n_dev.  n_dev_large is
+    // device memory of the caller (NULL: no device-side choice); small_max is set by the
+    // launcher.
+    unsigned long long *n_dev_large;
+    int64_t small_max;
 };
 
 // One fused sampler launch over p.n samples (the launch's bound: p.n_dev, when set, holds the

@@ -344,6 +344,13 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
     // samples to process: the launch's own count, or one the device holds (a captured graph
     // sized for a bucket of counts); noise and raw keep the row stride p.n
     const int64_t n_items = p.n_dev ? (int64_t)*p.n_dev : p.n;
+    if constexpr (TM == kSmallTileM) {
+        if (p.n_dev_large) {
+            const bool large = n_items > p.small_max;
+            if (blockIdx.x == 0 && threadIdx.x == 0) *p.n_dev_large = large ? (unsigned long long)n_items : 0ull;
+            if (large) return;
+        }
+    }
     const int64_t ntiles = (n_items + TM - 1) / TM;
     const float dt = 1.0f / (float)p.K;
     constexpr bool rk4 = (RK == 1);
@@ -776,11 +783,12 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
     }
 }
 
+// grid: one persistent workgroup per tile of a launch of at most `bound` samples, at most cu
 template <int MP, int H, int TM>
-hipError_t launch_tiles(const MlpParams &p, int cu, hipStream_t s)
+hipError_t launch_tiles(const MlpParams &p, int64_t bound, int cu, hipStream_t s)
 {
     constexpr int threads = Cfg<MP, H, TM>::THREADS;
-    const int64_t ntiles = (p.n + TM - 1) / TM;
+    const int64_t ntiles = (bound + TM - 1) / TM;
     const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cu));
     if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1, TM>), dim3(grid), dim3(threads), 0, s, p);
     else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0, TM>), dim3(grid), dim3(threads), 0, s, p);
@@ -791,13 +799,27 @@ hipError_t launch_tiles(const MlpParams &p, int cu, hipStream_t s)
 // run, small requests) take 32-sample tiles when the model runs the two-group schedule: a
 // tile's latency is then set by streaming the weights from L2 rather than by four column
 // tiles of matrix work.
+// When only the device knows the count (n_dev) and its bound p.n is larger than that, the
+// choice is made on the device (MlpParams::n_dev_large) without a read-back; a sample's result
+// is the same with either tile size.
 template <int MP, int H>
 hipError_t launch_one(const MlpParams &p, int cu, hipStream_t s)
 {
+    MlpParams q = p;
+    q.n_dev_large = nullptr;
     if constexpr (Cfg<MP, H>::GROUPS) {
-        if (p.n <= (int64_t)kSmallTileM * cu) return launch_tiles<MP, H, kSmallTileM>(p, cu, s);
+        const int64_t small = (int64_t)kSmallTileM * cu;
+        if (p.n <= small) return launch_tiles<MP, H, kSmallTileM>(q, p.n, cu, s);
+        if (p.n_dev && p.n_dev_large) {
+            q.n_dev_large = p.n_dev_large;
+            q.small_max = small;
+            const hipError_t e = launch_tiles<MP, H, kSmallTileM>(q, small, cu, s);
+            if (e != hipSuccess) return e;
+            q.n_dev = p.n_dev_large;
+            q.n_dev_large = nullptr;
+        }
     }
-    return launch_tiles<MP, H, kTileM>(p, cu, s);
+    return launch_tiles<MP, H, kTileM>(q, p.n, cu, s);
 }
 
 }  // namespace

@@ -645,6 +645,7 @@ struct gmc_world {
     int32_t *s_idx = nullptr, *s_face = nullptr;
     float *s_pos = nullptr, *s_dcos = nullptr, *s_dsin = nullptr, *s_path = nullptr;
     unsigned long long *s_count = nullptr;
+    unsigned long long *n_large = nullptr;       // sampler's device-side tile choice (count handoff)
     unsigned long long *streamed = nullptr;      // crossings finished inside split gathers
     int ff_max = 64;                             // cells a particle may stream through per step
     int64_t stepped = 0;                         // particles stepped (one crossing each)
@@ -729,6 +730,7 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->s_dsin, 4 * C);
     L.add((void **)&w->s_path, 4 * C);
     L.add((void **)&w->s_count, 8);
+    L.add((void **)&w->n_large, 8);
     L.add((void **)&w->streamed, 8);
     L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);
@@ -1131,6 +1133,7 @@ int enqueue_step(gmc_world *w, int sampler, const gmc_model *m, int K, hipStream
         p.path = split ? w->s_path : w->e_path;
         p.n = n_launch;
         p.n_dev = split ? w->s_count : n_dev;
+        p.n_dev_large = p.n_dev ? w->n_large : nullptr;
         p.K = K;
         p.integrator = w->integrator;
         p.seed = 0;

@@ -59,3 +59,31 @@ def test_small_launch_matches_the_emulating_oracle(orc, prec, H):
         assert np.quantile(err, 0.99) < 1e-5 and err.max() < 5e-5
     else:
         assert np.quantile(err, 0.99) < 1e-4 and err.max() < 3e-4
+
+
+@pytest.mark.parametrize("split,graphs", [(True, False), (False, True), (True, True)])
+def test_transport_does_not_depend_on_the_device_side_tile_choice(split, graphs):
+    # Steps whose sample count only the device knows (the collided crossings of a first-flight
+    # split step; a captured step's count below its bucket) choose the tile size on the device
+    # when the host's bound exceeds 32 samples per compute unit.  A bank that holds every
+    # history at once takes both choices as the count falls; a bank of at most 32 x cu slots
+    # only ever runs 32-sample tiles.  Histories draw their own random streams, so the tallies
+    # agree up to the order of the FP64 tally additions.
+    from paper_2512_13965_amd import transport
+    binding = require_gpu()
+    small = _small_limit()
+    prob = inputs.checkerboard_problem(16, src=2)
+    n = 6 * small
+    m = binding.Model(inputs.pack_blob(inputs.random_weights(256, 31, flags=2 if split else 0)), "bf16")
+    out = {}
+    for name, cap in (("large_bank", 8 * small), ("small_bank", small)):
+        w = binding.World(cap, 1, 1 << 12)
+        w.set_graphs(graphs)
+        out[name] = transport.run_problem(w, prob, n, 5, binding.SAMPLER_GMC, m, 4, chunk=cap)
+        w.close()
+    m.close()
+    a, b = out["large_bank"], out["small_bank"]
+    print(f"split={split} graphs={graphs}: steps {a['steps']} / {b['steps']}, transmissions {a['transmissions']}")
+    assert a["transmissions"] == b["transmissions"]
+    for k in ("flux", "absorbed", "leak", "cutoff", "wpath", "path", "visits"):
+        np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-12 * n, err_msg=k)
