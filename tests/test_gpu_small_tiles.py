@@ -42,6 +42,34 @@ def test_small_launch_equals_the_same_samples_in_a_large_launch(prec, H, integ, 
     m.close()
 
 
+def _exits(binding, m, cond_h, integ, K, raw):
+    dc = binding.DeviceCond.from_host(cond_h)
+    n = len(cond_h)
+    r = torch.empty(5 * n, dtype=torch.float32, device="cuda") if raw else None
+    out = binding.gmc_sample(m, dc, integ, K, 7, 3, raw=r)
+    torch.cuda.synchronize()
+    return out.to_host()
+
+
+@pytest.mark.parametrize("prec,H,integ,K", [("bf16", 512, "euler", 4), ("fp8", 256, "rk4", 1)])
+def test_last_round_on_small_tiles_equals_one_launch(prec, H, integ, K):
+    # a count known on the host whose last round of 128-sample tiles would hold at most 32
+    # samples per compute unit runs that remainder as a second launch of 32-sample tiles over
+    # the shifted arrays (ids id_base + i continue across it); a launch that also writes the raw
+    # [5][n] state runs as one launch.  Both must give the same exits bit for bit.
+    binding = require_gpu()
+    small = _small_limit()
+    rnd = 4 * small
+    m = binding.Model(inputs.pack_blob(inputs.random_weights(H, 25)), prec)
+    for n in (rnd + 1, rnd + 777, 2 * rnd + small, 2 * rnd + small + 1):
+        cond = inputs.transmission_conditions(n, 26)
+        two = _exits(binding, m, cond, integ, K, raw=False)
+        one = _exits(binding, m, cond, integ, K, raw=True)
+        for k in one:
+            np.testing.assert_array_equal(two[k], one[k], err_msg=f"n = {n}, {k}")
+    m.close()
+
+
 @pytest.mark.parametrize("prec,H", [("bf16", 512), ("fp8", 512), ("bf16", 256)])
 def test_small_launch_matches_the_emulating_oracle(orc, prec, H):
     binding = require_gpu()
@@ -61,29 +89,35 @@ def test_small_launch_matches_the_emulating_oracle(orc, prec, H):
         assert np.quantile(err, 0.99) < 1e-4 and err.max() < 3e-4
 
 
-@pytest.mark.parametrize("split,graphs", [(True, False), (False, True), (True, True)])
-def test_transport_does_not_depend_on_the_device_side_tile_choice(split, graphs):
+@pytest.mark.parametrize("split,graphs,births", [(True, False, False), (False, True, False), (True, True, False),
+                                                (False, False, True)])
+def test_transport_does_not_depend_on_the_tile_choice(split, graphs, births):
     # Steps whose sample count only the device knows (the collided crossings of a first-flight
     # split step; a captured step's count below its bucket) choose the tile size on the device
-    # when the host's bound exceeds 32 samples per compute unit.  A bank that holds every
-    # history at once takes both choices as the count falls; a bank of at most 32 x cu slots
-    # only ever runs 32-sample tiles.  Histories draw their own random streams, so the tallies
-    # agree up to the order of the FP64 tally additions.
+    # when the host's bound exceeds 32 samples per compute unit; direct steps and births with
+    # a count known on the host run a short last round on 32-sample tiles.  A bank that holds
+    # every history at once takes every choice as the count falls; a bank of at most 32 x cu
+    # slots only ever runs 32-sample tiles.  Histories draw their own random streams, so the
+    # tallies agree up to the order of the FP64 tally additions.
     from paper_2512_13965_amd import transport
     binding = require_gpu()
     small = _small_limit()
     prob = inputs.checkerboard_problem(16, src=2)
-    n = 6 * small
+    n = 5 * small                     # 4 x cu rounds of 128-sample tiles plus one of 32 samples per cu
     m = binding.Model(inputs.pack_blob(inputs.random_weights(256, 31, flags=2 if split else 0)), "bf16")
+    src = binding.Model(inputs.pack_blob(inputs.random_weights(256, 32, n_in=12)), "bf16") if births else None
     out = {}
     for name, cap in (("large_bank", 8 * small), ("small_bank", small)):
         w = binding.World(cap, 1, 1 << 12)
         w.set_graphs(graphs)
-        out[name] = transport.run_problem(w, prob, n, 5, binding.SAMPLER_GMC, m, 4, chunk=cap)
+        out[name] = transport.run_problem(w, prob, n, 5, binding.SAMPLER_GMC, m, 4, chunk=cap,
+                                          source_model=src, source_K=3)
         w.close()
     m.close()
+    if src is not None:
+        src.close()
     a, b = out["large_bank"], out["small_bank"]
-    print(f"split={split} graphs={graphs}: steps {a['steps']} / {b['steps']}, transmissions {a['transmissions']}")
+    print(f"split={split} graphs={graphs} births={births}: steps {a['steps']} / {b['steps']}, transmissions {a['transmissions']}")
     assert a["transmissions"] == b["transmissions"]
     for k in ("flux", "absorbed", "leak", "cutoff", "wpath", "path", "visits"):
         np.testing.assert_allclose(a[k], b[k], rtol=1e-12, atol=1e-12 * n, err_msg=k)
