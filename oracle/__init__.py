@@ -223,6 +223,9 @@ PREC_FP8 = "fp8"      # hidden H x H layers in e4m3 with per-layer scales, first
 # BF16 operands with the hidden activations carried scaled by -log2(e) (fold_exp2): the order
 # in which the library's BF16 sampler evaluates the network
 PREC_BF16_EXP2 = "bf16-exp2"
+# PREC_FP8's roundings applied to the network of fold_exp2, with the activations that enter an
+# e4m3 layer carried at half that factor (velocity_fp8_exp2): the order of the FP8 sampler
+PREC_FP8_EXP2 = "fp8-exp2"
 
 # -log2(e) and -ln 2 as float32 values
 NEG_LOG2E_F32 = np.float32(-1.0 / math.log(2.0))
@@ -346,14 +349,43 @@ def silu_exp2(a):
         return a / (1.0 + np.exp2(a))
 
 
+def velocity_fp8_exp2(weights, x, t, condf):
+    """The velocity network evaluated as PREC_FP8_EXP2: the network of fold_exp2 (every
+    pre-activation a' = -log2(e) a, scaled activation -log2(e) SiLU(a) = silu_exp2(a')) with
+    PREC_FP8's operand roundings, except that an activation entering one of the e4m3 hidden
+    layers is halved before that layer divides it by its activation scale and rounds it, and
+    the layer's exact sum is doubled with its scales: with e4m3's limit of 448 the halved value
+    keeps the headroom of the plain SiLU (|log2(e) / 2| < 1), and since the halving and the
+    doubling are exact, the network is unchanged in exact arithmetic.  The last hidden layer's
+    activation enters the BF16 output layer unhalved (whose -ln 2 undoes -log2(e))."""
+    f = fold_exp2(weights)
+    last = len(f.W) - 1
+    n = x.shape[0]
+    h = np.concatenate([x, np.full((n, 1), float(t)), condf], axis=1)
+    for l in range(last + 1):
+        W = f.W[l].astype(np.float64)
+        b = f.b[l].astype(np.float64)
+        if 0 < l < last:
+            sa, sw = float(f.act_scale[l]), float(f.w_scale[l])
+            a = (round_e4m3(h / sa) @ round_e4m3(W / sw).T) * (2.0 * sa * sw) + b
+        else:
+            a = round_bf16(h) @ round_bf16(W).T + b
+        if l == last:
+            return a
+        y = silu_exp2(a)
+        h = 0.5 * y if l + 1 < last else y
+
+
 def velocity(weights, x, t, condf, precision=PREC_FP64):
     """v_theta(x, t | c) for a batch: x [n,5], t scalar, condf [n,4] -> [n,5].
     Layers: Linear(10,H) SiLU, 3 x (Linear(H,H) SiLU), Linear(H,5); the input of the first
     layer is [x, t, condition].  Weights of the residual network (those with an embedding
     width `emb`) go to film_velocity.  PREC_BF16_EXP2: the network of fold_exp2 with BF16
-    operands."""
+    operands; PREC_FP8_EXP2: velocity_fp8_exp2."""
     if getattr(weights, "emb", None) is not None:
         return film_velocity(weights, x, t, condf, precision)
+    if precision == PREC_FP8_EXP2:
+        return velocity_fp8_exp2(weights, x, t, condf)
     if precision == PREC_BF16_EXP2:
         weights, precision = fold_exp2(weights), PREC_BF16
     act = silu_exp2 if getattr(weights, "exp2_folded", False) else silu

@@ -65,3 +65,63 @@ def test_bf16_exp2_rounds_the_scaled_values(orc):
     a = orc.sample_raw(w, cond, 1, z, orc.PREC_BF16)
     b = orc.sample_raw(w, cond, 1, z, orc.PREC_BF16_EXP2)
     assert np.abs(a - b).max() > 1e-4
+
+
+# PREC_FP8_EXP2 (the FP8 sampler's order): fold_exp2's network with PREC_FP8's roundings, the
+# activations entering an e4m3 layer halved before their rounding and that layer's sum doubled.
+
+@pytest.mark.parametrize("H,K", [(128, 1), (256, 3)])
+def test_fp8_exp2_without_its_roundings_is_the_plain_network(orc, monkeypatch, H, K):
+    # with both rounding functions replaced by the identity only the float32 rounding of the
+    # folded parameters remains: every factor (the fold's -log2(e) and -ln 2, the halving, the
+    # doubling, the layer scales) has to cancel exactly for this to hold
+    w = inputs.random_weights(H, 17)
+    cond = inputs.transmission_conditions(48, 18)
+    z = inputs.noise(48, 19).astype(np.float64)
+    plain = orc.sample_raw(w, cond, K, z, orc.PREC_FP64)
+    ident = lambda a: np.asarray(a, np.float64)
+    monkeypatch.setattr(orc, "round_e4m3", ident)
+    monkeypatch.setattr(orc, "round_bf16", ident)
+    got = orc.sample_raw(w, cond, K, z, orc.PREC_FP8_EXP2)
+    assert np.abs(got - plain).max() < 1e-7 * max(1.0, np.abs(plain).max())
+
+
+def _saturation_case(orc):
+    """10 -> 4 -> 4 -> 5: layer 1 (BF16) has no weights and bias 60 on row 0, so its folded
+    pre-activation is a' = float32(60 * -log2(e)) = -86.5617... and its scaled activation
+    a' / (1 + 2^a') is a' itself in FP64; layer 2 (e4m3, activation scale 2^-3, weight scale
+    2^-4: W / sw = 16 on the diagonal) copies row 0; the output layer (BF16) copies row 0 into
+    v0."""
+    W = [np.zeros((4, 10), np.float32), np.eye(4, dtype=np.float32), np.zeros((5, 4), np.float32)]
+    b = [np.array([60.0, 0, 0, 0], np.float32), np.zeros(4, np.float32), np.zeros(5, np.float32)]
+    W[2][0, 0] = 1.0
+    return inputs.Weights(4, W, b, np.array([1.0, 2.0 ** -3, 1.0], np.float32),
+                          np.array([1.0, 2.0 ** -4, 1.0], np.float32))
+
+
+def test_fp8_exp2_halves_before_rounding(orc):
+    # worked by hand: a' = -86.5617 enters the e4m3 layer halved: -43.2809 / 2^-3 = -346.25,
+    # which e4m3 (steps of 32 in [256, 448]) rounds to -352 (not saturated); the doubled sum is
+    # -352 * 16 * 2 * 2^-3 * 2^-4 = -88, whose scaled activation is -88 again; the output
+    # layer's weight is -ln 2 rounded to BF16, -0.69140625, so v0 = 88 * 0.69140625 = 60.84375.
+    # Rounding the unhalved -692.49 would have saturated at -448 (v0 = 38.72 without the
+    # doubling), and so would -43.28 divided by the weight scale instead (swapped scales).
+    w = _saturation_case(orc)
+    assert float(np.float32(60.0) * orc.NEG_LOG2E_F32) * 4 == pytest.approx(-346.247, abs=1e-3)
+    v = orc.velocity(w, np.zeros((1, 5)), 0.0, np.zeros((1, 4)), orc.PREC_FP8_EXP2)
+    assert v[0, 0] == 88 * 0.69140625
+    np.testing.assert_array_equal(v[0, 1:], 0.0)
+
+
+def test_fp8_exp2_rounds_other_values_than_fp8(orc):
+    # the two FP8 evaluation orders round different values, and both stay within FP8's error
+    # of the exact network
+    w = inputs.random_weights(256, 21)
+    cond = inputs.transmission_conditions(64, 22)
+    z = inputs.noise(64, 23).astype(np.float64)
+    exact = orc.sample_raw(w, cond, 4, z, orc.PREC_FP64)
+    a = orc.sample_raw(w, cond, 4, z, orc.PREC_FP8)
+    b = orc.sample_raw(w, cond, 4, z, orc.PREC_FP8_EXP2)
+    assert np.abs(a - b).max() > 1e-4
+    ea, eb = np.abs(a - exact).max(), np.abs(b - exact).max()
+    assert eb < 3 * ea and ea < 3 * eb
