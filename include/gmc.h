@@ -125,10 +125,12 @@ int gmc_device_init(void);
  * bit 1 a boundary model fitted on collided crossings only (the transport step then places
  * uncollided crossings itself, see gmc_uncollided_split); bit 2 the residual network with
  * adaptive modulation (below); other bits GMC_EINVAL.
- * GMC_BF16 models of the plain network are evaluated with their hidden activations scaled by
- * -log2(e): the first layer's weights and the hidden biases are multiplied by -log2(e) and the
- * output layer's weights by -ln 2 (float32 products) before the BF16 rounding (the same network
- * in exact arithmetic).
+ * GMC_BF16 and GMC_FP8_E4M3 models of the plain network are evaluated with their hidden
+ * activations scaled by -log2(e): the first layer's weights and the hidden biases are multiplied
+ * by -log2(e) and the output layer's weights by -ln 2 (float32 products) before the BF16
+ * rounding (the same network in exact arithmetic).  The e4m3 layers keep their weights and take
+ * half the scaled activation over their activation scale (so e4m3's limit of 448 leaves the
+ * plain SiLU's headroom); 2 w_scale act_scale must lie in [2^-127, 2^127] (GMC_EINVAL).
  * Residual network (flag bit 2; paper "Network Architecture and Inputs": learned embeddings of
  * t and c, residual blocks with adaptive modulation): n_layers = 3 (blocks), reserved = 32
  * (embedding width E), scales 1; layers in blob order: input W_in[H][13 + n_c] over

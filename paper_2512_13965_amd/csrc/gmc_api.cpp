@@ -255,11 +255,15 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     m->tmpl.xy = m->xy ? 1 : 0;
     m->tmpl.n_cond = NC;
     m->hidden = H;
-    // BF16 plain networks carry their hidden activations scaled by -log2(e) (the sampler's
-    // SiLU then takes its exponential without a multiply): the first layer's weights and every
-    // hidden bias times -log2(e), the output layer's weights times -ln 2, each product rounded
-    // to float32 before the BF16 rounding of the weights.
-    const bool fold = !film && precision == GMC_BF16;
+    // BF16 and FP8 plain networks carry their hidden activations scaled by -log2(e) (the
+    // sampler's SiLU then takes its exponential without a multiply): the first layer's weights
+    // and every hidden bias times -log2(e), the output layer's weights times -ln 2, each
+    // product rounded to float32 before the BF16 rounding of the weights.  The e4m3 hidden
+    // layers keep their weights; they take half the scaled activation over their activation
+    // scale sa (the same headroom below e4m3's 448 as the plain SiLU) and multiply their sum by
+    // 2 sw sa on the matrix core (its E8M0 operand scale), so their accumulators hold the
+    // scaled pre-activation with the bias added unscaled.
+    const bool fold = !film && (precision == GMC_BF16 || precision == GMC_FP8_E4M3);
     constexpr float kNegLog2e = -1.4426950408889634f, kNegLn2 = -0.6931471805599453f;
     auto weight_factor = [&](int l) { return !fold ? 1.0f : (l == 0 ? kNegLog2e : (l == NL - 1 ? kNegLn2 : 1.0f)); };
     auto bias_factor = [&](int l) { return (fold && l < NL - 1) ? kNegLog2e : 1.0f; };
@@ -284,8 +288,17 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         const bool f8 = (P == kFP8);
         const float sw = f8 ? hd.w_scale[l] : 1.0f, sa = f8 ? hd.act_scale[l] : 1.0f;
         if (l < 5) {
-            m->tmpl.oscale[l] = sw * sa;
-            m->tmpl.inv_in_scale[l] = 1.0f / sa;
+            m->tmpl.oscale[l] = 1.0f;
+            m->tmpl.inv_in_scale[l] = f8 ? 0.5f / sa : 1.0f;
+            m->tmpl.mscale[l] = 127;
+            if (f8) {
+                const int e = (int)std::lround(std::log2(2.0 * (double)sw * (double)sa));
+                if (e < -127 || e > 127) {
+                    delete m;
+                    return fail(GMC_EINVAL, "gmc_model_create: FP8 layer scales out of the E8M0 range");
+                }
+                m->tmpl.mscale[l] = 127 + e;
+            }
         }
         frag[l].assign((size_t)nt * nkb * 64 * FB, 0);
         for (int T = 0; T < nt; ++T)
@@ -311,7 +324,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         // the residual network's scale maps carry the "1 +" of the modulation in their bias
         const float one = (film && l >= 2 && l < NL - 1 && (l - 2) % 3 == 1) ? 1.0f : 0.0f;
         bias[l].assign((size_t)nt * 32, 0.0f);
-        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] * bias_factor(l) / (sw * sa) + one;
+        for (int r = 0; r < out_dim; ++r) bias[l][r] = B[l][r] * bias_factor(l) + one;
     }
     static_assert(3 + 3 * kFilmBlocks == kMaxLayers, "the residual network fills every layer slot");
     size_t total = 0;

@@ -268,8 +268,8 @@ __global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(
 #pragma unroll
                             for (int kb = 0; kb < C::NKB_E; ++kb) {
                                 const typename M::Frag b = M::load_s(sb + kb * KBB);
-                                M::run(sc, ga[kb], b);
-                                M::run(sh, sa[kb], b);
+                                M::run(sc, ga[kb], b, 127);
+                                M::run(sh, sa[kb], b, 127);
                             }
                             float hp[16], y[16];
                             load_tile<MP>(hp, TB + r, c, act, C::ACT_STRIDE, lane);

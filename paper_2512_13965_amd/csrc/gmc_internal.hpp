@@ -69,8 +69,10 @@ struct MlpParams {
     const void *wA[kMaxLayers];     // arranged operand fragments per layer
     const float *bias[kMaxLayers];  // per layer, rows padded to a multiple of 32, pre-divided by oscale
     uint32_t wA_bytes[kMaxLayers], bias_bytes[kMaxLayers];   // sizes (bounds of the buffer loads)
-    float oscale[5];          // accumulator multiplier per layer (FP8 hidden layers: sw * sa)
-    float inv_in_scale[5];    // 1 / activation scale of the input of layer l (FP8 hidden layers)
+    float oscale[5];          // accumulator multiplier per layer (1 in every model built here)
+    float inv_in_scale[5];    // factor of the activation stored as layer l's input: FP8 hidden
+                              // layers 1 / (2 sa) (the halved scaled activation over the
+                              // layer's activation scale), else 1
     const float *log_tau, *c, *y_in, *sin_th;
     const float *x_in, *cos_phi;   // internal model only: birth x and direction cosine
     const float *log_aspect;  // rectangular boundary model: ln(width / entry-face length), or NULL
@@ -97,6 +99,9 @@ struct MlpParams {
     // launcher.
     unsigned long long *n_dev_large;
     int64_t small_max;
+    // FP8 hidden layers: E8M0 byte (127 + e) of the matrix core's operand scale 2^e = 2 sw sa
+    // (weight and activation scales, and the 2 that undoes the halving), else 127
+    int32_t mscale[5];
 };
 
 // One fused sampler launch over p.n samples (the launch's bound: p.n_dev, when set, holds the

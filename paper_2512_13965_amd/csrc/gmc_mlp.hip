@@ -55,15 +55,18 @@
 namespace gmc {
 namespace {
 
-// BF16 models carry every hidden activation scaled by -log2(e): the host scales the first
-// layer's weights and every hidden bias by -log2(e) and the output layer's weights by -ln 2 (the
-// same network in exact arithmetic), so an accumulator holds a' = -log2(e) a, and the scaled
-// activation -log2(e) SiLU(a) is a' / (1 + 2^a'): the exponential takes the accumulator as it
-// is.  FP32 models keep plain activations; FP8 models (SCALE) fold their power-of-two scales.
+// BF16 and FP8 models carry every hidden activation scaled by -log2(e): the host scales the
+// first layer's weights and every hidden bias by -log2(e) and the output layer's weights by
+// -ln 2 (the same network in exact arithmetic), so an accumulator holds a' = -log2(e) a, and
+// the scaled activation -log2(e) SiLU(a) is a' / (1 + 2^a'): the exponential takes the
+// accumulator as it is.  FP8 models (SCALE) store half of it divided by the next layer's
+// activation scale (a power of two, folded into the reciprocal's argument) and their e4m3
+// layers apply 2 sw sa through the matrix core's operand scale.  FP32 models keep plain
+// activations.
 template <int PO, bool SCALE>
 constexpr bool exp2_folded()
 {
-    return PO == kBF16 && !SCALE;
+    return SCALE || PO == kBF16;
 }
 
 // -log2(e) SiLU(a) from a' = -log2(e) a.
@@ -75,15 +78,15 @@ __device__ __forceinline__ float silu_exp2(float a)
 // Multiplier of the accumulator that gives the exponential's argument: -log2(e) times the
 // scaled pre-activation, or 1 where the activations carry that factor already.
 template <int PO, bool SCALE>
-__device__ __forceinline__ float exp2_factor(float oscale)
+__device__ __forceinline__ float exp2_factor(float)
 {
-    if constexpr (SCALE) return -1.4426950408889634f * oscale;
-    else if constexpr (exp2_folded<PO, SCALE>()) return 1.0f;
+    if constexpr (exp2_folded<PO, SCALE>()) return 1.0f;
     else return -1.4426950408889634f;
 }
 
-// One epilogue unit: SiLU(acc * oscale) * inv_next for accumulator values 4g .. 4g+3, packed in
-// the consumer's operand type (BF16 models: the scaled activation, see exp2_folded).
+// One epilogue unit: the activation of accumulator values 4g .. 4g+3 times oscale * inv_next,
+// packed in the consumer's operand type (BF16 and FP8 models: the scaled activation, see
+// exp2_folded).
 template <int PO, bool SCALE>
 __device__ __forceinline__ void epi_unit(const f32x16 &acc, int g, float oscale, float inv_next,
                                          uint32_t *w)
@@ -91,8 +94,8 @@ __device__ __forceinline__ void epi_unit(const f32x16 &acc, int g, float oscale,
     float y[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const float a = SCALE ? acc[4 * g + j] * oscale : acc[4 * g + j];
-        if constexpr (SCALE) y[j] = silu(a) * inv_next;
+        const float a = acc[4 * g + j];
+        if constexpr (SCALE) y[j] = silu_exp2(a) * (oscale * inv_next);
         else if constexpr (exp2_folded<PO, SCALE>()) y[j] = silu_exp2(a);
         else y[j] = silu(a);
     }
@@ -114,9 +117,9 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
 {
 #if GMC_DRAIN_STAGED
     constexpr int DW = GMC_DRAIN_W;
-    // With per-layer scales (powers of two) the two scalings fold into the constants: acc * c1
-    // is -log2(e) * (acc * oscale) and (acc * c2) * sigmoid is (acc * oscale * sigmoid) * inv_next,
-    // each with its single rounding, since scaling by a power of two is exact.
+    // acc * c1 is the exponential's argument (c1 = 1 where the accumulator carries -log2(e));
+    // with per-layer scales (powers of two) (acc * c2) * sigmoid is (acc * sigmoid) * c2 with
+    // its single rounding, since scaling by a power of two is exact.
     const float c1 = exp2_factor<PO, SCALE>(oscale);
     const float c2 = oscale * inv_next;
     sfor<16 / DW>([&](auto HH) {
@@ -160,9 +163,9 @@ __device__ __forceinline__ void epi_tile(const f32x16 &acc, float oscale, float 
 // j - D, the add of value j - 2D, the reciprocal of value j - 3D and the final multiply of value
 // j - 4D -- independent instructions -- and packs groups of values as they complete;
 // store(t, words) receives each tile's packed words (the layout of epi_tile) once its last value
-// is done.  The arithmetic is epi_tile's: acc * c1 is -log2(e) times the scaled pre-activation
-// (c1 = 1 in BF16 models, whose accumulators carry the factor: the multiply drops out),
-// and with per-layer scales the output factor c2 = oscale * inv_next (a power of two) moves into
+// is done.  The arithmetic is epi_tile's: acc * c1 is -log2(e) times the pre-activation (c1 = 1
+// in BF16 and FP8 models, whose accumulators carry the factor: the multiply drops out), and
+// with per-layer scales the output factor c2 = oscale * inv_next (a power of two) moves into
 // the reciprocal's argument, acc * rcp((1 + e) / c2) being exactly (acc * c2) * rcp(1 + e).
 template <int PO, bool SCALE, int NT, typename Val, typename Store>
 __device__ __forceinline__ void drain_pipe(Val &&val, float oscale, float inv_next, Store &&store)
@@ -208,7 +211,7 @@ __device__ __forceinline__ void drain_pipe(Val &&val, float oscale, float inv_ne
 // epilogue is computed and stored after that barrier.
 template <int PIN, int POUT, int RTW, int NKB, bool SCALE, bool IN_PLACE>
 __device__ __forceinline__ void dense_silu(Rsrc wA, Rsrc bias, int T0, const char *in, int in_stride, char *out,
-                                           int out_stride, int lane, float oscale, float inv_next)
+                                           int out_stride, int lane, float oscale, float inv_next, int sc = 127)
 {
     constexpr int RP = RTW >= 4 ? RTW / 2 : 1;     // row tiles per pass
     constexpr int NP = RTW / RP;                   // passes
@@ -233,7 +236,7 @@ __device__ __forceinline__ void dense_silu(Rsrc wA, Rsrc bias, int T0, const cha
                     if constexpr (u < UNITS) epi(std::integral_constant<int, p - 1>{}, u);
                 });
             }
-        });
+        }, sc);
         if constexpr (p > 0 && NKB * UPK < UNITS) {
             sfor<UNITS - NKB * UPK>([&](auto J) {
                 epi(std::integral_constant<int, p - 1>{}, NKB * UPK + decltype(J)::value);
@@ -561,21 +564,22 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
                 __syncthreads();
                 auto hidden = [&](int l, auto OUTP) {
                     const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
+                    const int sc = (C::PH == kFP8) ? p.mscale[l] : 127;
                     if (grp == 0) {
                         init_bias<RG, C::CT>(acc, bl, TB, lane);
                         mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
-                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {}, sc);
                     } else {
                         drain(std::integral_constant<int, C::PH>{}, p.oscale[l - 1], p.inv_in_scale[l]);
                     }
                     __syncthreads();
                     if (grp == 0) {
                         mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
-                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {}, sc);
                     } else {
                         init_bias<RG, C::CT>(acc, bl, TB, lane);
                         mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>>(
-                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {}, sc);
                     }
                     __syncthreads();
                     if (grp == 0) {
@@ -583,7 +587,7 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
                               decltype(OUTP)::value != C::PH ? XT : 0);
                     } else {
                         mma_seq<C::PH, RG, C::CT, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
-                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                            acc, wl, TB, act, C::ACT_STRIDE, 0, lane, [](auto) {}, sc);
                     }
                     __syncthreads();
                 };
@@ -657,20 +661,21 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
                     const Rsrc wl = make_rsrc(p.wA[l], p.wA_bytes[l]), bl = make_rsrc(p.bias[l], p.bias_bytes[l]);
                     const float osc_prev = p.oscale[l - 1], inv_prev = p.inv_in_scale[l];
                     const float osc = p.oscale[l], inv = (l < 3) ? p.inv_in_scale[l + 1] : 1.0f;
+                    const int sc = (C::PH == kFP8) ? p.mscale[l] : 127;
                     init_bias<RP, 4>(X, bl, TX, lane);
                     mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH / 2, MapHalf0<C::GH>, GMC_VPM_A>(
                         X, wl, TX, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
                             drain_step<C::PH, C::SCALE, RP, C::NKBH / 2, decltype(J)::value>(Y, pk, osc_prev, inv_prev);
-                        });
+                        }, sc);
                     store_pass<C::PH, RP>(pk, TY, act, C::ACT_STRIDE, lane);
                     __syncthreads();
                     mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH / 2, MapHalf1<C::GH>>(
-                        X, wl, TX, act, C::ACT_STRIDE, 0, lane, [](auto) {});
+                        X, wl, TX, act, C::ACT_STRIDE, 0, lane, [](auto) {}, sc);
                     init_bias<RP, 4>(Y, bl, TY, lane);
                     mma_seq<C::PH, RP, 4, C::NKBH, C::NKBH, MapAll, GMC_VPM_P>(
                         Y, wl, TY, act, C::ACT_STRIDE, 0, lane, [&](auto J) {
                             drain_step<PO, C::SCALE, RP, C::NKBH, decltype(J)::value>(X, pk, osc, inv);
-                        });
+                        }, sc);
                     __syncthreads();
                     store_pass<PO, RP>(pk, TX, act, C::ACT_STRIDE, lane);
                     __syncthreads();
@@ -726,13 +731,14 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
                 dense_silu<C::PH, C::PH, C::RTW, C::NKBH, C::SCALE, true>(
                     make_rsrc(p.wA[l], p.wA_bytes[l]), make_rsrc(p.bias[l], p.bias_bytes[l]), T0,
                     act, C::ACT_STRIDE, act, C::ACT_STRIDE, lane, p.oscale[l],
-                    l < 3 ? p.inv_in_scale[l + 1] : 1.0f);
+                    l < 3 ? p.inv_in_scale[l + 1] : 1.0f, (C::PH == kFP8) ? p.mscale[l] : 127);
                 __syncthreads();
             }
             if constexpr (NSAME == 2) {
                 dense_silu<C::PH, C::P5, C::RTW, C::NKBH, C::SCALE, true>(
                     make_rsrc(p.wA[3], p.wA_bytes[3]), make_rsrc(p.bias[3], p.bias_bytes[3]), T0,
-                    act, C::ACT_STRIDE, act, C::ACT_STRIDE, lane, p.oscale[3], 1.0f);
+                    act, C::ACT_STRIDE, act, C::ACT_STRIDE, lane, p.oscale[3], 1.0f,
+                    (C::PH == kFP8) ? p.mscale[3] : 127);
                 __syncthreads();
             }
             // layer 5: H -> 5 (rows padded to 32); wave w handles sample column tile w

@@ -48,7 +48,7 @@ struct Mma;
 template <>
 struct Mma<kF32> {
     using Frag = u32x4;
-    static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b)
+    static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b, int)
     {
         // reinterpret whole vectors: a bit_cast of a single vector component reads the
         // vector's first component whatever the index
@@ -66,7 +66,7 @@ struct Mma<kF32> {
 template <>
 struct Mma<kBF16> {
     using Frag = u32x4;
-    static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b)
+    static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b, int)
     {
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
                                                       __builtin_bit_cast(bf16x8, b), acc, 0, 0, 0);
@@ -78,11 +78,13 @@ struct Mma<kBF16> {
 template <>
 struct Mma<kFP8> {
     using Frag = i32x8;
-    static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b)
+    // acc += 2^(sc - 127) (a . b): format 0 = OCP e4m3 for both operands; the E8M0 scale sc
+    // of the weight operand carries the layer's power-of-two factor (the activation operand's
+    // scale is 127 = 2^0).  Scaling by a power of two is exact, so this equals scaling the
+    // plain sum.
+    static __device__ __forceinline__ void run(f32x16 &acc, const Frag &a, const Frag &b, int sc)
     {
-        // format 0 = OCP e4m3 for both operands; E8M0 scales of 127 = 2^0 (scaling is done in
-        // the epilogue with the per-layer power-of-two factors)
-        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+        acc = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, acc, 0, 0, 0, sc, 0, 127);
     }
     static __device__ __forceinline__ Frag cat(u32x4 lo, u32x4 hi)
     {
@@ -122,7 +124,7 @@ __device__ __forceinline__ void sfor(F &&f)
 // A fragments are prefetched two k-blocks ahead, B fragments one.
 template <int P, int RP, int CT, int NKB, typename Hook>
 __device__ __forceinline__ void mma_pass(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, const char *act,
-                                         int stride, int col0, int lane, Hook &&hook)
+                                         int stride, int col0, int lane, Hook &&hook, int sc = 127)
 {
     using M = Mma<P>;
     using Frag = typename M::Frag;
@@ -151,7 +153,7 @@ __device__ __forceinline__ void mma_pass(f32x16 (&acc)[RP][CT], Rsrc wA, int T0,
 #pragma unroll
         for (int r = 0; r < RP; ++r)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[kb % 3][r], b[kb % 2][c]);
+            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[kb % 3][r], b[kb % 2][c], sc);
         hook(KB);
         // keep each k-block in its own scheduling region: otherwise the scheduler merges the
         // passes' k-loops (they are independent), which defeats both the prefetch distance and
@@ -245,7 +247,7 @@ struct MapHalf1 {
 // a layer with NKB k-blocks (same fragment layout and prefetch scheme as mma_pass).
 template <int P, int RP, int CT, int NKB, int NJ, typename Map, int VPM = 0, int SWAPB = 0, typename Hook>
 __device__ __forceinline__ void mma_seq(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, const char *act,
-                                        int stride, int col0, int lane, Hook &&hook)
+                                        int stride, int col0, int lane, Hook &&hook, int sc = 127)
 {
     constexpr int MFMA_PER_RUN = (P == kF32) ? 4 : 1;
     using M = Mma<P>;
@@ -279,7 +281,7 @@ __device__ __forceinline__ void mma_seq(f32x16 (&acc)[RP][CT], Rsrc wA, int T0, 
 #pragma unroll
         for (int r = 0; r < RP; ++r)
 #pragma unroll
-            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[j % (PA + 1)][r], b[j % 2][c]);
+            for (int c = 0; c < CT; ++c) M::run(acc[r][c], a[j % (PA + 1)][r], b[j % 2][c], sc);
         hook(JJ);
         if constexpr (VPM > 0) {
             // interleave the hook's epilogue arithmetic between the MFMAs: one MFMA, then up

@@ -101,7 +101,7 @@ def test_internal_sampler_quantised_parity(orc, prec, H):
     z = inputs.noise(n, 9)
     raw, _ = _sample(binding, w, prec, cond, "euler", 16, noise=z)
     idx = sample_indices(n, 250, seed=3)
-    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8
+    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8_EXP2
     ref = orc.sample_raw(w, cond.subset(idx), 16, z[:, idx].astype(np.float64), oprec)
     exact = orc.sample_raw(w, cond.subset(idx), 16, z[:, idx].astype(np.float64), orc.PREC_FP64)
     err = np.abs(raw[:, idx].T - ref).max(axis=1)

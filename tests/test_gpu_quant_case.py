@@ -1,10 +1,9 @@
 """The kernels on the hand-built network of tests/quant_case.py: one Euler step from a given
-z must reproduce, bit for bit, the values worked out by hand for FP32 and FP8 operands (where
-the e4m3 roundings happen, to nearest even, with which scale, the bias unrounded).  The BF16
-sampler evaluates the network with its hidden activations scaled by -log2(e) (the oracle's
-PREC_BF16_EXP2), whose folded parameters are no longer dyadic: it is held to that emulation of
-the same hand-built network (the exact sums there leave only the FP32 rounding of the bias
-additions, 1e-6 relative)."""
+z must reproduce, bit for bit, the values worked out by hand for FP32 operands.  The BF16 and
+FP8 samplers evaluate the network with its hidden activations scaled by -log2(e) (the oracle's
+PREC_BF16_EXP2 and PREC_FP8_EXP2), whose folded parameters are no longer dyadic: they are held
+to that emulation of the same hand-built network (the exact sums there leave only the FP32
+rounding of the bias additions, 1e-6 relative)."""
 import numpy as np
 import pytest
 import torch
@@ -29,10 +28,11 @@ def test_hand_network_exact_on_gpu(prec, H):
     binding.gmc_transmit(m, cond, 1, seed=1, id_base=0, noise=z, raw=raw)
     torch.cuda.synchronize()
     got = raw.view(5, n).cpu().numpy().T
-    if prec == "bf16":
+    if prec in ("bf16", "fp8"):
         import oracle
+        oprec = oracle.PREC_BF16_EXP2 if prec == "bf16" else oracle.PREC_FP8_EXP2
         ref = oracle.sample_raw(quant_case.network(H), quant_case.conditions(1), 1,
-                                quant_case.noise(1).astype(np.float64), oracle.PREC_BF16_EXP2)[0]
+                                quant_case.noise(1).astype(np.float64), oprec)[0]
         np.testing.assert_allclose(got, np.repeat(ref[None, :], n, axis=0), rtol=1e-6, atol=1e-6)
         m.close()
         return

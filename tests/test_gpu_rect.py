@@ -58,7 +58,7 @@ def test_rect_sampler_matches_oracle(orc, prec, H, K):
     raw, _ = _sample(binding, w, prec, cond, K)
     idx = sample_indices(n, 200, seed=4)
     z = np.stack([orc.noise(2, int(i), 1)[:, 0] for i in idx], axis=1)
-    oprec = {"fp32": orc.PREC_FP64, "bf16": orc.PREC_BF16_EXP2, "fp8": orc.PREC_FP8}[prec]
+    oprec = {"fp32": orc.PREC_FP64, "bf16": orc.PREC_BF16_EXP2, "fp8": orc.PREC_FP8_EXP2}[prec]
     ref = orc.sample_raw(w, cond.subset(idx), K, z, oprec)
     err = np.abs(raw[:, idx].T - ref).max(axis=1)
     print(f"rect {prec} H={H} K={K}: p99 {np.quantile(err, .99):.2e} max {err.max():.2e}")

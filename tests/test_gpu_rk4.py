@@ -74,7 +74,7 @@ def test_quantised_rk4_parity_vs_emulating_oracle(orc, prec, H):
     z = inputs.noise(n, 6)
     raw, _ = _run(binding, w, prec, cond, "rk4", K, noise=z)
     idx = sample_indices(n, 250, seed=2)
-    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8
+    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8_EXP2
     sub = cond.subset(idx)
     ref = orc.sample_raw_rk4(w, sub, K, _z(orc, idx, 0, z_full=z), oprec)
     exact = orc.sample_raw_rk4(w, sub, K, _z(orc, idx, 0, z_full=z), orc.PREC_FP64)

@@ -79,7 +79,7 @@ def test_small_launch_matches_the_emulating_oracle(orc, prec, H):
     m = binding.Model(inputs.pack_blob(w), prec)
     raw = _raw(binding, m, cond, "euler", 8).astype(np.float64)
     m.close()
-    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8
+    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8_EXP2
     ref = _oracle_raw(orc, w, cond, np.arange(n), 8, oprec, seed=7)
     err = np.abs(raw.T - ref).max(axis=1)
     print(f"{prec} H={H} small launch: p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
