@@ -302,14 +302,9 @@ def film_velocity(weights, x, t, condf, precision=PREC_FP64):
                                                   + (S_j e + s_j))
         v   = W_o h_B + b_o
     PREC_BF16: every layer's input and weights rounded to bfloat16 (layer_affine's reading),
-    and the residual stream h_j stored in bfloat16 (rounded after each block's sum).
-    PREC_BF16_EXP2: the same roundings applied to the network of fold_exp2_film, whose
-    residual stream carries -log2(e) h_j."""
-    if precision == PREC_BF16_EXP2:
-        weights, precision = fold_exp2_film(weights), PREC_BF16
+    and the residual stream h_j stored in bfloat16 (rounded after each block's sum)."""
     if precision not in (PREC_FP64, PREC_BF16):
         raise ValueError("the residual network is evaluated in FP64 or with BF16 operands")
-    act = silu_exp2 if getattr(weights, "exp2_folded", False) else silu
     rd = round_bf16 if precision == PREC_BF16 else (lambda a: np.asarray(a, np.float64))
     W = [w.astype(np.float64) for w in weights.W]
     b = [v.astype(np.float64) for v in weights.b]
@@ -323,31 +318,8 @@ def film_velocity(weights, x, t, condf, precision=PREC_FP64):
         a = lin(2 + 3 * j, h)
         scale = 1.0 + lin(3 + 3 * j, e)
         shift = lin(4 + 3 * j, e)
-        h = rd(h + act(scale * a + shift))
+        h = rd(h + silu(scale * a + shift))
     return lin(2 + 3 * nb, h)
-
-
-def fold_exp2_film(weights):
-    """The residual network with its residual stream carried scaled by -log2(e): the input
-    layer (weights and bias), every main map's bias and every shift map (weights and bias)
-    multiplied by -log2(e), the output layer's weights by -ln 2, each product rounded to
-    float32.  A block's pre-activation is then -log2(e) z = scale * (A h' + a') + shift' with
-    h' = -log2(e) h (the main maps A and the scale maps unchanged), its scaled activation
-    -log2(e) SiLU(z) is silu_exp2 of it and adds to h' directly; the embedding keeps the plain
-    SiLU.  In exact arithmetic this is the network unchanged (up to the float32 rounding of
-    the products)."""
-    from types import SimpleNamespace
-    W = [np.asarray(w, np.float32) for w in weights.W]
-    b = [np.asarray(v, np.float32) for v in weights.b]
-    last = len(W) - 1
-    nb = (len(W) - 3) // 3
-    W[0], b[0] = W[0] * NEG_LOG2E_F32, b[0] * NEG_LOG2E_F32
-    for j in range(nb):
-        b[2 + 3 * j] = b[2 + 3 * j] * NEG_LOG2E_F32
-        W[4 + 3 * j], b[4 + 3 * j] = W[4 + 3 * j] * NEG_LOG2E_F32, b[4 + 3 * j] * NEG_LOG2E_F32
-    W[last] = W[last] * NEG_LN2_F32
-    return SimpleNamespace(hidden=weights.hidden, emb=weights.emb, W=W, b=b, seed=weights.seed,
-                           n_in=weights.n_in, flags=weights.flags, exp2_folded=True)
 
 
 def fold_exp2(weights):

@@ -48,14 +48,7 @@ def residual_tie() -> inputs.FilmWeights:
       blocks 1 and 2 add SiLU(0) = 0; v0 = h3[0].
     With a bfloat16 residual stream 65.25 lies halfway between 65 and 65.5 and rounds to the
     even 65.  So x_1[0] = 1.25 + 65.25 = 66.5 exactly, or 66.25 in BF16; every other component
-    is z unchanged (zero velocity).
-    In the exp2-folded BF16 order (residual stream carried as -log2(e) h) no value is a tie:
-    the input weight becomes -log2(e) in BF16, -1.4453125, so h0'[0] = -1.806640625, stored as
-    -1.8046875; the main bias becomes a' = float32(31 * -log2(e)) = -44.72354...; the shift
-    weight 1/32 becomes BF16(-log2(e)) / 32, so the shift is -2.890625; the branch adds
-    2 a' - 2.890625 = -92.3377... (its scaled SiLU, 2^-92 being negligible), and the stream
-    stores -94.1424... as -94; the output weight is -ln 2 in BF16, -0.69140625, so
-    v0 = 64.9921875 and x_1[0] = 66.2421875."""
+    is z unchanged (zero velocity)."""
     w = zeros()
     w.W[0][0, 0] = 1.0
     w.b[1][0] = 64.0
@@ -67,4 +60,4 @@ def residual_tie() -> inputs.FilmWeights:
 
 
 RESIDUAL_TIE_Z0 = 1.25
-RESIDUAL_TIE_X1 = {"fp32": 66.5, "bf16": 66.25, "bf16_exp2": 66.2421875}
+RESIDUAL_TIE_X1 = {"fp32": 66.5, "bf16": 66.25}
