@@ -429,9 +429,10 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
         }
         __syncthreads();
 
-        // Two-group Euler: the layer-5 lanes apply the step and write the next input row
-        // themselves, so the input row is assembled here only for the first evaluation.
-        constexpr bool fold = C::GROUPS && !rk4;
+        // Two-group schedule: the layer-5 lanes apply the integrator's update (Euler step, RK4
+        // stage) and write the next input row themselves, so the input row is assembled here
+        // only for the first evaluation.
+        constexpr bool fold = C::GROUPS;
         for (int e = 0; e < nevals; ++e) {
             const int stage = rk4 ? (e & 3) : 0;
             const int k = rk4 ? (e >> 2) : e;
@@ -612,7 +613,7 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
                     mma_seq<C::P5, 1, 1, C::NKB5, C::NKB5 / 2, MapHalf1<C::G5>, 0, SW5>(
                         out, w4, 0, act, C::ACT_STRIDE, wg, lane, [](auto) {});
                     const int sn = wg * 32 + (lane & 31);
-                    if constexpr (fold) {
+                    if constexpr (fold && !rk4) {
                         // x += dt v, then the next input row's x (and t) in BF16
                         char *row = in0 + sn * C::IN_STRIDE;
                         if (lane < 32) {
@@ -627,6 +628,30 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
                             const float x4 = xs[4 * TM + sn] + out[0][0][0] * dt;
                             xs[4 * TM + sn] = x4;
                             *(uint32_t *)(row + 8) = pack_bf16(x4, (float)(e + 1) * dt);
+                        }
+                    } else if constexpr (fold) {
+                        // RK4 (the arithmetic of advance): stages 0..2 add v to the stage sum
+                        // and give the next stage's input, stage 3 finishes the step; then the
+                        // next input row's x (and t) in BF16
+                        auto update = [&](int d, float v) {
+                            const int o = d * TM + sn;
+                            if (stage < 3) {
+                                ksum[o] = stage == 0 ? v : ksum[o] + 2.0f * v;
+                                return xs[o] + (stage == 2 ? dt : 0.5f * dt) * v;
+                            }
+                            return xs[o] = xs[o] + (dt * (1.0f / 6.0f)) * (ksum[o] + v);
+                        };
+                        const int e1 = e + 1, st1 = e1 & 3;
+                        const float t1 = ((float)(e1 >> 2) + (st1 == 0 ? 0.0f : (st1 == 3 ? 1.0f : 0.5f))) * dt;
+                        char *row = in0 + sn * C::IN_STRIDE;
+                        if (lane < 32) {
+                            float x[4];
+#pragma unroll
+                            for (int d = 0; d < 4; ++d) x[d] = update(d, out[0][0][d]);
+                            *(u32x2 *)row = u32x2{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3])};
+                        } else {
+                            const float x4 = update(4, out[0][0][0]);
+                            *(uint32_t *)(row + 8) = pack_bf16(x4, t1);
                         }
                     } else if (lane < 32) {
 #pragma unroll
@@ -761,7 +786,7 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
         if (tid < TM) {
             const int64_t i = base + tid;
             float xk[5];
-            if constexpr (rk4) {
+            if constexpr (rk4 && !fold) {
                 advance(nevals - 1, xk);
             } else {
 #pragma unroll
