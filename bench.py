@@ -32,6 +32,7 @@ import math
 import os
 import re
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -626,7 +627,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the sampler shards by particle "
-              f"id with no communication between GPUs, and this build runs on a single GPU",
+              f"id with no communication between GPUs, and the library runs on a single GPU",
               file=sys.stderr)
         sys.exit(2)
     if args.profile:
@@ -648,7 +649,7 @@ def main():
     w512 = fitted("gmc_h512.bin")
     if w512 is None:
         raise SystemExit("weights/gmc_h512.bin is missing")
-    detail_path = args.detail or os.path.join(ROOT, "gpurun_out", "bench_detail.json")
+    detail_path = args.detail or os.path.join(tempfile.gettempdir(), "gmc_bench_detail.json")
     if args.study:
         fn = {"convergence": lambda: study_convergence(binding, inputs, w512),
               "transport": lambda: study_transport(binding, inputs, w512),

@@ -41,7 +41,7 @@ typedef enum {
     GMC_EINVAL = -1,         /* bad argument (null pointer, size, unsupported K, bad blob) */
     GMC_ENOMEM = -2,         /* device allocation failed or a capacity would be exceeded */
     GMC_EDEVICE = -3,        /* a HIP call or kernel launch failed */
-    GMC_EUNSUPPORTED = -4    /* valid request this build does not implement (e.g. width) */
+    GMC_EUNSUPPORTED = -4    /* valid request the library does not implement (e.g. width) */
 } gmc_status;
 
 typedef enum {
