@@ -8,10 +8,11 @@ namespace gmc {
 
 enum Prec { kF32 = 0, kBF16 = 1, kFP8 = 2 };
 
-// Samples per workgroup tile of the fused MLP/ODE kernel (and the small tile of launches with
-// at most kSmallTileM samples per compute unit) and waves per workgroup.
+// Samples per workgroup tile of the fused MLP/ODE kernel (and the small tiles of launches with
+// at most kSmallTileM or kMidTileM samples per compute unit) and waves per workgroup.
 constexpr int kTileM = 128;
 constexpr int kSmallTileM = 32;
+constexpr int kMidTileM = 64;
 constexpr int kWaves = 4;
 
 // Operand geometry of one "k-block" for each operand precision: features consumed per
@@ -91,12 +92,12 @@ struct MlpParams {
     int xy;                   // XY geometry: exit directions decoded into the unit disk
     uint64_t seed, id_base;
     // Device-side tile choice, for launches whose count n_dev is known only on the device and
-    // whose bound n exceeds what 32-sample tiles serve: the launcher runs the 32-sample kernel
-    // first; its first lane writes to n_dev_large the count left to the 128-sample kernel (0
-    // when the count is at most small_max, else the whole count) and it exits when that count
-    // is not 0; the 128-sample kernel then takes n_dev_large as its n_dev.  n_dev_large is
-    // device memory of the caller (NULL: no device-side choice); small_max is set by the
-    // launcher.
+    // whose bound n exceeds what 32-sample tiles serve: the launcher runs the smaller-tile
+    // kernels first, 32 then 64 samples; each reads its count, and its first lane writes to
+    // its n_dev_large the count left to the next kernel (0 when the count is at most its
+    // small_max, else the whole count); it exits when that count is not 0, and the next kernel
+    // takes that word as its n_dev.  The caller passes two words of device memory (NULL: no
+    // device-side choice), one per handoff; the launcher sets each kernel's word and small_max.
     unsigned long long *n_dev_large;
     int64_t small_max;
     // FP8 hidden layers: E8M0 byte (127 + e) of the matrix core's operand scale 2^e = 2 sw sa

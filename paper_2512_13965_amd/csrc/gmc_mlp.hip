@@ -326,8 +326,8 @@ template <int MP, int H, int RK, int TM>
 __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(MlpParams p)
 {
     using C = Cfg<MP, H, TM>;
-    static_assert(TM == kTileM || (C::GROUPS && TM == kSmallTileM),
-                  "small tiles run the two-group schedule only");
+    static_assert(TM == kTileM || (C::GROUPS && (TM == kSmallTileM || TM == kMidTileM)),
+                  "smaller tiles are built for the two-group schedule");
     static_assert(C::LDS_BYTES <= 160 * 1024, "LDS budget");
     static_assert(C::RTW >= 1 && C::NT % C::W == 0, "row tiles must split evenly over the waves");
     static_assert(C::GROUPS || C::PIPE || C::W == TM / 32,
@@ -347,7 +347,7 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
     // samples to process: the launch's own count, or one the device holds (a captured graph
     // sized for a bucket of counts); noise and raw keep the row stride p.n
     const int64_t n_items = p.n_dev ? (int64_t)*p.n_dev : p.n;
-    if constexpr (TM == kSmallTileM) {
+    if constexpr (TM != kTileM) {
         if (p.n_dev_large) {
             const bool large = n_items > p.small_max;
             if (blockIdx.x == 0 && threadIdx.x == 0) *p.n_dev_large = large ? (unsigned long long)n_items : 0ull;
@@ -840,36 +840,45 @@ inline MlpParams sample_range(const MlpParams &p, int64_t off, int64_t cnt)
     return q;
 }
 
-// Launches with at most kSmallTileM samples per compute unit (the tail steps of a transport
-// run, small requests) take 32-sample tiles when the model runs the two-group schedule: a
-// tile's latency is then set by streaming the weights from L2 rather than by four column
-// tiles of matrix work.
-// When only the device knows the count (n_dev) and its bound p.n is larger than that, the
-// choice is made on the device (MlpParams::n_dev_large) without a read-back; a sample's result
-// is the same with either tile size.  A count known on the host whose last round of 128-sample
-// tiles would hold at most 32 samples per CU runs that remainder as one round of 32-sample
-// tiles, which takes about half as long as a round of 128-sample tiles.
+// Launches with at most kSmallTileM (kMidTileM) samples per compute unit (the tail steps of a
+// transport run, small requests) take 32-sample (64-sample) tiles when the model runs the
+// two-group schedule: one round of them covers the launch on every CU, and a tile's latency
+// falls with its matrix work (RK4 x 12 at width 512: 0.75 ms for 32 samples, 1.6 ms for 128).
+// When only the device knows the count (n_dev) and its bound p.n is larger, the choice is made
+// on the device (MlpParams::n_dev_large) without a read-back; a sample's result is the same
+// with every tile size.  A count known on the host whose last round of 128-sample tiles would
+// hold at most 64 samples per CU runs that remainder as one round of smaller tiles.
 template <int MP, int H>
 hipError_t launch_one(const MlpParams &p, int cu, hipStream_t s)
 {
     MlpParams q = p;
     q.n_dev_large = nullptr;
     if constexpr (Cfg<MP, H>::GROUPS) {
-        const int64_t small = (int64_t)kSmallTileM * cu;
+        const int64_t small = (int64_t)kSmallTileM * cu, mid = (int64_t)kMidTileM * cu;
         if (p.n <= small) return launch_tiles<MP, H, kSmallTileM>(q, p.n, cu, s);
-        const int64_t round = (int64_t)kTileM * cu, rem = p.n % round;
-        if (!p.n_dev && !p.noise && !p.raw && rem > 0 && rem <= small) {
-            const MlpParams head = sample_range(q, 0, p.n - rem);
-            const hipError_t e = launch_tiles<MP, H, kTileM>(head, head.n, cu, s);
-            if (e != hipSuccess) return e;
-            return launch_tiles<MP, H, kSmallTileM>(sample_range(q, p.n - rem, rem), rem, cu, s);
-        }
-        if (p.n_dev && p.n_dev_large) {
+        if (!p.n_dev) {
+            if (p.n <= mid) return launch_tiles<MP, H, kMidTileM>(q, p.n, cu, s);
+            const int64_t round = (int64_t)kTileM * cu, rem = p.n % round;
+            if (!p.noise && !p.raw && rem > 0 && rem <= mid) {
+                const MlpParams head = sample_range(q, 0, p.n - rem);
+                const hipError_t e = launch_tiles<MP, H, kTileM>(head, head.n, cu, s);
+                if (e != hipSuccess) return e;
+                const MlpParams tail = sample_range(q, p.n - rem, rem);
+                return rem <= small ? launch_tiles<MP, H, kSmallTileM>(tail, rem, cu, s)
+                                    : launch_tiles<MP, H, kMidTileM>(tail, rem, cu, s);
+            }
+        } else if (p.n_dev_large) {
+            // 32-sample kernel, then the 64-sample one, each handing on what it does not take
             q.n_dev_large = p.n_dev_large;
             q.small_max = small;
-            const hipError_t e = launch_tiles<MP, H, kSmallTileM>(q, small, cu, s);
+            hipError_t e = launch_tiles<MP, H, kSmallTileM>(q, small, cu, s);
             if (e != hipSuccess) return e;
             q.n_dev = p.n_dev_large;
+            q.n_dev_large = p.n <= mid ? nullptr : p.n_dev_large + 1;
+            q.small_max = mid;
+            e = launch_tiles<MP, H, kMidTileM>(q, std::min<int64_t>(p.n, mid), cu, s);
+            if (e != hipSuccess || p.n <= mid) return e;
+            q.n_dev = p.n_dev_large + 1;
             q.n_dev_large = nullptr;
         }
     }

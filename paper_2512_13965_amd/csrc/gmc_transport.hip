@@ -645,7 +645,7 @@ struct gmc_world {
     int32_t *s_idx = nullptr, *s_face = nullptr;
     float *s_pos = nullptr, *s_dcos = nullptr, *s_dsin = nullptr, *s_path = nullptr;
     unsigned long long *s_count = nullptr;
-    unsigned long long *n_large = nullptr;       // sampler's device-side tile choice (count handoff)
+    unsigned long long *n_large = nullptr;       // sampler's device-side tile choice (two count handoffs)
     unsigned long long *streamed = nullptr;      // crossings finished inside split gathers
     int ff_max = 64;                             // cells a particle may stream through per step
     int64_t stepped = 0;                         // particles stepped (one crossing each)
@@ -730,7 +730,7 @@ void plan(gmc_world *w, Layout &L)
     L.add((void **)&w->s_dsin, 4 * C);
     L.add((void **)&w->s_path, 4 * C);
     L.add((void **)&w->s_count, 8);
-    L.add((void **)&w->n_large, 8);
+    L.add((void **)&w->n_large, 16);
     L.add((void **)&w->streamed, 8);
     L.add((void **)&w->c_cos, 4 * C);
     L.add((void **)&w->ids, 8 * C);

@@ -1,8 +1,9 @@
-"""Sampler launches with at most 32 samples per compute unit run 32-sample tiles (the tail steps
-of a transport run, small requests).  Every accumulator sums its k-blocks in the same order as
-with 128-sample tiles, so a sample's result does not depend on the tile size: the samples of a
-small launch must equal, bit for bit, the same samples inside a large launch (same conditions,
-same random-number ids), and match the rounding-emulating oracle like any launch."""
+"""Sampler launches with at most 32 (64) samples per compute unit run 32-sample (64-sample)
+tiles (the tail steps of a transport run, small requests).  Every accumulator sums its
+k-blocks in the same order as with 128-sample tiles, so a sample's result does not depend on
+the tile size: the samples of a small launch must equal, bit for bit, the same samples inside
+a large launch (same conditions, same random-number ids), and match the rounding-emulating
+oracle like any launch."""
 import numpy as np
 import pytest
 import torch
@@ -36,7 +37,7 @@ def test_small_launch_equals_the_same_samples_in_a_large_launch(prec, H, integ, 
     cond = inputs.transmission_conditions(big, 21)
     m = binding.Model(inputs.pack_blob(inputs.random_weights(H, 22)), prec)
     ref = _raw(binding, m, cond, integ, K)
-    for n in (1, 31, 32, 33, 1000, small):
+    for n in (1, 31, 32, 33, 1000, small, small + 1, 3 * small // 2, 2 * small, 2 * small + 1):
         got = _raw(binding, m, cond.subset(slice(0, n)), integ, K)
         np.testing.assert_array_equal(got, ref[:, :n], err_msg=f"n = {n}")
     m.close()
@@ -53,15 +54,17 @@ def _exits(binding, m, cond_h, integ, K, raw):
 
 @pytest.mark.parametrize("prec,H,integ,K", [("bf16", 512, "euler", 4), ("fp8", 256, "rk4", 1)])
 def test_last_round_on_small_tiles_equals_one_launch(prec, H, integ, K):
-    # a count known on the host whose last round of 128-sample tiles would hold at most 32
-    # samples per compute unit runs that remainder as a second launch of 32-sample tiles over
-    # the shifted arrays (ids id_base + i continue across it); a launch that also writes the raw
-    # [5][n] state runs as one launch.  Both must give the same exits bit for bit.
+    # a count known on the host whose last round of 128-sample tiles would hold at most 32 (64)
+    # samples per compute unit runs that remainder as a second launch of 32-sample (64-sample)
+    # tiles over the shifted arrays (ids id_base + i continue across it); a launch that also
+    # writes the raw [5][n] state runs as one launch.  Both must give the same exits bit for
+    # bit.
     binding = require_gpu()
     small = _small_limit()
     rnd = 4 * small
     m = binding.Model(inputs.pack_blob(inputs.random_weights(H, 25)), prec)
-    for n in (rnd + 1, rnd + 777, 2 * rnd + small, 2 * rnd + small + 1):
+    for n in (rnd + 1, rnd + 777, 2 * rnd + small, 2 * rnd + small + 1, 2 * rnd + 2 * small,
+              2 * rnd + 2 * small + 1):
         cond = inputs.transmission_conditions(n, 26)
         two = _exits(binding, m, cond, integ, K, raw=False)
         one = _exits(binding, m, cond, integ, K, raw=True)
