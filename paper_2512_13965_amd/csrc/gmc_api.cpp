@@ -225,6 +225,14 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
     for (int l = 0; l < 5; ++l)
         if (!is_pow2(hd.act_scale[l]) || !is_pow2(hd.w_scale[l]))
             return fail(GMC_EINVAL, "gmc_model_create: scales must be positive powers of two");
+    // FP8 layers apply 2 w_scale act_scale as the matrix core's E8M0 operand scale
+    if (precision == GMC_FP8_E4M3 && !film)
+        for (int l = 0; l < 5; ++l) {
+            if (layer_prec(precision, l) != kFP8) continue;
+            const double e = std::log2(2.0 * (double)hd.w_scale[l] * (double)hd.act_scale[l]);
+            if (e < -127.0 || e > 127.0)
+                return fail(GMC_EINVAL, "gmc_model_create: FP8 layer scales out of the E8M0 range");
+        }
 
     const float *src = (const float *)((const char *)host_blob + sizeof(BlobHeader));
     std::vector<const float *> W(NL), B(NL);
@@ -291,14 +299,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
             m->tmpl.oscale[l] = 1.0f;
             m->tmpl.inv_in_scale[l] = f8 ? 0.5f / sa : 1.0f;
             m->tmpl.mscale[l] = 127;
-            if (f8) {
-                const int e = (int)std::lround(std::log2(2.0 * (double)sw * (double)sa));
-                if (e < -127 || e > 127) {
-                    delete m;
-                    return fail(GMC_EINVAL, "gmc_model_create: FP8 layer scales out of the E8M0 range");
-                }
-                m->tmpl.mscale[l] = 127 + e;
-            }
+            if (f8) m->tmpl.mscale[l] = 127 + (int)std::lround(std::log2(2.0 * (double)sw * (double)sa));
         }
         frag[l].assign((size_t)nt * nkb * 64 * FB, 0);
         for (int T = 0; T < nt; ++T)

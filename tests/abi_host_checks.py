@@ -51,6 +51,11 @@ def run(L):
     w = inputs.random_weights(256, 1)
     w.act_scale[2] = 0.3
     assert _create(L, inputs.pack_blob(w), FP8) == EINVAL
+    # an FP8 layer's 2 w_scale act_scale must be an E8M0 value (2^-127 .. 2^127)
+    w = inputs.random_weights(256, 1)
+    w.act_scale[1], w.w_scale[1] = 2.0 ** -70, 2.0 ** -60
+    assert _create(L, inputs.pack_blob(w), FP8) == EINVAL
+    assert b"E8M0" in L.gmc_last_error()
     w = inputs.random_weights(256, 1)
     w.W[1][3, 4] = np.nan
     assert _create(L, inputs.pack_blob(w), FP32) == EINVAL
