@@ -69,20 +69,24 @@ __device__ __forceinline__ int lane_rank(uint64_t mask)
 }
 
 // Per-workgroup tally staging: the flux, deposit and path tallies of a workgroup's particles are
-// summed per cell in an LDS hash table and flushed with one FP64 global atomic per tally and
-// distinct cell.
+// summed per cell in an LDS hash table of SLOTS slots and flushed with one FP64 global atomic
+// per tally and distinct cell.
 // Particles near a source crowd into few cells, whose same-address global atomics would
-// otherwise serialise in L2.  A block holds at most 256 particles, so at most 256 of the 512
-// slots fill and linear probing always ends.
-constexpr int kTallySlots = 512;
-struct TallyLds {
-    int32_t key[kTallySlots];
-    double flux[kTallySlots], dep[kTallySlots], wpath[kTallySlots], path[kTallySlots], visits[kTallySlots];
+// otherwise serialise in L2.  A block of the one-visit-per-particle kernels holds at most 256
+// particles, so at most 256 of their 512 slots fill and linear probing always ends.
+template <int SLOTS>
+struct TallyTable {
+    static constexpr int kSlots = SLOTS;
+    static constexpr int kShift = 32 - __builtin_ctz(SLOTS);   // multiplicative hash to log2(SLOTS) bits
+    int32_t key[SLOTS];
+    double flux[SLOTS], dep[SLOTS], wpath[SLOTS], path[SLOTS], visits[SLOTS];
 };
+using TallyLds = TallyTable<512>;
 
-__device__ __forceinline__ void tally_init(TallyLds &tl)
+template <int SLOTS>
+__device__ __forceinline__ void tally_init(TallyTable<SLOTS> &tl)
 {
-    for (int s = threadIdx.x; s < kTallySlots; s += blockDim.x) {
+    for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
         tl.key[s] = -1;
         tl.flux[s] = 0.0;
         tl.dep[s] = 0.0;
@@ -94,11 +98,11 @@ __device__ __forceinline__ void tally_init(TallyLds &tl)
 
 __device__ __forceinline__ void tally_add(TallyLds &tl, int cell, double phi, double dw, double wl, double l)
 {
-    uint32_t s = ((uint32_t)cell * 2654435761u) >> 23;     // 9-bit multiplicative hash
+    uint32_t s = ((uint32_t)cell * 2654435761u) >> TallyLds::kShift;
     for (;;) {
         const int prev = atomicCAS(&tl.key[s], -1, cell);
         if (prev == -1 || prev == cell) break;
-        s = (s + 1) & (kTallySlots - 1);
+        s = (s + 1) & (TallyLds::kSlots - 1);
     }
     atomicAdd(&tl.flux[s], phi);
     atomicAdd(&tl.dep[s], dw);
@@ -107,9 +111,10 @@ __device__ __forceinline__ void tally_add(TallyLds &tl, int cell, double phi, do
     atomicAdd(&tl.visits[s], 1.0);
 }
 
-__device__ __forceinline__ void tally_flush(TallyLds &tl, const CellsDev &cd)
+template <int SLOTS>
+__device__ __forceinline__ void tally_flush(TallyTable<SLOTS> &tl, const CellsDev &cd)
 {
-    for (int s = threadIdx.x; s < kTallySlots; s += blockDim.x) {
+    for (int s = threadIdx.x; s < SLOTS; s += blockDim.x) {
         const int cell = tl.key[s];
         if (cell >= 0) {
             atomicAdd(&cd.flux[cell], tl.flux[s]);
@@ -137,21 +142,46 @@ __device__ __forceinline__ double visit_tally(const CellsDev &cd, const ProblemD
     return w - dw;
 }
 
-// visit_tally with the flux and deposit added straight to the global tallies (for a kernel
-// whose particles may visit more distinct cells than the LDS table holds).
-__device__ __forceinline__ double visit_tally_global(const CellsDev &cd, const ProblemDev &P, int cell,
-                                                     double w, float path_units, double unit)
+// tally_add for a kernel whose particles may visit more distinct cells than the table holds
+// (the split gather streams a particle through up to 64 cells): a cell that finds neither its
+// slot nor a free one within kTallyProbes probes adds to the global tallies directly, and a
+// deposit of exactly 0 (a cell without absorption) is not added.  The split gather's table has
+// 1,024 slots (45 KB of LDS: its registers already hold it to three workgroups per CU).
+constexpr int kTallyProbes = 4;
+using TallySplit = TallyTable<1024>;
+__device__ __forceinline__ void tally_add_bounded(TallySplit &tl, const CellsDev &cd, int cell, double phi,
+                                                  double dw, double wl, double l)
+{
+    uint32_t s = ((uint32_t)cell * 2654435761u) >> TallySplit::kShift;
+    for (int k = 0; k < kTallyProbes; ++k) {
+        const int prev = atomicCAS(&tl.key[s], -1, cell);
+        if (prev == -1 || prev == cell) {
+            atomicAdd(&tl.flux[s], phi);
+            if (dw != 0.0) atomicAdd(&tl.dep[s], dw);
+            atomicAdd(&tl.wpath[s], wl);
+            atomicAdd(&tl.path[s], l);
+            atomicAdd(&tl.visits[s], 1.0);
+            return;
+        }
+        s = (s + 1) & (TallySplit::kSlots - 1);
+    }
+    atomicAdd(&cd.flux[cell], phi);
+    if (dw != 0.0) atomicAdd(&cd.absorbed[cell], dw);
+    atomicAdd(&cd.wpath[cell], wl);
+    atomicAdd(&cd.path[cell], l);
+    atomicAdd(&cd.visits[cell], 1.0);
+}
+
+// visit_tally staged with tally_add_bounded.
+__device__ __forceinline__ double visit_tally_bounded(const CellsDev &cd, const ProblemDev &P, int cell,
+                                                      double w, float path_units, double unit, TallySplit &tl)
 {
     const double sig_a = (1.0 - cd.c[cell]) * cd.tau[cell] / P.L;
     const double ls = (double)path_units * unit;
     const double dw = w * (-expm1(-sig_a * ls));
     const double V = P.L * P.Ly;
     const double phi = sig_a > 0.0 ? dw / (V * sig_a) : w * ls / V;
-    atomicAdd(&cd.flux[cell], phi);
-    atomicAdd(&cd.absorbed[cell], dw);
-    atomicAdd(&cd.wpath[cell], w * ls);
-    atomicAdd(&cd.path[cell], ls);
-    atomicAdd(&cd.visits[cell], 1.0);
+    tally_add_bounded(tl, cd, cell, phi, dw, w * ls, ls);
     return w - dw;
 }
 
@@ -427,9 +457,9 @@ constexpr int32_t kFaceEnded = -1000;
 // Stage 1 with the first-flight split (models fitted on collided exits, blob flag bit 1).  Each
 // particle draws its crossing's split (uncollided_exit, keyed by history and cell visit); while
 // the crossings stay uncollided it is streamed through up to ff_max cells inside this kernel:
-// stages 3-4 of each such crossing (FP64 attenuation and tallies, here with global atomics, and
-// the move to the neighbour) exactly as the apply stage would do them with the same random
-// numbers, its bank slot then updated in place.  The crossing that ends the loop is
+// stages 3-4 of each such crossing (FP64 attenuation and tallies, staged in the workgroup's LDS
+// table with bounded probing, and the move to the neighbour) exactly as the apply stage would
+// do them with the same random numbers, its bank slot then updated in place.  The crossing that ends the loop is
 //   * collided: canonical conditions compacted (one atomic per wave) into the sampler's staging
 //     with the bank index in sidx;
 //   * the ff_max-th uncollided one: its exit record written at the particle's own index, for
@@ -446,6 +476,9 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
                                                            float *e_path, int ff_max,
                                                            unsigned long long *streamed)
 {
+    __shared__ TallySplit tl;
+    tally_init(tl);
+    __syncthreads();
     const int64_t n = n_dev ? (int64_t)*n_dev : n_arg;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -488,7 +521,7 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
                 e_path[i] = ex.path;
                 break;
             }
-            const double w_out = visit_tally_global(cd, P, cell, w, ex.path, (e & 1) ? P.Ly : P.L);
+            const double w_out = visit_tally_bounded(cd, P, cell, w, ex.path, (e & 1) ? P.Ly : P.L, tl);
             float ngx, ngy;
             rot_quarter(k, ex.u, ex.v, ngx, ngy);
             Next nx = move_on(cd, P, cell, (ex.face + k) & 3, ex.pos, ngx, ngy, w_out);
@@ -520,6 +553,8 @@ __global__ __launch_bounds__(256) void gather_split_kernel(BankDev b, int64_t n_
             b.event[i] = ev;
         }
     }
+    __syncthreads();
+    tally_flush(tl, cd);
     // crossings beyond the one per particle that the step counts (a history that ended here
     // finished its step's own crossing inside the loop)
     uint32_t tot = ended ? nstream - 1 : nstream;
