@@ -118,7 +118,7 @@ __device__ __forceinline__ void tally_flush(TallyTable<SLOTS> &tl, const CellsDe
         const int cell = tl.key[s];
         if (cell >= 0) {
             atomicAdd(&cd.flux[cell], tl.flux[s]);
-            atomicAdd(&cd.absorbed[cell], tl.dep[s]);
+            if (tl.dep[s] != 0.0) atomicAdd(&cd.absorbed[cell], tl.dep[s]);   // 0 without absorption
             atomicAdd(&cd.wpath[cell], tl.wpath[s]);
             atomicAdd(&cd.path[cell], tl.path[s]);
             atomicAdd(&cd.visits[cell], tl.visits[s]);
