@@ -263,12 +263,14 @@ def bench_samplers(binding, inputs, dev, stream, w512, reps=3):
     return rows
 
 
-def bench_serving(binding, inputs, w512, n_req, hist_log10=(4.0, 7.0), load=0.7):
+def bench_serving(binding, inputs, w512, n_req, hist_log10=(4.0, 7.0), load=0.7, rate_hz=None,
+                  label="GMC BF16 H=512 K=16 fitted weights"):
     """Continuous batching of a Poisson stream of transport requests of the 2-D transport kind
     (grids 16^2 .. 128^2, per-cell tau log-uniform in [0.1, 200], c ~ U[0, 1], central
     (side/8)^2 source, histories log-uniform in [10^a, 10^b]); generative sampler BF16,
     H = 512, K = 16, fitted weights; step graphs per particle-count bucket.  The arrival rate
-    is `load` times the capacity measured on a burst of 24 requests all arriving at once."""
+    is `load` times the capacity measured on a burst of 24 requests all arriving at once, or
+    `rate_hz` when given (the same arrivals for another model)."""
     from paper_2512_13965_amd import serving
     model = binding.Model(inputs.pack_blob(w512), "bf16")
     world = binding.World(1 << 20, 16, 1 << 18)
@@ -282,7 +284,7 @@ def bench_serving(binding, inputs, w512, n_req, hist_log10=(4.0, 7.0), load=0.7)
     cap = serve(burst)
     capacity_hz = len(cap.requests) / cap.wall
     log(f"serving capacity {capacity_hz:.2f} req/s ({cap.wall:.1f} s burst)")
-    rate = load * capacity_hz
+    rate = load * capacity_hz if rate_hz is None else rate_hz
     st = serve(serving.poisson_requests(n_req, rate_hz=rate, seed=11, make_problem=make))
     model.close()
     world.close()
@@ -296,7 +298,7 @@ def bench_serving(binding, inputs, w512, n_req, hist_log10=(4.0, 7.0), load=0.7)
             "histories": {"total": int(hist.sum()), "min": int(hist.min()), "max": int(hist.max())},
             "workload": f"Poisson stream at {load:.0%} of the measured capacity; grids 16^2-128^2, "
                         f"tau log-U[0.1,200], c U[0,1], 10^{hist_log10[0]:g}-10^{hist_log10[1]:g} "
-                        f"histories/request; GMC BF16 H=512 K=16 fitted weights; step graphs"}
+                        f"histories/request; {label}; step graphs"}
 
 
 # ------------------------------------------------------------------------------------------
@@ -311,6 +313,19 @@ def sampler_health(r: dict, n: int) -> dict:
     return {"rejected_fraction": float(np.sum(r["rejected_n"]) / tx),
             "rejected_weight_per_history": float(np.sum(r["rejected_w"]) / n),
             "cutoff_per_history": float(np.sum(r["cutoff"]) / n)}
+
+
+def study_serving(binding, inputs, w512, n_req=200):
+    """The bench's serving stream served twice with the same arrivals: with the plain boundary
+    model, and with the model fitted on collided crossings, whose steps run the first-flight
+    split (uncollided crossings streamed inside the step); BF16, H = 512, K = 16."""
+    out = {"plain": bench_serving(binding, inputs, w512, n_req)}
+    wc = fitted("gmc_h512_collided.bin")
+    if wc is not None:
+        out["collided_split"] = bench_serving(binding, inputs, wc, n_req,
+                                              rate_hz=out["plain"]["arrival_rate_hz"],
+                                              label="GMC BF16 H=512 K=16 collided model, first-flight split")
+    return out
 
 
 def study_convergence(binding, inputs, w512, Ns=None, runs=5):
@@ -617,7 +632,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the serving stream")
     ap.add_argument("--serve-requests", type=int, default=200, help="requests in the serving stream")
     ap.add_argument("--detail", default=None, help="file for the full results (JSON)")
-    ap.add_argument("--study", default=None, choices=["convergence", "transport", "paper_scale", "thick", "film"],
+    ap.add_argument("--study", default=None, choices=["convergence", "transport", "paper_scale", "thick", "film",
+                                                      "serving"],
                     help="run one longer study instead of the benchmark")
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: bf16 | fp8 | rk4 | film | film_rk4 (H = 512, 2^20, "
@@ -654,6 +670,7 @@ def main():
         fn = {"convergence": lambda: study_convergence(binding, inputs, w512),
               "transport": lambda: study_transport(binding, inputs, w512),
               "paper_scale": lambda: study_paper_scale(binding, inputs, w512),
+              "serving": lambda: study_serving(binding, inputs, w512),
               "thick": lambda: study_thick(binding, inputs),
               "film": lambda: study_film(binding, inputs, w512)}[args.study]
         res = {"study": args.study, "result": fn()}
