@@ -160,12 +160,16 @@ __global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(
         }
         __syncthreads();
 
+        // Two-group kernels: the output layer's lanes apply the integrator's update and write
+        // the next input row's x and time features themselves, so the row is assembled here only
+        // for the first evaluation.
+        constexpr bool fold = C::GROUPS;
         for (int e = 0; e < nevals; ++e) {
             const int stage = rk4 ? (e & 3) : 0;
             const int k = rk4 ? (e >> 2) : e;
             const float t = ((float)k + (stage == 0 ? 0.0f : (stage == 3 ? 1.0f : 0.5f))) * dt;
             // input row of sample tid: [x0..x4, sin pi t, cos pi t, ..., cos 8 pi t, condition, 0...]
-            if (tid < kTileM) {
+            if ((!fold || e == 0) && tid < kTileM) {
                 float v[kFilmIn];
                 if (!rk4 || e == 0) {
 #pragma unroll
@@ -196,7 +200,7 @@ __global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(
                                   pack_bf16(v[8 * q + 4], v[8 * q + 5]), pack_bf16(v[8 * q + 6], v[8 * q + 7])};
                 }
             }
-            __syncthreads();
+            if (!fold || e == 0) __syncthreads();
 
             if constexpr (C::GROUPS) {
                 // Two-group schedule.  Per block, three barrier-separated phases (as in the plain
@@ -321,11 +325,43 @@ __global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(
                 if (grp == 0) {
                     mma_seq<MP, 1, 1, C::NKBH, GH, MapHalf1<GH>>(out, wO, 0, act, C::ACT_STRIDE, wg, lane, nohook);
                     const int sn = wg * 32 + (lane & 31);
+                    // the integrator's update of component d of sample sn by the velocity v
+                    // (the arithmetic of emit / advance); returns the next evaluation's input
+                    auto update = [&](int d, float v) {
+                        const int o = d * kTileM + sn;
+                        if constexpr (rk4) {
+                            if (stage < 3) {
+                                ksum[o] = stage == 0 ? v : ksum[o] + 2.0f * v;
+                                return xs[o] + (stage == 2 ? dt : 0.5f * dt) * v;
+                            }
+                            return xs[o] = xs[o] + (dt * (1.0f / 6.0f)) * (ksum[o] + v);
+                        } else {
+                            return xs[o] = xs[o] + v * dt;
+                        }
+                    };
+                    // the next input row in BF16: x0..x3 (bytes 0-7) from lanes 0-31, x4 and the
+                    // eight time features of the next evaluation's t (bytes 8-25) from lanes
+                    // 32-63; the condition columns keep what the first evaluation wrote
+                    char *row = in0 + sn * C::IN_STRIDE;
                     if (lane < 32) {
+                        float x[4];
 #pragma unroll
-                        for (int d = 0; d < 4; ++d) emit(d, sn, out[0][0][d]);
+                        for (int d = 0; d < 4; ++d) x[d] = update(d, out[0][0][d]);
+                        *(u32x2 *)row = u32x2{pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3])};
                     } else {
-                        emit(4, sn, out[0][0][0]);
+                        const int e1 = e + 1, st1 = rk4 ? (e1 & 3) : 0, k1 = rk4 ? (e1 >> 2) : e1;
+                        const float t1 = ((float)k1 + (st1 == 0 ? 0.0f : (st1 == 3 ? 1.0f : 0.5f))) * dt;
+                        float f[9];
+                        f[0] = update(4, out[0][0][0]);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float a = (float)(1 << j) * t1;
+                            f[1 + 2 * j] = sinpif(a);
+                            f[2 + 2 * j] = cospif(a);
+                        }
+                        *(u32x2 *)(row + 8) = u32x2{pack_bf16(f[0], f[1]), pack_bf16(f[2], f[3])};
+                        *(u32x2 *)(row + 16) = u32x2{pack_bf16(f[4], f[5]), pack_bf16(f[6], f[7])};
+                        *(uint16_t *)(row + 24) = (uint16_t)(pack_bf16(f[8], 0.0f) & 0xFFFFu);
                     }
                 }
                 __syncthreads();
@@ -418,7 +454,7 @@ __global__ __launch_bounds__((FilmCfg<MP, H>::THREADS), 1) void film_ode_kernel(
         if (tid < kTileM) {
             const int64_t i = base + tid;
             float xk[5];
-            if constexpr (rk4) {
+            if constexpr (rk4 && !fold) {
                 advance(nevals - 1, xk);
             } else {
 #pragma unroll
