@@ -772,7 +772,8 @@ def main():
         detail["cpu_baseline"] = cb
         ca = cpu_baseline_analog()
         detail["cpu_baseline_analog_tau100"] = ca
-    head["detail"] = os.path.relpath(detail_path, ROOT)
+    dpath = os.path.abspath(detail_path)
+    head["detail"] = os.path.relpath(dpath, ROOT) if dpath.startswith(ROOT + os.sep) else dpath
     detail["headline"] = head
     try:
         os.makedirs(os.path.dirname(detail_path), exist_ok=True)
