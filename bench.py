@@ -396,31 +396,50 @@ def study_transport(binding, inputs, w512, n=1_000_000):
 def study_paper_scale(binding, inputs, w512, n=200_000):
     """The paper's two benchmark problems at its mesh size and cross sections, on layouts
     defined here (lattice: 112^2 cells, central volumetric source; hohlraum: 112^2 cells,
-    isotropic incident flux on the left side): analog MC against the generative sampler (BF16,
-    H = 512, RK4 x 12; and with the first-flight split and the collided model)."""
+    isotropic incident flux on the left side): analog MC against the generative sampler (H =
+    512, RK4 x 12): every transmission sampled (BF16); the first-flight split with the collided
+    model (BF16 and FP8 e4m3); and in the lattice the full method, births from the internal
+    model as well (BF16 and FP8)."""
     import torch
     from paper_2512_13965_amd import transport
-    model = binding.Model(inputs.pack_blob(w512), "bf16")
-    wc = fitted("gmc_h512_collided.bin")
-    col = None if wc is None else binding.Model(inputs.pack_blob(wc), "bf16")
+    opened = []
+
+    def model(w, prec):
+        if w is None:
+            return None
+        m = binding.Model(inputs.pack_blob(w), prec)
+        opened.append(m)
+        return m
+
+    plain = model(w512, "bf16")
+    wc, wi = fitted("gmc_h512_collided.bin"), fitted("gmc_h512_internal.bin")
+    col = {p: model(wc, p) for p in ("bf16", "fp8")}
+    src = {p: model(wi, p) for p in ("bf16", "fp8")}
     world = binding.World(1 << 20, 2, 1 << 14)
     out = {"histories": n}
     for pname, prob in (("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))):
-        runs = [("analog", binding.SAMPLER_MC, None), ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, model)]
-        if col is not None:
-            runs.append(("gmc_bf16_h512_rk4x12_split", binding.SAMPLER_GMC, col))
+        runs = [("analog", binding.SAMPLER_MC, None, {}),
+                ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, plain, {})]
+        for prec in ("bf16", "fp8"):
+            if col[prec] is not None:
+                runs.append((f"gmc_{prec}_h512_rk4x12_split", binding.SAMPLER_GMC, col[prec], {}))
+        if pname.startswith("lattice"):
+            for prec in ("bf16", "fp8"):
+                if col[prec] is not None and src[prec] is not None:
+                    runs.append((f"gmc_{prec}_h512_rk4x12_full", binding.SAMPLER_GMC, col[prec],
+                                 {"source_model": src[prec], "source_K": 12}))
         res, flux = {}, {}
-        for name, smp, m in runs:
-            transport.run_problem(world, prob, 5_000, 7, smp, m, 12, integrator="rk4")
+        for name, smp, m, kw in runs:
+            transport.run_problem(world, prob, 5_000, 7, smp, m, 12, integrator="rk4", streaming=64, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = transport.run_problem(world, prob, n, 1, smp, m, 12, integrator="rk4")
+            r = transport.run_problem(world, prob, n, 1, smp, m, 12, integrator="rk4", streaming=64, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             flux[name] = r["flux"] / n
             res[name] = {"seconds": dt, "transmissions_per_s": r["transmissions"] / dt,
                          "leak_per_history": float(r["leak"].sum() / n), **sampler_health(r, n)}
-            log(f"{pname} {name}: {dt:.2f} s")
+            log(f"{pname} {name}: {dt:.3f} s")
         l1 = lambda a: float(np.abs(a - flux["analog"]).sum() / np.abs(flux["analog"]).sum())
         for name in flux:
             if name != "analog":
@@ -428,9 +447,8 @@ def study_paper_scale(binding, inputs, w512, n=200_000):
         res["mc_noise_rel_l1"] = l1(transport.run_problem(world, prob, n, 2, binding.SAMPLER_MC)["flux"] / n)
         out[pname] = res
     world.close()
-    model.close()
-    if col is not None:
-        col.close()
+    for m in opened:
+        m.close()
     return out
 
 
