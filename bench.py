@@ -610,9 +610,11 @@ def profile_launches(args):
         # the paper's lattice (112^2 cells) with the full method at width 512: births from the
         # internal model, collided crossings from the collided boundary model (RK4 x 12), the
         # uncollided ones streamed through up to 64 cells inside a step
+        # (lattice_split:fp8: both models in FP8 e4m3)
         from paper_2512_13965_amd import transport
-        col = binding.Model(inputs.pack_blob(fitted("gmc_h512_collided.bin")), "bf16")
-        src = binding.Model(inputs.pack_blob(fitted("gmc_h512_internal.bin")), "bf16")
+        mprec = "fp8" if args.profile.split(":")[1:] == ["fp8"] else "bf16"
+        col = binding.Model(inputs.pack_blob(fitted("gmc_h512_collided.bin")), mprec)
+        src = binding.Model(inputs.pack_blob(fitted("gmc_h512_internal.bin")), mprec)
         w = binding.World(1 << 20, 2, 1 << 14)
         N = 200_000
         walls = []
@@ -626,7 +628,8 @@ def profile_launches(args):
         w.close()
         col.close()
         src.close()
-        print(json.dumps({"lattice_split_s": walls, "steps": r["steps"], "transmissions": int(r["transmissions"])}))
+        print(json.dumps({"lattice_split_s": walls, "precision": mprec, "steps": r["steps"],
+                          "transmissions": int(r["transmissions"])}))
     elif kind == "transport":
         from paper_2512_13965_amd import transport
         w = binding.World(1 << 20, 1, 1 << 12)
@@ -655,7 +658,7 @@ def main():
                     help="run one longer study instead of the benchmark")
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: bf16 | fp8 | rk4 | film | film_rk4 (H = 512, 2^20, "
-                         "fitted weights) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport | lattice_split")
+                         "fitted weights) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport | lattice_split[:fp8]")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
