@@ -396,10 +396,11 @@ def study_transport(binding, inputs, w512, n=1_000_000):
 def study_paper_scale(binding, inputs, w512, n=200_000):
     """The paper's two benchmark problems at its mesh size and cross sections, on layouts
     defined here (lattice: 112^2 cells, central volumetric source; hohlraum: 112^2 cells,
-    isotropic incident flux on the left side): analog MC against the generative sampler (H =
-    512, RK4 x 12): every transmission sampled (BF16); the first-flight split with the collided
-    model (BF16 and FP8 e4m3); and in the lattice the full method, births from the internal
-    model as well (BF16 and FP8)."""
+    isotropic incident flux on the left side): analog MC against the generative sampler: at
+    width 512 with RK4 x 12, every transmission sampled (BF16), the first-flight split with the
+    collided model (BF16 and FP8 e4m3) and in the lattice the full method, births from the
+    internal model as well (BF16 and FP8); at width 128 (BF16) the split and the full method
+    with RK4 x 12 and with Euler K = 16."""
     import torch
     from paper_2512_13965_amd import transport
     opened = []
@@ -415,25 +416,32 @@ def study_paper_scale(binding, inputs, w512, n=200_000):
     wc, wi = fitted("gmc_h512_collided.bin"), fitted("gmc_h512_internal.bin")
     col = {p: model(wc, p) for p in ("bf16", "fp8")}
     src = {p: model(wi, p) for p in ("bf16", "fp8")}
+    col128, src128 = model(fitted("gmc_h128_collided.bin"), "bf16"), model(fitted("gmc_h128_internal.bin"), "bf16")
     world = binding.World(1 << 20, 2, 1 << 14)
     out = {"histories": n}
+    rk4, eul = ("rk4", 12), ("euler", 16)
     for pname, prob in (("lattice_112", inputs.lattice_problem(16)), ("hohlraum_112", inputs.hohlraum_problem(112))):
-        runs = [("analog", binding.SAMPLER_MC, None, {}),
-                ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, plain, {})]
+        lattice = pname.startswith("lattice")
+        runs = [("analog", binding.SAMPLER_MC, None, rk4, {}),
+                ("gmc_bf16_h512_rk4x12", binding.SAMPLER_GMC, plain, rk4, {})]
         for prec in ("bf16", "fp8"):
             if col[prec] is not None:
-                runs.append((f"gmc_{prec}_h512_rk4x12_split", binding.SAMPLER_GMC, col[prec], {}))
-        if pname.startswith("lattice"):
-            for prec in ("bf16", "fp8"):
-                if col[prec] is not None and src[prec] is not None:
-                    runs.append((f"gmc_{prec}_h512_rk4x12_full", binding.SAMPLER_GMC, col[prec],
-                                 {"source_model": src[prec], "source_K": 12}))
+                runs.append((f"gmc_{prec}_h512_rk4x12_split", binding.SAMPLER_GMC, col[prec], rk4, {}))
+            if lattice and col[prec] is not None and src[prec] is not None:
+                runs.append((f"gmc_{prec}_h512_rk4x12_full", binding.SAMPLER_GMC, col[prec], rk4,
+                             {"source_model": src[prec], "source_K": 12}))
+        if col128 is not None:
+            for integ, tag in ((rk4, "rk4x12"), (eul, "euler16")):
+                runs.append((f"gmc_bf16_h128_{tag}_split", binding.SAMPLER_GMC, col128, integ, {}))
+                if lattice and src128 is not None:
+                    runs.append((f"gmc_bf16_h128_{tag}_full", binding.SAMPLER_GMC, col128, integ,
+                                 {"source_model": src128, "source_K": integ[1]}))
         res, flux = {}, {}
-        for name, smp, m, kw in runs:
-            transport.run_problem(world, prob, 5_000, 7, smp, m, 12, integrator="rk4", streaming=64, **kw)
+        for name, smp, m, (integ, K), kw in runs:
+            transport.run_problem(world, prob, 5_000, 7, smp, m, K, integrator=integ, streaming=64, **kw)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            r = transport.run_problem(world, prob, n, 1, smp, m, 12, integrator="rk4", streaming=64, **kw)
+            r = transport.run_problem(world, prob, n, 1, smp, m, K, integrator=integ, streaming=64, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             flux[name] = r["flux"] / n
@@ -455,34 +463,44 @@ def study_paper_scale(binding, inputs, w512, n=200_000):
 def study_thick(binding, inputs, n=50_000):
     """Transport through optically thick, highly scattering media (16 x 16 checkerboards of
     (tau, c) = (100, 0.99) / (300, 0.999) and (300, 0.999) / (1000, 0.99), central 2 x 2
-    source): analog MC against the fitted H = 128 model (BF16, RK4 x 12)."""
+    source): analog MC against the fitted H = 128 model (BF16, RK4 x 12), with analog births and
+    with births from the fitted H = 128 internal model."""
     import torch
     from paper_2512_13965_amd import transport
-    w128 = fitted("gmc_h128.bin")
+    w128, wi = fitted("gmc_h128.bin"), fitted("gmc_h128_internal.bin")
     m = binding.Model(inputs.pack_blob(w128), "bf16")
+    src = None if wi is None else binding.Model(inputs.pack_blob(wi), "bf16")
     out = {"histories": n}
     for name, tau, c in (("checker16_tau100_300", (100.0, 300.0), (0.99, 0.999)),
                          ("checker16_tau300_1000", (300.0, 1000.0), (0.999, 0.99))):
         prob = inputs.checkerboard_problem(16, tau=tau, c=c, src=2)
         world = binding.World(1 << 18, 1, 1 << 12)
         res, runs = {}, {}
-        for rn, smp, mm, integ, K, seed in (("analog", binding.SAMPLER_MC, None, "euler", 16, 1),
-                                            ("analog_seed2", binding.SAMPLER_MC, None, "euler", 16, 2),
-                                            ("gmc_bf16_h128_rk4x12", binding.SAMPLER_GMC, m, "rk4", 12, 3)):
-            transport.run_problem(world, prob, 2_000, 7, smp, mm, K, integrator=integ)
+        cases = [("analog", binding.SAMPLER_MC, None, "euler", 16, 1, None),
+                 ("analog_seed2", binding.SAMPLER_MC, None, "euler", 16, 2, None),
+                 ("gmc_bf16_h128_rk4x12", binding.SAMPLER_GMC, m, "rk4", 12, 3, None)]
+        if src is not None:
+            cases.append(("gmc_bf16_h128_rk4x12_internal_births", binding.SAMPLER_GMC, m, "rk4", 12, 3, src))
+        for rn, smp, mm, integ, K, seed, sm in cases:
+            transport.run_problem(world, prob, 2_000, 7, smp, mm, K, integrator=integ, source_model=sm, source_K=K)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            runs[rn] = transport.run_problem(world, prob, n, seed, smp, mm, K, integrator=integ)
+            runs[rn] = transport.run_problem(world, prob, n, seed, smp, mm, K, integrator=integ, source_model=sm,
+                                             source_K=K)
             torch.cuda.synchronize()
             res[rn] = {"seconds": time.perf_counter() - t0, **sampler_health(runs[rn], n)}
             log(f"{name} {rn}: {res[rn]['seconds']:.2f} s")
         world.close()
         l1 = lambda a, b: float(np.abs(a["flux"] - b["flux"]).sum() / np.abs(b["flux"]).sum())
-        res["gmc_bf16_h128_rk4x12"]["flux_rel_l1_vs_mc"] = l1(runs["gmc_bf16_h128_rk4x12"], runs["analog"])
-        res["gmc_bf16_h128_rk4x12"]["speedup_vs_analog"] = res["analog"]["seconds"] / res["gmc_bf16_h128_rk4x12"]["seconds"]
+        for rn in runs:
+            if rn.startswith("gmc"):
+                res[rn]["flux_rel_l1_vs_mc"] = l1(runs[rn], runs["analog"])
+                res[rn]["speedup_vs_analog"] = res["analog"]["seconds"] / res[rn]["seconds"]
         res["mc_noise_rel_l1"] = l1(runs["analog_seed2"], runs["analog"])
         out[name] = res
     m.close()
+    if src is not None:
+        src.close()
     return out
 
 

@@ -355,6 +355,7 @@ int gmc_model_create(const void *host_blob, size_t nbytes, int precision, gmc_mo
         delete m;
         return hip_fail(e, "gmc_model_create: upload");
     }
+    if (!film) mlp_prepare(precision, H);
     *out = m;
     return GMC_OK;
 }

@@ -110,6 +110,9 @@ struct MlpParams {
 // the launcher picks the tile size and a grid of at most cu persistent workgroups.
 hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s);
 bool mlp_supported(int prec, int hidden);
+// Takes the occupancy query behind the persistent grid of the plain network's kernels at this
+// precision and width (outside any stream capture: called when a model is created).
+void mlp_prepare(int prec, int hidden);
 hipError_t launch_film_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s);
 bool film_supported(int prec, int hidden);
 

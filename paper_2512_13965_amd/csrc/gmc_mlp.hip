@@ -51,6 +51,11 @@
 #ifndef GMC_WIDE_WAVES
 #define GMC_WIDE_WAVES 8
 #endif
+// Largest number of persistent workgroups per compute unit for the four-wave kernels (FP32, and
+// BF16 / FP8 at width 128), as far as registers and LDS allow.
+#ifndef GMC_MAX_WG_PER_CU
+#define GMC_MAX_WG_PER_CU 4
+#endif
 
 namespace gmc {
 namespace {
@@ -815,12 +820,36 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
 }
 
 // grid: one persistent workgroup per tile of a launch of at most `bound` samples, at most cu
+// Persistent workgroups per compute unit of one kernel instance.  The two-group kernels fill
+// a CU's LDS and keep one.  A four-wave kernel has one wave per SIMD, which leaves the vector
+// units idle while it runs matrix work and the matrix core idle during its epilogue; where
+// registers and LDS leave room, several of its workgroups share a CU and their phases
+// interleave (the occupancy query, at most GMC_MAX_WG_PER_CU; queried once per instance).
+template <int MP, int H, int RK, int TM>
+int resident_per_cu()
+{
+    if constexpr (Cfg<MP, H, TM>::GROUPS) {
+        return 1;
+    } else {
+        static const int n = [] {
+            int b = 1;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &b, reinterpret_cast<const void *>(&mlp_ode_kernel<MP, H, RK, TM>), Cfg<MP, H, TM>::THREADS,
+                    0) != hipSuccess || b < 1)
+                b = 1;
+            return std::min(b, GMC_MAX_WG_PER_CU);
+        }();
+        return n;
+    }
+}
+
 template <int MP, int H, int TM>
 hipError_t launch_tiles(const MlpParams &p, int64_t bound, int cu, hipStream_t s)
 {
     constexpr int threads = Cfg<MP, H, TM>::THREADS;
     const int64_t ntiles = (bound + TM - 1) / TM;
-    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, cu));
+    const int per_cu = p.integrator == 1 ? resident_per_cu<MP, H, 1, TM>() : resident_per_cu<MP, H, 0, TM>();
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ntiles, (int64_t)cu * per_cu));
     if (p.integrator == 1) hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 1, TM>), dim3(grid), dim3(threads), 0, s, p);
     else hipLaunchKernelGGL((mlp_ode_kernel<MP, H, 0, TM>), dim3(grid), dim3(threads), 0, s, p);
     return hipGetLastError();
@@ -892,6 +921,28 @@ bool mlp_supported(int prec, int hidden)
     if (prec == kF32) return hidden == 128 || hidden == 256;
     if (prec == kBF16 || prec == kFP8) return hidden == 128 || hidden == 256 || hidden == 512;
     return false;
+}
+
+template <int MP, int H>
+void prepare_one()
+{
+    (void)resident_per_cu<MP, H, 0, kTileM>();
+    (void)resident_per_cu<MP, H, 1, kTileM>();
+}
+
+void mlp_prepare(int prec, int hidden)
+{
+    switch (prec * 1000 + hidden) {
+    case kF32 * 1000 + 128: prepare_one<kF32, 128>(); break;
+    case kF32 * 1000 + 256: prepare_one<kF32, 256>(); break;
+    case kBF16 * 1000 + 128: prepare_one<kBF16, 128>(); break;
+    case kBF16 * 1000 + 256: prepare_one<kBF16, 256>(); break;
+    case kBF16 * 1000 + 512: prepare_one<kBF16, 512>(); break;
+    case kFP8 * 1000 + 128: prepare_one<kFP8, 128>(); break;
+    case kFP8 * 1000 + 256: prepare_one<kFP8, 256>(); break;
+    case kFP8 * 1000 + 512: prepare_one<kFP8, 512>(); break;
+    default: break;
+    }
 }
 
 hipError_t launch_mlp_ode(int prec, int hidden, const MlpParams &p, int cu, hipStream_t s)
