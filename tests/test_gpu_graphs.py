@@ -72,6 +72,21 @@ def test_graph_steps_match_direct_launches(sampler):
         model.close()
 
 
+def test_graph_steps_of_a_grid_with_several_workgroups_per_cu():
+    # width 128: the four-wave kernel's persistent grid holds several workgroups per CU once a
+    # step has more than 128 samples per CU (chunks of 60,000 particles); the grid size, taken
+    # from the occupancy query when the model is created, is baked into each captured graph
+    binding = require_gpu()
+    prob = inputs.checkerboard_problem(16, src=2)
+    n = 120_000
+    model = binding.Model(inputs.pack_blob(inputs.random_weights(128, 3)), "bf16")
+    eager = _run(binding, prob, n, 8, binding.SAMPLER_GMC, model, 4, False, 60_000)
+    graph = _run(binding, prob, n, 8, binding.SAMPLER_GMC, model, 4, True, 60_000)
+    model.close()
+    assert graph["steps"] == eager["steps"] and graph["transmissions"] == eager["transmissions"]
+    _same(graph, eager, n)
+
+
 def test_graph_replays_with_eager_work_between():
     binding = require_gpu()
     prob = inputs.checkerboard_problem(8, src=2)

@@ -152,6 +152,35 @@ def test_quantised_parity_vs_emulating_oracle(orc, prec, H, K):
     assert np.median(err) < 0.1 * np.median(err_exact)
 
 
+@pytest.mark.parametrize("prec,integ,K", [("bf16", "euler", 16), ("bf16", "rk4", 2), ("fp8", "euler", 16)])
+def test_width_128_grid_of_several_workgroups_per_cu(orc, prec, integ, K):
+    # 802 tiles of 128 samples: more than three per CU, so the four-wave kernel's persistent grid
+    # holds several workgroups per CU and some loop over a second tile; the first and last
+    # tiles and a ragged tail included
+    binding = require_gpu()
+    n = 3 * 128 * 256 + 4321
+    cond = inputs.transmission_conditions(n, SEED_COND)
+    w = inputs.random_weights(128, SEED_W)
+    m = binding.Model(inputs.pack_blob(w), prec)
+    dc = binding.DeviceCond.from_host(cond)
+    raw = torch.empty(5 * n, dtype=torch.float32, device="cuda")
+    binding.gmc_sample(m, dc, integ, K, SEED_NOISE, 0, raw=raw)
+    torch.cuda.synchronize()
+    m.close()
+    got = raw.view(5, n).cpu().numpy().astype(np.float64)
+    idx = np.unique(np.concatenate([sample_indices(n, 200, seed=4), np.arange(130), np.arange(n - 130, n)]))
+    sub = cond.subset(idx)
+    z = np.stack([orc.noise(SEED_NOISE, int(i), 1)[:, 0] for i in idx], axis=1)
+    oprec = orc.PREC_BF16_EXP2 if prec == "bf16" else orc.PREC_FP8_EXP2
+    ref = orc.sample_raw_rk4(w, sub, K, z, oprec) if integ == "rk4" else orc.sample_raw(w, sub, K, z, oprec)
+    err = np.abs(got[:, idx].T - ref).max(axis=1)
+    print(f"{prec} H=128 {integ} K={K}, n={n}: p99 {np.quantile(err, 0.99):.2e} max {err.max():.2e}")
+    if prec == "bf16":
+        assert np.quantile(err, 0.99) < 1e-5 and err.max() < 5e-5
+    else:
+        assert np.quantile(err, 0.99) < 1e-4 and err.max() < 3e-4
+
+
 TRAINED = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
                        "paper_2512_13965_amd", "weights", "gmc_h512.bin")
 
