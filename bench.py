@@ -246,8 +246,10 @@ def bench_samplers(binding, inputs, dev, stream, w512, reps=3):
             fn = lambda: binding.gmc_sample(m, cond, integ, KK, 2, 0, out=out_b)
             fn()
             t = float(np.median(time_launches(fn, reps, stream)))
+            ev = KK * (4 if integ == "rk4" else 1)
             rows.append({"precision": "bf16", "hidden": 128, "integrator": integ, "K": KK, "batch": NB,
-                         "ms": t, "tps": NB / (t * 1e-3)})
+                         "ms": t, "tps": NB / (t * 1e-3),
+                         "frac_peak": flops_per_sample(128, ev) * NB / (t * 1e-3) / PEAK["bf16"]})
         m.close()
     N1 = 65536
     m = binding.Model(inputs.pack_blob(inputs.random_weights(256, 1)), "fp32")
@@ -788,6 +790,7 @@ def main():
             "fp8_h512_euler16": tau_star(rate("fp8", "euler", 16), analog["tps"]),
             "bf16_h512_rk4x12": tau_star(rate("bf16", "rk4", 12), analog["tps"])}
     if any(r["hidden"] == 128 for r in rows):
+        star["bf16_h128_euler16"] = tau_star(rate("bf16", "euler", 16, 128), analog["tps"])
         star["bf16_h128_rk4x12"] = tau_star(rate("bf16", "rk4", 12, 128), analog["tps"])
     head["tau_star"] = star
     head["fp8_h512_k16"] = {"tps": rate("fp8", "euler", 16),
