@@ -609,6 +609,15 @@ def profile_launches(args):
         o = binding.DeviceExit.empty(N)
         for s in range(args.steps):
             binding.gmc_sample(m, c, integ, K, 2, s * N, out=o)
+    elif kind in ("h128", "h128_rk4"):
+        # the fitted width-128 model (BF16), 2^20 transmissions
+        integ, K = ("rk4", 12) if kind == "h128_rk4" else ("euler", HEAD_K)
+        m = binding.Model(inputs.pack_blob(fitted("gmc_h128.bin")), "bf16")
+        N = HEAD_N
+        c = binding.DeviceCond.from_host(inputs.transmission_conditions(N, 3))
+        o = binding.DeviceExit.empty(N)
+        for s in range(args.steps):
+            binding.gmc_sample(m, c, integ, K, 2, s * N, out=o)
     elif kind in ("film", "film_rk4"):
         integ, K = ("rk4", 12) if kind == "film_rk4" else ("euler", HEAD_K)
         w = fitted("gmc_film_h512.bin") or inputs.random_film_weights(HEAD_H, 1)
@@ -678,7 +687,7 @@ def main():
                     help="run one longer study instead of the benchmark")
     ap.add_argument("--profile", default=None,
                     help="only launch one kernel --steps times: bf16 | fp8 | rk4 | film | film_rk4 (H = 512, 2^20, "
-                         "fitted weights) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport | lattice_split[:fp8]")
+                         "fitted weights) | h128 | h128_rk4 (fitted width 128, 2^20) | fp32 (H = 256, 65,536) | walk:TAU[:LOG2N] | transport | lattice_split[:fp8]")
     ap.add_argument("--copy-ref", action="store_true",
                     help="only run plain device copies of 256 MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
