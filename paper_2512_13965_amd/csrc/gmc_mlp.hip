@@ -1,11 +1,13 @@
-// Fused velocity-MLP + Euler ODE sampler for gfx950 (paper: section "Conditional Flow
+// Fused velocity-MLP + ODE sampler for gfx950 (paper: section "Conditional Flow
 // Matching", eq. 8; network of section "Network Architecture and Inputs"; decoding of eq. 11).
 //
-// One persistent workgroup per CU (4 waves, 256 lanes) owns a tile of 128 samples at a time and
-// carries it through all K Euler steps x <- x + v(x, k/K | c) / K:
+// Persistent workgroups (four waves, or eight in the two-group schedule of BF16 / FP8 models
+// of width 256 and more) each own a tile of samples at a time and carry it through all ODE
+// steps (Euler x <- x + v(x, k/K | c) / K, or classic RK4):
 //   * the tile's activations live in LDS (128 x H), the ODE state x and the condition in LDS;
-//   * each hidden layer is a [H x H] x [H x 128] contraction on MFMA; wave w owns the output
-//     rows [w*H/4, (w+1)*H/4) and keeps its 32x32 accumulator tiles in registers;
+//   * each hidden layer is a [H x H] x [H x 128] contraction on MFMA; each wave owns a set of
+//     32-row output tiles (four-wave kernels: wave w the rows [w*H/4, (w+1)*H/4); two-group
+//     schedule: see Cfg) and keeps its 32x32 accumulator tiles in registers;
 //   * weights stream from L2 straight into MFMA operand registers, pre-arranged on the host in
 //     per-lane fragment order so each lane issues one 16-byte load per 32-row tile and k-block
 //     and a wave's loads are one contiguous 1 KB line;
@@ -819,7 +821,6 @@ __global__ __launch_bounds__((Cfg<MP, H, TM>::THREADS), 1) void mlp_ode_kernel(M
     }
 }
 
-// grid: one persistent workgroup per tile of a launch of at most `bound` samples, at most cu
 // Persistent workgroups per compute unit of one kernel instance.  The two-group kernels fill
 // a CU's LDS and keep one.  A four-wave kernel has one wave per SIMD, which leaves the vector
 // units idle while it runs matrix work and the matrix core idle during its epilogue; where
@@ -843,6 +844,8 @@ int resident_per_cu()
     }
 }
 
+// grid: one persistent workgroup per tile of a launch of at most `bound` samples, at most
+// cu x resident_per_cu
 template <int MP, int H, int TM>
 hipError_t launch_tiles(const MlpParams &p, int64_t bound, int cu, hipStream_t s)
 {
