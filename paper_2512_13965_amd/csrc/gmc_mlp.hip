@@ -834,11 +834,13 @@ int resident_per_cu()
     } else {
         static const int n = [] {
             int b = 1;
-            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &b, reinterpret_cast<const void *>(&mlp_ode_kernel<MP, H, RK, TM>), Cfg<MP, H, TM>::THREADS,
-                    0) != hipSuccess || b < 1)
+            const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &b, reinterpret_cast<const void *>(&mlp_ode_kernel<MP, H, RK, TM>), Cfg<MP, H, TM>::THREADS, 0);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();   // fall back to one workgroup; keep the error off later launches
                 b = 1;
-            return std::min(b, GMC_MAX_WG_PER_CU);
+            }
+            return std::max(1, std::min(b, GMC_MAX_WG_PER_CU));
         }();
         return n;
     }
