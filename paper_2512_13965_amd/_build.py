@@ -27,8 +27,14 @@ SOURCE_FLAGS = {"gmc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 def _compile(src: str) -> str:
     out = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *FLAGS, *SOURCE_FLAGS.get(src, []), "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+    extra = SOURCE_FLAGS.get(src, [])
+    cmd = [HIPCC, *FLAGS, *extra, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0 and extra and "Unknown command line argument" in r.stdout + r.stderr:
+        # a compiler without the register-form option: the same kernels, one more move per value
+        print(f"{src}: compiler rejects {' '.join(extra)}; building without it", file=sys.stderr)
+        cmd = [HIPCC, *FLAGS, "-x", "hip", "-c", os.path.join(CSRC, src), "-o", out]
+        r = subprocess.run(cmd, capture_output=True, text=True)
     errs = "\n".join(l for l in (r.stdout + r.stderr).splitlines()
                      if "packed-fp32-ops" not in l and "hip-link" not in l)
     if r.returncode != 0:
