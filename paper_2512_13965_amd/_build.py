@@ -18,11 +18,12 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-mcode-object-v
          # never emit packed FP32 arithmetic (v_pk_{add,mul,fma}_f32)
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable"]
-# Per-source device flags.  The sampler's MFMA accumulators stay in ordinary vector registers:
+# Per-source device flags.  The samplers' MFMA accumulators stay in ordinary vector registers:
 # the four-wave kernels (width 128, FP32) otherwise keep them in accumulation registers and move
 # every value out with one extra vector instruction in the epilogue (width 128: 7-8 % of the
 # launch); the two-group kernels already keep them there and compile to the same code.
-SOURCE_FLAGS = {"gmc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
+SOURCE_FLAGS = {"gmc_mlp.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"],
+                "gmc_film.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form=1"]}
 
 
 def _compile(src: str) -> str:
